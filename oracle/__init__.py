@@ -1,0 +1,4 @@
+"""FP64 CPU oracle: test infrastructure only (tests, smoke check, CPU baseline).
+
+The product library never imports this package.
+"""

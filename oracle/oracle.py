@@ -1,0 +1,239 @@
+"""Python face of the FP64 CPU oracle (``ot_oracle.c``) plus small helpers.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg; never by the product library, which must fail
+loudly rather than fall back to anything here. The oracle shares no code with
+the HIP path.
+
+What it computes (paper sections in parentheses):
+* ``rates`` / ``rates_rows``: R_ij = W log2(1 + SINR_ji) with full-power
+  interference from all other RRHs (Sec. II-A);
+* ``cost``: C_ij = (1/R_ij) / median(1/R), the load-per-unit-traffic cost of
+  Sec. IV choice (ii), median-normalised;
+* ``sinkhorn``: FP64 log-domain Sinkhorn (Sec. III-B, Sinkhorn algorithm),
+  stopping on the total absolute marginal residual (Sec. III, "Sinkhorn vs LP");
+* ``plan`` / ``plan_stats``: pi = exp((f + g - C)/eps) (the KKT form of
+  Sec. III-B), its marginals, <C, pi>, the objective of eq. (5) and the dual;
+* ``brute_force_ot``: the unregularised OT of eqs. (2)-(4) on tiny square
+  instances with uniform marginals, by enumeration of permutations;
+* ``maxsinr_traffic`` and ``lemma1_lower_bound``: the maxSINR rule and the
+  RRH traffic it induces (Sec. IV), and the total-load bound behind Lemma 1.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import itertools
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libot_oracle.so")
+SRC_PATH = os.path.join(HERE, "ot_oracle.c")
+
+OK, WARN_MAXITER, EINVAL, ENOMEM, ENUMERIC = 0, 1, -1, -2, -4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (strict IEEE: no fast-math, no contraction)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                        "-shared", "-std=c11", "-D_DEFAULT_SOURCE", "-o", tmp, SRC_PATH, "-lm"],
+                       check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Radio(ct.Structure):
+    _fields_ = [("tx_power_w", ct.c_double), ("ref_gain", ct.c_double), ("pathloss_exp", ct.c_double),
+                ("min_dist_m", ct.c_double), ("shadow_sigma_db", ct.c_double), ("noise_w", ct.c_double),
+                ("bandwidth_hz", ct.c_double), ("shadow_key", ct.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ct.CDLL(LIB_PATH)
+        dp, fp, i64, i64p = ct.POINTER(ct.c_double), ct.POINTER(ct.c_float), ct.c_int64, ct.POINTER(ct.c_int64)
+        L.ora_splitmix64.restype = ct.c_uint64
+        L.ora_splitmix64.argtypes = [ct.c_uint64]
+        L.ora_shadow_normal.restype = ct.c_double
+        L.ora_shadow_normal.argtypes = [ct.c_uint64, i64, i64]
+        L.ora_rates_rows.argtypes = [fp, fp, i64, ct.POINTER(_Radio), i64p, i64, dp]
+        L.ora_rates.argtypes = [fp, fp, i64, i64, ct.POINTER(_Radio), dp]
+        L.ora_lower_median.restype = ct.c_double
+        L.ora_lower_median.argtypes = [dp, i64]
+        L.ora_cost_from_rates.argtypes = [dp, i64, dp, dp]
+        L.ora_sinkhorn.argtypes = [dp, i64, i64, dp, dp, ct.c_double, ct.c_double, ct.c_int32, dp, dp, dp, dp,
+                                   ct.POINTER(ct.c_int32), dp]
+        L.ora_plan.argtypes = [dp, i64, i64, dp, dp, ct.c_double, dp]
+        L.ora_plan_stats.argtypes = [dp, i64, i64, dp, dp, dp, dp, ct.c_double, dp, dp, dp]
+        L.ora_sum.restype = ct.c_double
+        L.ora_sum.argtypes = [dp, i64]
+        _lib = L
+    return _lib
+
+
+def _d(x):
+    return x.ctypes.data_as(ct.POINTER(ct.c_double)) if x is not None else None
+
+
+def _c64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def radio_struct(layout) -> _Radio:
+    r = layout.radio
+    return _Radio(r["tx_power_w"], r["ref_gain"], r["pathloss_exp"], r["min_dist_m"], r["shadow_sigma_db"],
+                  r["noise_w"], r["bandwidth_hz"], ct.c_uint64(layout.shadow_key & (2**64 - 1)))
+
+
+def splitmix64(x: int) -> int:
+    return int(lib().ora_splitmix64(ct.c_uint64(x & (2**64 - 1))))
+
+
+def shadow_normal(key: int, i: int, j: int) -> float:
+    return float(lib().ora_shadow_normal(ct.c_uint64(key & (2**64 - 1)), i, j))
+
+
+def rates_rows(layout, rows) -> np.ndarray:
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    dev = np.ascontiguousarray(layout.dev_xy, dtype=np.float32)
+    rrh = np.ascontiguousarray(layout.rrh_xy, dtype=np.float32)
+    out = np.empty((rows.size, layout.J))
+    rad = radio_struct(layout)
+    st = lib().ora_rates_rows(dev.ctypes.data_as(ct.POINTER(ct.c_float)), rrh.ctypes.data_as(ct.POINTER(ct.c_float)),
+                              layout.J, ct.byref(rad), rows.ctypes.data_as(ct.POINTER(ct.c_int64)), rows.size, _d(out))
+    if st != OK:
+        raise RuntimeError(f"ora_rates_rows failed: {st}")
+    return out
+
+
+def rates(layout) -> np.ndarray:
+    return rates_rows(layout, np.arange(layout.I))
+
+
+def lower_median(x) -> float:
+    x = _c64(x).ravel()
+    return float(lib().ora_lower_median(_d(x), x.size))
+
+
+def cost(layout, scale: float = 0.0, R=None):
+    """Returns (C, scale). scale <= 0 means: the lower median of 1/R."""
+    R = _c64(rates(layout) if R is None else R)
+    C = np.empty_like(R)
+    s = ct.c_double(scale)
+    st = lib().ora_cost_from_rates(_d(R), R.size, ct.byref(s), _d(C))
+    if st != OK:
+        raise RuntimeError(f"ora_cost_from_rates failed: {st}")
+    return C, float(s.value)
+
+
+def cost_rows(layout, rows, scale: float) -> np.ndarray:
+    """Cost rows for a given (already known) scale, e.g. a sample of a large instance."""
+    if not scale > 0:
+        raise ValueError("cost_rows needs the scale")
+    return (1.0 / rates_rows(layout, rows)) / scale
+
+
+class SinkhornResult:
+    def __init__(self, status, f, g, iters, residual, hist):
+        self.status, self.f, self.g, self.iters, self.residual, self.hist = status, f, g, iters, residual, hist
+
+    def __repr__(self):
+        return f"SinkhornResult(status={self.status}, iters={self.iters}, residual={self.residual:.3e})"
+
+
+def sinkhorn(C, a, b, eps, tol, max_iter, g0=None, history=False) -> SinkhornResult:
+    C, a, b = _c64(C), _c64(a), _c64(b)
+    I, J = C.shape
+    f, g = np.empty(I), np.empty(J)
+    r, it = ct.c_double(0.0), ct.c_int32(0)
+    hist = np.full(max_iter, np.nan) if history else None
+    g0 = None if g0 is None else _c64(g0)
+    st = lib().ora_sinkhorn(_d(C), I, J, _d(a), _d(b), eps, tol, max_iter, _d(g0), _d(f), _d(g), ct.byref(r),
+                            ct.byref(it), _d(hist))
+    if st < 0:
+        raise ValueError(f"ora_sinkhorn rejected its inputs (status {st})")
+    if hist is not None:
+        hist = hist[: it.value]
+    return SinkhornResult(st, f, g, it.value, r.value, hist)
+
+
+def plan(C, f, g, eps) -> np.ndarray:
+    C, f, g = _c64(C), _c64(f), _c64(g)
+    pi = np.empty_like(C)
+    st = lib().ora_plan(_d(C), C.shape[0], C.shape[1], _d(f), _d(g), eps, _d(pi))
+    if st != OK:
+        raise ValueError(f"ora_plan failed: {st}")
+    return pi
+
+
+def plan_stats(C, a, b, f, g, eps) -> dict:
+    C, a, b, f, g = _c64(C), _c64(a), _c64(b), _c64(f), _c64(g)
+    I, J = C.shape
+    out, rs, cs = np.empty(5), np.empty(I), np.empty(J)
+    st = lib().ora_plan_stats(_d(C), I, J, _d(a), _d(b), _d(f), _d(g), eps, _d(out), _d(rs), _d(cs))
+    if st != OK:
+        raise ValueError(f"ora_plan_stats failed: {st}")
+    return dict(marginal_violation=out[0], objective=out[1], reg_objective=out[2], dual_objective=out[3],
+                mass=out[4], row_sums=rs, col_sums=cs)
+
+
+def osum(x) -> float:
+    x = _c64(x).ravel()
+    return float(lib().ora_sum(_d(x), x.size))
+
+
+# --------------------------------------------------------------- helpers --
+
+def brute_force_ot(C) -> tuple[float, tuple]:
+    """Unregularised OT of eqs. (2)-(4) for a square n x n cost with uniform
+    marginals 1/n: by Birkhoff's theorem an optimal plan is a permutation
+    matrix divided by n, so enumerate all permutations. Returns (value, sigma)."""
+    C = np.asarray(C, dtype=np.float64)
+    n = C.shape[0]
+    if C.shape != (n, n) or n > 9:
+        raise ValueError("brute force is for square instances with n <= 9")
+    best, arg = np.inf, None
+    rows = np.arange(n)
+    for perm in itertools.permutations(range(n)):
+        v = C[rows, perm].sum() / n
+        if v < best:
+            best, arg = v, perm
+    return float(best), arg
+
+
+def maxsinr_association(R) -> np.ndarray:
+    """maxSINR rule (Sec. II-A / IV): each device to its highest-rate RRH,
+    lowest index on ties. Returns the RRH index per device."""
+    return np.argmax(np.asarray(R), axis=1)
+
+
+def maxsinr_traffic(R, lam) -> np.ndarray:
+    """Lambda_j = sum_i pi^SINR_ij lambda_i: the RRH traffic under maxSINR."""
+    R = np.asarray(R)
+    out = np.zeros(R.shape[1])
+    np.add.at(out, maxsinr_association(R), np.asarray(lam, dtype=np.float64))
+    return out
+
+
+def lemma1_lower_bound(C, a) -> float:
+    """Every coupling with row sums a pays at least sum_i a_i min_j C_ij; with
+    q = maxSINR traffic and C = 1/R this bound is attained (Lemma 1)."""
+    C = np.asarray(C, dtype=np.float64)
+    return osum(np.asarray(a, dtype=np.float64) * C.min(axis=1))
+
+
+def entropy(x) -> float:
+    x = np.asarray(x, dtype=np.float64)
+    x = x[x > 0]
+    return float(-(x * np.log(x)).sum())
