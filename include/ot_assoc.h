@@ -1,0 +1,208 @@
+/*
+ * ot_assoc.h - entropy-regularised optimal-transport device association on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the regularised OT problem of eq. (5) of "Computational
+ * Optimal Transport for 5G Massive C-RAN Device Association" (Sec. III-B):
+ *
+ *     min_pi  sum_ij C_ij pi_ij + eps sum_ij pi_ij (log pi_ij - 1)
+ *     s.t.    sum_j pi_ij = a_i  (device traffic, the paper's p = lambda)
+ *             sum_i pi_ij = b_j  (RRH load target, the paper's q)
+ *
+ * with the Sinkhorn iteration of Sec. III-B, written on log-domain dual
+ * potentials f_i, g_j so that pi_ij = exp((f_i + g_j - C_ij) / eps) (the KKT
+ * form of the Lagrangian, Sec. III-B). The cost is either a dense matrix, a
+ * rate matrix R_ij with C_ij = (1/R_ij) / scale (Sec. IV, cost choice (ii):
+ * load per unit traffic), or device/RRH geometry from which the rates of the
+ * downlink model of Sec. II-A are regenerated on the fly and never stored.
+ *
+ * Conventions for every call
+ *   - Return value: OT_OK (0), a warning (> 0) or an error (< 0). No
+ *     exception, abort or exit crosses this boundary. On error the outputs are
+ *     left untouched and ot_assoc_last_error() describes the cause.
+ *   - Ownership: the caller owns every pointer it passes. Marginals,
+ *     positions and host-memory matrices are copied into the handle's device
+ *     workspace. One exception avoids copying large matrices: a DENSE or
+ *     RATES matrix in device memory is referenced, not copied, and must stay
+ *     valid and unchanged until the next call on the handle that takes a cost
+ *     descriptor (ot_assoc_plan and ot_assoc_time_sweep read it again). The
+ *     handle owns its device workspace.
+ *   - Layout: matrices are row-major I x J (devices are rows, RRHs are
+ *     columns) with leading dimension J, contiguous. Positions are I x 2 and
+ *     J x 2 float arrays of (x, y) in metres.
+ *   - Memory spaces: OT_MEM_HOST pointers are ordinary host memory;
+ *     OT_MEM_DEVICE pointers are device memory of the handle's device
+ *     (e.g. torch tensors' data_ptr()).
+ *   - Synchrony: every call returns with its outputs final. Work is issued on
+ *     the stream given at creation; with NULL the handle creates its own
+ *     stream, which is ordered after earlier work on the legacy default stream.
+ *   - Threading: a handle is used by one host thread at a time; distinct
+ *     handles may be used concurrently.
+ */
+#ifndef OT_ASSOC_H
+#define OT_ASSOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ot_assoc ot_assoc; /* opaque solver handle */
+
+typedef enum {
+    OT_OK = 0,
+    OT_WARN_MAXITER = 1, /* max_iter reached before tol; the result is valid */
+    OT_EINVAL = -1,      /* an argument failed validation */
+    OT_ENOMEM = -2,      /* device or host allocation failed */
+    OT_EDEVICE = -3,     /* a HIP runtime call failed */
+    OT_ENUMERIC = -4,    /* a non-finite residual or potential appeared */
+    OT_ESTATE = -5       /* call made in the wrong state (e.g. plan before solve) */
+} ot_status;
+
+typedef enum { OT_COST_DENSE = 0, OT_COST_RATES = 1, OT_COST_GEOMETRY = 2 } ot_cost_kind;
+typedef enum { OT_MEM_HOST = 0, OT_MEM_DEVICE = 1 } ot_mem;
+typedef enum { OT_F32 = 0, OT_F64 = 1 } ot_dtype;
+
+/* Arithmetic of the Sinkhorn sweeps. In both modes the potentials f, g are
+ * kept in FP64 and the returned plan's statistics are computed in FP64.
+ *   OT_PREC_FP32: sweeps use FP32 exponentials (and, for geometry costs, an
+ *     FP32 cost functor) until the residual stalls or meets tol, then FP64
+ *     sweeps polish the iterate until the FP64 residual meets tol.
+ *   OT_PREC_FP64: every sweep is FP64. */
+typedef enum { OT_PREC_FP32 = 0, OT_PREC_FP64 = 1 } ot_precision;
+
+/* Downlink geometry (Sec. II-A): R_ij = W log2(1 + SINR_ji) with
+ *   SINR_ji = P G_ji / (sum_{k != j} P G_ki + N0),
+ *   G_ji = ref_gain * max(d_ij, min_dist_m)^(-pathloss_exp) * 10^(sigma X_ij / 10),
+ * X_ij standard normal from the counter-based draw: h = SplitMix64 output
+ * for state shadow_key ^ (i * 2^32 + j); u1, u2 = (high, low 32 bits of h
+ * + 1/2) * 2^-32; X = sqrt(-2 ln u1) cos(2 pi u2) (Box-Muller). */
+typedef struct {
+    const float *dev_xy; /* I x 2, metres, in the descriptor's memory space */
+    const float *rrh_xy; /* J x 2, metres, in the descriptor's memory space */
+    double tx_power_w;   /* P (same for every RRH, all at full power) */
+    double ref_gain;     /* K0: gain at 1 m */
+    double pathloss_exp; /* alpha */
+    double min_dist_m;   /* d_min */
+    double shadow_sigma_db;
+    double noise_w;      /* N0 */
+    double bandwidth_hz; /* W */
+    uint64_t shadow_key;
+} ot_geometry;
+
+/* The association instance (C, a, b). a (I) and b (J) are FP64 and live in
+ * the memory space `mem`, as do `data` and the geometry arrays. */
+typedef struct {
+    ot_cost_kind kind;
+    int64_t I, J;
+    ot_mem mem;
+    ot_dtype dtype;   /* element type of `data` (DENSE / RATES) */
+    const void *data; /* DENSE: C_ij; RATES: R_ij > 0 */
+    double scale;     /* RATES / GEOMETRY: C_ij = (1 / R_ij) / scale, scale > 0 */
+    ot_geometry geom; /* GEOMETRY only */
+} ot_cost_desc;
+
+typedef struct {
+    int device;         /* HIP device ordinal */
+    void *stream;       /* hipStream_t to issue work on; NULL = a stream owned by the handle */
+    ot_precision precision;
+    int polish_iters;   /* FP64 iterations run before the first exact check (default 1) */
+    int chunk;          /* iterations per graph launch between host checks (default 8) */
+    int use_graphs;     /* capture iteration chunks in HIP graphs (default 1) */
+    int sweep_blocks;   /* 0 = choose automatically; else workgroups per sweep */
+    int sweep_waves;    /* 0 = choose automatically; 4 or 8 waves per workgroup (dense FP32 costs) */
+    int sweep_rows;     /* 0 = choose automatically; else 1, 2, 4 or 8 row steps in flight per wave */
+    int sweep_lanes;    /* 0 = choose automatically; else 16, 32 or 64 lanes per row */
+} ot_assoc_options;
+
+typedef struct {
+    int32_t iterations;      /* full (row + column) iterations of the returned iterate */
+    int32_t fp64_iterations; /* FP64 sweeps run by the solve (polish and exact phases) */
+    int32_t status;          /* ot_status of the solve */
+    int32_t reserved;
+    double marginal_violation; /* (sum_i |rowsum_i - a_i| + sum_j |colsum_j - b_j|) / sum(a), FP64 */
+    double objective;          /* <C, pi> (transport cost) */
+    double reg_objective;      /* <C, pi> + eps sum pi (log pi - 1), eq. (5) */
+    double dual_objective;     /* <f, a> + <g, b> - eps sum pi */
+    double seconds;            /* device time of the solve (HIP events) */
+} ot_assoc_result;
+
+/* Fills *opt with the defaults listed above (device 0, default stream). */
+ot_status ot_assoc_default_options(ot_assoc_options *opt);
+
+/* Creates a handle able to solve instances up to I_max x J_max on
+ * opt->device (opt NULL = defaults). Allocates the device workspace:
+ * O(I_max + J_max) vectors plus per-workgroup partials, and an
+ * I_max x J_max staging matrix only when a host-memory dense or rate cost is
+ * later passed. Errors: OT_EINVAL (I_max or J_max < 1), OT_ENOMEM, OT_EDEVICE. */
+ot_status ot_assoc_create(ot_assoc **h, int64_t I_max, int64_t J_max, const ot_assoc_options *opt);
+
+/* Solves one instance (eq. (5) with the Sinkhorn iteration of Sec. III-B).
+ *   eps > 0: regularisation strength; tol >= 0: stop when the total absolute
+ *   marginal residual of the iterate, relative to sum(a), is below tol (the
+ *   stop rule of the paper's Sinkhorn-vs-LP experiment); max_iter >= 1.
+ *   warm_start != 0 starts from the handle's current potentials (those of
+ *   the previous solve of the same shape, or set by ot_assoc_set_potentials);
+ *   otherwise from g = 0 (the all-ones column scaling of the algorithm).
+ * Validation (OT_EINVAL, nothing written): 1 <= I <= I_max, 1 <= J <= J_max;
+ * a_i > 0, b_j > 0, all finite; |sum a - sum b| <= 1e-12 sum a; eps > 0 and
+ * finite; tol >= 0; max_iter >= 1; scale > 0 for RATES / GEOMETRY; geometry
+ * constants positive (noise_w >= 0, shadow_sigma_db >= 0). Dense costs and
+ * rates are checked on the device (non-finite C or R <= 0 give OT_EINVAL).
+ * Returns OT_OK, OT_WARN_MAXITER (result valid, tol not met) or an error.
+ * `out` may be NULL. */
+ot_status ot_assoc_solve(ot_assoc *h, const ot_cost_desc *cost, const double *a, const double *b, double eps,
+                         double tol, int32_t max_iter, int warm_start, ot_assoc_result *out);
+
+/* Writes the plan pi_ij = exp((f_i + g_j - C_ij) / eps) of the last
+ * successful solve (the output step of the Sinkhorn algorithm) into the
+ * caller's I x J row-major buffer of element type `dtype` in space `mem`,
+ * computed in FP64 from the retained cost. Errors: OT_ESTATE before any
+ * successful solve or after ot_assoc_cost_median / ot_assoc_materialize_cost
+ * replaced the retained cost, OT_EINVAL for NULL pi. */
+ot_status ot_assoc_plan(ot_assoc *h, void *pi, ot_mem mem, ot_dtype dtype);
+
+/* Copies out the FP64 potentials (f: I, g: J) of the last solve. Either
+ * pointer may be NULL. Errors: OT_ESTATE before any solve. */
+ot_status ot_assoc_potentials(ot_assoc *h, double *f, double *g, ot_mem mem);
+
+/* Sets the potentials used by the next warm-started solve of an I x J
+ * instance. Errors: OT_EINVAL on sizes out of range or NULL pointers. */
+ot_status ot_assoc_set_potentials(ot_assoc *h, const double *f, const double *g, int64_t I, int64_t J, ot_mem mem);
+
+/* Lower median (element floor((IJ - 1) / 2) in sorted order) of the I*J
+ * values 1/R_ij of a RATES or GEOMETRY descriptor, computed on the device in
+ * FP32 by radix selection over the regenerated values; the normalisation of
+ * the cost C = (1/R)/median. The descriptor's `scale` is ignored.
+ * Errors: OT_EINVAL (bad descriptor or sizes), OT_EDEVICE. */
+ot_status ot_assoc_cost_median(ot_assoc *h, const ot_cost_desc *cost, double *median_out);
+
+/* Writes the FP32 cost C_ij of a RATES or GEOMETRY descriptor into the
+ * caller's device buffer C (I x J row-major): the materialised form of the
+ * cost that the geometry sweeps regenerate on the fly. */
+ot_status ot_assoc_materialize_cost(ot_assoc *h, const ot_cost_desc *cost, float *C_dev);
+
+/* (instrumentation) Average device duration, in milliseconds, of one launch
+ * of the fused sweep kernel that the last successful solve used (same cost,
+ * shape and launch configuration; FP32 exponentials if fp64 == 0, else FP64).
+ * Runs `reps` (1..4096) extra iterations, each sweep bracketed by HIP events
+ * on the handle's stream, then restores the solve's potentials, so a later
+ * ot_assoc_plan / ot_assoc_potentials is unaffected.
+ * Errors: OT_ESTATE before a successful solve, OT_EINVAL for bad reps. */
+ot_status ot_assoc_time_sweep(ot_assoc *h, int32_t reps, int fp64, double *ms_per_launch);
+
+/* Frees the handle and its device workspace. NULL-safe. */
+void ot_assoc_destroy(ot_assoc *h);
+
+/* Human-readable description of the last error on this handle ("" if none).
+ * The string is owned by the handle and valid until its next call. With
+ * h == NULL it describes the last failed ot_assoc_create on this thread. */
+const char *ot_assoc_last_error(const ot_assoc *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OT_ASSOC_H */

@@ -1,0 +1,140 @@
+// Device-side helpers shared by the association kernels: wavefront (64-lane)
+// reductions, the per-solve control block and the constants of the log2
+// domain in which every exponential is taken.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace otk {
+
+constexpr int kWave = 64;
+constexpr double kLog2e = 1.4426950408889634074;  // 1 / ln 2
+constexpr double kLn2 = 0.69314718055994530942;
+
+// ---------------------------------------------------------------- reductions
+// Reductions over the 64 lanes of a wavefront with DPP lane moves: xor-1 and
+// xor-2 quad permutes, the 8-lane half-row mirror and the 16-lane row mirror
+// leave every row of 16 lanes holding its row total; the four row totals are
+// then read out and combined as (r0 + r1) + (r2 + r3). Every lane ends with
+// the same value, in the same order on every call, so results are bitwise
+// reproducible. DPP control codes: quad_perm(1,0,3,2) = 0xB1,
+// quad_perm(2,3,0,1) = 0x4E, row_mirror = 0x140, row_half_mirror = 0x141.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float readlane_f(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_d<0xB1>(v));
+    v = fmax(v, dpp_d<0x4E>(v));
+    v = fmax(v, dpp_d<0x141>(v));
+    v = fmax(v, dpp_d<0x140>(v));
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+__device__ __forceinline__ float wave_max(float v) {
+    v = fmaxf(v, dpp_f<0xB1>(v));
+    v = fmaxf(v, dpp_f<0x4E>(v));
+    v = fmaxf(v, dpp_f<0x141>(v));
+    v = fmaxf(v, dpp_f<0x140>(v));
+    return fmaxf(fmaxf(readlane_f(v, 0), readlane_f(v, 16)), fmaxf(readlane_f(v, 32), readlane_f(v, 48)));
+}
+
+// Reductions over a group of LPR (16, 32 or 64) consecutive lanes; every lane
+// of the group ends with the group's value. Within 16 lanes the same DPP
+// steps as above; wider groups add xor-16 and xor-32 exchanges. Each step
+// combines a lane's value with its partner's, so all lanes of a group agree.
+template <int LPR>
+__device__ __forceinline__ double group_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    if constexpr (LPR >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (LPR >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+template <int LPR>
+__device__ __forceinline__ float group_max(float v) {
+    v = fmaxf(v, dpp_f<0xB1>(v));
+    v = fmaxf(v, dpp_f<0x4E>(v));
+    v = fmaxf(v, dpp_f<0x141>(v));
+    v = fmaxf(v, dpp_f<0x140>(v));
+    if constexpr (LPR >= 32) v = fmaxf(v, __shfl_xor(v, 16, 64));
+    if constexpr (LPR >= 64) v = fmaxf(v, __shfl_xor(v, 32, 64));
+    return v;
+}
+template <int LPR>
+__device__ __forceinline__ double group_max(double v) {
+    v = fmax(v, dpp_d<0xB1>(v));
+    v = fmax(v, dpp_d<0x4E>(v));
+    v = fmax(v, dpp_d<0x141>(v));
+    v = fmax(v, dpp_d<0x140>(v));
+    if constexpr (LPR >= 32) v = fmax(v, __shfl_xor(v, 16, 64));
+    if constexpr (LPR >= 64) v = fmax(v, __shfl_xor(v, 32, 64));
+    return v;
+}
+
+// 2^x for x <= 0 in FP32 (one v_exp_f32).
+__device__ __forceinline__ float exp2_f32(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ------------------------------------------------------------- control block
+// Per-solve state that lives in device memory so that a captured chunk of
+// iterations can decide on the device when to stop, without a host round
+// trip per iteration.
+enum : int {
+    kModeFast = 0,    // FP32 sweeps: stop the chunk when the residual meets tol or stalls
+    kModePolish = 1,  // FP64 sweeps run unconditionally (no stop decision)
+    kModeExact = 2,   // FP64 sweeps: stop when an FP64 iterate meets tol
+};
+
+struct Ctl {
+    int32_t iter;          // full iterations completed (the current iterate's number)
+    int32_t stop;          // 1: remaining launches of the current chunk do nothing
+    int32_t done;          // 1: converged (or failed); result_iter names the iterate
+    int32_t result_iter;   // iterate to return when done
+    int32_t numeric_bad;   // a non-finite value appeared
+    int32_t fp64_iters;    // FP64 sweeps completed
+    int32_t last_fp64;     // 1 if the current iterate came from an FP64 sweep
+    int32_t max_iter;
+    uint32_t arrive;       // last-block-done counter of the combine kernel
+    uint32_t arrive2;      // same, for the check kernel
+    int32_t has_prev;      // 1 if a previous iterate f^(k-1) exists (k >= 1 or warm start)
+    int32_t pad_;
+    double tol;
+    double mass;           // sum(a)
+    double r_last;         // residual of iterate (iter - 1), measured during iteration iter
+    double r_hist[4];      // recent fast-mode residuals (stall detection)
+    // results of the exact check of the current iterate
+    double chk_violation, chk_objective, chk_reg_objective, chk_dual, chk_mass;
+    double chk_row_res, chk_col_res;
+};
+
+}  // namespace otk

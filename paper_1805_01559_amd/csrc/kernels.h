@@ -1,0 +1,705 @@
+// Association kernels for gfx950: one launch per Sinkhorn iteration (fused
+// row update, column partials and the column combine), the exact FP64 check
+// of an iterate, the plan writer and the per-instance set-up passes.
+//
+// Iteration k of the Sinkhorn algorithm (Sec. III-B), in log-domain form with
+// FP64 potentials (f = eps log of the row scaling, g = eps log of the column
+// scaling), is two launches:
+//
+//  k_iter    one read (or regeneration) of C per iteration. For every row i,
+//            in base 2 with kk = log2(e) / eps,
+//              t_ij = g_j kk - C_ij kk,  m_i = max_j t_ij,
+//              e_ij = 2^(t_ij - m_i),   s_i = sum_j e_ij,
+//              f_i  = eps (ln a_i - ln 2 (m_i + log2 s_i))      (row update)
+//            and, from the same registers, the half-iterate plan entries
+//              pi_ij = exp((f_i + g_j - C_ij)/eps) = e_ij a_i / s_i,
+//            summed per column over the workgroup's rows. The row residual
+//            |rowsum_i(pi^(k-1)) - a_i| = a_i |expm1((f_i^(k-1) - f_i)/eps)| of the
+//            previous full iterate falls out of the change in f.
+//  k_colsum  a second, small launch: each workgroup owns a slice of columns and
+//            sums all workgroup partials of them in a fixed order, then
+//              g_j <- g_j + eps (ln b_j - ln colsum_j)               (column update)
+//            which is exactly eps ln b_j - eps LSE_i((f_i - C_ij)/eps). Its
+//            first workgroup also sums the row residuals and takes the stop
+//            decision for the chunk of iterations in flight.
+//
+// The exponentials e_ij are FP32 (v_exp_f32) in the fast sweeps and FP64 in
+// the polish sweeps; arguments t_ij and every accumulation across lanes,
+// rows and workgroups are FP64. Every reduction has a fixed order, so results
+// are bitwise reproducible for a given launch shape. Workgroups never exchange
+// data inside a launch: on this GPU a device-scope fence writes back the
+// whole L2 of its XCD, so cross-workgroup results travel through the kernel
+// boundary instead.
+#pragma once
+
+#include <type_traits>
+
+#include "cost_sources.h"
+#include "device_common.h"
+
+namespace otk {
+
+struct SolveParams {
+    double kk;   // log2(e) / eps
+    double eps;
+};
+
+// ------------------------------------------------- block-level reductions --
+// Sums acc[NCH][VEC] over the WAVES waves of a workgroup through LDS in a
+// fixed tree order; wave 0 ends with the block total.
+template <int NCH, int VEC, int WAVES>
+__device__ __forceinline__ void block_tree(double (&acc)[NCH][VEC], int nch, double* red, int ncols, int w, int lane) {
+#pragma unroll
+    for (int half = WAVES / 2; half >= 1; half >>= 1) {
+        if (w >= half && w < 2 * half) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) red[(w - half) * ncols + (ch * kWave + lane) * VEC + v] = acc[ch][v];
+        }
+        __syncthreads();
+        if (w < half) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[ch][v] += red[w * ncols + (ch * kWave + lane) * VEC + v];
+        }
+        __syncthreads();
+    }
+}
+
+// Fixed-order sum of rows [q0, q1) of a row-major (rows x J) array, column j.
+__device__ __forceinline__ double sum_rows(const double* p, int q0, int q1, int J, int j) {
+    double s = 0.0;
+    int q = q0;
+    for (; q + 8 <= q1; q += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = p[(int64_t)(q + u) * J + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; q < q1; ++q) s += p[(int64_t)q * J + j];
+    return s;
+}
+
+// ------------------------------------------------------------ iteration --
+struct IterArgs {
+    int64_t I;
+    int J;
+    int nch;  // column chunks of 64 * VEC actually used (<= NCH)
+    int64_t rows_per_block;
+    const double* a;
+    const double* f_in;  // f^(k-1) (read only when ctl->has_prev)
+    double* f_out;       // f^k
+    const double* g_in;  // g^(k-1)
+    double* col_part;    // gridDim.x x J partial column sums of the half-iterate
+    double* res_part;    // gridDim.x partial row residuals of iterate k-1
+    const Ctl* ctl;
+    const SolveParams* prm;
+};
+
+__device__ __forceinline__ void bookkeep(Ctl* c, double rsum, int mode, double stall_below) {
+    const int k = c->iter + 1;
+    const double r = c->has_prev ? rsum / c->mass : pinf64();
+    const bool bad = c->numeric_bad || (c->has_prev && !isfinite(r));
+    const int prev64 = c->last_fp64;
+    c->r_last = r;
+    c->iter = k;
+    c->has_prev = 1;
+    if (mode == kModeFast) {
+        c->last_fp64 = 0;
+        // stalled: the residual sits below the FP32 noise threshold and no
+        // longer falls against the recent (finite) residuals
+        double mn = pinf64();
+        int nfin = 0;
+        for (int q = 0; q < 4; ++q)
+            if (isfinite(c->r_hist[q])) { mn = fmin(mn, c->r_hist[q]); ++nfin; }
+        const bool stall = (nfin >= 1) && isfinite(r) && (r < stall_below) && (r > 0.95 * mn);
+        for (int q = 3; q > 0; --q) c->r_hist[q] = c->r_hist[q - 1];
+        c->r_hist[0] = r;
+        if (r < c->tol || stall || k >= c->max_iter) c->stop = 1;
+    } else {
+        c->fp64_iters += 1;
+        c->last_fp64 = 1;
+        if (mode == kModeExact && prev64 && r < c->tol) {
+            c->done = 1;
+            c->stop = 1;
+            c->result_iter = k - 1;
+        } else if (k >= c->max_iter) {
+            c->stop = 1;
+        }
+    }
+    if (bad) {
+        c->numeric_bad = 1;
+        c->done = 1;
+        c->stop = 1;
+        c->result_iter = k;
+    }
+}
+
+// Lane layout: a row is handled by a group of LPR lanes (16, 32 or 64), so a
+// wavefront advances R = 64 / LPR rows per step; lane `sub` of a group owns
+// columns (ch * LPR + sub) * VEC + v. Short rows (a few hundred RRHs) thus
+// share one instruction stream four or two at a time, which amortises the
+// per-row reductions and scalars over more cells. Each wave keeps RB steps of
+// rows in flight and refills a slot as soon as its row is consumed.
+template <class Src, bool P64, int VEC, int NCH, int LPR, int WAVES, int RB>
+__global__ __launch_bounds__(WAVES * kWave) void k_iter(IterArgs A, Src src) {
+    const Ctl* ctl = A.ctl;
+    constexpr int R = kWave / LPR;
+    const int J = A.J, nch = A.nch;
+    const int ncols = nch * LPR * VEC;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int sub = lane % LPR, rg = lane / LPR;
+    const int64_t r0 = (int64_t)blockIdx.x * A.rows_per_block;
+    const int64_t r1 = min(A.I, r0 + A.rows_per_block);
+    // first row of step `st` for this wave; this lane's row is that + rg
+    auto step_base = [&](int64_t st) { return r0 + (st * WAVES + w) * R; };
+
+    // 1. issue the loads of this wave's first RB steps before anything else;
+    //    a slot holds a step's row data and its a_i (rows past the range load
+    //    as fully masked, i.e. C = +inf, and get a_i = 0)
+    using Raw = typename Src::template Raw<VEC>;
+    Raw raw[RB][NCH];
+    double aq[RB];
+    auto issue = [&](int q, int64_t i) {
+        const bool ok = i < r1;
+        auto row = src.row(ok ? i : r0);
+        const int Jl = ok ? J : 0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+            if (ch < nch) raw[q][ch] = src.template load<VEC>(row, (ch * LPR + sub) * VEC, Jl);
+        aq[q] = ok ? A.a[i] : 0.0;
+    };
+#pragma unroll
+    for (int q = 0; q < RB; ++q) issue(q, step_base(q) + rg);
+    // a stopped chunk does nothing (the loads above are simply dropped)
+    if (ctl->stop | ctl->done) return;
+
+    // 2. per-column state in LDS: staged source data, g kk in FP64 and FP32
+    const double kk = A.prm->kk, eps = A.prm->eps;
+    const float kk32 = (float)kk;
+    const int has_prev = ctl->has_prev;
+    extern __shared__ double sm[];
+    src.stage(sm, J);
+    double* gs64 = sm + Src::kStageDoubles * ncols;
+    float* gs32 = reinterpret_cast<float*>(gs64 + ncols);
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        const double v = (c < J) ? A.g_in[c] * kk : -pinf64();
+        gs64[c] = v;
+        gs32[c] = (float)v;
+    }
+    __syncthreads();
+
+    using E = typename std::conditional<P64, double, float>::type;
+    E acc[NCH][VEC];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[ch][v] = 0;
+    double res = 0.0;
+
+    // Deferred row outputs (f_i and the residual term) need only (m_i, S_i):
+    // lane L keeps those of the wave's L-th row since the last flush, and a
+    // flush finishes up to 64 rows at once, so the FP64 logarithms run once
+    // per 64 rows instead of once per row.
+    double stash_m = 0.0, stash_S = 1.0;
+    int64_t stash_i = -1;
+    int nstash = 0;
+    auto flush = [&]() {
+        if (lane < nstash && stash_i < r1) {
+            const double ai = A.a[stash_i];
+            const double fi = eps * (log(ai) - kLn2 * (stash_m + log2(stash_S)));
+            if (has_prev) res += ai * fabs(expm1((A.f_in[stash_i] - fi) / eps));
+            A.f_out[stash_i] = fi;
+        }
+        nstash = 0;
+    };
+
+    for (int64_t st0 = 0; step_base(st0) < r1; st0 += RB) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int64_t base = step_base(st0 + q);
+            if (base >= r1) break;  // uniform over the wave
+            const int64_t i = base + rg;
+            const bool vrow = i < r1;
+            const int Jl = vrow ? J : 0;
+            auto row = src.row(vrow ? i : r0);
+            auto cost_at = [&](int ch, int v) -> double {
+                const int col = (ch * LPR + sub) * VEC + v;
+                if constexpr (Src::kCheap) return src.template cost<P64, VEC>(row, raw[q][ch], v, i, col, sm);
+                else return (col < Jl) ? src.template cost<P64, VEC>(row, raw[q][ch], v, i, col, sm) : pinf64();
+            };
+            // pass 1: row maximum, an FP32 estimate (it only sets the shift)
+            E ck[Src::kCheap ? 1 : NCH][Src::kCheap ? 1 : VEC];
+            float mx = -__builtin_huge_valf();
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        const double c = cost_at(ch, v);
+                        if constexpr (!Src::kCheap) ck[ch][v] = (E)c;  // exact: the functor's own precision
+                        mx = fmaxf(mx, fmaf((float)c, -kk32, gs32[(ch * LPR + sub) * VEC + v]));
+                    }
+            // (an all-masked row has max -inf: shift by 0 so its terms are 0)
+            const double m = fmax((double)group_max<LPR>(mx), -1e300);
+            // pass 2: exponentials (arguments in FP64) and the row sum
+            E ev[NCH][VEC];
+            E s = 0;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        const double c = Src::kCheap ? cost_at(ch, v) : (double)ck[ch][v];
+                        const double t = fma(c, -kk, gs64[(ch * LPR + sub) * VEC + v]) - m;
+                        E e;
+                        if constexpr (P64) e = exp2(t);
+                        else e = exp2_f32((float)t);
+                        ev[ch][v] = e;
+                        s += e;
+                    }
+            const double ai = aq[q];
+            // slot q is free: load its rows of the next batch
+            issue(q, step_base(st0 + q + RB) + rg);
+            const double S = group_sum<LPR>((double)s);
+            // column partials of the half-iterate plan, pi_ij = e_ij a_i / S_i
+            E wq = 0;
+            if (vrow) {
+                if constexpr (P64) wq = ai / S;
+                else wq = (float)ai / (float)S;
+            }
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[ch][v] = fma(ev[ch][v], wq, acc[ch][v]);
+            // hand (m, S, i) of each row group to lane nstash + r
+            const int src_lane = (lane - nstash) * LPR;
+            const int sl = (src_lane < 0 || src_lane >= kWave) ? 0 : src_lane;
+            const double mm = __shfl(m, sl, kWave);
+            const double ss = __shfl(S, sl, kWave);
+            if (lane >= nstash && lane < nstash + R) {
+                stash_m = mm;
+                stash_S = ss;
+                stash_i = base + (lane - nstash);
+            }
+            nstash += R;
+            if (nstash == kWave) flush();
+        }
+    }
+    flush();
+    res = wave_sum(res);
+
+    // 3. the workgroup's column partials: every (wave, row group) writes its
+    //    partial row to LDS once; then each thread sums whole columns over the
+    //    WAVES * R contributors in a fixed order, in FP64, and writes them out
+    __syncthreads();  // LDS is reused from here on
+    E* red = reinterpret_cast<E*>(sm);
+    const int contrib = w * R + rg;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+        if (ch < nch)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) red[contrib * ncols + (ch * LPR + sub) * VEC + v] = acc[ch][v];
+    __shared__ double wres[WAVES];
+    if (lane == 0) wres[w] = res;
+    __syncthreads();
+    double* out = A.col_part + (int64_t)blockIdx.x * J;
+    for (int c = threadIdx.x; c < J; c += blockDim.x) {
+        double t = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < WAVES * R; ++k) t += (double)red[k * ncols + c];
+        out[c] = t;
+    }
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int q = 0; q < WAVES; ++q) r += wres[q];
+        A.res_part[blockIdx.x] = r;
+    }
+}
+
+// -------------------------------------------------------- column combine --
+struct ColArgs {
+    int J;
+    int nb;  // partial rows
+    const double* b;
+    const double* g_in;
+    double* g_out;
+    const double* col_part;
+    const double* res_part;
+    Ctl* ctl;
+    const SolveParams* prm;
+    int mode;
+    double stall_below;  // fast mode: residuals below this may be declared stalled
+};
+
+// Workgroup of 1024 threads = 64 row-lanes x 16 columns: thread (r, c) sums
+// partial rows r, r + 64, ... of column c; the 64 row-lanes are then summed
+// in a fixed order. Workgroup 0 also closes the iteration's bookkeeping.
+constexpr int kColsPerWg = 16;
+__global__ __launch_bounds__(1024) void k_colsum(ColArgs A) {
+    Ctl* ctl = A.ctl;
+    if (ctl->stop | ctl->done) return;
+    const int c = threadIdx.x % kColsPerWg, r = threadIdx.x / kColsPerWg;
+    const int j = blockIdx.x * kColsPerWg + c;
+    double s = 0.0;
+    if (j < A.J) {
+        int q = r;
+        for (; q + 3 * 64 < A.nb; q += 4 * 64) {
+            const double x0 = A.col_part[(int64_t)q * A.J + j], x1 = A.col_part[(int64_t)(q + 64) * A.J + j];
+            const double x2 = A.col_part[(int64_t)(q + 128) * A.J + j], x3 = A.col_part[(int64_t)(q + 192) * A.J + j];
+            s += x0; s += x1; s += x2; s += x3;
+        }
+        for (; q < A.nb; q += 64) s += A.col_part[(int64_t)q * A.J + j];
+    }
+    __shared__ double red[64][kColsPerWg + 1];
+    __shared__ int s_bad;
+    red[r][c] = s;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    if (threadIdx.x < kColsPerWg && j < A.J) {
+        double cs = 0.0;
+        for (int q = 0; q < 64; ++q) cs += red[q][c];
+        const double gn = A.g_in[j] + A.prm->eps * (log(A.b[j]) - log(cs));
+        if (!isfinite(gn)) s_bad = 1;
+        A.g_out[j] = gn;
+    }
+    if (blockIdx.x != 0) {
+        __syncthreads();
+        if (threadIdx.x == 0 && s_bad) ctl->numeric_bad = 1;  // read by the next launch
+        return;
+    }
+    // workgroup 0: total row residual of iterate k-1, then the stop decision
+    __shared__ double wr[16];
+    double rr = 0.0;
+    for (int q = threadIdx.x; q < A.nb; q += blockDim.x) rr += A.res_part[q];
+    rr = wave_sum(rr);
+    if ((threadIdx.x & 63) == 0) wr[threadIdx.x >> 6] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int q = 0; q < 16; ++q) tot += wr[q];
+        if (s_bad) ctl->numeric_bad = 1;
+        bookkeep(ctl, tot, A.mode, A.stall_below);
+    }
+}
+
+// ------------------------------------------------------------ exact check --
+// Statistics of the iterate (f, g) in FP64: row sums, column sums, <C, pi>,
+// sum pi (log pi - 1), sum pi and <f, a>, combined in two fixed-order levels
+// like k_iter. The last workgroup writes the results into the control block.
+struct CheckArgs {
+    int64_t I;
+    int J;
+    int nch;
+    int64_t rows_per_block;
+    const double* a;
+    const double* f;
+    const double* g;
+    double* col_part;   // gridDim.x x J
+    double* stat_part;  // gridDim.x x 5
+    const SolveParams* prm;
+};
+
+template <class Src, int VEC, int NCH, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
+    const double kk = A.prm->kk;
+    const int J = A.J, nch = A.nch;
+    const int ncols = nch * kWave * VEC;
+    extern __shared__ double sm[];
+    src.stage(sm, J);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    double gsr[NCH][VEC];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int col = (ch * kWave + lane) * VEC + v;
+            gsr[ch][v] = (ch < nch && col < J) ? A.g[col] * kk : -pinf64();
+        }
+    __syncthreads();
+    double acc[NCH][VEC];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[ch][v] = 0.0;
+    double st[5] = {0, 0, 0, 0, 0};  // rowres, cost, ent, mass, fa (lane 0 of each wave)
+    const int64_t r0 = (int64_t)blockIdx.x * A.rows_per_block;
+    const int64_t r1 = min(A.I, r0 + A.rows_per_block);
+    for (int64_t i = r0 + w; i < r1; i += WAVES) {
+        auto row = src.row(i);
+        const double fk = A.f[i] * kk;
+        double rs = 0.0, cost = 0.0, ent = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            if (ch < nch) {
+                const int col0 = (ch * kWave + lane) * VEC;
+                double c[VEC];
+                src.template get<true, VEC>(row, i, col0, J, sm, c);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    if (col0 + v < J) {
+                        const double t = fk + fma(c[v], -kk, gsr[ch][v]);  // log2 pi_ij
+                        const double p = exp2(t);
+                        rs += p;
+                        cost = fma(c[v], p, cost);
+                        ent = fma(p, t * kLn2 - 1.0, ent);
+                        acc[ch][v] += p;
+                    }
+                }
+            }
+        }
+        rs = wave_sum(rs);
+        cost = wave_sum(cost);
+        ent = wave_sum(ent);
+        if (lane == 0) {
+            const double ai = A.a[i];
+            st[0] += fabs(rs - ai);
+            st[1] += cost;
+            st[2] += ent;
+            st[3] += rs;
+            st[4] += A.f[i] * ai;
+        }
+    }
+    __syncthreads();
+    __shared__ double wst[WAVES][5];
+    if (lane == 0)
+        for (int q = 0; q < 5; ++q) wst[w][q] = st[q];
+    block_tree<NCH, VEC, WAVES>(acc, nch, sm, ncols, w, lane);
+    if (w == 0) {
+        double* out = A.col_part + (int64_t)blockIdx.x * J;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+            if (ch < nch)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const int col = (ch * kWave + lane) * VEC + v;
+                    if (col < J) out[col] = acc[ch][v];
+                }
+        if (lane < 5) {
+            double r = 0.0;
+            for (int q = 0; q < WAVES; ++q) r += wst[q][lane];
+            A.stat_part[(int64_t)blockIdx.x * 5 + lane] = r;
+        }
+    }
+}
+
+// Column sums of the check: per column |colsum_j - b_j| and g_j b_j, summed
+// per workgroup of 16 columns (same layout as k_colsum).
+struct CheckColArgs {
+    int J;
+    int nb;
+    const double* b;
+    const double* g;
+    const double* col_part;
+    double* cpart;  // gridDim.x x 2
+};
+
+__global__ __launch_bounds__(1024) void k_check_cols(CheckColArgs A) {
+    const int c = threadIdx.x % kColsPerWg, r = threadIdx.x / kColsPerWg;
+    const int j = blockIdx.x * kColsPerWg + c;
+    double s = 0.0;
+    if (j < A.J)
+        for (int q = r; q < A.nb; q += 64) s += A.col_part[(int64_t)q * A.J + j];
+    __shared__ double red[64][kColsPerWg + 1];
+    red[r][c] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double cres = 0.0, gb = 0.0;
+        for (int cc = 0; cc < kColsPerWg; ++cc) {
+            const int jj = blockIdx.x * kColsPerWg + cc;
+            if (jj >= A.J) break;
+            double cs = 0.0;
+            for (int q = 0; q < 64; ++q) cs += red[q][cc];
+            cres += fabs(cs - A.b[jj]);
+            gb += A.g[jj] * A.b[jj];
+        }
+        A.cpart[blockIdx.x * 2] = cres;
+        A.cpart[blockIdx.x * 2 + 1] = gb;
+    }
+}
+
+// One workgroup: the check's scalars, in a fixed order, into the control block.
+__global__ __launch_bounds__(256) void k_check_finish(const double* stat_part, int nb, const double* cpart, int ncb,
+                                                      Ctl* ctl, const SolveParams* prm) {
+    __shared__ double red[4][7];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int q = threadIdx.x; q < nb; q += blockDim.x)
+        for (int u = 0; u < 5; ++u) v[u] += stat_part[(int64_t)q * 5 + u];
+    for (int q = threadIdx.x; q < ncb; q += blockDim.x) { v[5] += cpart[q * 2]; v[6] += cpart[q * 2 + 1]; }
+    for (int u = 0; u < 7; ++u) {
+        v[u] = wave_sum(v[u]);
+        if (lane == 0) red[w][u] = v[u];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[7];
+        for (int u = 0; u < 7; ++u) t[u] = ((red[0][u] + red[1][u]) + red[2][u]) + red[3][u];
+        const double eps = prm->eps;
+        ctl->chk_row_res = t[0];
+        ctl->chk_col_res = t[5];
+        ctl->chk_violation = (t[0] + t[5]) / ctl->mass;
+        ctl->chk_objective = t[1];
+        ctl->chk_reg_objective = t[1] + eps * t[2];
+        ctl->chk_mass = t[3];
+        ctl->chk_dual = t[4] + t[6] - eps * t[3];
+    }
+}
+
+// -------------------------------------------------------------------- plan --
+// pi_ij = exp((f_i + g_j - C_ij) / eps) in FP64, stored as OutT.
+template <class Src, typename OutT, int VEC>
+__global__ __launch_bounds__(512) void k_plan(int64_t I, int J, int nch, const double* f, const double* g,
+                                              const SolveParams* prm, OutT* out, Src src) {
+    const double kk = prm->kk;
+    const int ncols = nch * kWave * VEC;
+    extern __shared__ double sm[];
+    double* stage = sm;
+    double* gs = sm + Src::kStageDoubles * ncols;
+    src.stage(stage, J);
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) gs[c] = (c < J) ? g[c] * kk : -pinf64();
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    for (int64_t i = (int64_t)blockIdx.x * nw + w; i < I; i += (int64_t)gridDim.x * nw) {
+        auto row = src.row(i);
+        const double fk = f[i] * kk;
+        OutT* o = out + i * J;
+        for (int ch = 0; ch < nch; ++ch) {
+            const int col0 = (ch * kWave + lane) * VEC;
+            double c[VEC];
+            src.template get<true, VEC>(row, i, col0, J, stage, c);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                if (col0 + v < J) o[col0 + v] = (OutT)exp2(fk + fma(c[v], -kk, gs[col0 + v]));
+        }
+    }
+}
+
+// ------------------------------------------------------------- validation --
+// Flags a non-finite dense cost, or a rate that is not finite and positive.
+template <typename T, bool RATES>
+__global__ void k_validate(const T* x, int64_t n, int* bad) {
+    int flag = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)x[q];
+        if (RATES ? !(v > 0.0 && isfinite(v)) : !isfinite(v)) flag = 1;
+    }
+    if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+__global__ void k_validate_xy(const float* xy, int64_t n, int* bad) {
+    int flag = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(xy[q])) flag = 1;
+    if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+// Clears the stop flag between phases (kept as a kernel so that it may sit in
+// a captured graph).
+__global__ void k_ctl_resume(Ctl* ctl) {
+    if (threadIdx.x == 0) ctl->stop = 0;
+}
+
+// ------------------------------------------------------- geometry set-up --
+// One wavefront per device: the strongest RRH j1 (lowest index on ties),
+// s_all = sum_j pg_ij + n0n and s_ex = sum_{j != j1} pg_ij + n0n (FP64,
+// per-lane index order, then a fixed butterfly).
+template <int NCH>
+__global__ __launch_bounds__(256) void k_geo_prepass(GeoSrc src, int64_t I, int J, double* s_all, double* s_ex, int* j1) {
+    __shared__ float2 xy[2048];
+    for (int c = threadIdx.x; c < J; c += blockDim.x) xy[c] = reinterpret_cast<const float2*>(src.rrh_xy)[c];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (i >= I) return;
+    const float2 p = reinterpret_cast<const float2*>(src.dev_xy)[i];
+    double pg[NCH];
+    double bv = -1.0;
+    int bj = 0x7fffffff;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int j = ch * 64 + lane;
+        pg[ch] = 0.0;
+        if (j < J) {
+            const double dx = (double)p.x - (double)xy[j].x, dy = (double)p.y - (double)xy[j].y;
+            const double d2 = fmax(dx * dx + dy * dy, src.k.dmin2);
+            const double X = normal_f64(link_hash(src.k.key, i, j));
+            pg[ch] = exp2(src.k.shadow_c * X - src.k.alpha_half * log2(d2));
+            if (pg[ch] > bv) { bv = pg[ch]; bj = j; }
+        }
+    }
+    // argmax across lanes, lowest index on ties
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oj = __shfl_xor(bj, o, 64);
+        if (ov > bv || (ov == bv && oj < bj)) { bv = ov; bj = oj; }
+    }
+    double sa = 0.0, se = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int j = ch * 64 + lane;
+        if (j < J) {
+            sa += pg[ch];
+            if (j != bj) se += pg[ch];
+        }
+    }
+    sa = wave_sum(sa);
+    se = wave_sum(se);
+    if (lane == 0) {
+        s_all[i] = sa + src.k.n0n;
+        s_ex[i] = se + src.k.n0n;
+        j1[i] = bj;
+    }
+}
+
+// Materialised FP32 cost: the FP64 functor rounded once to FP32.
+template <class Src>
+__global__ void k_materialize(int64_t I, int J, float* C, Src src) {
+    extern __shared__ double sm[];
+    src.stage(sm, J);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t i = (int64_t)blockIdx.x * nw + w; i < I; i += (int64_t)gridDim.x * nw) {
+        auto row = src.row(i);
+        for (int j = lane; j < J; j += 64) C[i * J + j] = (float)src.at64(row, i, j, sm);
+    }
+}
+
+// Radix-select histogram over the FP32 bit patterns of 1/R (positive, so the
+// bit order is the value order). Pass p looks at the 11 / 11 / 10-bit digit
+// below the prefix fixed by earlier passes.
+template <class Src>
+__global__ void k_median_hist(int64_t I, int J, int pass, uint32_t prefix, unsigned long long* hist, Src src) {
+    extern __shared__ double sm[];
+    __shared__ uint32_t h[2048];
+    for (int q = threadIdx.x; q < 2048; q += blockDim.x) h[q] = 0;
+    src.stage(sm, J);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t i = (int64_t)blockIdx.x * nw + w; i < I; i += (int64_t)gridDim.x * nw) {
+        auto row = src.row(i);
+        for (int j = lane; j < J; j += 64) {
+            double c[1];
+            src.template get<false, 1>(row, i, j, J, sm, c);
+            const uint32_t u = __float_as_uint((float)c[0]);
+            uint32_t bin;
+            bool take;
+            if (pass == 0) { take = true; bin = u >> 21; }
+            else if (pass == 1) { take = (u >> 21) == prefix; bin = (u >> 10) & 0x7FFu; }
+            else { take = (u >> 10) == prefix; bin = u & 0x3FFu; }
+            if (take) atomicAdd(&h[bin], 1u);
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2048; q += blockDim.x)
+        if (h[q]) atomicAdd(&hist[q], (unsigned long long)h[q]);
+}
+
+}  // namespace otk

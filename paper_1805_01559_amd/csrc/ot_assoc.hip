@@ -1,0 +1,1049 @@
+// Host runtime and C ABI of the association solver (include/ot_assoc.h).
+//
+// A solve runs three phases on one HIP stream:
+//   fast    FP32-exponential sweeps, captured in HIP graphs CHUNK iterations at
+//           a time; the combine kernel stops the chunk on the device when the
+//           residual meets tol or stalls at the FP32 noise floor;
+//   polish  a few FP64 sweeps, then an exact FP64 check of the iterate;
+//   exact   (only if the check misses tol) FP64 sweeps until an FP64 iterate
+//           meets tol, then the check again.
+// The host reads a small control block once per chunk, one chunk behind the
+// device, so there is no host round trip per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ot_assoc.h"
+#include "kernels.h"
+
+using namespace otk;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kMaxNb = 1024;    // workgroups per sweep (partial rows)
+constexpr int kMaxJ = 2048;     // RRHs per instance
+constexpr int kGraphCache = 24;
+
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct ot_assoc {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    ot_assoc_options opt{};
+    int64_t I_max = 0, J_max = 0;
+    // device workspace
+    double *a = nullptr, *b = nullptr;
+    double *f[2] = {nullptr, nullptr}, *g[2] = {nullptr, nullptr};
+    double *col_part = nullptr, *res_part = nullptr, *stat_part = nullptr;
+    double* cpart = nullptr;  // per-column-group partials of the check
+    Ctl* ctl = nullptr;
+    SolveParams* prm = nullptr;
+    int* bad = nullptr;
+    unsigned long long* hist = nullptr;
+    float* xy_dev = nullptr;  // I_max x 2
+    float* xy_rrh = nullptr;  // J_max x 2
+    double *s_all = nullptr, *s_ex = nullptr;
+    int* j1 = nullptr;
+    void* stage = nullptr;  // host-memory dense / rate matrices are copied here
+    size_t stage_bytes = 0;
+    // pinned host mirrors
+    Ctl* ctl_h = nullptr;  // 2 slots
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_slot[2] = {nullptr, nullptr};
+    std::vector<GraphEntry> graphs;
+    // state of the last solve
+    bool solved = false;
+    bool have_pot = false;
+    int64_t I = 0, J = 0;
+    int res_par = 0;  // parity of the buffers holding the returned iterate
+    double eps = 0.0;
+    ot_cost_desc last{};       // descriptor of the retained cost (pointers below replace the caller's)
+    const void* cost_dev = nullptr;  // device copy (host inputs) or the caller's device matrix
+    bool retained = false;     // the handle still holds the cost of the last solve
+    std::string err;
+};
+
+namespace {
+
+ot_status fail(ot_assoc* h, ot_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    else g_create_error = buf;
+    return st;
+}
+
+#define HIPCHK(h, call)                                                                                  \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess)                                                                            \
+            return fail((h), (e_ == hipErrorOutOfMemory) ? OT_ENOMEM : OT_EDEVICE, "%s failed: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                               \
+    } while (0)
+
+int pow2_at_least(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// ------------------------------------------------------------- launch shape --
+struct Shape {
+    int vec = 1, lpr = 64, nch = 1, nchT = 1, waves = 8, nb = 1, rb = 1;
+    int64_t rpb = 1;
+};
+
+template <class Src>
+int vec_for(int64_t J, const void* d) {
+    if (Src::kVecWide == 1) return 1;
+    return (J % Src::kVecWide == 0 && ((uintptr_t)d % 16) == 0) ? Src::kVecWide : 1;
+}
+
+template <class Src>
+constexpr int max_rb(bool p64) {
+    return Src::kCheap ? (p64 ? 2 : (Src::kTag == 1 || Src::kTag == 3 ? 8 : 2)) : 1;
+}
+constexpr int max_nch(int vec, int lpr) { return lpr < 64 ? 8 : 2048 / (64 * vec); }
+
+// Iteration shape: a row per group of LPR lanes (the narrowest of 16, 32, 64
+// that keeps at most 8 column chunks of LPR * VEC), contiguous row ranges per
+// workgroup, RB steps of rows in flight per wave.
+template <class Src>
+Shape make_shape(const ot_assoc* h, int64_t I, int64_t J, int vec, bool p64 = false) {
+    Shape s;
+    s.vec = vec;
+    s.lpr = 64;
+    for (int cand : {16, 32})
+        if ((J + cand * vec - 1) / (cand * vec) <= 8) { s.lpr = cand; break; }
+    if (h->opt.sweep_lanes == 16 || h->opt.sweep_lanes == 32 || h->opt.sweep_lanes == 64)
+        if ((J + h->opt.sweep_lanes * vec - 1) / (h->opt.sweep_lanes * vec) <= max_nch(vec, h->opt.sweep_lanes))
+            s.lpr = h->opt.sweep_lanes;
+    s.nch = (int)((J + s.lpr * vec - 1) / (s.lpr * vec));
+    s.nchT = pow2_at_least(s.nch);
+    if (s.lpr == 64) s.nchT = std::max(s.nchT, vec == 1 ? 4 : 8);  // the instantiated widths
+    s.waves = (Src::kTag == 1 && h->opt.sweep_waves > 0) ? h->opt.sweep_waves : 8;
+    const int R = 64 / s.lpr;
+    int nb = h->opt.sweep_blocks > 0 ? h->opt.sweep_blocks : 512;
+    nb = (int)std::min<int64_t>(nb, (I + s.waves * R - 1) / (s.waves * R));
+    nb = std::max(1, std::min(nb, kMaxNb));
+    s.rpb = (I + nb - 1) / nb;
+    s.nb = (int)((I + s.rpb - 1) / s.rpb);
+    const int steps = (int)((s.rpb + s.waves * R - 1) / (s.waves * R));
+    const int want = h->opt.sweep_rows > 0 ? h->opt.sweep_rows : pow2_at_least(steps);
+    const int cap = (s.lpr < 64) ? 2 : std::max(1, 16 / s.nchT);
+    s.rb = std::min({want, max_rb<Src>(p64), cap});
+    return s;
+}
+
+// LDS of the iteration kernel: staged per-column source data and g in FP64
+// and FP32, reused afterwards by the workgroup reduction tree.
+template <class Src>
+size_t sweep_lds(const Shape& s, bool p64) {
+    const size_t ncols = (size_t)s.nch * s.lpr * s.vec;
+    const size_t a = sizeof(double) * ((size_t)Src::kStageDoubles * ncols + ncols + (ncols + 1) / 2);
+    const size_t b = (p64 ? sizeof(double) : sizeof(float)) * (size_t)s.waves * (64 / s.lpr) * ncols;
+    return std::max(a, b);
+}
+
+// The check and plan kernels use one 64-lane wavefront per row.
+inline Shape row64(Shape s, int64_t J) {
+    s.lpr = 64;
+    s.nch = (int)((J + 64 * s.vec - 1) / (64 * s.vec));
+    s.nchT = pow2_at_least(s.nch);
+    return s;
+}
+
+// LDS of the check kernel (64 lanes per row): staged data plus the reduction tree.
+template <class Src>
+size_t check_lds(const Shape& s) {
+    const size_t ncols = (size_t)s.nch * 64 * s.vec;
+    return sizeof(double) * std::max((size_t)(Src::kStageDoubles + 1) * ncols, (size_t)4 * ncols);
+}
+
+// While set, the launch helpers only raise the kernels' LDS limits and launch
+// nothing: run before a graph capture so no attribute call happens inside it.
+thread_local bool g_prepare_only = false;
+
+template <class K>
+void set_lds(K kern, size_t lds) {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <class Src, bool P64, int VEC, int NCH, int LPR, int W, int RB>
+void launch_iter_t(const Shape& s, const IterArgs& A, const Src& src, size_t lds, hipStream_t st) {
+    auto kern = k_iter<Src, P64, VEC, NCH, LPR, W, RB>;
+    set_lds(kern, lds);
+    if (g_prepare_only) return;
+    hipLaunchKernelGGL(kern, dim3(s.nb), dim3(W * 64), lds, st, A, src);
+}
+
+template <class Src, bool P64, int VEC, int NCH, int LPR, int W>
+bool launch_iter_r(const Shape& s, const IterArgs& A, const Src& src, size_t lds, hipStream_t st) {
+    constexpr int kMaxRb = std::min(max_rb<Src>(P64), LPR < 64 ? 2 : std::max(1, 16 / NCH));
+    switch (s.rb) {
+        case 1: launch_iter_t<Src, P64, VEC, NCH, LPR, W, 1>(s, A, src, lds, st); return true;
+        case 2: if constexpr (kMaxRb >= 2) { launch_iter_t<Src, P64, VEC, NCH, LPR, W, 2>(s, A, src, lds, st); return true; } break;
+        case 4: if constexpr (kMaxRb >= 4) { launch_iter_t<Src, P64, VEC, NCH, LPR, W, 4>(s, A, src, lds, st); return true; } break;
+        case 8: if constexpr (kMaxRb >= 8) { launch_iter_t<Src, P64, VEC, NCH, LPR, W, 8>(s, A, src, lds, st); return true; } break;
+    }
+    return false;
+}
+
+template <class Src, bool P64, int VEC, int LPR, int W>
+bool launch_iter_n(const Shape& s, const IterArgs& A, const Src& src, size_t lds, hipStream_t st) {
+    if constexpr (LPR < 64) {
+        switch (s.nchT) {
+            case 1: return launch_iter_r<Src, P64, VEC, 1, LPR, W>(s, A, src, lds, st);
+            case 2: return launch_iter_r<Src, P64, VEC, 2, LPR, W>(s, A, src, lds, st);
+            case 4: return launch_iter_r<Src, P64, VEC, 4, LPR, W>(s, A, src, lds, st);
+            case 8: return launch_iter_r<Src, P64, VEC, 8, LPR, W>(s, A, src, lds, st);
+        }
+    } else {
+        switch (s.nchT) {
+            case 4: if constexpr (VEC == 1) return launch_iter_r<Src, P64, VEC, 4, LPR, W>(s, A, src, lds, st); break;
+            case 8: return launch_iter_r<Src, P64, VEC, 8, LPR, W>(s, A, src, lds, st);
+            case 16: if constexpr (VEC <= 2) return launch_iter_r<Src, P64, VEC, 16, LPR, W>(s, A, src, lds, st); break;
+            case 32: if constexpr (VEC == 1) return launch_iter_r<Src, P64, VEC, 32, LPR, W>(s, A, src, lds, st); break;
+        }
+    }
+    return false;
+}
+
+template <class Src, bool P64, int VEC, int W>
+bool launch_iter_l(const Shape& s, const IterArgs& A, const Src& src, size_t lds, hipStream_t st) {
+    switch (s.lpr) {
+        case 16: return launch_iter_n<Src, P64, VEC, 16, W>(s, A, src, lds, st);
+        case 32: return launch_iter_n<Src, P64, VEC, 32, W>(s, A, src, lds, st);
+        case 64: return launch_iter_n<Src, P64, VEC, 64, W>(s, A, src, lds, st);
+    }
+    return false;
+}
+
+template <class Src, bool P64, int VEC>
+bool launch_iter_v(const Shape& s, const IterArgs& A, const Src& src, size_t lds, hipStream_t st) {
+    if constexpr (Src::kTag == 1) {  // the dense FP32 hot path is tunable in waves per workgroup
+        if (s.waves == 4) return launch_iter_l<Src, P64, VEC, 4>(s, A, src, lds, st);
+    }
+    if (s.waves == 8) return launch_iter_l<Src, P64, VEC, 8>(s, A, src, lds, st);
+    return false;
+}
+
+template <class Src, bool P64>
+bool launch_iter(const Shape& s, const IterArgs& A, const Src& src, hipStream_t st) {
+    const size_t lds = sweep_lds<Src>(s, P64);
+    if (s.vec == 1) return launch_iter_v<Src, P64, 1>(s, A, src, lds, st);
+    if constexpr (Src::kVecWide > 1)
+        if (s.vec == Src::kVecWide) return launch_iter_v<Src, P64, Src::kVecWide>(s, A, src, lds, st);
+    return false;
+}
+
+template <int VEC>
+constexpr int check_nch() { return VEC == 4 ? 8 : VEC == 2 ? 16 : 32; }  // J <= 2048
+
+template <class Src, int VEC>
+void launch_check_v(const Shape& s, const CheckArgs& A, const Src& src, hipStream_t st) {
+    const size_t lds = check_lds<Src>(s);
+    auto kern = k_check<Src, VEC, check_nch<VEC>(), 8>;
+    set_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3(s.nb), dim3(512), lds, st, A, src);
+}
+
+template <class Src>
+bool launch_check(const Shape& s, const CheckArgs& A, const Src& src, hipStream_t st) {
+    if (s.vec == 1) { launch_check_v<Src, 1>(s, A, src, st); return true; }
+    if constexpr (Src::kVecWide > 1)
+        if (s.vec == Src::kVecWide) { launch_check_v<Src, Src::kVecWide>(s, A, src, st); return true; }
+    return false;
+}
+
+template <class Src, typename OutT, int VEC>
+void launch_plan_v(const Shape& s, int64_t I, int J, const double* f, const double* g, const SolveParams* prm,
+                   OutT* out, const Src& src, hipStream_t st) {
+    const size_t ncols = (size_t)s.nch * 64 * VEC;
+    const size_t lds = sizeof(double) * (Src::kStageDoubles + 1) * ncols;
+    auto kern = k_plan<Src, OutT, VEC>;
+    set_lds(kern, lds);
+    const int grid = (int)std::min<int64_t>(4096, (I + 7) / 8);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, st, I, J, s.nch, f, g, prm, out, src);
+}
+
+template <class Src, typename OutT>
+bool launch_plan(const Shape& s, int64_t I, int J, const double* f, const double* g, const SolveParams* prm, OutT* out,
+                 const Src& src, hipStream_t st) {
+    if (s.vec == 1) { launch_plan_v<Src, OutT, 1>(s, I, J, f, g, prm, out, src, st); return true; }
+    if constexpr (Src::kVecWide > 1)
+        if (s.vec == Src::kVecWide) { launch_plan_v<Src, OutT, Src::kVecWide>(s, I, J, f, g, prm, out, src, st); return true; }
+    return false;
+}
+
+// ---------------------------------------------------------------- helpers --
+ot_status copy_in(ot_assoc* h, void* dst, const void* src, size_t bytes, ot_mem mem) {
+    HIPCHK(h, hipMemcpyAsync(dst, src, bytes, mem == OT_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                             h->stream));
+    return OT_OK;
+}
+
+ot_status read_vec(ot_assoc* h, const double* p, int64_t n, ot_mem mem, std::vector<double>& out) {
+    out.resize((size_t)n);
+    if (mem == OT_MEM_HOST) {
+        std::memcpy(out.data(), p, sizeof(double) * (size_t)n);
+    } else {
+        HIPCHK(h, hipMemcpyAsync(out.data(), p, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    return OT_OK;
+}
+
+double ksum(const std::vector<double>& v) {
+    double s = 0.0, c = 0.0;
+    for (double x : v) {
+        double t = s + x;
+        c += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+ot_status validate_desc(ot_assoc* h, const ot_cost_desc* c) {
+    if (!c) return fail(h, OT_EINVAL, "cost descriptor is NULL");
+    if (c->I < 1 || c->J < 1 || c->I > h->I_max || c->J > h->J_max)
+        return fail(h, OT_EINVAL, "instance %lld x %lld outside 1..%lld x 1..%lld", (long long)c->I, (long long)c->J,
+                    (long long)h->I_max, (long long)h->J_max);
+    if (c->mem != OT_MEM_HOST && c->mem != OT_MEM_DEVICE) return fail(h, OT_EINVAL, "bad memory space");
+    switch (c->kind) {
+        case OT_COST_DENSE:
+        case OT_COST_RATES:
+            if (!c->data) return fail(h, OT_EINVAL, "cost data is NULL");
+            if (c->dtype != OT_F32 && c->dtype != OT_F64) return fail(h, OT_EINVAL, "bad dtype");
+            if (c->kind == OT_COST_RATES && !(c->scale > 0.0 && std::isfinite(c->scale)))
+                return fail(h, OT_EINVAL, "rates need a positive finite scale");
+            break;
+        case OT_COST_GEOMETRY: {
+            const ot_geometry& g = c->geom;
+            if (!g.dev_xy || !g.rrh_xy) return fail(h, OT_EINVAL, "geometry positions are NULL");
+            if (!(g.tx_power_w > 0) || !(g.ref_gain > 0) || !(g.pathloss_exp > 0) || !(g.min_dist_m > 0) ||
+                !(g.shadow_sigma_db >= 0) || !(g.noise_w >= 0) || !(g.bandwidth_hz > 0) ||
+                !std::isfinite(g.tx_power_w + g.ref_gain + g.pathloss_exp + g.min_dist_m + g.shadow_sigma_db +
+                               g.noise_w + g.bandwidth_hz))
+                return fail(h, OT_EINVAL, "geometry constants out of range");
+            if (!(c->scale > 0.0 && std::isfinite(c->scale)))
+                return fail(h, OT_EINVAL, "geometry costs need a positive finite scale");
+            break;
+        }
+        default:
+            return fail(h, OT_EINVAL, "unknown cost kind %d", (int)c->kind);
+    }
+    return OT_OK;
+}
+
+ot_status ensure_stage(ot_assoc* h, size_t bytes) {
+    if (h->stage_bytes >= bytes) return OT_OK;
+    if (h->stage) hipFree(h->stage);
+    h->stage = nullptr;
+    h->stage_bytes = 0;
+    HIPCHK(h, hipMalloc(&h->stage, bytes));
+    h->stage_bytes = bytes;
+    return OT_OK;
+}
+
+GeoConst geo_const(const ot_geometry& g, double scale) {
+    GeoConst k{};
+    k.alpha_half = 0.5 * g.pathloss_exp;
+    k.shadow_c = g.shadow_sigma_db * std::log2(10.0) / 10.0;
+    k.dmin2 = g.min_dist_m * g.min_dist_m;
+    k.cscale = std::log(2.0) / (g.bandwidth_hz * scale);
+    k.n0n = g.noise_w / (g.tx_power_w * g.ref_gain);
+    k.key = g.shadow_key;
+    return k;
+}
+
+// Brings the cost of `c` onto the device: host matrices are staged, device
+// matrices are referenced, geometry is copied and its per-device set-up pass
+// runs. Afterwards the handle can rebuild the source without the caller.
+ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, bool validate_values) {
+    const int64_t I = c->I, J = c->J, n = I * J;
+    h->retained = false;
+    h->last = *c;
+    if (c->kind != OT_COST_GEOMETRY) {
+        const size_t esz = c->dtype == OT_F32 ? 4 : 8;
+        const void* data = c->data;
+        if (c->mem == OT_MEM_HOST) {
+            ot_status st = ensure_stage(h, (size_t)n * esz);
+            if (st) return st;
+            HIPCHK(h, hipMemcpyAsync(h->stage, data, (size_t)n * esz, hipMemcpyHostToDevice, h->stream));
+            data = h->stage;
+        }
+        if (validate_values) {
+            HIPCHK(h, hipMemsetAsync(h->bad, 0, sizeof(int), h->stream));
+            const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+            if (c->dtype == OT_F32) {
+                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<float, false>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, n, h->bad);
+                else hipLaunchKernelGGL((k_validate<float, true>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, n, h->bad);
+            } else {
+                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<double, false>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, n, h->bad);
+                else hipLaunchKernelGGL((k_validate<double, true>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, n, h->bad);
+            }
+            int bad = 0;
+            HIPCHK(h, hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            if (bad)
+                return fail(h, OT_EINVAL, c->kind == OT_COST_DENSE ? "cost matrix has non-finite entries"
+                                                                  : "rate matrix has entries that are not finite and positive");
+        }
+        h->cost_dev = data;
+        h->retained = true;
+        return OT_OK;
+    }
+    ot_status st = copy_in(h, h->xy_dev, c->geom.dev_xy, sizeof(float) * 2 * (size_t)I, c->mem);
+    if (st) return st;
+    st = copy_in(h, h->xy_rrh, c->geom.rrh_xy, sizeof(float) * 2 * (size_t)J, c->mem);
+    if (st) return st;
+    if (validate_values) {
+        HIPCHK(h, hipMemsetAsync(h->bad, 0, sizeof(int), h->stream));
+        hipLaunchKernelGGL(k_validate_xy, dim3((unsigned)std::min<int64_t>(1024, (2 * I + 255) / 256)), dim3(256), 0, h->stream, h->xy_dev, 2 * I, h->bad);
+        hipLaunchKernelGGL(k_validate_xy, dim3((unsigned)std::min<int64_t>(1024, (2 * J + 255) / 256)), dim3(256), 0, h->stream, h->xy_rrh, 2 * J, h->bad);
+        int bad = 0;
+        HIPCHK(h, hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        if (bad) return fail(h, OT_EINVAL, "geometry positions have non-finite entries");
+    }
+    GeoSrc s{};
+    s.dev_xy = h->xy_dev;
+    s.rrh_xy = h->xy_rrh;
+    s.s_all = h->s_all;
+    s.s_ex = h->s_ex;
+    s.j1 = h->j1;
+    s.k = geo_const(c->geom, c->scale);
+    const dim3 pg((unsigned)((I + 3) / 4)), pb(256);
+    switch (pow2_at_least((int)((J + 63) / 64))) {
+        case 1: hipLaunchKernelGGL(k_geo_prepass<1>, pg, pb, 0, h->stream, s, I, (int)J, h->s_all, h->s_ex, h->j1); break;
+        case 2: hipLaunchKernelGGL(k_geo_prepass<2>, pg, pb, 0, h->stream, s, I, (int)J, h->s_all, h->s_ex, h->j1); break;
+        case 4: hipLaunchKernelGGL(k_geo_prepass<4>, pg, pb, 0, h->stream, s, I, (int)J, h->s_all, h->s_ex, h->j1); break;
+        case 8: hipLaunchKernelGGL(k_geo_prepass<8>, pg, pb, 0, h->stream, s, I, (int)J, h->s_all, h->s_ex, h->j1); break;
+        case 16: hipLaunchKernelGGL(k_geo_prepass<16>, pg, pb, 0, h->stream, s, I, (int)J, h->s_all, h->s_ex, h->j1); break;
+        default: hipLaunchKernelGGL(k_geo_prepass<32>, pg, pb, 0, h->stream, s, I, (int)J, h->s_all, h->s_ex, h->j1); break;
+    }
+    HIPCHK(h, hipGetLastError());
+    h->cost_dev = nullptr;
+    h->retained = true;
+    return OT_OK;
+}
+
+// Calls fn(src, data) with the source of the retained cost.
+template <class F>
+ot_status with_retained(ot_assoc* h, F&& fn) {
+    const ot_cost_desc& c = h->last;
+    const int64_t J = c.J;
+    if (c.kind == OT_COST_DENSE) {
+        if (c.dtype == OT_F32) { DenseSrc<float> s{}; s.C = (const float*)h->cost_dev; s.ld = J; return fn(s, h->cost_dev); }
+        DenseSrc<double> s{}; s.C = (const double*)h->cost_dev; s.ld = J; return fn(s, h->cost_dev);
+    }
+    if (c.kind == OT_COST_RATES) {
+        if (c.dtype == OT_F32) { RatesSrc<float> s{}; s.R = (const float*)h->cost_dev; s.ld = J; s.inv_scale = 1.0 / c.scale; return fn(s, h->cost_dev); }
+        RatesSrc<double> s{}; s.R = (const double*)h->cost_dev; s.ld = J; s.inv_scale = 1.0 / c.scale; return fn(s, h->cost_dev);
+    }
+    GeoSrc s{};
+    s.dev_xy = h->xy_dev;
+    s.rrh_xy = h->xy_rrh;
+    s.s_all = h->s_all;
+    s.s_ex = h->s_ex;
+    s.j1 = h->j1;
+    s.k = geo_const(c.geom, c.scale);
+    return fn(s, (const void*)nullptr);
+}
+
+// --------------------------------------------------------------- iteration --
+struct Solver {
+    ot_assoc* h;
+    int64_t I;
+    int J;
+    Shape shape;    // fast (FP32-exponential) iterations
+    Shape shape64;  // FP64 iterations
+    bool graphs;
+
+    // Iteration k_from + 1: reads iterate k_from (parity k_from & 1) and
+    // writes the other parity. ev_a / ev_b (optional) bracket the sweep.
+    template <class Src, bool P64>
+    ot_status issue_iter(const Src& src, int k_from, int mode, double stall_below, hipEvent_t ev_a = nullptr,
+                         hipEvent_t ev_b = nullptr) {
+        const Shape& sh = P64 ? shape64 : shape;
+        const int pin = k_from & 1, pout = pin ^ 1;
+        IterArgs A{};
+        A.I = I; A.J = J; A.nch = sh.nch; A.rows_per_block = sh.rpb;
+        A.a = h->a; A.f_in = h->f[pin]; A.f_out = h->f[pout]; A.g_in = h->g[pin];
+        A.col_part = h->col_part; A.res_part = h->res_part; A.ctl = h->ctl; A.prm = h->prm;
+        if (ev_a) hipEventRecord(ev_a, h->stream);
+        if (!launch_iter<Src, P64>(sh, A, src, h->stream))
+            return fail(h, OT_EINVAL, "no iteration kernel for vec=%d nch=%d waves=%d rb=%d", sh.vec, sh.nchT, sh.waves, sh.rb);
+        if (ev_b) hipEventRecord(ev_b, h->stream);
+        ColArgs B{};
+        B.J = J; B.nb = sh.nb; B.b = h->b; B.g_in = h->g[pin]; B.g_out = h->g[pout];
+        B.col_part = h->col_part; B.res_part = h->res_part; B.ctl = h->ctl; B.prm = h->prm;
+        B.mode = mode; B.stall_below = stall_below;
+        if (!g_prepare_only)
+            hipLaunchKernelGGL(k_colsum, dim3((unsigned)((J + kColsPerWg - 1) / kColsPerWg)), dim3(1024), 0, h->stream, B);
+        return OT_OK;
+    }
+
+    template <class Src, bool P64>
+    ot_status issue_chunk(const Src& src, int k0, int n, int mode, double stall_below) {
+        for (int q = 0; q < n; ++q) {
+            ot_status st = issue_iter<Src, P64>(src, k0 + q, mode, stall_below);
+            if (st) return st;
+        }
+        return OT_OK;
+    }
+
+    template <class Src, bool P64>
+    ot_status launch_chunk(const Src& src, int k0, int n, int mode, double stall_below) {
+        if (!graphs) return issue_chunk<Src, P64>(src, k0, n, mode, stall_below);
+        std::string key;
+        auto put = [&](const void* p, size_t b) { key.append((const char*)p, b); };
+        const Shape& sh = P64 ? shape64 : shape;
+        const int tag[10] = {Src::kTag, (int)P64, k0 & 1, n, mode, J, sh.vec, sh.waves, sh.nb, sh.rb};
+        put(tag, sizeof tag);
+        put(&I, sizeof I);
+        put(&sh.rpb, sizeof sh.rpb);
+        put(&stall_below, sizeof stall_below);
+        put(&src, sizeof src);
+        hipGraphExec_t exec = nullptr;
+        for (auto& e : h->graphs)
+            if (e.key == key) { exec = e.exec; break; }
+        if (!exec) {
+            g_prepare_only = true;
+            ot_status pst = issue_chunk<Src, P64>(src, k0, n, mode, stall_below);
+            g_prepare_only = false;
+            if (pst) return pst;
+            HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            ot_status st = issue_chunk<Src, P64>(src, k0, n, mode, stall_below);
+            hipGraph_t graph = nullptr;
+            hipError_t e1 = hipStreamEndCapture(h->stream, &graph);
+            if (st) { if (graph) hipGraphDestroy(graph); return st; }
+            if (e1 != hipSuccess) return fail(h, OT_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
+            hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e2 != hipSuccess) return fail(h, OT_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e2));
+            if ((int)h->graphs.size() >= kGraphCache) {
+                hipGraphExecDestroy(h->graphs.front().exec);
+                h->graphs.erase(h->graphs.begin());
+            }
+            h->graphs.push_back(GraphEntry{key, exec});
+        }
+        HIPCHK(h, hipGraphLaunch(exec, h->stream));
+        return OT_OK;
+    }
+
+    ot_status snapshot(int slot) {
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipMemcpyAsync(&h->ctl_h[slot], h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipEventRecord(h->ev_slot[slot], h->stream));
+        return OT_OK;
+    }
+    ot_status wait(int slot) {
+        HIPCHK(h, hipEventSynchronize(h->ev_slot[slot]));
+        return OT_OK;
+    }
+
+    // Runs chunks until the device sets stop (or done). One chunk stays in
+    // flight while the host inspects the previous chunk's control block; the
+    // extra chunk issued after the stop does nothing on the device.
+    template <class Src, bool P64>
+    ot_status run_phase(const Src& src, int mode, int chunk, double stall_below, Ctl& state) {
+        hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, h->stream, h->ctl);
+        const int k0 = state.iter;  // chunks are even, so every chunk starts on this parity
+        int slot = 0;
+        ot_status st = launch_chunk<Src, P64>(src, k0, chunk, mode, stall_below);
+        if (st || (st = snapshot(slot))) return st;
+        for (;;) {
+            if ((st = launch_chunk<Src, P64>(src, k0, chunk, mode, stall_below))) return st;
+            if ((st = snapshot(slot ^ 1))) return st;
+            if ((st = wait(slot))) return st;
+            const Ctl& c = h->ctl_h[slot];
+            if (c.stop || c.done) {
+                if ((st = wait(slot ^ 1))) return st;
+                state = h->ctl_h[slot ^ 1];
+                return OT_OK;
+            }
+            slot ^= 1;
+        }
+    }
+
+    template <class Src>
+    ot_status run_check(const Src& src, int k, Ctl& out) {
+        const Shape cs = row64(shape64, J);
+        CheckArgs A{};
+        A.I = I; A.J = J; A.nch = cs.nch; A.rows_per_block = cs.rpb;
+        A.a = h->a; A.f = h->f[k & 1]; A.g = h->g[k & 1];
+        A.col_part = h->col_part; A.stat_part = h->stat_part; A.prm = h->prm;
+        if (!launch_check<Src>(cs, A, src, h->stream)) return fail(h, OT_EINVAL, "no check kernel for this shape");
+        CheckColArgs B{};
+        const int ncb = (J + kColsPerWg - 1) / kColsPerWg;
+        B.J = J; B.nb = shape64.nb; B.b = h->b; B.g = h->g[k & 1]; B.col_part = h->col_part; B.cpart = h->cpart;
+        hipLaunchKernelGGL(k_check_cols, dim3((unsigned)ncb), dim3(1024), 0, h->stream, B);
+        hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(256), 0, h->stream, (const double*)h->stat_part, shape64.nb,
+                           (const double*)h->cpart, ncb, h->ctl, (const SolveParams*)h->prm);
+        ot_status st = snapshot(0);
+        if (st || (st = wait(0))) return st;
+        out = h->ctl_h[0];
+        return OT_OK;
+    }
+};
+
+// The three phases of a solve. `c` enters with the initial control state and
+// leaves with the final one; result_iter names the returned iterate.
+template <class Src>
+ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, int J, double tol, int32_t max_iter,
+                     Ctl& c, int& result_iter) {
+    const int vec = vec_for<Src>(J, data);
+    Solver S{h, I, J, make_shape<Src>(h, I, J, vec, false), make_shape<Src>(h, I, J, vec, true), h->opt.use_graphs != 0};
+    if (S.shape.nchT > (S.shape.vec == 4 ? 8 : S.shape.vec == 2 ? 16 : 32))
+        return fail(h, OT_EINVAL, "J = %d too large for this cost layout", J);
+    int chunk = std::max(2, h->opt.chunk);
+    chunk += chunk & 1;  // even: every chunk starts on the same buffer parity
+    ot_status st;
+    const double stall_below = 1e-7;  // FP32 sweeps are not trusted below this
+    if (h->opt.precision == OT_PREC_FP32) {
+        if ((st = S.run_phase<Src, false>(src, kModeFast, chunk, stall_below, c))) return st;
+        if (!c.done && c.iter < max_iter) {
+            const int np = std::max(0, std::min(h->opt.polish_iters, max_iter - c.iter));
+            if (np > 0) {
+                hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, h->stream, h->ctl);
+                if ((st = S.issue_chunk<Src, true>(src, c.iter, np, kModePolish, 0.0))) return st;
+                if ((st = S.snapshot(0)) || (st = S.wait(0))) return st;
+                c = h->ctl_h[0];
+            }
+        }
+    }
+    if (c.done) {  // numeric failure in the fast phase
+        result_iter = c.result_iter;
+        return OT_OK;
+    }
+    if ((st = S.run_check<Src>(src, c.iter, c))) return st;
+    result_iter = c.iter;
+    if (!(c.chk_violation < tol) && c.iter < max_iter) {
+        if ((st = S.run_phase<Src, true>(src, kModeExact, chunk, 0.0, c))) return st;
+        const int k = c.done ? c.result_iter : c.iter;
+        const Ctl loop = c;
+        if ((st = S.run_check<Src>(src, k, c))) return st;
+        c.done = loop.done;
+        c.numeric_bad = loop.numeric_bad;
+        c.iter = loop.iter;
+        c.fp64_iters = loop.fp64_iters;
+        result_iter = k;
+    }
+    return OT_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI ==
+extern "C" {
+
+ot_status ot_assoc_default_options(ot_assoc_options* opt) {
+    if (!opt) return OT_EINVAL;
+    std::memset(opt, 0, sizeof *opt);
+    opt->device = 0;
+    opt->stream = nullptr;
+    opt->precision = OT_PREC_FP32;
+    opt->polish_iters = 1;
+    opt->chunk = 8;
+    opt->use_graphs = 1;
+    return OT_OK;
+}
+
+const char* ot_assoc_last_error(const ot_assoc* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+void ot_assoc_destroy(ot_assoc* h) {
+    if (!h) return;
+    hipSetDevice(h->device);
+    for (auto& e : h->graphs) hipGraphExecDestroy(e.exec);
+    void* bufs[] = {h->a, h->b, h->f[0], h->f[1], h->g[0], h->g[1], h->col_part, h->res_part, h->stat_part,
+                    h->cpart, h->ctl, h->prm, h->bad, h->hist,
+                    h->xy_dev, h->xy_rrh, h->s_all, h->s_ex, h->j1, h->stage};
+    for (void* p : bufs)
+        if (p) hipFree(p);
+    if (h->ctl_h) hipHostFree(h->ctl_h);
+    hipEvent_t evs[] = {h->ev_start, h->ev_stop, h->ev_slot[0], h->ev_slot[1]};
+    for (auto e : evs)
+        if (e) hipEventDestroy(e);
+    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    delete h;
+}
+
+ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot_assoc_options* opt) {
+    if (!out) return fail(nullptr, OT_EINVAL, "handle pointer is NULL");
+    *out = nullptr;
+    if (I_max < 1 || J_max < 1) return fail(nullptr, OT_EINVAL, "I_max and J_max must be >= 1");
+    if (J_max > kMaxJ) return fail(nullptr, OT_EINVAL, "J_max %lld exceeds the supported %d RRHs", (long long)J_max, kMaxJ);
+    if (I_max > ((int64_t)1 << 31)) return fail(nullptr, OT_EINVAL, "I_max too large");
+    ot_assoc_options o;
+    ot_assoc_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision != OT_PREC_FP32 && o.precision != OT_PREC_FP64) return fail(nullptr, OT_EINVAL, "bad precision");
+    if (o.sweep_blocks < 0 || o.sweep_blocks > kMaxNb) return fail(nullptr, OT_EINVAL, "sweep_blocks out of range");
+    if (o.chunk < 0 || o.polish_iters < 0) return fail(nullptr, OT_EINVAL, "negative chunk or polish_iters");
+    if (o.sweep_rows != 0 && o.sweep_rows != 1 && o.sweep_rows != 2 && o.sweep_rows != 4 && o.sweep_rows != 8)
+        return fail(nullptr, OT_EINVAL, "sweep_rows must be 0, 1, 2, 4 or 8");
+    if (o.sweep_lanes != 0 && o.sweep_lanes != 16 && o.sweep_lanes != 32 && o.sweep_lanes != 64)
+        return fail(nullptr, OT_EINVAL, "sweep_lanes must be 0, 16, 32 or 64");
+    if (o.sweep_waves != 0 && o.sweep_waves != 4 && o.sweep_waves != 8)
+        return fail(nullptr, OT_EINVAL, "sweep_waves must be 0, 4 or 8");
+    if (o.chunk == 0) o.chunk = 8;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, OT_EDEVICE, "no HIP device");
+    if (o.device < 0 || o.device >= ndev) return fail(nullptr, OT_EINVAL, "device %d out of range", o.device);
+    if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, OT_EDEVICE, "hipSetDevice failed");
+    ot_assoc* h = new ot_assoc();
+    h->device = o.device;
+    h->stream = (hipStream_t)o.stream;
+    h->opt = o;
+    h->I_max = I_max;
+    h->J_max = J_max;
+    auto al = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)); };
+    hipError_t e = hipSuccess;
+    const size_t I8 = sizeof(double) * (size_t)I_max, J8 = sizeof(double) * (size_t)J_max;
+    if (e == hipSuccess) e = al((void**)&h->a, I8);
+    if (e == hipSuccess) e = al((void**)&h->b, J8);
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+        e = al((void**)&h->f[q], I8);
+        if (e == hipSuccess) e = al((void**)&h->g[q], J8);
+    }
+    if (e == hipSuccess) e = al((void**)&h->col_part, (size_t)kMaxNb * J8);
+    if (e == hipSuccess) e = al((void**)&h->res_part, sizeof(double) * kMaxNb);
+    if (e == hipSuccess) e = al((void**)&h->stat_part, sizeof(double) * 5 * kMaxNb);
+    if (e == hipSuccess) e = al((void**)&h->cpart, sizeof(double) * 2 * ((kMaxJ + kColsPerWg - 1) / kColsPerWg));
+    if (e == hipSuccess) e = al((void**)&h->ctl, sizeof(Ctl));
+    if (e == hipSuccess) e = al((void**)&h->prm, sizeof(SolveParams));
+    if (e == hipSuccess) e = al((void**)&h->bad, sizeof(int));
+    if (e == hipSuccess) e = al((void**)&h->hist, sizeof(unsigned long long) * 2048);
+    if (e == hipSuccess) e = al((void**)&h->xy_dev, sizeof(float) * 2 * (size_t)I_max);
+    if (e == hipSuccess) e = al((void**)&h->xy_rrh, sizeof(float) * 2 * (size_t)J_max);
+    if (e == hipSuccess) e = al((void**)&h->s_all, I8);
+    if (e == hipSuccess) e = al((void**)&h->s_ex, I8);
+    if (e == hipSuccess) e = al((void**)&h->j1, sizeof(int) * (size_t)I_max);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&h->ctl_h, 2 * sizeof(Ctl), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev_stop);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_slot[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_slot[1], hipEventDisableTiming);
+    if (e == hipSuccess && !h->stream) {  // graphs cannot be captured on the legacy default stream
+        e = hipStreamCreate(&h->stream);
+        h->own_stream = (e == hipSuccess);
+    }
+    if (e != hipSuccess) {
+        ot_status st = (e == hipErrorOutOfMemory) ? OT_ENOMEM : OT_EDEVICE;
+        fail(nullptr, st, "workspace allocation failed: %s", hipGetErrorString(e));
+        ot_assoc_destroy(h);
+        return st;
+    }
+    *out = h;
+    return OT_OK;
+}
+
+ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a, const double* b, double eps,
+                         double tol, int32_t max_iter, int warm_start, ot_assoc_result* out) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    ot_status st = validate_desc(h, cost);
+    if (st) return st;
+    if (!a || !b) return fail(h, OT_EINVAL, "marginals are NULL");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(h, OT_EINVAL, "eps must be positive and finite");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(h, OT_EINVAL, "tol must be >= 0");
+    if (max_iter < 1) return fail(h, OT_EINVAL, "max_iter must be >= 1");
+    const int64_t I = cost->I, J = cost->J;
+    if (warm_start && !(h->have_pot && h->I == I && h->J == J))
+        return fail(h, OT_ESTATE, "warm start needs potentials of a %lld x %lld instance", (long long)I, (long long)J);
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    std::vector<double> ah, bh;
+    if ((st = read_vec(h, a, I, cost->mem, ah)) || (st = read_vec(h, b, J, cost->mem, bh))) return st;
+    for (double v : ah)
+        if (!(v > 0.0) || !std::isfinite(v)) return fail(h, OT_EINVAL, "device marginal a must be positive and finite");
+    for (double v : bh)
+        if (!(v > 0.0) || !std::isfinite(v)) return fail(h, OT_EINVAL, "RRH marginal b must be positive and finite");
+    const double sa = ksum(ah), sb = ksum(bh);
+    if (std::fabs(sa - sb) > 1e-12 * sa) return fail(h, OT_EINVAL, "marginals are unbalanced: sum a = %.17g, sum b = %.17g", sa, sb);
+
+    const int res_par_prev = h->res_par;
+    HIPCHK(h, hipEventRecord(h->ev_start, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->a, ah.data(), sizeof(double) * I, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->b, bh.data(), sizeof(double) * J, hipMemcpyHostToDevice, h->stream));
+    if (warm_start) {
+        if (res_par_prev != 0) {
+            HIPCHK(h, hipMemcpyAsync(h->f[0], h->f[1], sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(h->g[0], h->g[1], sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
+        }
+    } else {
+        HIPCHK(h, hipMemsetAsync(h->g[0], 0, sizeof(double) * J, h->stream));
+    }
+    SolveParams p{std::log2(std::exp(1.0)) / eps, eps};
+    HIPCHK(h, hipMemcpyAsync(h->prm, &p, sizeof p, hipMemcpyHostToDevice, h->stream));
+    Ctl c{};
+    c.has_prev = warm_start ? 1 : 0;
+    c.last_fp64 = 0;
+    c.max_iter = max_iter;
+    c.tol = tol;
+    c.mass = sa;
+    c.r_last = __builtin_huge_val();
+    for (double& r : c.r_hist) r = __builtin_huge_val();
+    std::memcpy(&h->ctl_h[0], &c, sizeof c);
+    HIPCHK(h, hipMemcpyAsync(h->ctl, &h->ctl_h[0], sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // ctl_h[0] is reused as the initial-state mirror below
+
+    Ctl fin = c;
+    int result_iter = 0;
+    st = upload_cost(h, cost, true);
+    if (!st)
+        st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
+            return solve_with(h, src, data, I, (int)J, tol, max_iter, fin, result_iter);
+        });
+    if (st) {
+        h->solved = false;
+        h->have_pot = false;
+        h->retained = false;
+        return st;
+    }
+    HIPCHK(h, hipEventRecord(h->ev_stop, h->stream));
+    HIPCHK(h, hipEventSynchronize(h->ev_stop));
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, h->ev_start, h->ev_stop);
+    HIPCHK(h, hipGetLastError());
+
+    h->I = I;
+    h->J = J;
+    h->eps = eps;
+    h->res_par = result_iter & 1;
+    h->have_pot = true;
+    ot_status rs = OT_OK;
+    if (fin.numeric_bad || !std::isfinite(fin.chk_violation)) rs = OT_ENUMERIC;
+    else if (!(fin.chk_violation < tol)) rs = OT_WARN_MAXITER;
+    h->solved = (rs >= 0);
+    if (out) {
+        out->iterations = result_iter;
+        out->fp64_iterations = fin.fp64_iters;
+        out->status = rs;
+        out->reserved = 0;
+        out->marginal_violation = fin.chk_violation;
+        out->objective = fin.chk_objective;
+        out->reg_objective = fin.chk_reg_objective;
+        out->dual_objective = fin.chk_dual;
+        out->seconds = ms * 1e-3;
+    }
+    if (rs == OT_ENUMERIC) return fail(h, OT_ENUMERIC, "non-finite residual or potential during the solve");
+    return rs;
+}
+
+ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!h->solved || !h->retained) return fail(h, OT_ESTATE, "no successful solve to take a plan from");
+    if (!pi) return fail(h, OT_EINVAL, "plan buffer is NULL");
+    if (dtype != OT_F32 && dtype != OT_F64) return fail(h, OT_EINVAL, "bad dtype");
+    if (mem != OT_MEM_HOST && mem != OT_MEM_DEVICE) return fail(h, OT_EINVAL, "bad memory space");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const int64_t I = h->I, J = h->J;
+    const size_t bytes = (size_t)(I * J) * (dtype == OT_F32 ? 4 : 8);
+    void* dst = pi;
+    void* tmp = nullptr;
+    if (mem == OT_MEM_HOST) {
+        HIPCHK(h, hipMalloc(&tmp, bytes));
+        dst = tmp;
+    }
+    ot_status st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
+        using S = std::decay_t<decltype(src)>;
+        const Shape s = row64(make_shape<S>(h, I, J, vec_for<S>(J, data)), J);
+        bool ok = dtype == OT_F32 ? launch_plan<S, float>(s, I, (int)J, h->f[h->res_par], h->g[h->res_par], h->prm, (float*)dst, src, h->stream)
+                                  : launch_plan<S, double>(s, I, (int)J, h->f[h->res_par], h->g[h->res_par], h->prm, (double*)dst, src, h->stream);
+        if (!ok) return fail(h, OT_EINVAL, "no plan kernel for this shape");
+        return OT_OK;
+    });
+    if (!st && mem == OT_MEM_HOST) {
+        hipError_t e = hipMemcpyAsync(pi, tmp, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) st = fail(h, OT_EDEVICE, "plan copy failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (tmp) hipFree(tmp);
+    if (!st && e != hipSuccess) st = fail(h, OT_EDEVICE, "plan failed: %s", hipGetErrorString(e));
+    return st;
+}
+
+ot_status ot_assoc_potentials(ot_assoc* h, double* f, double* g, ot_mem mem) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!h->have_pot) return fail(h, OT_ESTATE, "no potentials yet");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const hipMemcpyKind k = mem == OT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (f) HIPCHK(h, hipMemcpyAsync(f, h->f[h->res_par], sizeof(double) * h->I, k, h->stream));
+    if (g) HIPCHK(h, hipMemcpyAsync(g, h->g[h->res_par], sizeof(double) * h->J, k, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return OT_OK;
+}
+
+ot_status ot_assoc_set_potentials(ot_assoc* h, const double* f, const double* g, int64_t I, int64_t J, ot_mem mem) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!f || !g) return fail(h, OT_EINVAL, "potentials are NULL");
+    if (I < 1 || J < 1 || I > h->I_max || J > h->J_max) return fail(h, OT_EINVAL, "sizes out of range");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const hipMemcpyKind k = mem == OT_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIPCHK(h, hipMemcpyAsync(h->f[0], f, sizeof(double) * I, k, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->g[0], g, sizeof(double) * J, k, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->I = I;
+    h->J = J;
+    h->res_par = 0;
+    h->have_pot = true;
+    h->solved = false;
+    return OT_OK;
+}
+
+ot_status ot_assoc_cost_median(ot_assoc* h, const ot_cost_desc* cost, double* median_out) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!median_out) return fail(h, OT_EINVAL, "median_out is NULL");
+    if (!cost || (cost->kind != OT_COST_RATES && cost->kind != OT_COST_GEOMETRY))
+        return fail(h, OT_EINVAL, "the median needs a RATES or GEOMETRY descriptor");
+    ot_cost_desc c = *cost;
+    c.scale = 1.0;  // C = 1/R
+    ot_status st = validate_desc(h, &c);
+    if (st) return st;
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const int64_t I = c.I, J = c.J;
+    uint64_t rank = (uint64_t)((I * J - 1) / 2);
+    uint32_t prefix = 0;
+    std::vector<unsigned long long> hh(2048);
+    h->solved = false;  // the handle's retained cost is replaced below
+    st = upload_cost(h, &c, true);
+    if (st) return st;
+    st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
+        using S = std::decay_t<decltype(src)>;
+        const size_t lds = sizeof(double) * S::kStageDoubles * (size_t)J + 8;
+        const int grid = (int)std::min<int64_t>(2048, (I + 7) / 8);
+        for (int pass = 0; pass < 3; ++pass) {
+            HIPCHK(h, hipMemsetAsync(h->hist, 0, sizeof(unsigned long long) * 2048, h->stream));
+            hipLaunchKernelGGL(k_median_hist<S>, dim3(grid), dim3(512), lds, h->stream, I, (int)J, pass, prefix, h->hist, src);
+            HIPCHK(h, hipMemcpyAsync(hh.data(), h->hist, sizeof(unsigned long long) * 2048, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            const int nbins = pass == 2 ? 1024 : 2048;
+            uint64_t cum = 0;
+            int bin = -1;
+            for (int q = 0; q < nbins; ++q) {
+                if (cum + hh[q] > rank) { bin = q; break; }
+                cum += hh[q];
+            }
+            if (bin < 0) return fail(h, OT_ENUMERIC, "median selection lost its rank (non-finite rates?)");
+            rank -= cum;
+            prefix = pass == 0 ? (uint32_t)bin : pass == 1 ? ((prefix << 11) | (uint32_t)bin) : ((prefix << 10) | (uint32_t)bin);
+        }
+        return OT_OK;
+    });
+    if (st) return st;
+    float m;
+    std::memcpy(&m, &prefix, sizeof m);
+    *median_out = (double)m;
+    return OT_OK;
+}
+
+ot_status ot_assoc_materialize_cost(ot_assoc* h, const ot_cost_desc* cost, float* C_dev) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!C_dev) return fail(h, OT_EINVAL, "output buffer is NULL");
+    if (!cost || (cost->kind != OT_COST_RATES && cost->kind != OT_COST_GEOMETRY))
+        return fail(h, OT_EINVAL, "materialisation needs a RATES or GEOMETRY descriptor");
+    ot_status st = validate_desc(h, cost);
+    if (st) return st;
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const int64_t I = cost->I, J = cost->J;
+    h->solved = false;  // the handle's retained cost is replaced below
+    st = upload_cost(h, cost, true);
+    if (st) return st;
+    st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
+        using S = std::decay_t<decltype(src)>;
+        const size_t lds = sizeof(double) * S::kStageDoubles * (size_t)J + 8;
+        const int grid = (int)std::min<int64_t>(4096, (I + 7) / 8);
+        hipLaunchKernelGGL(k_materialize<S>, dim3(grid), dim3(512), lds, h->stream, I, (int)J, C_dev, src);
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return OT_OK;
+    });
+    return st;
+}
+
+ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_per_launch) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!ms_per_launch || reps < 1 || reps > 4096) return fail(h, OT_EINVAL, "reps must be in 1..4096");
+    if (!h->solved || !h->retained) return fail(h, OT_ESTATE, "no successful solve to time");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const int64_t I = h->I, J = h->J;
+    const int p = h->res_par;
+    double *fs = nullptr, *gs = nullptr;
+    HIPCHK(h, hipMalloc(&fs, sizeof(double) * I));
+    hipError_t e = hipMalloc(&gs, sizeof(double) * J);
+    if (e != hipSuccess) { hipFree(fs); return fail(h, OT_ENOMEM, "hipMalloc failed"); }
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    ot_status st = OT_OK;
+    for (auto& x : ev)
+        if (hipEventCreate(&x) != hipSuccess) st = fail(h, OT_EDEVICE, "hipEventCreate failed");
+    Ctl saved{};
+    if (!st) {
+        hipMemcpyAsync(fs, h->f[p], sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream);
+        hipMemcpyAsync(gs, h->g[p], sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream);
+        hipMemcpyAsync(&saved, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+        hipStreamSynchronize(h->stream);
+        Ctl c = saved;
+        c.stop = 0; c.done = 0; c.has_prev = 1; c.iter = p; c.max_iter = 1 << 30; c.arrive = 0; c.arrive2 = 0;
+        c.numeric_bad = 0;
+        std::memcpy(&h->ctl_h[0], &c, sizeof c);
+        hipMemcpyAsync(h->ctl, &h->ctl_h[0], sizeof(Ctl), hipMemcpyHostToDevice, h->stream);
+        st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
+            using S = std::decay_t<decltype(src)>;
+            const int vec = vec_for<S>(J, data);
+            Solver sv{h, I, (int)J, make_shape<S>(h, I, J, vec, false), make_shape<S>(h, I, J, vec, true), false};
+            for (int r = 0; r < reps; ++r) {
+                // iteration from parity (p + r) & 1; only the sweep kernel is bracketed
+                const ot_status s2 = fp64 ? sv.issue_iter<S, true>(src, p + r, kModePolish, 0.0, ev[2 * r], ev[2 * r + 1])
+                                          : sv.issue_iter<S, false>(src, p + r, kModePolish, 0.0, ev[2 * r], ev[2 * r + 1]);
+                if (s2) return s2;
+            }
+            return OT_OK;
+        });
+        hipError_t e2 = hipStreamSynchronize(h->stream);
+        if (!st && e2 != hipSuccess) st = fail(h, OT_EDEVICE, "timed sweeps failed: %s", hipGetErrorString(e2));
+        if (!st) {
+            double tot = 0.0;
+            for (int r = 0; r < reps; ++r) {
+                float ms = 0.0f;
+                hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
+                tot += ms;
+            }
+            *ms_per_launch = tot / reps;
+        }
+        hipMemcpyAsync(h->f[p], fs, sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream);
+        hipMemcpyAsync(h->g[p], gs, sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream);
+        std::memcpy(&h->ctl_h[0], &saved, sizeof saved);
+        hipMemcpyAsync(h->ctl, &h->ctl_h[0], sizeof(Ctl), hipMemcpyHostToDevice, h->stream);
+        hipStreamSynchronize(h->stream);
+    }
+    for (auto& x : ev)
+        if (x) hipEventDestroy(x);
+    hipFree(fs);
+    hipFree(gs);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+"""The C-ABI library loads and exports every symbol its header declares; host
+logic that needs no GPU. No compute calls are made here."""
+
+import ctypes as ct
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1805_01559_amd import ot_assoc as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ot_assoc.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ot_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(A.LIB_PATH):
+        pytest.skip("libot_assoc.so not built")
+    return A.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    assert set(names) == set(A.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", A.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (ot_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ot_assoc.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(ot_cost_desc), sizeof(ot_assoc_options),'
+                   ' sizeof(ot_assoc_result), offsetof(ot_cost_desc, geom), offsetof(ot_assoc_result, seconds));'
+                   'return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
+    want = [ct.sizeof(A.ot_cost_desc), ct.sizeof(A.ot_assoc_options), ct.sizeof(A.ot_assoc_result),
+            A.ot_cost_desc.geom.offset, A.ot_assoc_result.seconds.offset]
+    assert got == want
+
+
+def test_default_options(lib):
+    o = A.ot_assoc_default_options()
+    assert (o.device, o.precision, o.polish_iters, o.chunk, o.use_graphs) == (0, A.OT_PREC_FP32, 1, 8, 1)
+
+
+def test_argument_errors_without_a_device(lib):
+    # invalid sizes are rejected before any device is touched
+    with pytest.raises(A.OTError) as e:
+        A.ot_assoc_create(0, 10)
+    assert e.value.status == A.OT_EINVAL
+    with pytest.raises(A.OTError) as e:
+        A.ot_assoc_create(10, 5000)
+    assert e.value.status == A.OT_EINVAL
+    # NULL handles are rejected, destroy is NULL-safe
+    assert lib.ot_assoc_solve(None, None, None, None, 0.1, 1e-6, 10, 0, None) == A.OT_EINVAL
+    assert lib.ot_assoc_plan(None, None, 0, 0) == A.OT_EINVAL
+    lib.ot_assoc_destroy(None)
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1805_01559_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "oracle" not in text.lower().replace("# the oracle", ""), fn
