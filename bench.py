@@ -154,6 +154,41 @@ def main():
     ms_sweep_geo = solver.time_sweep(max(10, args.sweep_reps // 4), fp64=False)
     log(f"on-the-fly: {t_geo * 1e3:.3f} ms/solve, iters={res_g.iterations}, sweep {ms_sweep_geo * 1e3:.2f} us")
 
+    # copy ceiling of this GPU: a plain device-to-device copy of 256 MiB
+    # (read + write), also the calibration kernel of the traffic counters
+    src_buf = torch.empty(64 << 20, dtype=torch.float32, device=dev).uniform_()
+    dst_buf = torch.empty_like(src_buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        dst_buf.copy_(src_buf)
+    e0.record()
+    for _ in range(5):
+        dst_buf.copy_(src_buf)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * src_buf.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src_buf, dst_buf
+    log(f"copy ceiling: {copy_gbps:.0f} GB/s")
+
+    # the same sweep above the 256 MB last-level cache: 200000 x 400 FP32
+    # (320 MB) materialised from a 15 km layout with 16 hot spots
+    LB = S.make_layout(200000, 400, 15000.0, hot_spots=16, hot_share=0.4, seed=2400)
+    big = A.Solver(LB.I, LB.J)
+    xyb = torch.from_numpy(LB.dev_xy).to(dev)
+    rxyb = torch.from_numpy(LB.rrh_xy).to(dev)
+    ab = torch.from_numpy(LB.a).to(dev)
+    bb = torch.from_numpy(LB.b).to(dev)
+    dB, keepB = A.geometry_desc(xyb, rxyb, LB.radio, LB.shadow_key, 1.0)
+    dB.scale = big.cost_median(dB)
+    CB = torch.empty((LB.I, LB.J), dtype=torch.float32, device=dev)
+    big.materialize_cost(dB, CB)
+    _, resB = big.solve_dense(CB, ab, bb, eps, tol, 2000)
+    ms_big = big.time_sweep(max(20, args.sweep_reps // 4), fp64=False)
+    gbps_big = 4.0 * LB.I * LB.J / (ms_big * 1e-3) / 1e9
+    log(f"320 MB sweep: {ms_big * 1e3:.2f} us = {gbps_big:.0f} GB/s ({resB.iterations} iterations to converge)")
+    big.close()
+    del CB
+
     cells = I * J
     alg_bytes = 4.0 * cells  # one FP32 read of C per iteration
     achieved = alg_bytes / (ms_sweep * 1e-3) / 1e9
@@ -182,6 +217,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_iter<DenseSrc<float>, fp32 exp> (fused row update + column partials)",
                      "avg_launch_us": ms_sweep * 1e3},
+        "copy_gbps": copy_gbps,
+        "sweep_above_llc": {"workload": "200000x400 dense FP32 (320 MB), same kernel", "sweep_us": ms_big * 1e3,
+                            "achieved_gbps": gbps_big, "frac": gbps_big / HBM_PEAK_GBS,
+                            "iterations": resB.iterations, "marginal_violation": resB.marginal_violation},
         "fp64_sweep_us": ms_sweep64 * 1e3,
         "on_the_fly": {"ms_per_solve": t_geo * 1e3, "cells_per_s": cells * res_g.iterations / t_geo,
                        "iterations": res_g.iterations, "fp64_iterations": res_g.fp64_iterations,

@@ -115,6 +115,8 @@ typedef struct {
     int sweep_waves;    /* 0 = choose automatically; 4 or 8 waves per workgroup (dense FP32 costs) */
     int sweep_rows;     /* 0 = choose automatically; else 1, 2, 4 or 8 row steps in flight per wave */
     int sweep_lanes;    /* 0 = choose automatically; else 16, 32 or 64 lanes per row */
+    int batch_tune;     /* ot_assoc_solve_batch: 1 (default) times the (waves, rows per part)
+                           candidates once per batch shape and keeps the fastest; 0 uses 8, 128 */
 } ot_assoc_options;
 
 typedef struct {
@@ -187,9 +189,10 @@ ot_status ot_assoc_materialize_cost(ot_assoc *h, const ot_cost_desc *cost, float
 /* (instrumentation) Average device duration, in milliseconds, of one launch
  * of the fused sweep kernel that the last successful solve used (same cost,
  * shape and launch configuration; FP32 exponentials if fp64 == 0, else FP64).
- * Runs `reps` (1..4096) extra iterations, each sweep bracketed by HIP events
- * on the handle's stream, then restores the solve's potentials, so a later
- * ot_assoc_plan / ot_assoc_potentials is unaffected.
+ * Runs `reps` (1..4096) extra sweeps back to back on the handle's stream
+ * between one pair of HIP events (so the figure includes the gap between
+ * dependent launches), then restores the solve's potentials and control
+ * state, so a later ot_assoc_plan / ot_assoc_potentials is unaffected.
  * Errors: OT_ESTATE before a successful solve, OT_EINVAL for bad reps. */
 ot_status ot_assoc_time_sweep(ot_assoc *h, int32_t reps, int fp64, double *ms_per_launch);
 
@@ -200,6 +203,108 @@ void ot_assoc_destroy(ot_assoc *h);
  * The string is owned by the handle and valid until its next call. With
  * h == NULL it describes the last failed ot_assoc_create on this thread. */
 const char *ot_assoc_last_error(const ot_assoc *h);
+
+/* ------------------------------------------------------------ batched solves
+ * Many independent association instances solved together, as one engine:
+ * each is the problem of eq. (5) with its own cost, marginals and eps, solved
+ * by the same Sinkhorn iterations (Sec. III-B) and the same phases as
+ * ot_assoc_solve with OT_PREC_FP32 (FP32 sweeps, FP64 polish, exact FP64
+ * check, FP64 sweeps if the check misses tol). Instances advance together,
+ * three persistent launches per iteration, captured in HIP graphs; an
+ * instance leaves the work lists as soon as it is done, so uneven sizes and
+ * iteration counts cost only their own work.
+ *
+ * Every cost is held as a padded FP32 row-major matrix: a DENSE FP32 matrix in
+ * device memory whose J is a multiple of 4 and whose rows are 16-byte aligned
+ * is referenced in place (keep it valid until the next batch on the handle);
+ * other DENSE / RATES inputs (host or device, FP32 or FP64) are converted,
+ * GEOMETRY inputs (device memory) are materialised (scale <= 0 takes the
+ * median of 1/R). 1 <= J <= 512; a[k] and b[k] live in costs[k].mem
+ * (GEOMETRY: device memory). eps[k] > 0 per instance; tol and max_iter are
+ * shared. out[k] (may be NULL) receives instance k's result; `seconds` is the
+ * device time of the whole batch.
+ *
+ * Returns OT_OK when every instance met tol, OT_WARN_MAXITER if some stopped
+ * at max_iter, OT_ENUMERIC if some failed numerically (see out[k].status),
+ * OT_EINVAL / OT_ENOMEM with nothing solved when an input is invalid or the
+ * batch does not fit (4096 instances, 2^20 row parts of 64 rows, 90% of free
+ * device memory). The previous batch's instances are released first. */
+ot_status ot_assoc_solve_batch(ot_assoc *h, int n, const ot_cost_desc *costs, const double *const *a,
+                               const double *const *b, const double *eps, double tol, int32_t max_iter,
+                               ot_assoc_result *out);
+
+/* Potentials (f: I, g: J, FP64) of instance k of the last batch, into host or
+ * device memory. OT_ESTATE before a batch, OT_EINVAL for a bad k. */
+ot_status ot_assoc_batch_potentials(ot_assoc *h, int k, double *f, double *g, ot_mem mem);
+
+/* Plan of instance k of the last batch, pi_ij = exp((f_i + g_j - C_ij) / eps)
+ * (eq. (7)) with the FP32 cost the batch used, I x J row-major, FP32 or FP64. */
+ot_status ot_assoc_batch_plan(ot_assoc *h, int k, void *pi, ot_mem mem, ot_dtype dtype);
+
+/* ------------------------------------------------------------------ serving
+ * A request server over the batched engine: requests (one association solve
+ * per scheduling instant) are queued on submit and admitted, oldest first, as
+ * instance slots, work-list room and the device-memory budget allow, while
+ * earlier requests are still iterating; every ot_serve_progress call admits
+ * what fits, runs one chunk of iterations of everything in flight and returns
+ * the requests that finished. A request with a nonzero layout_key starts from
+ * the potentials that the last finished request of the same key (same I x J)
+ * left resident, and leaves its own; resident sets are evicted least recently
+ * used first when memory or keep_layouts runs out. A request's result does
+ * not depend on what else is in flight (fixed-order reductions per instance).
+ * Every buffer a request points to must stay valid and unchanged until its
+ * completion is returned. One thread per server. */
+typedef struct ot_serve ot_serve;
+
+typedef struct {
+    int device;
+    void *stream;          /* hipStream_t; NULL = a stream owned by the server */
+    double budget_bytes;   /* device memory for requests and resident potentials
+                              (0 = 90% of free memory, at most 256 GiB) */
+    int max_slots;         /* requests in flight (0 = 1024) */
+    int max_items;         /* row parts in flight (0 = 2^19) */
+    int polish_iters;      /* FP64 sweeps before the exact check (default 1) */
+    int sweep_waves;       /* 4 or 8 waves per sweep workgroup (default 8) */
+    int rows_per_part;     /* 64, 128 or 256 rows per work item (default 128) */
+    int keep_layouts;      /* resident potential sets kept (0 = 4096) */
+} ot_serve_options;
+
+typedef struct {
+    ot_cost_desc cost;     /* as for ot_assoc_solve_batch */
+    const double *a, *b;   /* marginals, in cost.mem (GEOMETRY: device memory) */
+    double eps, tol;
+    int32_t max_iter;
+    int32_t reserved;
+    uint64_t layout_key;   /* 0: cold start; else warm start / keep potentials under this key */
+    uint64_t user_tag;     /* returned with the completion */
+} ot_request;
+
+typedef struct {
+    uint64_t ticket, user_tag, layout_key;
+    int32_t warm;          /* 1 if the solve started from resident potentials */
+    int32_t reserved;
+    double t_submit, t_admit, t_done; /* host steady clock, seconds (ot_serve_now) */
+    ot_assoc_result result; /* result.status < 0: the request was rejected or failed */
+} ot_completion;
+
+ot_status ot_serve_default_options(ot_serve_options *opt);
+/* Errors: OT_EINVAL for bad options, OT_EDEVICE / OT_ENOMEM from the device. */
+ot_status ot_serve_create(ot_serve **s, const ot_serve_options *opt);
+/* Queues a request (validated for shape and settings now, marginals at
+ * admission); *ticket identifies its completion. Never waits on the GPU. */
+ot_status ot_serve_submit(ot_serve *s, const ot_request *req, uint64_t *ticket);
+/* Admits, runs one chunk, and writes up to max_out completions to out
+ * (*n_out of them); later completions wait for the next call. A request that
+ * can never fit is completed with OT_ENOMEM. */
+ot_status ot_serve_progress(ot_serve *s, ot_completion *out, int max_out, int *n_out);
+/* Requests queued / in flight, resident potential sets, device bytes held. */
+ot_status ot_serve_counts(const ot_serve *s, int *queued, int *running, int *resident, double *bytes_in_use);
+/* Resident potentials of a layout (f: I, g: J), into host or device memory. */
+ot_status ot_serve_potentials(ot_serve *s, uint64_t layout_key, double *f, double *g, ot_mem mem);
+/* The clock of the completion timestamps. */
+double ot_serve_now(void);
+const char *ot_serve_last_error(const ot_serve *s);
+void ot_serve_destroy(ot_serve *s);
 
 #ifdef __cplusplus
 }

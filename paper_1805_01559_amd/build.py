@@ -16,7 +16,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # keep hipcc from forming packed FP32 instructions on its own
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
@@ -24,19 +23,38 @@ FLAGS = [
 
 
 def sources():
-    return [os.path.join(CSRC, "ot_assoc.hip")]
+    return [os.path.join(CSRC, f) for f in ("ot_assoc.hip", "batch.hip")]
+
+
+def _compile(src: str, obj: str, inc: str):
+    cmd = [HIPCC, *FLAGS, "-c", "-I", inc, "-o", obj, src]
+    return cmd, subprocess.run(cmd, capture_output=True, text=True)
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source of the library; always rebuilds."""
+    """Compile every HIP source of the library (one process per source) and
+    link libot_assoc.so; always rebuilds."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(bdir, os.path.basename(s) + ".o") for s in srcs]
+    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        results = list(ex.map(lambda so: _compile(so[0], so[1], inc), zip(srcs, objs)))
+    for cmd, r in results:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed building libot_assoc.so")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(os.path.dirname(HERE), "include"), "-o", tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libot_assoc.so")
+        raise RuntimeError("linking libot_assoc.so failed")
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,0 +1,1306 @@
+// Host runtime of the batched engine and of the request server.
+//
+// BatchEngine keeps a table of instance slots in device memory, a device
+// memory pool that admission draws from (bounded by a byte budget), and two
+// generations of work lists that the kernels of batch_kernels.h consume and
+// rebuild. A chunk of CHUNK iterations (three persistent launches each) is
+// captured once into a HIP graph and replayed for the life of the engine:
+// which instances and parts are live is data, not graph structure. The host
+// admits new instances between chunks and learns about finished ones from a
+// copy of the control blocks taken one chunk behind the device.
+//
+// ot_assoc_solve_batch admits a whole batch and runs chunks until every
+// instance is done. The ot_serve_* entry points admit requests as they
+// arrive, as slots and the byte budget allow, while earlier requests are
+// still iterating (continuous batching), and keep the potentials of each
+// layout resident for warm starts of its next snapshot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ot_assoc.h"
+#include "batch_kernels.h"
+#include "handle.h"
+
+using namespace otk;
+
+namespace {
+
+constexpr int kChunk = 8;  // iterations per captured chunk (even: list generations alternate)
+constexpr size_t kAlign = 256;
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// ------------------------------------------------------------ device pool --
+// First-fit sub-allocator over slabs of device memory, with coalescing of
+// neighbouring free blocks inside a slab. Slabs are taken from the device
+// only while the total stays within the budget; nothing is returned to the
+// device before the pool is destroyed (hipFree would synchronise the device).
+class DevicePool {
+  public:
+    size_t budget = 0;
+    size_t reserved = 0;  // bytes of all slabs
+    size_t in_use = 0;
+    size_t slab_min = (size_t)256 << 20;
+
+    ~DevicePool() { release_all(); }
+
+    void release_all() {
+        for (auto& s : slabs_) hipFree(s.base);
+        slabs_.clear();
+        free_.clear();
+        used_.clear();
+        reserved = in_use = 0;
+    }
+
+    // nullptr when the budget (or the device) cannot provide the bytes
+    char* alloc(size_t bytes) {
+        bytes = align_up(std::max<size_t>(bytes, 1));
+        if (in_use + bytes > budget) return nullptr;
+        char* p = take(bytes);
+        if (!p) {
+            const size_t want = std::max(bytes, slab_min);
+            size_t sz = std::min(want, budget - std::min(budget, reserved));
+            if (sz < bytes) return nullptr;
+            char* base = nullptr;
+            if (hipMalloc(&base, sz) != hipSuccess) {
+                (void)hipGetLastError();
+                if (sz > bytes && hipMalloc(&base, bytes) == hipSuccess) sz = bytes;
+                else { (void)hipGetLastError(); return nullptr; }
+            }
+            slabs_.push_back({base, sz});
+            reserved += sz;
+            free_[base] = sz;
+            p = take(bytes);
+            if (!p) return nullptr;
+        }
+        used_[p] = bytes;
+        in_use += bytes;
+        return p;
+    }
+
+    void release(char* p) {
+        auto it = used_.find(p);
+        if (it == used_.end()) return;
+        size_t sz = it->second;
+        used_.erase(it);
+        in_use -= sz;
+        const Slab* s = slab_of(p);
+        auto nx = free_.lower_bound(p);
+        if (nx != free_.end() && nx->first == p + sz && slab_of(nx->first) == s) {
+            sz += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == p && slab_of(pv->first) == s) {
+                pv->second += sz;
+                return;
+            }
+        }
+        free_[p] = sz;
+    }
+
+  private:
+    struct Slab {
+        char* base;
+        size_t size;
+    };
+    std::vector<Slab> slabs_;
+    std::map<char*, size_t> free_, used_;
+
+    const Slab* slab_of(char* p) const {
+        for (auto& s : slabs_)
+            if (p >= s.base && p < s.base + s.size) return &s;
+        return nullptr;
+    }
+    char* take(size_t bytes) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            char* p = it->first;
+            const size_t rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[p + bytes] = rest;
+            return p;
+        }
+        return nullptr;
+    }
+};
+
+// One admitted instance, as the host sees it.
+struct Slot {
+    bool live = false;      // admitted and not yet released
+    bool finished = false;  // seen done in a control-block snapshot
+    int64_t I = 0;
+    int J = 0;
+    int64_t ld = 0;
+    int parts_cap = 0;
+    char* mem = nullptr;  // pool block holding everything below
+    BInst d{};
+    SolveParams* prm = nullptr;  // for the plan kernel
+    double eps = 0.0, mass = 0.0;
+    uint64_t ticket = 0, user_tag = 0, layout_key = 0;
+    double t_submit = 0.0, t_admit = 0.0;
+    long adm_seq = 0;  // snapshots taken before admission (older ones say nothing about it)
+    Ctl fin{};
+};
+
+}  // namespace
+
+// What one admitted instance needs: its cost, marginals and solve settings,
+// plus optional resident potentials to start from.
+struct AdmitReq {
+    const ot_cost_desc* cost;
+    const double* a;
+    const double* b;
+    double eps, tol;
+    int32_t max_iter;
+    const double* f0 = nullptr;  // device, warm start (with g0)
+    const double* g0 = nullptr;
+};
+
+struct BatchEngine {
+    int device = 0;
+    int num_cu = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    DevicePool pool;
+    int cap_slots = 0;
+    int cap_items = 0;
+    int polish_iters = 1;
+    int waves = 8;          // FP32 sweep workgroup size in waves (4 or 8)
+    int64_t rpp_rows = 128;  // rows per part
+    bool autotune = true;
+
+    // device state
+    BInst* tab = nullptr;
+    Ctl* ctl = nullptr;
+    BList L[2]{};
+    char* lists_mem = nullptr;
+    BItem* adm_items = nullptr;  // admission staging (device)
+    int* adm_insts = nullptr;
+    // pinned host
+    Ctl* snap[2] = {nullptr, nullptr};
+    BItem* adm_items_h = nullptr;
+    int* adm_insts_h = nullptr;
+    BInst* tab_h = nullptr;  // staging of table entries
+    Ctl* ctl_init_h = nullptr;
+    hipEvent_t ev_snap[2] = {nullptr, nullptr}, ev_adm = nullptr;
+    bool adm_pending = false;
+    char* hstage = nullptr;  // marginals and constants of the pending admission
+    size_t hstage_cap = 0;
+
+    std::vector<Slot> slots;
+    std::vector<int> free_slots;
+    int hi_slot = 0;  // slots [0, hi_slot) may be live
+    int n_live_running = 0;
+    int64_t items_running = 0;  // parts of admitted, unfinished instances (bounds the lists)
+    long seq = 0;               // snapshots taken so far
+
+    // captured chunks, per FP32 workgroup size
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int grid32[2] = {0, 0}, grid64 = 0, gridc = 0;
+    size_t lds32[2] = {0, 0}, lds64 = 0;
+
+    // snapshot pipeline
+    long chunks = 0;
+    int snap_pending = -1;  // slot of the snapshot in flight, -1 none
+    int snap_hi = 0;
+    long snap_seq[2] = {0, 0};
+
+    // tuned (waves, rows per part) per batch signature
+    std::map<std::string, std::pair<int, int64_t>> tuned;
+
+    ot_assoc* helper = nullptr;  // materialises geometry costs
+    std::vector<int> tab_order;  // slots of the last ot_assoc_solve_batch, in request order
+
+    ~BatchEngine();
+    ot_status fail(ot_status st, const char* fmt, ...);
+    ot_status init(int dev, hipStream_t st, int slots_cap, int items_cap, size_t budget);
+    ot_status prepare_kernels();
+    ot_status capture(int widx);
+    ot_status admit(const std::vector<AdmitReq>& reqs, std::vector<int>& out_slots, bool strict);
+    ot_status upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage);
+    ot_status launch_chunk();
+    ot_status collect(bool wait, std::vector<int>& finished);
+    ot_status drain_snapshot(std::vector<int>* finished);
+    void apply_snapshot(int which, int hi, std::vector<int>* finished);
+    void release(int slot);
+    ot_status tune(const std::vector<int>& batch_slots);
+    ot_status relayout(const std::vector<int>& batch_slots, int w, int64_t rpp);
+    int widx() const { return waves == 4 ? 0 : 1; }
+};
+
+#define ECHK(e, call)                                                                                          \
+    do {                                                                                                       \
+        hipError_t e_ = (call);                                                                                \
+        if (e_ != hipSuccess)                                                                                  \
+            return (e)->fail((e_ == hipErrorOutOfMemory) ? OT_ENOMEM : OT_EDEVICE, "%s failed: %s (%s:%d)", #call, \
+                             hipGetErrorString(e_), __FILE__, __LINE__);                                        \
+    } while (0)
+
+ot_status BatchEngine::fail(ot_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return st;
+}
+
+BatchEngine::~BatchEngine() {
+    hipSetDevice(device);
+    if (stream) hipStreamSynchronize(stream);
+    for (auto g : graph)
+        if (g) hipGraphExecDestroy(g);
+    void* dev_bufs[] = {tab, ctl, lists_mem, adm_items, adm_insts};
+    for (void* p : dev_bufs)
+        if (p) hipFree(p);
+    void* host_bufs[] = {snap[0], snap[1], adm_items_h, adm_insts_h, tab_h, ctl_init_h, hstage};
+    for (void* p : host_bufs)
+        if (p) hipHostFree(p);
+    hipEvent_t evs[] = {ev_snap[0], ev_snap[1], ev_adm};
+    for (auto e : evs)
+        if (e) hipEventDestroy(e);
+    if (helper) ot_assoc_destroy(helper);
+    pool.release_all();
+    if (own_stream && stream) hipStreamDestroy(stream);
+}
+
+void batch_engine_destroy(BatchEngine* e) { delete e; }
+
+ot_status BatchEngine::init(int dev, hipStream_t st, int slots_cap, int items_cap, size_t budget) {
+    device = dev;
+    ECHK(this, hipSetDevice(dev));
+    if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || num_cu <= 0)
+        return fail(OT_EDEVICE, "cannot query the number of compute units");
+    if (st) {
+        stream = st;
+    } else {
+        ECHK(this, hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        own_stream = true;
+    }
+    cap_slots = slots_cap;
+    cap_items = items_cap;
+    pool.budget = budget;
+    ECHK(this, hipMalloc(&tab, sizeof(BInst) * cap_slots));
+    ECHK(this, hipMalloc(&ctl, sizeof(Ctl) * cap_slots));
+    const size_t item_bytes = align_up(sizeof(BItem) * (size_t)cap_items);
+    const size_t inst_bytes = align_up(sizeof(int) * (size_t)cap_slots);
+    const size_t gen_bytes = 2 * item_bytes + inst_bytes + kAlign;
+    ECHK(this, hipMalloc(&lists_mem, 2 * gen_bytes));
+    for (int g = 0; g < 2; ++g) {
+        char* p = lists_mem + g * gen_bytes;
+        L[g].it32 = (BItem*)p;
+        L[g].it64 = (BItem*)(p + item_bytes);
+        L[g].inst = (int*)(p + 2 * item_bytes);
+        L[g].cnt = (int*)(p + 2 * item_bytes + inst_bytes);
+    }
+    ECHK(this, hipMemsetAsync(lists_mem, 0, 2 * gen_bytes, stream));
+    ECHK(this, hipMalloc(&adm_items, sizeof(BItem) * (size_t)cap_items));
+    ECHK(this, hipMalloc(&adm_insts, sizeof(int) * cap_slots));
+    for (auto& s : snap) ECHK(this, hipHostMalloc(&s, sizeof(Ctl) * cap_slots));
+    ECHK(this, hipHostMalloc(&adm_items_h, sizeof(BItem) * (size_t)cap_items));
+    ECHK(this, hipHostMalloc(&adm_insts_h, sizeof(int) * cap_slots));
+    ECHK(this, hipHostMalloc(&tab_h, sizeof(BInst) * cap_slots));
+    ECHK(this, hipHostMalloc(&ctl_init_h, sizeof(Ctl) * cap_slots));
+    for (auto& e : ev_snap) ECHK(this, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ECHK(this, hipEventCreateWithFlags(&ev_adm, hipEventDisableTiming));
+    slots.assign(cap_slots, Slot{});
+    free_slots.clear();
+    for (int q = cap_slots - 1; q >= 0; --q) free_slots.push_back(q);
+    ECHK(this, hipStreamSynchronize(stream));
+    return prepare_kernels();
+}
+
+// LDS of the batch sweeps: the largest column class (32 lanes x 4 chunks x 4)
+// staged as FP64 + FP32 g, or reused by the workgroup reduction.
+static size_t bsweep_lds(bool p64, int w) {
+    const size_t ncols = 512;
+    const size_t a = sizeof(double) * (ncols + ncols / 2);
+    const size_t red = (p64 ? 8 : 4) * (size_t)w * 4 * 256;  // LPR 16: R = 4 rows, 256 columns
+    const size_t red32 = (p64 ? 8 : 4) * (size_t)w * 2 * 512;  // LPR 32: R = 2 rows, 512 columns
+    const size_t chk = sizeof(double) * (size_t)(w / 2) * 2 * 64 * 4;
+    return std::max({a, red, red32, chk});
+}
+
+template <class K>
+static int occupancy(K kern, int threads, size_t lds) {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, lds) != hipSuccess) n = 0;
+    return n;
+}
+
+ot_status BatchEngine::prepare_kernels() {
+    lds32[0] = bsweep_lds(false, 4);
+    lds32[1] = bsweep_lds(false, 8);
+    lds64 = bsweep_lds(true, 8);
+    const int o4 = occupancy(k_bsweep<false, 4>, 256, lds32[0]);
+    const int o8 = occupancy(k_bsweep<false, 8>, 512, lds32[1]);
+    const int o64 = occupancy(k_bsweep<true, 8>, 512, lds64);
+    const int oc = occupancy(k_bcombine, 1024, 0);
+    if (o4 <= 0 || o8 <= 0 || o64 <= 0 || oc <= 0) return fail(OT_EDEVICE, "batch kernels do not fit on a CU");
+    grid32[0] = o4 * num_cu;
+    grid32[1] = o8 * num_cu;
+    grid64 = o64 * num_cu;
+    gridc = oc * num_cu;
+    return OT_OK;
+}
+
+ot_status BatchEngine::capture(int wi) {
+    if (graph[wi]) return OT_OK;
+    BParams P{polish_iters, 1e-7};
+    hipGraph_t g = nullptr;
+    ECHK(this, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    for (int t = 0; t < kChunk; ++t) {
+        const BList& in = L[t & 1];
+        const BList& out = L[(t + 1) & 1];
+        if (wi == 0) hipLaunchKernelGGL((k_bsweep<false, 4>), dim3(grid32[0]), dim3(256), lds32[0], stream, tab, in, out);
+        else hipLaunchKernelGGL((k_bsweep<false, 8>), dim3(grid32[1]), dim3(512), lds32[1], stream, tab, in, out);
+        hipLaunchKernelGGL((k_bsweep<true, 8>), dim3(grid64), dim3(512), lds64, stream, tab, in, out);
+        hipLaunchKernelGGL(k_bcombine, dim3(gridc), dim3(1024), 0, stream, tab, in, out, P);
+    }
+    hipError_t e1 = hipStreamEndCapture(stream, &g);
+    if (e1 != hipSuccess) return fail(OT_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
+    hipError_t e2 = hipGraphInstantiate(&graph[wi], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(OT_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e2));
+    return OT_OK;
+}
+
+// Bytes of one instance's block: cost (unless referenced), marginals,
+// potentials (two parities), parts partials, solve constants.
+static size_t slot_bytes(int64_t I, int J, int64_t ld, int parts_cap, bool own_cost) {
+    size_t b = 0;
+    if (own_cost) b += align_up(sizeof(float) * (size_t)I * ld);
+    b += align_up(sizeof(double) * I) + align_up(sizeof(double) * J);                      // a, b
+    b += 2 * align_up(sizeof(double) * I) + 2 * align_up(sizeof(double) * J);              // f, g
+    b += align_up(sizeof(double) * (size_t)parts_cap * J) + align_up(sizeof(double) * parts_cap);  // col, res
+    b += align_up(sizeof(double) * (size_t)parts_cap * 5) + align_up(sizeof(SolveParams));
+    return b;
+}
+
+static int64_t parts_of(int64_t I, int64_t rpp) { return (I + rpp - 1) / rpp; }
+
+ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage) {
+    const int64_t I = s.I;
+    const int J = s.J;
+    const int64_t ld = s.ld;
+    float* dst = (float*)C_mem;
+    const unsigned grid = (unsigned)std::min<int64_t>(4096, (I * ld + 255) / 256);
+    if (c->kind == OT_COST_GEOMETRY) {
+        if (!helper || helper->I_max < I) {
+            if (helper) ot_assoc_destroy(helper);
+            helper = nullptr;
+            ot_assoc_options o;
+            ot_assoc_default_options(&o);
+            o.device = device;
+            o.stream = stream;
+            ot_status st = ot_assoc_create(&helper, std::max<int64_t>(I, 1 << 15), kBatchMaxJ, &o);
+            if (st) return fail(st, "helper handle: %s", ot_assoc_last_error(nullptr));
+        }
+        ot_cost_desc d = *c;
+        if (!(d.scale > 0.0)) {
+            double med = 0.0;
+            ot_status st = ot_assoc_cost_median(helper, &d, &med);
+            if (st) return fail(st, "cost median: %s", ot_assoc_last_error(helper));
+            d.scale = med;
+        }
+        // unpadded FP32 matrix into the block, then spread rows to stride ld
+        ot_status st = ot_assoc_materialize_cost(helper, &d, dst);
+        if (st) return fail(st, "materialise: %s", ot_assoc_last_error(helper));
+        if (ld != J) {
+            ECHK(this, hipMemcpyAsync(stage, dst, sizeof(float) * (size_t)I * J, hipMemcpyDeviceToDevice, stream));
+            hipLaunchKernelGGL((k_bpad<float, 0>), dim3(grid), dim3(256), 0, stream, (const float*)stage, I, J,
+                               (int64_t)J, dst, ld, 1.0);
+        }
+        return OT_OK;
+    }
+    const size_t esz = c->dtype == OT_F32 ? 4 : 8;
+    const void* src = c->data;
+    if (c->mem == OT_MEM_HOST) {
+        ECHK(this, hipMemcpyAsync(stage, c->data, esz * (size_t)I * J, hipMemcpyHostToDevice, stream));
+        src = stage;
+    }
+    const double inv = c->kind == OT_COST_RATES ? 1.0 / c->scale : 1.0;
+    if (c->kind == OT_COST_DENSE) {
+        if (c->dtype == OT_F32)
+            hipLaunchKernelGGL((k_bpad<float, 0>), dim3(grid), dim3(256), 0, stream, (const float*)src, I, J, (int64_t)J, dst, ld, inv);
+        else
+            hipLaunchKernelGGL((k_bpad<double, 0>), dim3(grid), dim3(256), 0, stream, (const double*)src, I, J, (int64_t)J, dst, ld, inv);
+    } else {
+        if (c->dtype == OT_F32)
+            hipLaunchKernelGGL((k_bpad<float, 1>), dim3(grid), dim3(256), 0, stream, (const float*)src, I, J, (int64_t)J, dst, ld, inv);
+        else
+            hipLaunchKernelGGL((k_bpad<double, 1>), dim3(grid), dim3(256), 0, stream, (const double*)src, I, J, (int64_t)J, dst, ld, inv);
+    }
+    return OT_OK;
+}
+
+static ot_status read_host(BatchEngine* e, const double* p, int64_t n, ot_mem mem, std::vector<double>& out) {
+    out.resize((size_t)n);
+    if (mem == OT_MEM_HOST) {
+        std::memcpy(out.data(), p, sizeof(double) * n);
+        return OT_OK;
+    }
+    ECHK(e, hipMemcpyAsync(out.data(), p, sizeof(double) * n, hipMemcpyDeviceToHost, e->stream));
+    ECHK(e, hipStreamSynchronize(e->stream));
+    return OT_OK;
+}
+
+static double ksum(const std::vector<double>& v) {
+    double s = 0.0, c = 0.0;
+    for (double x : v) {
+        const double t = s + x;
+        c += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+static ot_status check_desc(BatchEngine* e, const ot_cost_desc* c) {
+    if (!c) return e->fail(OT_EINVAL, "cost descriptor is NULL");
+    if (c->I < 1 || c->J < 1 || c->J > kBatchMaxJ || c->I > ((int64_t)1 << 26))
+        return e->fail(OT_EINVAL, "batched instance %lld x %lld outside 1..2^26 x 1..%d", (long long)c->I,
+                       (long long)c->J, kBatchMaxJ);
+    if (c->mem != OT_MEM_HOST && c->mem != OT_MEM_DEVICE) return e->fail(OT_EINVAL, "bad memory space");
+    switch (c->kind) {
+        case OT_COST_DENSE:
+        case OT_COST_RATES:
+            if (!c->data) return e->fail(OT_EINVAL, "cost matrix is NULL");
+            if (c->dtype != OT_F32 && c->dtype != OT_F64) return e->fail(OT_EINVAL, "bad dtype");
+            if (c->kind == OT_COST_RATES && !(c->scale > 0.0 && std::isfinite(c->scale)))
+                return e->fail(OT_EINVAL, "rates need scale > 0");
+            break;
+        case OT_COST_GEOMETRY:
+            if (c->mem != OT_MEM_DEVICE) return e->fail(OT_EINVAL, "batched geometry must be in device memory");
+            if (!c->geom.dev_xy || !c->geom.rrh_xy) return e->fail(OT_EINVAL, "positions are NULL");
+            break;
+        default:
+            return e->fail(OT_EINVAL, "unknown cost kind");
+    }
+    return OT_OK;
+}
+
+// Admits the requests in order. strict: every request must fit now (else
+// OT_ENOMEM and nothing is admitted); otherwise admits the longest prefix
+// that fits and reports the admitted slots.
+ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>& out_slots, bool strict) {
+    out_slots.clear();
+    if (reqs.empty()) return OT_OK;
+    ECHK(this, hipSetDevice(device));
+    // validate everything first
+    std::vector<std::vector<double>> ah(reqs.size()), bh(reqs.size());
+    for (size_t q = 0; q < reqs.size(); ++q) {
+        const AdmitReq& r = reqs[q];
+        if (ot_status st = check_desc(this, r.cost)) return st;
+        if (!r.a || !r.b) return fail(OT_EINVAL, "marginals are NULL");
+        if (!(r.eps > 0.0) || !std::isfinite(r.eps)) return fail(OT_EINVAL, "eps must be positive and finite");
+        if (!(r.tol >= 0.0) || !std::isfinite(r.tol)) return fail(OT_EINVAL, "tol must be >= 0");
+        if (r.max_iter < 1) return fail(OT_EINVAL, "max_iter must be >= 1");
+        const ot_mem m = r.cost->kind == OT_COST_GEOMETRY ? OT_MEM_DEVICE : r.cost->mem;
+        if (ot_status st = read_host(this, r.a, r.cost->I, m, ah[q])) return st;
+        if (ot_status st = read_host(this, r.b, r.cost->J, m, bh[q])) return st;
+        for (double v : ah[q])
+            if (!(v > 0.0) || !std::isfinite(v)) return fail(OT_EINVAL, "instance %zu: a must be positive and finite", q);
+        for (double v : bh[q])
+            if (!(v > 0.0) || !std::isfinite(v)) return fail(OT_EINVAL, "instance %zu: b must be positive and finite", q);
+        const double sa = ksum(ah[q]), sb = ksum(bh[q]);
+        if (std::fabs(sa - sb) > 1e-12 * sa) return fail(OT_EINVAL, "instance %zu: unbalanced marginals", q);
+    }
+    // the staging buffers of the previous admission must have been consumed
+    if (adm_pending) {
+        ECHK(this, hipEventSynchronize(ev_adm));
+        adm_pending = false;
+    }
+    // pinned staging of the marginals and solve constants (async copies)
+    size_t hbytes = 0;
+    for (auto& r : reqs) hbytes += sizeof(double) * (r.cost->I + r.cost->J) + sizeof(SolveParams);
+    if (hbytes > hstage_cap) {
+        if (hstage) hipHostFree(hstage);
+        hstage = nullptr;
+        hstage_cap = 0;
+        ECHK(this, hipHostMalloc(&hstage, hbytes));
+        hstage_cap = hbytes;
+    }
+    char* hp = hstage;
+    int n_items = 0;
+    int n_insts = 0;
+    const int64_t rpp = rpp_rows;
+    for (size_t q = 0; q < reqs.size(); ++q) {
+        const AdmitReq& r = reqs[q];
+        const ot_cost_desc* c = r.cost;
+        const int64_t I = c->I;
+        const int J = (int)c->J;
+        const int parts_cap = (int)parts_of(I, 64);  // the finest layout the tuner may choose
+        const int parts = (int)parts_of(I, rpp);
+        const bool ref = c->kind == OT_COST_DENSE && c->mem == OT_MEM_DEVICE && c->dtype == OT_F32 && J % 4 == 0 &&
+                         ((uintptr_t)c->data % 16) == 0;
+        const int64_t ld = ref ? J : (J + 3) / 4 * 4;
+        if (free_slots.empty() || items_running + n_items + parts > cap_items) {
+            if (strict) return fail(OT_ENOMEM, "batch exceeds %d slots / %d work items", cap_slots, cap_items);
+            break;
+        }
+        // staging for host inputs and for padding a materialised geometry
+        // cost; released once the conversion is queued (stream order)
+        const size_t esz = c->dtype == OT_F64 ? 8 : 4;
+        size_t stage_b = 0;
+        if (!ref && c->kind != OT_COST_GEOMETRY && c->mem == OT_MEM_HOST) stage_b = esz * (size_t)I * J;
+        if (c->kind == OT_COST_GEOMETRY && ld != J) stage_b = sizeof(float) * (size_t)I * J;
+        char* stage = stage_b ? pool.alloc(stage_b) : nullptr;
+        char* mem = (stage_b && !stage) ? nullptr : pool.alloc(slot_bytes(I, J, ld, parts_cap, !ref));
+        if (!mem) {
+            if (stage) pool.release(stage);
+            if (strict) {
+                for (int k : out_slots) release(k);
+                out_slots.clear();
+                return fail(OT_ENOMEM, "batch exceeds the device memory budget (%.3g GB)", pool.budget / 1e9);
+            }
+            break;
+        }
+        const int k = free_slots.back();
+        free_slots.pop_back();
+        hi_slot = std::max(hi_slot, k + 1);
+        Slot& s = slots[k];
+        s = Slot{};
+        s.live = true;
+        s.I = I;
+        s.J = J;
+        s.ld = ld;
+        s.parts_cap = parts_cap;
+        s.mem = mem;
+        s.eps = r.eps;
+        s.mass = ksum(ah[q]);
+        char* p = mem;
+        auto carve = [&](size_t bytes) {
+            char* x = p;
+            p += align_up(bytes);
+            return x;
+        };
+        BInst& d = s.d;
+        char* C_mem = ref ? nullptr : carve(sizeof(float) * (size_t)I * ld);
+        d.C = ref ? (const float*)c->data : (const float*)C_mem;
+        d.ld = ld;
+        d.I = I;
+        d.J = J;
+        d.cls = batch_class(J);
+        d.nch = (J + batch_class_lpr(d.cls) * 4 - 1) / (batch_class_lpr(d.cls) * 4);
+        d.nchk = (J + 255) / 256;
+        d.parts = parts;
+        d.rpp = rpp;
+        double* a_d = (double*)carve(sizeof(double) * I);
+        double* b_d = (double*)carve(sizeof(double) * J);
+        d.a = a_d;
+        d.b = b_d;
+        d.f[0] = (double*)carve(sizeof(double) * I);
+        d.f[1] = (double*)carve(sizeof(double) * I);
+        d.g[0] = (double*)carve(sizeof(double) * J);
+        d.g[1] = (double*)carve(sizeof(double) * J);
+        d.col_part = (double*)carve(sizeof(double) * (size_t)parts_cap * J);
+        d.res_part = (double*)carve(sizeof(double) * parts_cap);
+        d.stat_part = (double*)carve(sizeof(double) * (size_t)parts_cap * 5);
+        s.prm = (SolveParams*)carve(sizeof(SolveParams));
+        d.ctl = ctl + k;
+        d.kk = std::log2(std::exp(1.0)) / r.eps;
+        d.eps = r.eps;
+        if (!ref) {
+            ot_status st = upload_cost(s, c, C_mem, stage);
+            if (stage) pool.release(stage);
+            if (st) {
+                release(k);
+                for (int kk : out_slots) release(kk);
+                out_slots.clear();
+                return st;
+            }
+        }
+        std::memcpy(hp, ah[q].data(), sizeof(double) * I);
+        ECHK(this, hipMemcpyAsync(a_d, hp, sizeof(double) * I, hipMemcpyHostToDevice, stream));
+        hp += sizeof(double) * I;
+        std::memcpy(hp, bh[q].data(), sizeof(double) * J);
+        ECHK(this, hipMemcpyAsync(b_d, hp, sizeof(double) * J, hipMemcpyHostToDevice, stream));
+        hp += sizeof(double) * J;
+        const bool warm = r.f0 && r.g0;
+        if (warm) {
+            ECHK(this, hipMemcpyAsync(d.f[0], r.f0, sizeof(double) * I, hipMemcpyDeviceToDevice, stream));
+            ECHK(this, hipMemcpyAsync(d.g[0], r.g0, sizeof(double) * J, hipMemcpyDeviceToDevice, stream));
+        } else {
+            ECHK(this, hipMemsetAsync(d.g[0], 0, sizeof(double) * J, stream));
+        }
+        const SolveParams sp{d.kk, d.eps};
+        Ctl ci{};
+        ci.has_prev = warm ? 1 : 0;
+        ci.max_iter = r.max_iter;
+        ci.tol = r.tol;
+        ci.mass = s.mass;
+        ci.r_last = __builtin_huge_val();
+        for (double& x : ci.r_hist) x = __builtin_huge_val();
+        ci.phase = kPhFast;
+        // stage the table entry, control block and solve constants
+        tab_h[k] = d;
+        ctl_init_h[k] = ci;
+        ECHK(this, hipMemcpyAsync(tab + k, tab_h + k, sizeof(BInst), hipMemcpyHostToDevice, stream));
+        ECHK(this, hipMemcpyAsync(ctl + k, ctl_init_h + k, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+        std::memcpy(&s.fin, &ci, sizeof ci);
+        std::memcpy(hp, &sp, sizeof sp);
+        ECHK(this, hipMemcpyAsync(s.prm, hp, sizeof sp, hipMemcpyHostToDevice, stream));
+        hp += sizeof sp;
+        for (int pq = 0; pq < parts; ++pq) adm_items_h[n_items + pq] = BItem{k, pq, warm ? kItPrev : 0, 0};
+        n_items += parts;
+        adm_insts_h[n_insts++] = k;
+        s.t_admit = now_s();
+        s.adm_seq = seq;
+        items_running += parts;
+        out_slots.push_back(k);
+    }
+    if (n_insts) {
+        ECHK(this, hipMemcpyAsync(adm_items, adm_items_h, sizeof(BItem) * n_items, hipMemcpyHostToDevice, stream));
+        ECHK(this, hipMemcpyAsync(adm_insts, adm_insts_h, sizeof(int) * n_insts, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(k_badmit, dim3(1), dim3(256), 0, stream, L[0], (const BItem*)adm_items, n_items,
+                           (const int*)adm_insts, n_insts);
+        ECHK(this, hipGetLastError());
+        ECHK(this, hipEventRecord(ev_adm, stream));
+        adm_pending = true;
+        n_live_running += n_insts;
+    }
+    return OT_OK;
+}
+
+void BatchEngine::release(int k) {
+    Slot& s = slots[k];
+    if (!s.live) return;
+    if (!s.finished) {
+        --n_live_running;
+        items_running -= s.d.parts;
+    }
+    pool.release(s.mem);
+    s = Slot{};
+    free_slots.push_back(k);
+    while (hi_slot > 0 && !slots[hi_slot - 1].live) --hi_slot;
+}
+
+ot_status BatchEngine::launch_chunk() {
+    if (ot_status st = capture(widx())) return st;
+    ECHK(this, hipGraphLaunch(graph[widx()], stream));
+    ++chunks;
+    return OT_OK;
+}
+
+// Takes a snapshot of the control blocks behind the work queued so far;
+// with `wait`, also waits for the previous snapshot and marks every
+// instance it shows done as finished (returned in `finished`).
+ot_status BatchEngine::collect(bool wait, std::vector<int>& finished) {
+    finished.clear();
+    const int cur = snap_pending < 0 ? 0 : (snap_pending ^ 1);
+    const int prev = snap_pending;
+    const int hi = hi_slot;
+    ECHK(this, hipMemcpyAsync(snap[cur], ctl, sizeof(Ctl) * std::max(hi, 1), hipMemcpyDeviceToHost, stream));
+    ECHK(this, hipEventRecord(ev_snap[cur], stream));
+    const int prev_hi = snap_hi;
+    snap_pending = cur;
+    snap_hi = hi;
+    snap_seq[cur] = ++seq;
+    if (!wait || prev < 0) return OT_OK;
+    ECHK(this, hipEventSynchronize(ev_snap[prev]));
+    apply_snapshot(prev, prev_hi, &finished);
+    return OT_OK;
+}
+
+void BatchEngine::apply_snapshot(int which, int hi, std::vector<int>* finished) {
+    for (int k = 0; k < hi; ++k) {
+        Slot& s = slots[k];
+        if (!s.live || s.finished || snap_seq[which] <= s.adm_seq) continue;
+        const Ctl& c = snap[which][k];
+        if (c.phase == kPhDone) {
+            s.fin = c;
+            s.finished = true;
+            --n_live_running;
+            items_running -= s.d.parts;
+            if (finished) finished->push_back(k);
+        }
+    }
+}
+
+// Waits for the newest snapshot and applies it.
+ot_status BatchEngine::drain_snapshot(std::vector<int>* finished) {
+    if (snap_pending < 0) return OT_OK;
+    ECHK(this, hipEventSynchronize(ev_snap[snap_pending]));
+    apply_snapshot(snap_pending, snap_hi, finished);
+    return OT_OK;
+}
+
+// Rebuilds the parts of the given (not yet started) instances for another
+// rows-per-part value and re-queues their first sweep items.
+ot_status BatchEngine::relayout(const std::vector<int>& ks, int w, int64_t rpp) {
+    if (adm_pending) {  // the staging below is still being read by the admission's copies
+        ECHK(this, hipEventSynchronize(ev_adm));
+        adm_pending = false;
+    }
+    waves = w;
+    rpp_rows = rpp;
+    int n_items = 0;
+    for (int k : ks) {
+        Slot& s = slots[k];
+        items_running -= s.d.parts;
+        s.d.rpp = rpp;
+        s.d.parts = (int)parts_of(s.I, rpp);
+        items_running += s.d.parts;
+        tab_h[k] = s.d;
+        ECHK(this, hipMemcpyAsync(tab + k, tab_h + k, sizeof(BInst), hipMemcpyHostToDevice, stream));
+        const int fl = ctl_init_h[k].has_prev ? kItPrev : 0;
+        for (int pq = 0; pq < s.d.parts; ++pq) adm_items_h[n_items + pq] = BItem{k, pq, fl, 0};
+        n_items += s.d.parts;
+    }
+    for (size_t q = 0; q < ks.size(); ++q) adm_insts_h[q] = ks[q];
+    ECHK(this, hipMemcpyAsync(adm_items, adm_items_h, sizeof(BItem) * n_items, hipMemcpyHostToDevice, stream));
+    ECHK(this, hipMemcpyAsync(adm_insts, adm_insts_h, sizeof(int) * ks.size(), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, stream, L[0]);
+    hipLaunchKernelGGL(k_badmit, dim3(1), dim3(256), 0, stream, L[0], (const BItem*)adm_items, n_items,
+                       (const int*)adm_insts, (int)ks.size());
+    ECHK(this, hipGetLastError());
+    ECHK(this, hipStreamSynchronize(stream));
+    return OT_OK;
+}
+
+// Autotuner: times the first FP32 sweep of the admitted batch under each
+// (workgroup waves, rows per part) candidate and keeps the fastest. The sweep
+// reads f and g of parity 0 and writes only the other parity and partials, so
+// the trial launches leave the starting state intact.
+ot_status BatchEngine::tune(const std::vector<int>& ks) {
+    std::string key;
+    for (int k : ks) {
+        const int64_t dims[2] = {slots[k].I, slots[k].J};
+        key.append((const char*)dims, sizeof dims);
+    }
+    auto it = tuned.find(key);
+    if (it != tuned.end()) return relayout(ks, it->second.first, it->second.second);
+    hipEvent_t e0, e1;
+    ECHK(this, hipEventCreate(&e0));
+    ECHK(this, hipEventCreate(&e1));
+    float best = 1e30f;
+    int bw = 8;
+    int64_t br = 128;
+    ot_status st = OT_OK;
+    for (int w : {4, 8}) {
+        for (int64_t rpp : {64, 128, 256}) {
+            if ((st = relayout(ks, w, rpp))) break;
+            const int wi = w == 4 ? 0 : 1;
+            auto launch = [&]() {
+                if (wi == 0) hipLaunchKernelGGL((k_bsweep<false, 4>), dim3(grid32[0]), dim3(256), lds32[0], stream, tab, L[0], L[1]);
+                else hipLaunchKernelGGL((k_bsweep<false, 8>), dim3(grid32[1]), dim3(512), lds32[1], stream, tab, L[0], L[1]);
+            };
+            launch();  // warm-up
+            hipEventRecord(e0, stream);
+            for (int rep = 0; rep < 3; ++rep) launch();
+            hipEventRecord(e1, stream);
+            if (hipEventSynchronize(e1) != hipSuccess) { st = fail(OT_EDEVICE, "tuning sweep failed"); break; }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) { best = ms; bw = w; br = rpp; }
+        }
+        if (st) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    tuned[key] = {bw, br};
+    return relayout(ks, bw, br);
+}
+
+static void fill_result(const Slot& s, ot_assoc_result* r) {
+    const Ctl& c = s.fin;
+    ot_status rs = OT_OK;
+    if (c.numeric_bad || !std::isfinite(c.chk_violation)) rs = OT_ENUMERIC;
+    else if (!(c.chk_violation < c.tol)) rs = OT_WARN_MAXITER;
+    r->iterations = c.result_iter;
+    r->fp64_iterations = c.fp64_iters;
+    r->status = rs;
+    r->reserved = 0;
+    r->marginal_violation = c.chk_violation;
+    r->objective = c.chk_objective;
+    r->reg_objective = c.chk_reg_objective;
+    r->dual_objective = c.chk_dual;
+    r->seconds = 0.0;
+}
+
+static ot_status slot_potentials(BatchEngine* e, const Slot& s, double* f, double* g, ot_mem mem) {
+    const int par = s.fin.result_iter & 1;
+    const hipMemcpyKind k = mem == OT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (f) ECHK(e, hipMemcpyAsync(f, s.d.f[par], sizeof(double) * s.I, k, e->stream));
+    if (g) ECHK(e, hipMemcpyAsync(g, s.d.g[par], sizeof(double) * s.J, k, e->stream));
+    ECHK(e, hipStreamSynchronize(e->stream));
+    return OT_OK;
+}
+
+static ot_status slot_plan(BatchEngine* e, const Slot& s, void* pi, ot_mem mem, ot_dtype dtype) {
+    const int par = s.fin.result_iter & 1;
+    const size_t bytes = (size_t)s.I * s.J * (dtype == OT_F32 ? 4 : 8);
+    void* dst = pi;
+    char* tmp = nullptr;
+    if (mem == OT_MEM_HOST) {
+        tmp = e->pool.alloc(bytes);
+        if (!tmp) return e->fail(OT_ENOMEM, "no device memory for the plan");
+        dst = tmp;
+    }
+    const int nch = (s.J + 255) / 256;
+    const size_t lds = sizeof(double) * (size_t)nch * 256;
+    const int grid = (int)std::min<int64_t>(4096, (s.I + 7) / 8);
+    const DenseSrc<float> src{s.d.C, s.d.ld};
+    if (dtype == OT_F32)
+        hipLaunchKernelGGL((k_plan<DenseSrc<float>, float, 4>), dim3(grid), dim3(512), lds, e->stream, s.I, s.J, nch,
+                           (const double*)s.d.f[par], (const double*)s.d.g[par], (const SolveParams*)s.prm, (float*)dst, src);
+    else
+        hipLaunchKernelGGL((k_plan<DenseSrc<float>, double, 4>), dim3(grid), dim3(512), lds, e->stream, s.I, s.J, nch,
+                           (const double*)s.d.f[par], (const double*)s.d.g[par], (const SolveParams*)s.prm, (double*)dst, src);
+    ot_status st = OT_OK;
+    hipError_t er = hipGetLastError();
+    if (er != hipSuccess) st = e->fail(OT_EDEVICE, "plan launch failed: %s", hipGetErrorString(er));
+    if (!st && tmp) {
+        er = hipMemcpyAsync(pi, tmp, bytes, hipMemcpyDeviceToHost, e->stream);
+        if (er != hipSuccess) st = e->fail(OT_EDEVICE, "plan copy failed: %s", hipGetErrorString(er));
+    }
+    er = hipStreamSynchronize(e->stream);
+    if (!st && er != hipSuccess) st = e->fail(OT_EDEVICE, "plan failed: %s", hipGetErrorString(er));
+    if (tmp) e->pool.release(tmp);
+    return st;
+}
+
+static size_t default_budget(int device) {
+    size_t fr = 0, tot = 0;
+    if (hipSetDevice(device) != hipSuccess || hipMemGetInfo(&fr, &tot) != hipSuccess) return (size_t)8 << 30;
+    return std::min<size_t>((size_t)256 << 30, fr / 10 * 9);
+}
+
+// Runs chunks until every listed slot is finished. Chunk c + 1 is queued
+// before the snapshot behind chunk c is read, so the device never idles on
+// the host; max_chunks bounds the loop (every instance ends within
+// max_iter + 2 iterations of its own, so this is only a guard).
+static ot_status run_to_completion(BatchEngine* e, const std::vector<int>& ks, long max_chunks) {
+    std::vector<int> fin;
+    auto open_count = [&]() {
+        int n = 0;
+        for (int k : ks) n += e->slots[k].finished ? 0 : 1;
+        return n;
+    };
+    for (long c = 0; c < max_chunks && open_count() > 0; ++c) {
+        if (ot_status st = e->launch_chunk()) return st;
+        if (ot_status st = e->collect(true, fin)) return st;
+    }
+    if (ot_status st = e->drain_snapshot(nullptr)) return st;
+    if (open_count() > 0) return e->fail(OT_EDEVICE, "batch did not finish within %ld chunks", max_chunks);
+    return OT_OK;
+}
+
+extern "C" {
+
+ot_status ot_assoc_solve_batch(ot_assoc* h, int n, const ot_cost_desc* costs, const double* const* a,
+                               const double* const* b, const double* eps, double tol, int32_t max_iter,
+                               ot_assoc_result* out) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (n < 1 || !costs || !a || !b || !eps) {
+        h->err = "n must be >= 1 and the arrays non-NULL";
+        return OT_EINVAL;
+    }
+    if (hipSetDevice(h->device) != hipSuccess) {
+        h->err = "hipSetDevice failed";
+        return OT_EDEVICE;
+    }
+    if (!h->batch) {
+        BatchEngine* e = new BatchEngine();
+        ot_status st = e->init(h->device, h->stream, 4096, 1 << 20, default_budget(h->device));
+        if (st) {
+            h->err = e->err;
+            delete e;
+            return st;
+        }
+        h->batch = e;
+    }
+    BatchEngine* e = h->batch;
+    e->err.clear();
+    e->polish_iters = std::max(0, h->opt.polish_iters);
+    // the previous batch's instances are released first
+    if (e->n_live_running > 0) {
+        h->err = "a batch is still running on this handle";
+        return OT_ESTATE;
+    }
+    for (int k = 0; k < e->cap_slots; ++k)
+        if (e->slots[k].live) e->release(k);
+    if (n > e->cap_slots) {
+        h->err = "batch larger than 4096 instances";
+        return OT_EINVAL;
+    }
+    std::vector<AdmitReq> reqs((size_t)n);
+    for (int q = 0; q < n; ++q) {
+        reqs[q].cost = costs + q;
+        reqs[q].a = a[q];
+        reqs[q].b = b[q];
+        reqs[q].eps = eps[q];
+        reqs[q].tol = tol;
+        reqs[q].max_iter = max_iter;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    std::vector<int> ks;
+    ot_status st = e->admit(reqs, ks, true);
+    if (!st && h->opt.batch_tune) st = e->tune(ks);
+    if (!st && !h->opt.batch_tune) st = e->relayout(ks, 8, 128);
+    if (!st) {
+        hipEventRecord(e0, e->stream);
+        st = run_to_completion(e, ks, (long)max_iter / kChunk + 16);
+        hipEventRecord(e1, e->stream);
+        hipEventSynchronize(e1);
+    }
+    float ms = 0.0f;
+    if (!st) hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) {
+        h->err = e->err;
+        for (int k : ks) e->release(k);
+        return st;
+    }
+    ot_status worst = OT_OK;
+    for (int q = 0; q < n; ++q) {
+        ot_assoc_result r{};
+        fill_result(e->slots[ks[q]], &r);
+        r.seconds = ms * 1e-3;
+        if (out) out[q] = r;
+        if (r.status < 0 && worst >= 0) worst = (ot_status)r.status;
+        else if (r.status > 0 && worst == OT_OK) worst = (ot_status)r.status;
+    }
+    e->tab_order = ks;
+    if (worst < 0) h->err = "an instance of the batch failed numerically";
+    return worst;
+}
+
+ot_status ot_assoc_batch_potentials(ot_assoc* h, int k, double* f, double* g, ot_mem mem) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    BatchEngine* e = h->batch;
+    if (!e || k < 0 || k >= (int)e->tab_order.size()) {
+        h->err = "no batched instance with that index";
+        return e ? OT_EINVAL : OT_ESTATE;
+    }
+    if (mem != OT_MEM_HOST && mem != OT_MEM_DEVICE) {
+        h->err = "bad memory space";
+        return OT_EINVAL;
+    }
+    const Slot& s = e->slots[e->tab_order[k]];
+    if (!s.live || !s.finished) {
+        h->err = "batched instance not available";
+        return OT_ESTATE;
+    }
+    ot_status st = slot_potentials(e, s, f, g, mem);
+    if (st) h->err = e->err;
+    return st;
+}
+
+ot_status ot_assoc_batch_plan(ot_assoc* h, int k, void* pi, ot_mem mem, ot_dtype dtype) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    BatchEngine* e = h->batch;
+    if (!e || k < 0 || k >= (int)e->tab_order.size()) {
+        h->err = "no batched instance with that index";
+        return e ? OT_EINVAL : OT_ESTATE;
+    }
+    if (!pi || (mem != OT_MEM_HOST && mem != OT_MEM_DEVICE) || (dtype != OT_F32 && dtype != OT_F64)) {
+        h->err = "bad plan buffer, memory space or dtype";
+        return OT_EINVAL;
+    }
+    const Slot& s = e->slots[e->tab_order[k]];
+    if (!s.live || !s.finished) {
+        h->err = "batched instance not available";
+        return OT_ESTATE;
+    }
+    ot_status st = slot_plan(e, s, pi, mem, dtype);
+    if (st) h->err = e->err;
+    return st;
+}
+
+}  // extern "C"
+
+// ================================================================ serving ==
+struct Resident {
+    char* mem = nullptr;
+    double* f = nullptr;
+    double* g = nullptr;
+    int64_t I = 0;
+    int J = 0;
+    long last_use = 0;
+};
+
+struct Pending {
+    uint64_t ticket;
+    ot_request req;
+    double t_submit;
+};
+
+struct ot_serve {
+    BatchEngine eng;
+    std::string err;
+    uint64_t next_ticket = 1;
+    long tick = 0;
+    std::deque<Pending> queue;
+    std::unordered_map<uint64_t, Resident> resident;
+    std::deque<ot_completion> done;
+    int keep_layouts = 4096;
+    std::vector<int> running;  // slots in flight
+    std::unordered_map<int, int> warm_of;  // slot -> 1 if warm started
+    std::unordered_map<int, uint64_t> pinned_key;
+};
+
+static ot_status serve_fail(ot_serve* s, ot_status st, const std::string& m) {
+    s->err = m;
+    return st;
+}
+
+// Copies a finished slot's potentials into the resident set of its layout.
+static ot_status keep_resident(ot_serve* s, const Slot& sl) {
+    BatchEngine& e = s->eng;
+    Resident& r = s->resident[sl.layout_key];
+    // (an admission copies from a resident set on the same stream before any
+    // later update or reuse of its memory, so no set is ever pinned)
+    if (r.mem && (r.I != sl.I || r.J != sl.J)) {
+        e.pool.release(r.mem);
+        r = Resident{};
+    }
+    if (!r.mem) {
+        r.mem = e.pool.alloc(align_up(sizeof(double) * sl.I) + align_up(sizeof(double) * sl.J));
+        if (!r.mem) {
+            s->resident.erase(sl.layout_key);
+            return OT_OK;  // no room: the layout will start cold next time
+        }
+        r.f = (double*)r.mem;
+        r.g = (double*)(r.mem + align_up(sizeof(double) * sl.I));
+        r.I = sl.I;
+        r.J = sl.J;
+    }
+    const int par = sl.fin.result_iter & 1;
+    ECHK(&e, hipMemcpyAsync(r.f, sl.d.f[par], sizeof(double) * sl.I, hipMemcpyDeviceToDevice, e.stream));
+    ECHK(&e, hipMemcpyAsync(r.g, sl.d.g[par], sizeof(double) * sl.J, hipMemcpyDeviceToDevice, e.stream));
+    r.last_use = ++s->tick;
+    return OT_OK;
+}
+
+// Frees the least recently used resident set that no admission still reads.
+static bool evict_one(ot_serve* s, uint64_t keep_key) {
+    auto victim = s->resident.end();
+    for (auto it = s->resident.begin(); it != s->resident.end(); ++it) {
+        if (it->first == keep_key) continue;
+        if (victim == s->resident.end() || it->second.last_use < victim->second.last_use) victim = it;
+    }
+    if (victim == s->resident.end()) return false;
+    s->eng.pool.release(victim->second.mem);
+    s->resident.erase(victim);
+    return true;
+}
+
+extern "C" {
+
+double ot_serve_now(void) { return now_s(); }
+
+ot_status ot_serve_default_options(ot_serve_options* o) {
+    if (!o) return OT_EINVAL;
+    std::memset(o, 0, sizeof *o);
+    o->polish_iters = 1;
+    o->sweep_waves = 8;
+    o->rows_per_part = 128;
+    return OT_OK;
+}
+
+ot_status ot_serve_create(ot_serve** out, const ot_serve_options* opt) {
+    if (!out) return OT_EINVAL;
+    *out = nullptr;
+    ot_serve_options o;
+    ot_serve_default_options(&o);
+    if (opt) o = *opt;
+    if (o.max_slots < 0 || o.max_items < 0 || o.polish_iters < 0 || o.budget_bytes < 0) return OT_EINVAL;
+    if (o.sweep_waves != 0 && o.sweep_waves != 4 && o.sweep_waves != 8) return OT_EINVAL;
+    if (o.rows_per_part != 0 && o.rows_per_part != 64 && o.rows_per_part != 128 && o.rows_per_part != 256)
+        return OT_EINVAL;
+    ot_serve* s = new ot_serve();
+    const size_t budget = o.budget_bytes > 0 ? (size_t)o.budget_bytes : default_budget(o.device);
+    ot_status st = s->eng.init(o.device, (hipStream_t)o.stream, o.max_slots ? o.max_slots : 1024,
+                               o.max_items ? o.max_items : (1 << 19), budget);
+    if (st) {
+        delete s;
+        return st;
+    }
+    s->eng.polish_iters = o.polish_iters;
+    s->eng.waves = o.sweep_waves ? o.sweep_waves : 8;
+    s->eng.rpp_rows = o.rows_per_part ? o.rows_per_part : 128;
+    s->keep_layouts = o.keep_layouts > 0 ? o.keep_layouts : 4096;
+    *out = s;
+    return OT_OK;
+}
+
+const char* ot_serve_last_error(const ot_serve* s) { return s ? s->err.c_str() : ""; }
+
+ot_status ot_serve_submit(ot_serve* s, const ot_request* r, uint64_t* ticket) {
+    if (!s) return OT_EINVAL;
+    s->err.clear();
+    if (!r || !r->a || !r->b) return serve_fail(s, OT_EINVAL, "request or marginals are NULL");
+    if (ot_status st = check_desc(&s->eng, &r->cost)) return serve_fail(s, st, s->eng.err);
+    if (!(r->eps > 0.0) || !std::isfinite(r->eps) || !(r->tol >= 0.0) || r->max_iter < 1)
+        return serve_fail(s, OT_EINVAL, "bad eps, tol or max_iter");
+    Pending p{s->next_ticket++, *r, now_s()};
+    s->queue.push_back(p);
+    if (ticket) *ticket = p.ticket;
+    return OT_OK;
+}
+
+// Admits from the head of the queue while slots, work-list room and the
+// byte budget allow (evicting idle resident potentials if that makes room),
+// runs one chunk when anything is in flight, and hands back completions.
+ot_status ot_serve_progress(ot_serve* s, ot_completion* out, int max_out, int* n_out) {
+    if (!s) return OT_EINVAL;
+    s->err.clear();
+    if (n_out) *n_out = 0;
+    BatchEngine& e = s->eng;
+    if (hipSetDevice(e.device) != hipSuccess) return serve_fail(s, OT_EDEVICE, "hipSetDevice failed");
+    // 1. admission
+    while (!s->queue.empty()) {
+        Pending& p = s->queue.front();
+        AdmitReq ar;
+        ar.cost = &p.req.cost;
+        ar.a = p.req.a;
+        ar.b = p.req.b;
+        ar.eps = p.req.eps;
+        ar.tol = p.req.tol;
+        ar.max_iter = p.req.max_iter;
+        Resident* res = nullptr;
+        if (p.req.layout_key) {
+            auto it = s->resident.find(p.req.layout_key);
+            if (it != s->resident.end() && it->second.I == p.req.cost.I && it->second.J == p.req.cost.J) {
+                res = &it->second;
+                ar.f0 = res->f;
+                ar.g0 = res->g;
+            }
+        }
+        std::vector<int> ks;
+        ot_status st = e.admit({ar}, ks, false);
+        if (st) {
+            // a request the engine rejects is completed with its error
+            ot_completion c{};
+            c.ticket = p.ticket;
+            c.user_tag = p.req.user_tag;
+            c.layout_key = p.req.layout_key;
+            c.t_submit = p.t_submit;
+            c.t_admit = c.t_done = now_s();
+            c.result.status = st;
+            s->done.push_back(c);
+            s->queue.pop_front();
+            continue;
+        }
+        if (ks.empty()) {
+            if (evict_one(s, p.req.layout_key)) continue;  // retry with more room
+            if (e.n_live_running > 0) break;                // wait for running requests to finish
+            ot_completion c{};  // it cannot fit even on an idle engine
+            c.ticket = p.ticket;
+            c.user_tag = p.req.user_tag;
+            c.layout_key = p.req.layout_key;
+            c.t_submit = p.t_submit;
+            c.t_admit = c.t_done = now_s();
+            c.result.status = OT_ENOMEM;
+            s->done.push_back(c);
+            s->queue.pop_front();
+            continue;
+        }
+        Slot& sl = e.slots[ks[0]];
+        sl.ticket = p.ticket;
+        sl.user_tag = p.req.user_tag;
+        sl.layout_key = p.req.layout_key;
+        sl.t_submit = p.t_submit;
+        s->warm_of[ks[0]] = res ? 1 : 0;
+        if (res) res->last_use = ++s->tick;
+        s->running.push_back(ks[0]);
+        s->queue.pop_front();
+    }
+    // 2. one chunk, and the snapshot behind the previous one
+    std::vector<int> fin;
+    if (e.n_live_running > 0) {
+        if (ot_status st = e.launch_chunk()) return serve_fail(s, st, e.err);
+        if (ot_status st = e.collect(true, fin)) return serve_fail(s, st, e.err);
+    } else if (e.snap_pending >= 0) {
+        if (ot_status st = e.drain_snapshot(&fin)) return serve_fail(s, st, e.err);
+        e.snap_pending = -1;
+    }
+    // 3. completions: keep the layout's potentials, free the slot
+    const double t = now_s();
+    for (int k : fin) {
+        Slot& sl = e.slots[k];
+        ot_completion c{};
+        c.ticket = sl.ticket;
+        c.user_tag = sl.user_tag;
+        c.layout_key = sl.layout_key;
+        c.warm = s->warm_of[k];
+        c.t_submit = sl.t_submit;
+        c.t_admit = sl.t_admit;
+        c.t_done = t;
+        fill_result(sl, &c.result);
+        if (sl.layout_key && c.result.status >= 0) {
+            if ((int)s->resident.size() >= s->keep_layouts && !s->resident.count(sl.layout_key)) evict_one(s, 0);
+            if (ot_status st = keep_resident(s, sl)) return serve_fail(s, st, e.err);
+        }
+        s->warm_of.erase(k);
+        s->running.erase(std::remove(s->running.begin(), s->running.end(), k), s->running.end());
+        e.release(k);
+        s->done.push_back(c);
+    }
+    int n = 0;
+    while (n < max_out && !s->done.empty()) {
+        out[n++] = s->done.front();
+        s->done.pop_front();
+    }
+    if (n_out) *n_out = n;
+    return OT_OK;
+}
+
+ot_status ot_serve_counts(const ot_serve* s, int* queued, int* running, int* resident, double* bytes_in_use) {
+    if (!s) return OT_EINVAL;
+    if (queued) *queued = (int)s->queue.size();
+    if (running) *running = (int)s->running.size();
+    if (resident) *resident = (int)s->resident.size();
+    if (bytes_in_use) *bytes_in_use = (double)s->eng.pool.in_use;
+    return OT_OK;
+}
+
+ot_status ot_serve_potentials(ot_serve* s, uint64_t layout_key, double* f, double* g, ot_mem mem) {
+    if (!s) return OT_EINVAL;
+    s->err.clear();
+    auto it = s->resident.find(layout_key);
+    if (it == s->resident.end()) return serve_fail(s, OT_ESTATE, "no resident potentials for that layout");
+    if (mem != OT_MEM_HOST && mem != OT_MEM_DEVICE) return serve_fail(s, OT_EINVAL, "bad memory space");
+    BatchEngine& e = s->eng;
+    const hipMemcpyKind k = mem == OT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (f && hipMemcpyAsync(f, it->second.f, sizeof(double) * it->second.I, k, e.stream) != hipSuccess)
+        return serve_fail(s, OT_EDEVICE, "copy failed");
+    if (g && hipMemcpyAsync(g, it->second.g, sizeof(double) * it->second.J, k, e.stream) != hipSuccess)
+        return serve_fail(s, OT_EDEVICE, "copy failed");
+    if (hipStreamSynchronize(e.stream) != hipSuccess) return serve_fail(s, OT_EDEVICE, "copy failed");
+    return OT_OK;
+}
+
+void ot_serve_destroy(ot_serve* s) { delete s; }
+
+}  // extern "C"

@@ -105,6 +105,12 @@ __device__ __forceinline__ double group_max(double v) {
 // 2^x for x <= 0 in FP32 (one v_exp_f32).
 __device__ __forceinline__ float exp2_f32(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// Per-solve constants read by the kernels.
+struct SolveParams {
+    double kk;   // log2(e) / eps
+    double eps;
+};
+
 // ------------------------------------------------------------- control block
 // Per-solve state that lives in device memory so that a captured chunk of
 // iterations can decide on the device when to stop, without a host round
@@ -135,6 +141,11 @@ struct Ctl {
     // results of the exact check of the current iterate
     double chk_violation, chk_objective, chk_reg_objective, chk_dual, chk_mass;
     double chk_row_res, chk_col_res;
+    // per-instance phase of the batched engine (unused by single solves)
+    int32_t phase;         // kPhFast .. kPhDone
+    int32_t polish_left;   // FP64 polish sweeps still to run
+    int32_t check_iter;    // iterate the pending check examines
+    int32_t exact_done;    // 1: the next check ends the solve whatever it finds
 };
 
 }  // namespace otk

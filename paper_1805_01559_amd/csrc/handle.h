@@ -1,0 +1,60 @@
+// The solver handle shared by the single-instance and the batched entry
+// points of the library (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ot_assoc.h"
+#include "device_common.h"
+
+namespace otk_host {
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+};
+}  // namespace otk_host
+
+struct BatchEngine;
+void batch_engine_destroy(BatchEngine* e);
+
+struct ot_assoc {
+    int device = 0;
+    int num_cu = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    ot_assoc_options opt{};
+    int64_t I_max = 0, J_max = 0;
+    // device workspace
+    double *a = nullptr, *b = nullptr;
+    double *f[2] = {nullptr, nullptr}, *g[2] = {nullptr, nullptr};
+    double *col_part = nullptr, *res_part = nullptr, *stat_part = nullptr;
+    double* cpart = nullptr;  // per-column-group partials of the check
+    otk::Ctl* ctl = nullptr;
+    otk::SolveParams* prm = nullptr;
+    int* bad = nullptr;
+    unsigned long long* hist = nullptr;
+    float* xy_dev = nullptr;  // I_max x 2
+    float* xy_rrh = nullptr;  // J_max x 2
+    double *s_all = nullptr, *s_ex = nullptr;
+    int* j1 = nullptr;
+    void* stage = nullptr;  // host-memory dense / rate matrices are copied here
+    size_t stage_bytes = 0;
+    // pinned host mirrors
+    otk::Ctl* ctl_h = nullptr;  // 2 slots
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_slot[2] = {nullptr, nullptr};
+    std::vector<otk_host::GraphEntry> graphs;
+    // state of the last solve
+    bool solved = false;
+    bool have_pot = false;
+    int64_t I = 0, J = 0;
+    int res_par = 0;  // parity of the buffers holding the returned iterate
+    double eps = 0.0;
+    ot_cost_desc last{};       // descriptor of the retained cost (pointers below replace the caller's)
+    const void* cost_dev = nullptr;  // device copy (host inputs) or the caller's device matrix
+    bool retained = false;     // the handle still holds the cost of the last solve
+    std::string err;
+    BatchEngine* batch = nullptr;  // engine of ot_assoc_solve_batch, created on first use
+};

@@ -39,11 +39,6 @@
 
 namespace otk {
 
-struct SolveParams {
-    double kk;   // log2(e) / eps
-    double eps;
-};
-
 // ------------------------------------------------- block-level reductions --
 // Sums acc[NCH][VEC] over the WAVES waves of a workgroup through LDS in a
 // fixed tree order; wave 0 ends with the block total.
@@ -146,16 +141,34 @@ __device__ __forceinline__ void bookkeep(Ctl* c, double rsum, int mode, double s
 // share one instruction stream four or two at a time, which amortises the
 // per-row reductions and scalars over more cells. Each wave keeps RB steps of
 // rows in flight and refills a slot as soon as its row is consumed.
+// One workgroup's share of a sweep: rows [r0, r1) of one instance, with the
+// column partials and the residual partial of those rows as outputs.
+struct SweepJob {
+    int64_t r0, r1;
+    int J;
+    int nch;
+    int has_prev;
+    double kk, eps;
+    const double* a;
+    const double* f_in;
+    double* f_out;
+    const double* g_in;
+    double* col_out;  // J partial column sums of the half-iterate
+    double* res_out;  // one partial row residual of the previous iterate
+};
+
+// The sweep of rows [r0, r1) by one workgroup. With stop_ctl set, the first
+// loads are issued before the control block is read and the workgroup does
+// nothing more if the chunk has been stopped. LDS is reused from the previous
+// call of a persistent workgroup only after a barrier.
 template <class Src, bool P64, int VEC, int NCH, int LPR, int WAVES, int RB>
-__global__ __launch_bounds__(WAVES * kWave) void k_iter(IterArgs A, Src src) {
-    const Ctl* ctl = A.ctl;
+__device__ __forceinline__ void sweep_rows(const SweepJob& A, const Src& src, double* sm, const Ctl* stop_ctl) {
     constexpr int R = kWave / LPR;
     const int J = A.J, nch = A.nch;
     const int ncols = nch * LPR * VEC;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int sub = lane % LPR, rg = lane / LPR;
-    const int64_t r0 = (int64_t)blockIdx.x * A.rows_per_block;
-    const int64_t r1 = min(A.I, r0 + A.rows_per_block);
+    const int64_t r0 = A.r0, r1 = A.r1;
     // first row of step `st` for this wave; this lane's row is that + rg
     auto step_base = [&](int64_t st) { return r0 + (st * WAVES + w) * R; };
 
@@ -177,13 +190,13 @@ __global__ __launch_bounds__(WAVES * kWave) void k_iter(IterArgs A, Src src) {
 #pragma unroll
     for (int q = 0; q < RB; ++q) issue(q, step_base(q) + rg);
     // a stopped chunk does nothing (the loads above are simply dropped)
-    if (ctl->stop | ctl->done) return;
+    if (stop_ctl && (stop_ctl->stop | stop_ctl->done)) return;
 
     // 2. per-column state in LDS: staged source data, g kk in FP64 and FP32
-    const double kk = A.prm->kk, eps = A.prm->eps;
+    const double kk = A.kk, eps = A.eps;
     const float kk32 = (float)kk;
-    const int has_prev = ctl->has_prev;
-    extern __shared__ double sm[];
+    const int has_prev = A.has_prev;
+    __syncthreads();  // LDS may still be read by this workgroup's previous job
     src.stage(sm, J);
     double* gs64 = sm + Src::kStageDoubles * ncols;
     float* gs32 = reinterpret_cast<float*>(gs64 + ncols);
@@ -309,18 +322,39 @@ __global__ __launch_bounds__(WAVES * kWave) void k_iter(IterArgs A, Src src) {
     __shared__ double wres[WAVES];
     if (lane == 0) wres[w] = res;
     __syncthreads();
-    double* out = A.col_part + (int64_t)blockIdx.x * J;
     for (int c = threadIdx.x; c < J; c += blockDim.x) {
         double t = 0.0;
 #pragma unroll 8
         for (int k = 0; k < WAVES * R; ++k) t += (double)red[k * ncols + c];
-        out[c] = t;
+        A.col_out[c] = t;
     }
     if (threadIdx.x == 0) {
         double r = 0.0;
         for (int q = 0; q < WAVES; ++q) r += wres[q];
-        A.res_part[blockIdx.x] = r;
+        *A.res_out = r;
     }
+}
+
+// One Sinkhorn sweep of a single instance: workgroup b owns rows
+// [b rows_per_block, (b + 1) rows_per_block).
+template <class Src, bool P64, int VEC, int NCH, int LPR, int WAVES, int RB>
+__global__ __launch_bounds__(WAVES * kWave) void k_iter(IterArgs A, Src src) {
+    extern __shared__ double sm[];
+    SweepJob job;
+    job.r0 = (int64_t)blockIdx.x * A.rows_per_block;
+    job.r1 = min(A.I, job.r0 + A.rows_per_block);
+    job.J = A.J;
+    job.nch = A.nch;
+    job.has_prev = A.ctl->has_prev;
+    job.kk = A.prm->kk;
+    job.eps = A.prm->eps;
+    job.a = A.a;
+    job.f_in = A.f_in;
+    job.f_out = A.f_out;
+    job.g_in = A.g_in;
+    job.col_out = A.col_part + (int64_t)blockIdx.x * A.J;
+    job.res_out = A.res_part + blockIdx.x;
+    sweep_rows<Src, P64, VEC, NCH, LPR, WAVES, RB>(job, src, sm, A.ctl);
 }
 
 // -------------------------------------------------------- column combine --
@@ -342,7 +376,7 @@ struct ColArgs {
 // partial rows r, r + 64, ... of column c; the 64 row-lanes are then summed
 // in a fixed order. Workgroup 0 also closes the iteration's bookkeeping.
 constexpr int kColsPerWg = 16;
-__global__ __launch_bounds__(1024) void k_colsum(ColArgs A) {
+static __global__ __launch_bounds__(1024) void k_colsum(ColArgs A) {
     Ctl* ctl = A.ctl;
     if (ctl->stop | ctl->done) return;
     const int c = threadIdx.x % kColsPerWg, r = threadIdx.x / kColsPerWg;
@@ -406,12 +440,26 @@ struct CheckArgs {
     const SolveParams* prm;
 };
 
+// The exact statistics of rows [r0, r1) by one workgroup (one wavefront per
+// row): column partials of pi and the five row statistics.
+struct CheckJob {
+    int64_t r0, r1;
+    int J;
+    int nch;
+    double kk;
+    const double* a;
+    const double* f;
+    const double* g;
+    double* col_out;   // J
+    double* stat_out;  // 5
+};
+
 template <class Src, int VEC, int NCH, int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
-    const double kk = A.prm->kk;
+__device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src, double* sm) {
+    const double kk = A.kk;
     const int J = A.J, nch = A.nch;
     const int ncols = nch * kWave * VEC;
-    extern __shared__ double sm[];
+    __syncthreads();  // LDS may still be read by this workgroup's previous job
     src.stage(sm, J);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     double gsr[NCH][VEC];
@@ -429,9 +477,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[ch][v] = 0.0;
     double st[5] = {0, 0, 0, 0, 0};  // rowres, cost, ent, mass, fa (lane 0 of each wave)
-    const int64_t r0 = (int64_t)blockIdx.x * A.rows_per_block;
-    const int64_t r1 = min(A.I, r0 + A.rows_per_block);
-    for (int64_t i = r0 + w; i < r1; i += WAVES) {
+    for (int64_t i = A.r0 + w; i < A.r1; i += WAVES) {
         auto row = src.row(i);
         const double fk = A.f[i] * kk;
         double rs = 0.0, cost = 0.0, ent = 0.0;
@@ -472,7 +518,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
         for (int q = 0; q < 5; ++q) wst[w][q] = st[q];
     block_tree<NCH, VEC, WAVES>(acc, nch, sm, ncols, w, lane);
     if (w == 0) {
-        double* out = A.col_part + (int64_t)blockIdx.x * J;
+        double* out = A.col_out;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
             if (ch < nch)
@@ -484,9 +530,26 @@ __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
         if (lane < 5) {
             double r = 0.0;
             for (int q = 0; q < WAVES; ++q) r += wst[q][lane];
-            A.stat_part[(int64_t)blockIdx.x * 5 + lane] = r;
+            A.stat_out[lane] = r;
         }
     }
+}
+
+template <class Src, int VEC, int NCH, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
+    extern __shared__ double sm[];
+    CheckJob job;
+    job.r0 = (int64_t)blockIdx.x * A.rows_per_block;
+    job.r1 = min(A.I, job.r0 + A.rows_per_block);
+    job.J = A.J;
+    job.nch = A.nch;
+    job.kk = A.prm->kk;
+    job.a = A.a;
+    job.f = A.f;
+    job.g = A.g;
+    job.col_out = A.col_part + (int64_t)blockIdx.x * A.J;
+    job.stat_out = A.stat_part + (int64_t)blockIdx.x * 5;
+    check_rows<Src, VEC, NCH, WAVES>(job, src, sm);
 }
 
 // Column sums of the check: per column |colsum_j - b_j| and g_j b_j, summed
@@ -500,7 +563,7 @@ struct CheckColArgs {
     double* cpart;  // gridDim.x x 2
 };
 
-__global__ __launch_bounds__(1024) void k_check_cols(CheckColArgs A) {
+static __global__ __launch_bounds__(1024) void k_check_cols(CheckColArgs A) {
     const int c = threadIdx.x % kColsPerWg, r = threadIdx.x / kColsPerWg;
     const int j = blockIdx.x * kColsPerWg + c;
     double s = 0.0;
@@ -525,7 +588,7 @@ __global__ __launch_bounds__(1024) void k_check_cols(CheckColArgs A) {
 }
 
 // One workgroup: the check's scalars, in a fixed order, into the control block.
-__global__ __launch_bounds__(256) void k_check_finish(const double* stat_part, int nb, const double* cpart, int ncb,
+static __global__ __launch_bounds__(256) void k_check_finish(const double* stat_part, int nb, const double* cpart, int ncb,
                                                       Ctl* ctl, const SolveParams* prm) {
     __shared__ double red[4][7];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -593,7 +656,7 @@ __global__ void k_validate(const T* x, int64_t n, int* bad) {
     if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
 }
 
-__global__ void k_validate_xy(const float* xy, int64_t n, int* bad) {
+static __global__ void k_validate_xy(const float* xy, int64_t n, int* bad) {
     int flag = 0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
         if (!isfinite(xy[q])) flag = 1;
@@ -602,7 +665,7 @@ __global__ void k_validate_xy(const float* xy, int64_t n, int* bad) {
 
 // Clears the stop flag between phases (kept as a kernel so that it may sit in
 // a captured graph).
-__global__ void k_ctl_resume(Ctl* ctl) {
+static __global__ void k_ctl_resume(Ctl* ctl) {
     if (threadIdx.x == 0) ctl->stop = 0;
 }
 

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/ot_assoc.h"
+#include "handle.h"
 #include "kernels.h"
 
 using namespace otk;
@@ -32,49 +33,10 @@ constexpr int kMaxNb = 1024;    // workgroups per sweep (partial rows)
 constexpr int kMaxJ = 2048;     // RRHs per instance
 constexpr int kGraphCache = 24;
 
-struct GraphEntry {
-    std::string key;
-    hipGraphExec_t exec = nullptr;
-};
+using otk_host::GraphEntry;
 
 }  // namespace
 
-struct ot_assoc {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    ot_assoc_options opt{};
-    int64_t I_max = 0, J_max = 0;
-    // device workspace
-    double *a = nullptr, *b = nullptr;
-    double *f[2] = {nullptr, nullptr}, *g[2] = {nullptr, nullptr};
-    double *col_part = nullptr, *res_part = nullptr, *stat_part = nullptr;
-    double* cpart = nullptr;  // per-column-group partials of the check
-    Ctl* ctl = nullptr;
-    SolveParams* prm = nullptr;
-    int* bad = nullptr;
-    unsigned long long* hist = nullptr;
-    float* xy_dev = nullptr;  // I_max x 2
-    float* xy_rrh = nullptr;  // J_max x 2
-    double *s_all = nullptr, *s_ex = nullptr;
-    int* j1 = nullptr;
-    void* stage = nullptr;  // host-memory dense / rate matrices are copied here
-    size_t stage_bytes = 0;
-    // pinned host mirrors
-    Ctl* ctl_h = nullptr;  // 2 slots
-    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_slot[2] = {nullptr, nullptr};
-    std::vector<GraphEntry> graphs;
-    // state of the last solve
-    bool solved = false;
-    bool have_pot = false;
-    int64_t I = 0, J = 0;
-    int res_par = 0;  // parity of the buffers holding the returned iterate
-    double eps = 0.0;
-    ot_cost_desc last{};       // descriptor of the retained cost (pointers below replace the caller's)
-    const void* cost_dev = nullptr;  // device copy (host inputs) or the caller's device matrix
-    bool retained = false;     // the handle still holds the cost of the last solve
-    std::string err;
-};
 
 namespace {
 
@@ -121,16 +83,20 @@ constexpr int max_rb(bool p64) {
 }
 constexpr int max_nch(int vec, int lpr) { return lpr < 64 ? 8 : 2048 / (64 * vec); }
 
-// Iteration shape: a row per group of LPR lanes (the narrowest of 16, 32, 64
-// that keeps at most 8 column chunks of LPR * VEC), contiguous row ranges per
-// workgroup, RB steps of rows in flight per wave.
+// Iteration shape: a row per group of LPR lanes (the narrowest of 16 and 32
+// that keeps at most 4 column chunks of LPR * VEC, else at most 8, else 64
+// lanes), contiguous row ranges per workgroup, RB steps of rows in flight per
+// wave. The grid is sized afterwards by fit_grid.
 template <class Src>
 Shape make_shape(const ot_assoc* h, int64_t I, int64_t J, int vec, bool p64 = false) {
     Shape s;
     s.vec = vec;
     s.lpr = 64;
-    for (int cand : {16, 32})
-        if ((J + cand * vec - 1) / (cand * vec) <= 8) { s.lpr = cand; break; }
+    for (int lim : {4, 8}) {  // prefer at most 4 column chunks per lane (register budget)
+        for (int cand : {16, 32})
+            if ((J + cand * vec - 1) / (cand * vec) <= lim) { s.lpr = cand; break; }
+        if (s.lpr < 64) break;
+    }
     if (h->opt.sweep_lanes == 16 || h->opt.sweep_lanes == 32 || h->opt.sweep_lanes == 64)
         if ((J + h->opt.sweep_lanes * vec - 1) / (h->opt.sweep_lanes * vec) <= max_nch(vec, h->opt.sweep_lanes))
             s.lpr = h->opt.sweep_lanes;
@@ -145,7 +111,9 @@ Shape make_shape(const ot_assoc* h, int64_t I, int64_t J, int vec, bool p64 = fa
     s.rpb = (I + nb - 1) / nb;
     s.nb = (int)((I + s.rpb - 1) / s.rpb);
     const int steps = (int)((s.rpb + s.waves * R - 1) / (s.waves * R));
-    const int want = h->opt.sweep_rows > 0 ? h->opt.sweep_rows : pow2_at_least(steps);
+    // one step in flight measured best whenever a row is shared by lanes (the
+    // registers of a second step cost more occupancy than they hide latency)
+    const int want = h->opt.sweep_rows > 0 ? h->opt.sweep_rows : (s.lpr < 64 ? 1 : pow2_at_least(steps));
     const int cap = (s.lpr < 64) ? 2 : std::max(1, 16 / s.nchT);
     s.rb = std::min({want, max_rb<Src>(p64), cap});
     return s;
@@ -185,10 +153,20 @@ void set_lds(K kern, size_t lds) {
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+// While set, the iteration launcher stores the kernel's resident workgroups
+// per CU here instead of launching (used to size the grid to one full wave).
+thread_local int* g_occupancy_query = nullptr;
+
 template <class Src, bool P64, int VEC, int NCH, int LPR, int W, int RB>
 void launch_iter_t(const Shape& s, const IterArgs& A, const Src& src, size_t lds, hipStream_t st) {
     auto kern = k_iter<Src, P64, VEC, NCH, LPR, W, RB>;
     set_lds(kern, lds);
+    if (g_occupancy_query) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, W * 64, lds) != hipSuccess) n = 0;
+        *g_occupancy_query = n;
+        return;
+    }
     if (g_prepare_only) return;
     hipLaunchKernelGGL(kern, dim3(s.nb), dim3(W * 64), lds, st, A, src);
 }
@@ -290,6 +268,26 @@ bool launch_plan(const Shape& s, int64_t I, int J, const double* f, const double
     if constexpr (Src::kVecWide > 1)
         if (s.vec == Src::kVecWide) { launch_plan_v<Src, OutT, Src::kVecWide>(s, I, J, f, g, prm, out, src, st); return true; }
     return false;
+}
+
+// Default grid of the iteration kernel: one full wave of resident workgroups
+// (as many as fit on every CU at once, at most kMaxNb partial rows and no more
+// than the rows need), so that no workgroup waits for a second round.
+template <class Src, bool P64>
+void fit_grid(const ot_assoc* h, int64_t I, Shape& s) {
+    if (h->opt.sweep_blocks > 0 || h->num_cu <= 0) return;
+    int occ = 0;
+    g_occupancy_query = &occ;
+    IterArgs A{};
+    Src src{};
+    const bool known = launch_iter<Src, P64>(s, A, src, nullptr);
+    g_occupancy_query = nullptr;
+    if (!known || occ <= 0) return;
+    const int64_t R = 64 / s.lpr;
+    int64_t nb = std::min<int64_t>({(int64_t)kMaxNb, (int64_t)occ * h->num_cu, (I + s.waves * R - 1) / (s.waves * R)});
+    nb = std::max<int64_t>(1, nb);
+    s.rpb = (I + nb - 1) / nb;
+    s.nb = (int)((I + s.rpb - 1) / s.rpb);
 }
 
 // ---------------------------------------------------------------- helpers --
@@ -477,21 +475,28 @@ struct Solver {
     Shape shape64;  // FP64 iterations
     bool graphs;
 
-    // Iteration k_from + 1: reads iterate k_from (parity k_from & 1) and
-    // writes the other parity. ev_a / ev_b (optional) bracket the sweep.
+    // The sweep of iteration k_from + 1: reads iterate k_from (parity
+    // k_from & 1), writes f of the other parity and the column partials.
     template <class Src, bool P64>
-    ot_status issue_iter(const Src& src, int k_from, int mode, double stall_below, hipEvent_t ev_a = nullptr,
-                         hipEvent_t ev_b = nullptr) {
+    ot_status issue_sweep(const Src& src, int k_from) {
         const Shape& sh = P64 ? shape64 : shape;
         const int pin = k_from & 1, pout = pin ^ 1;
         IterArgs A{};
         A.I = I; A.J = J; A.nch = sh.nch; A.rows_per_block = sh.rpb;
         A.a = h->a; A.f_in = h->f[pin]; A.f_out = h->f[pout]; A.g_in = h->g[pin];
         A.col_part = h->col_part; A.res_part = h->res_part; A.ctl = h->ctl; A.prm = h->prm;
-        if (ev_a) hipEventRecord(ev_a, h->stream);
         if (!launch_iter<Src, P64>(sh, A, src, h->stream))
             return fail(h, OT_EINVAL, "no iteration kernel for vec=%d nch=%d waves=%d rb=%d", sh.vec, sh.nchT, sh.waves, sh.rb);
-        if (ev_b) hipEventRecord(ev_b, h->stream);
+        return OT_OK;
+    }
+
+    // Iteration k_from + 1: the sweep, then the column combine (new g, the
+    // residual and the stop decision).
+    template <class Src, bool P64>
+    ot_status issue_iter(const Src& src, int k_from, int mode, double stall_below) {
+        if (ot_status st = issue_sweep<Src, P64>(src, k_from)) return st;
+        const Shape& sh = P64 ? shape64 : shape;
+        const int pin = k_from & 1, pout = pin ^ 1;
         ColArgs B{};
         B.J = J; B.nb = sh.nb; B.b = h->b; B.g_in = h->g[pin]; B.g_out = h->g[pout];
         B.col_part = h->col_part; B.res_part = h->res_part; B.ctl = h->ctl; B.prm = h->prm;
@@ -612,6 +617,8 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
                      Ctl& c, int& result_iter) {
     const int vec = vec_for<Src>(J, data);
     Solver S{h, I, J, make_shape<Src>(h, I, J, vec, false), make_shape<Src>(h, I, J, vec, true), h->opt.use_graphs != 0};
+    fit_grid<Src, false>(h, I, S.shape);
+    fit_grid<Src, true>(h, I, S.shape64);
     if (S.shape.nchT > (S.shape.vec == 4 ? 8 : S.shape.vec == 2 ? 16 : 32))
         return fail(h, OT_EINVAL, "J = %d too large for this cost layout", J);
     int chunk = std::max(2, h->opt.chunk);
@@ -664,6 +671,7 @@ ot_status ot_assoc_default_options(ot_assoc_options* opt) {
     opt->polish_iters = 1;
     opt->chunk = 8;
     opt->use_graphs = 1;
+    opt->batch_tune = 1;
     return OT_OK;
 }
 
@@ -682,6 +690,7 @@ void ot_assoc_destroy(ot_assoc* h) {
     hipEvent_t evs[] = {h->ev_start, h->ev_stop, h->ev_slot[0], h->ev_slot[1]};
     for (auto e : evs)
         if (e) hipEventDestroy(e);
+    if (h->batch) batch_engine_destroy(h->batch);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
 }
@@ -711,6 +720,7 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, OT_EDEVICE, "hipSetDevice failed");
     ot_assoc* h = new ot_assoc();
     h->device = o.device;
+    if (hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, o.device) != hipSuccess) h->num_cu = 0;
     h->stream = (hipStream_t)o.stream;
     h->opt = o;
     h->I_max = I_max;
@@ -995,7 +1005,7 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
     HIPCHK(h, hipMalloc(&fs, sizeof(double) * I));
     hipError_t e = hipMalloc(&gs, sizeof(double) * J);
     if (e != hipSuccess) { hipFree(fs); return fail(h, OT_ENOMEM, "hipMalloc failed"); }
-    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    std::vector<hipEvent_t> ev(2, nullptr);
     ot_status st = OT_OK;
     for (auto& x : ev)
         if (hipEventCreate(&x) != hipSuccess) st = fail(h, OT_EDEVICE, "hipEventCreate failed");
@@ -1014,24 +1024,24 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
             using S = std::decay_t<decltype(src)>;
             const int vec = vec_for<S>(J, data);
             Solver sv{h, I, (int)J, make_shape<S>(h, I, J, vec, false), make_shape<S>(h, I, J, vec, true), false};
+            fit_grid<S, false>(h, I, sv.shape);
+            fit_grid<S, true>(h, I, sv.shape64);
+            // the sweep kernel alone, back to back from alternating parities,
+            // between one pair of events: launch gaps included, no event per launch
+            HIPCHK(h, hipEventRecord(ev[0], h->stream));
             for (int r = 0; r < reps; ++r) {
-                // iteration from parity (p + r) & 1; only the sweep kernel is bracketed
-                const ot_status s2 = fp64 ? sv.issue_iter<S, true>(src, p + r, kModePolish, 0.0, ev[2 * r], ev[2 * r + 1])
-                                          : sv.issue_iter<S, false>(src, p + r, kModePolish, 0.0, ev[2 * r], ev[2 * r + 1]);
+                const ot_status s2 = fp64 ? sv.issue_sweep<S, true>(src, p + r) : sv.issue_sweep<S, false>(src, p + r);
                 if (s2) return s2;
             }
+            HIPCHK(h, hipEventRecord(ev[1], h->stream));
             return OT_OK;
         });
         hipError_t e2 = hipStreamSynchronize(h->stream);
         if (!st && e2 != hipSuccess) st = fail(h, OT_EDEVICE, "timed sweeps failed: %s", hipGetErrorString(e2));
         if (!st) {
-            double tot = 0.0;
-            for (int r = 0; r < reps; ++r) {
-                float ms = 0.0f;
-                hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
-                tot += ms;
-            }
-            *ms_per_launch = tot / reps;
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, ev[0], ev[1]);
+            *ms_per_launch = (double)ms / reps;
         }
         hipMemcpyAsync(h->f[p], fs, sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream);
         hipMemcpyAsync(h->g[p], gs, sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream);

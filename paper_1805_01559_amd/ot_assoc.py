@@ -31,7 +31,9 @@ OT_PREC_FP32, OT_PREC_FP64 = 0, 1
 EXPORTS = [
     "ot_assoc_default_options", "ot_assoc_create", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
     "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep",
-    "ot_assoc_destroy", "ot_assoc_last_error",
+    "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_potentials",
+    "ot_assoc_batch_plan", "ot_serve_default_options", "ot_serve_create", "ot_serve_submit", "ot_serve_progress",
+    "ot_serve_counts", "ot_serve_potentials", "ot_serve_now", "ot_serve_last_error", "ot_serve_destroy",
 ]
 
 
@@ -50,7 +52,7 @@ class ot_cost_desc(ct.Structure):
 class ot_assoc_options(ct.Structure):
     _fields_ = [("device", ct.c_int), ("stream", ct.c_void_p), ("precision", ct.c_int), ("polish_iters", ct.c_int),
                 ("chunk", ct.c_int), ("use_graphs", ct.c_int), ("sweep_blocks", ct.c_int), ("sweep_waves", ct.c_int),
-                ("sweep_rows", ct.c_int), ("sweep_lanes", ct.c_int)]
+                ("sweep_rows", ct.c_int), ("sweep_lanes", ct.c_int), ("batch_tune", ct.c_int)]
 
 
 class ot_assoc_result(ct.Structure):
@@ -60,6 +62,24 @@ class ot_assoc_result(ct.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class ot_serve_options(ct.Structure):
+    _fields_ = [("device", ct.c_int), ("stream", ct.c_void_p), ("budget_bytes", ct.c_double), ("max_slots", ct.c_int),
+                ("max_items", ct.c_int), ("polish_iters", ct.c_int), ("sweep_waves", ct.c_int),
+                ("rows_per_part", ct.c_int), ("keep_layouts", ct.c_int)]
+
+
+class ot_request(ct.Structure):
+    _fields_ = [("cost", ot_cost_desc), ("a", ct.c_void_p), ("b", ct.c_void_p), ("eps", ct.c_double),
+                ("tol", ct.c_double), ("max_iter", ct.c_int32), ("reserved", ct.c_int32),
+                ("layout_key", ct.c_uint64), ("user_tag", ct.c_uint64)]
+
+
+class ot_completion(ct.Structure):
+    _fields_ = [("ticket", ct.c_uint64), ("user_tag", ct.c_uint64), ("layout_key", ct.c_uint64),
+                ("warm", ct.c_int32), ("reserved", ct.c_int32), ("t_submit", ct.c_double),
+                ("t_admit", ct.c_double), ("t_done", ct.c_double), ("result", ot_assoc_result)]
 
 
 _lib = None
@@ -87,8 +107,27 @@ def lib():
         L.ot_assoc_destroy.restype = None
         L.ot_assoc_last_error.argtypes = [vp]
         L.ot_assoc_last_error.restype = ct.c_char_p
+        PP = ct.POINTER(ct.c_void_p)
+        L.ot_assoc_solve_batch.argtypes = [vp, ct.c_int, ct.POINTER(ot_cost_desc), PP, PP, ct.POINTER(d), d,
+                                           ct.c_int32, ct.POINTER(ot_assoc_result)]
+        L.ot_assoc_batch_potentials.argtypes = [vp, ct.c_int, vp, vp, ct.c_int]
+        L.ot_assoc_batch_plan.argtypes = [vp, ct.c_int, vp, ct.c_int, ct.c_int]
+        L.ot_serve_default_options.argtypes = [ct.POINTER(ot_serve_options)]
+        L.ot_serve_create.argtypes = [ct.POINTER(vp), ct.POINTER(ot_serve_options)]
+        L.ot_serve_submit.argtypes = [vp, ct.POINTER(ot_request), ct.POINTER(ct.c_uint64)]
+        L.ot_serve_progress.argtypes = [vp, ct.POINTER(ot_completion), ct.c_int, ct.POINTER(ct.c_int)]
+        L.ot_serve_counts.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
+                                      ct.POINTER(d)]
+        L.ot_serve_potentials.argtypes = [vp, ct.c_uint64, vp, vp, ct.c_int]
+        L.ot_serve_now.argtypes = []
+        L.ot_serve_now.restype = d
+        L.ot_serve_last_error.argtypes = [vp]
+        L.ot_serve_last_error.restype = ct.c_char_p
+        L.ot_serve_destroy.argtypes = [vp]
+        L.ot_serve_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("ot_assoc_destroy", "ot_assoc_last_error"):
+            if name not in ("ot_assoc_destroy", "ot_assoc_last_error", "ot_serve_now", "ot_serve_last_error",
+                            "ot_serve_destroy"):
                 getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -165,6 +204,83 @@ def ot_assoc_time_sweep(h, reps: int, fp64: bool = False) -> float:
 def ot_assoc_destroy(h):
     if h:
         lib().ot_assoc_destroy(h)
+
+
+def ot_assoc_solve_batch(h, descs, a_ptrs, b_ptrs, eps, tol, max_iter):
+    n = len(descs)
+    D = (ot_cost_desc * n)(*descs)
+    A = (ct.c_void_p * n)(*a_ptrs)
+    B = (ct.c_void_p * n)(*b_ptrs)
+    E = (ct.c_double * n)(*[float(e) for e in eps])
+    R = (ot_assoc_result * n)()
+    st = lib().ot_assoc_solve_batch(h, n, D, A, B, E, float(tol), int(max_iter), R)
+    _check(h, st)
+    return st, list(R)
+
+
+def ot_assoc_batch_potentials(h, k, f_ptr, g_ptr, mem):
+    return _check(h, lib().ot_assoc_batch_potentials(h, int(k), f_ptr, g_ptr, mem))
+
+
+def ot_assoc_batch_plan(h, k, pi_ptr, mem, dtype):
+    return _check(h, lib().ot_assoc_batch_plan(h, int(k), pi_ptr, mem, dtype))
+
+
+def ot_serve_default_options() -> ot_serve_options:
+    o = ot_serve_options()
+    lib().ot_serve_default_options(ct.byref(o))
+    return o
+
+
+def ot_serve_last_error(s) -> str:
+    m = lib().ot_serve_last_error(s)
+    return m.decode() if m else ""
+
+
+def _scheck(s, st):
+    if st < 0:
+        raise OTError(st, ot_serve_last_error(s))
+    return st
+
+
+def ot_serve_create(options: ot_serve_options | None = None):
+    s = ct.c_void_p()
+    st = lib().ot_serve_create(ct.byref(s), ct.byref(options) if options is not None else None)
+    if st < 0:
+        raise OTError(st, "ot_serve_create failed")
+    return s
+
+
+def ot_serve_submit(s, req: ot_request) -> int:
+    t = ct.c_uint64()
+    _scheck(s, lib().ot_serve_submit(s, ct.byref(req), ct.byref(t)))
+    return t.value
+
+
+def ot_serve_progress(s, max_out: int = 256):
+    out = (ot_completion * max_out)()
+    n = ct.c_int()
+    _scheck(s, lib().ot_serve_progress(s, out, max_out, ct.byref(n)))
+    return [out[q] for q in range(n.value)]
+
+
+def ot_serve_counts(s):
+    q, r, k, b = ct.c_int(), ct.c_int(), ct.c_int(), ct.c_double()
+    _scheck(s, lib().ot_serve_counts(s, ct.byref(q), ct.byref(r), ct.byref(k), ct.byref(b)))
+    return q.value, r.value, k.value, b.value
+
+
+def ot_serve_potentials(s, key, f_ptr, g_ptr, mem):
+    return _scheck(s, lib().ot_serve_potentials(s, int(key), f_ptr, g_ptr, mem))
+
+
+def ot_serve_now() -> float:
+    return lib().ot_serve_now()
+
+
+def ot_serve_destroy(s):
+    if s:
+        lib().ot_serve_destroy(s)
 
 
 # ---------------------------------------------------------- marshalling ----
@@ -317,3 +433,115 @@ class Solver:
         if m != OT_MEM_DEVICE:
             raise ValueError("materialize_cost writes a device buffer")
         return ot_assoc_materialize_cost(self.h, desc, p)
+
+    # ------------------------------------------------------------ batches --
+    def solve_batch(self, costs, a_list, b_list, eps, tol=1e-6, max_iter=2000):
+        """Solves instances together. costs: list of cost matrices (numpy or
+        torch) or (desc, keep) pairs; a_list / b_list in the costs' memory."""
+        descs, keep = [], []
+        for c in costs:
+            if isinstance(c, tuple):
+                descs.append(c[0])
+                keep.append(c[1])
+            else:
+                d, k = matrix_desc(c, OT_COST_DENSE)
+                descs.append(d)
+                keep.append(k)
+        pa, pb = [], []
+        for d, a, b in zip(descs, a_list, b_list):
+            p1, m1, k1 = _ptr_mem(a, np.float64)
+            p2, m2, k2 = _ptr_mem(b, np.float64)
+            want = OT_MEM_DEVICE if d.kind == OT_COST_GEOMETRY else d.mem
+            if m1 != want or m2 != want:
+                raise ValueError("marginals must be in the cost's memory space")
+            pa.append(p1)
+            pb.append(p2)
+            keep += [k1, k2]
+        eps_l = list(eps) if hasattr(eps, "__len__") else [eps] * len(descs)
+        st, res = ot_assoc_solve_batch(self.h, descs, pa, pb, eps_l, tol, max_iter)
+        self._batch_dims = [(d.I, d.J) for d in descs]
+        del keep
+        return st, res
+
+    def batch_potentials(self, k):
+        I, J = self._batch_dims[k]
+        f = np.empty(I)
+        g = np.empty(J)
+        ot_assoc_batch_potentials(self.h, k, f.ctypes.data, g.ctypes.data, OT_MEM_HOST)
+        return f, g
+
+    def batch_plan(self, k, dtype=np.float64):
+        I, J = self._batch_dims[k]
+        out = np.empty((I, J), dtype=dtype)
+        ot_assoc_batch_plan(self.h, k, out.ctypes.data, OT_MEM_HOST, OT_F32 if dtype == np.float32 else OT_F64)
+        return out
+
+
+class Server:
+    """Request server over the batched engine (ot_serve_*). Requests keep
+    references to their buffers until their completion is returned."""
+
+    def __init__(self, device=0, stream=None, **opts):
+        o = ot_serve_default_options()
+        o.device = device
+        o.stream = stream
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.s = ot_serve_create(o)
+        self._keep = {}
+
+    def close(self):
+        s = getattr(self, "s", None)
+        self.s = None
+        if s:
+            try:
+                ot_serve_destroy(s)
+            except Exception:
+                pass
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, cost, a, b, eps, tol=1e-6, max_iter=2000, layout_key=0, user_tag=0):
+        """cost: a matrix (numpy / torch) or a (desc, keep) pair."""
+        if isinstance(cost, tuple):
+            d, kc = cost
+        else:
+            d, kc = matrix_desc(cost, OT_COST_DENSE)
+        p1, m1, k1 = _ptr_mem(a, np.float64)
+        p2, m2, k2 = _ptr_mem(b, np.float64)
+        want = OT_MEM_DEVICE if d.kind == OT_COST_GEOMETRY else d.mem
+        if m1 != want or m2 != want:
+            raise ValueError("marginals must be in the cost's memory space")
+        r = ot_request()
+        r.cost = d
+        r.a, r.b = p1, p2
+        r.eps, r.tol, r.max_iter = float(eps), float(tol), int(max_iter)
+        r.layout_key, r.user_tag = int(layout_key), int(user_tag)
+        t = ot_serve_submit(self.s, r)
+        self._keep[t] = (kc, k1, k2, cost)
+        return t
+
+    def progress(self, max_out=256):
+        done = ot_serve_progress(self.s, max_out)
+        for c in done:
+            self._keep.pop(c.ticket, None)
+        return done
+
+    def counts(self):
+        return ot_serve_counts(self.s)
+
+    def potentials(self, key, I, J):
+        f = np.empty(I)
+        g = np.empty(J)
+        ot_serve_potentials(self.s, key, f.ctypes.data, g.ctypes.data, OT_MEM_HOST)
+        return f, g
+
+    @staticmethod
+    def now():
+        return ot_serve_now()

@@ -39,21 +39,52 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "sz.c"
+    fields = ["sizeof(ot_cost_desc)", "sizeof(ot_assoc_options)", "sizeof(ot_assoc_result)",
+              "offsetof(ot_cost_desc, geom)", "offsetof(ot_assoc_result, seconds)",
+              "offsetof(ot_assoc_options, batch_tune)", "sizeof(ot_serve_options)",
+              "offsetof(ot_serve_options, keep_layouts)", "sizeof(ot_request)", "offsetof(ot_request, layout_key)",
+              "offsetof(ot_request, user_tag)", "sizeof(ot_completion)", "offsetof(ot_completion, result)",
+              "offsetof(ot_completion, t_done)"]
+    fmt = " ".join(["%zu"] * len(fields))
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ot_assoc.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(ot_cost_desc), sizeof(ot_assoc_options),'
-                   ' sizeof(ot_assoc_result), offsetof(ot_cost_desc, geom), offsetof(ot_assoc_result, seconds));'
-                   'return 0;}\n')
+                   'int main(void){printf("' + fmt + '\\n", ' + ", ".join(fields) + ');return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
     want = [ct.sizeof(A.ot_cost_desc), ct.sizeof(A.ot_assoc_options), ct.sizeof(A.ot_assoc_result),
-            A.ot_cost_desc.geom.offset, A.ot_assoc_result.seconds.offset]
+            A.ot_cost_desc.geom.offset, A.ot_assoc_result.seconds.offset, A.ot_assoc_options.batch_tune.offset,
+            ct.sizeof(A.ot_serve_options), A.ot_serve_options.keep_layouts.offset, ct.sizeof(A.ot_request),
+            A.ot_request.layout_key.offset, A.ot_request.user_tag.offset, ct.sizeof(A.ot_completion),
+            A.ot_completion.result.offset, A.ot_completion.t_done.offset]
     assert got == want
 
 
 def test_default_options(lib):
     o = A.ot_assoc_default_options()
-    assert (o.device, o.precision, o.polish_iters, o.chunk, o.use_graphs) == (0, A.OT_PREC_FP32, 1, 8, 1)
+    assert (o.device, o.precision, o.polish_iters, o.chunk, o.use_graphs, o.batch_tune) == \
+        (0, A.OT_PREC_FP32, 1, 8, 1, 1)
+    s = A.ot_serve_default_options()
+    assert (s.polish_iters, s.sweep_waves, s.rows_per_part, s.max_slots, s.budget_bytes) == (1, 8, 128, 0, 0.0)
+
+
+def test_batch_and_serve_argument_errors_without_a_device(lib):
+    assert lib.ot_assoc_solve_batch(None, 1, None, None, None, None, 1e-6, 10, None) == A.OT_EINVAL
+    assert lib.ot_assoc_batch_potentials(None, 0, None, None, 0) == A.OT_EINVAL
+    assert lib.ot_assoc_batch_plan(None, 0, None, 0, 0) == A.OT_EINVAL
+    assert lib.ot_serve_submit(None, None, None) == A.OT_EINVAL
+    assert lib.ot_serve_progress(None, None, 0, None) == A.OT_EINVAL
+    assert lib.ot_serve_counts(None, None, None, None, None) == A.OT_EINVAL
+    # bad options are rejected before any device is touched
+    o = A.ot_serve_default_options()
+    o.rows_per_part = 100
+    with pytest.raises(A.OTError):
+        A.ot_serve_create(o)
+    o = A.ot_serve_default_options()
+    o.sweep_waves = 6
+    with pytest.raises(A.OTError):
+        A.ot_serve_create(o)
+    lib.ot_serve_destroy(None)
+    assert lib.ot_serve_now() > 0.0
 
 
 def test_argument_errors_without_a_device(lib):
