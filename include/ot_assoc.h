@@ -102,6 +102,8 @@ typedef struct {
     const void *data; /* DENSE: C_ij; RATES: R_ij > 0 */
     double scale;     /* RATES / GEOMETRY: C_ij = (1 / R_ij) / scale, scale > 0 */
     ot_geometry geom; /* GEOMETRY only */
+    int64_t ld;       /* DENSE / RATES: row stride of `data` in elements (0 = J, else >= J;
+                         the padding entries are never used as costs) */
 } ot_cost_desc;
 
 typedef struct {
@@ -215,11 +217,13 @@ const char *ot_assoc_last_error(const ot_assoc *h);
  * iteration counts cost only their own work.
  *
  * Every cost is held as a padded FP32 row-major matrix: a DENSE FP32 matrix in
- * device memory whose J is a multiple of 4 and whose rows are 16-byte aligned
- * is referenced in place (keep it valid until the next batch on the handle);
- * other DENSE / RATES inputs (host or device, FP32 or FP64) are converted,
- * GEOMETRY inputs (device memory) are materialised (scale <= 0 takes the
- * median of 1/R). 1 <= J <= 512; a[k] and b[k] live in costs[k].mem
+ * device memory whose row stride (ld, else J) is a multiple of 4 and whose
+ * base is 16-byte aligned is referenced in place (keep it valid until the
+ * next batch on the handle); other DENSE / RATES inputs (host or device, FP32
+ * or FP64) are converted, GEOMETRY inputs (device memory; positions read at
+ * admission) are materialised (scale <= 0 takes the median of 1/R, which
+ * waits on the host). Cost values are not screened: a non-finite cost ends
+ * that instance with OT_ENUMERIC. 1 <= J <= 512; a[k] and b[k] live in costs[k].mem
  * (GEOMETRY: device memory). eps[k] > 0 per instance; tol and max_iter are
  * shared. out[k] (may be NULL) receives instance k's result; `seconds` is the
  * device time of the whole batch.

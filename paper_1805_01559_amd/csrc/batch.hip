@@ -408,50 +408,67 @@ ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, 
     float* dst = (float*)C_mem;
     const unsigned grid = (unsigned)std::min<int64_t>(4096, (I * ld + 255) / 256);
     if (c->kind == OT_COST_GEOMETRY) {
-        if (!helper || helper->I_max < I) {
-            if (helper) ot_assoc_destroy(helper);
-            helper = nullptr;
-            ot_assoc_options o;
-            ot_assoc_default_options(&o);
-            o.device = device;
-            o.stream = stream;
-            ot_status st = ot_assoc_create(&helper, std::max<int64_t>(I, 1 << 15), kBatchMaxJ, &o);
-            if (st) return fail(st, "helper handle: %s", ot_assoc_last_error(nullptr));
-        }
-        ot_cost_desc d = *c;
-        if (!(d.scale > 0.0)) {
-            double med = 0.0;
-            ot_status st = ot_assoc_cost_median(helper, &d, &med);
+        double scale = c->scale;
+        if (!(scale > 0.0)) {
+            // the median of 1/R needs host read-backs: a handle of the
+            // single-instance path on this engine's stream computes it
+            if (!helper || helper->I_max < I) {
+                if (helper) ot_assoc_destroy(helper);
+                helper = nullptr;
+                ot_assoc_options o;
+                ot_assoc_default_options(&o);
+                o.device = device;
+                o.stream = stream;
+                ot_status st = ot_assoc_create(&helper, std::max<int64_t>(I, 1 << 15), kBatchMaxJ, &o);
+                if (st) return fail(st, "helper handle: %s", ot_assoc_last_error(nullptr));
+            }
+            ot_status st = ot_assoc_cost_median(helper, c, &scale);
             if (st) return fail(st, "cost median: %s", ot_assoc_last_error(helper));
-            d.scale = med;
         }
-        // unpadded FP32 matrix into the block, then spread rows to stride ld
-        ot_status st = ot_assoc_materialize_cost(helper, &d, dst);
-        if (st) return fail(st, "materialise: %s", ot_assoc_last_error(helper));
-        if (ld != J) {
-            ECHK(this, hipMemcpyAsync(stage, dst, sizeof(float) * (size_t)I * J, hipMemcpyDeviceToDevice, stream));
-            hipLaunchKernelGGL((k_bpad<float, 0>), dim3(grid), dim3(256), 0, stream, (const float*)stage, I, J,
-                               (int64_t)J, dst, ld, 1.0);
+        // per-device interference sums (the staging block), then the padded
+        // FP32 matrix, both queued on the engine stream without a host wait;
+        // non-finite positions surface as a numeric failure of the solve
+        GeoSrc g{};
+        g.dev_xy = (const float*)c->geom.dev_xy;
+        g.rrh_xy = (const float*)c->geom.rrh_xy;
+        double* s_all = (double*)stage;
+        double* s_ex = s_all + I;
+        int* j1 = (int*)(s_ex + I);
+        g.s_all = s_all;
+        g.s_ex = s_ex;
+        g.j1 = j1;
+        g.k = geo_const(c->geom, scale);
+        const dim3 pg((unsigned)((I + 3) / 4)), pb(256);
+        switch ((J + 63) / 64) {
+            case 1: hipLaunchKernelGGL(k_geo_prepass<1>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
+            case 2: hipLaunchKernelGGL(k_geo_prepass<2>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
+            case 3: case 4: hipLaunchKernelGGL(k_geo_prepass<4>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
+            default: hipLaunchKernelGGL(k_geo_prepass<8>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
         }
+        const size_t lds = sizeof(double) * (size_t)J + 8;
+        const int mg = (int)std::min<int64_t>(4096, (I + 7) / 8);
+        hipLaunchKernelGGL(k_materialize<GeoSrc>, dim3(mg), dim3(512), lds, stream, I, J, ld, dst, g);
+        ECHK(this, hipGetLastError());
         return OT_OK;
     }
     const size_t esz = c->dtype == OT_F32 ? 4 : 8;
+    const int64_t lds = c->ld ? c->ld : J;
     const void* src = c->data;
     if (c->mem == OT_MEM_HOST) {
-        ECHK(this, hipMemcpyAsync(stage, c->data, esz * (size_t)I * J, hipMemcpyHostToDevice, stream));
+        ECHK(this, hipMemcpyAsync(stage, c->data, esz * (size_t)(I * lds), hipMemcpyHostToDevice, stream));
         src = stage;
     }
     const double inv = c->kind == OT_COST_RATES ? 1.0 / c->scale : 1.0;
     if (c->kind == OT_COST_DENSE) {
         if (c->dtype == OT_F32)
-            hipLaunchKernelGGL((k_bpad<float, 0>), dim3(grid), dim3(256), 0, stream, (const float*)src, I, J, (int64_t)J, dst, ld, inv);
+            hipLaunchKernelGGL((k_bpad<float, 0>), dim3(grid), dim3(256), 0, stream, (const float*)src, I, J, lds, dst, ld, inv);
         else
-            hipLaunchKernelGGL((k_bpad<double, 0>), dim3(grid), dim3(256), 0, stream, (const double*)src, I, J, (int64_t)J, dst, ld, inv);
+            hipLaunchKernelGGL((k_bpad<double, 0>), dim3(grid), dim3(256), 0, stream, (const double*)src, I, J, lds, dst, ld, inv);
     } else {
         if (c->dtype == OT_F32)
-            hipLaunchKernelGGL((k_bpad<float, 1>), dim3(grid), dim3(256), 0, stream, (const float*)src, I, J, (int64_t)J, dst, ld, inv);
+            hipLaunchKernelGGL((k_bpad<float, 1>), dim3(grid), dim3(256), 0, stream, (const float*)src, I, J, lds, dst, ld, inv);
         else
-            hipLaunchKernelGGL((k_bpad<double, 1>), dim3(grid), dim3(256), 0, stream, (const double*)src, I, J, (int64_t)J, dst, ld, inv);
+            hipLaunchKernelGGL((k_bpad<double, 1>), dim3(grid), dim3(256), 0, stream, (const double*)src, I, J, lds, dst, ld, inv);
     }
     return OT_OK;
 }
@@ -490,6 +507,7 @@ static ot_status check_desc(BatchEngine* e, const ot_cost_desc* c) {
             if (c->dtype != OT_F32 && c->dtype != OT_F64) return e->fail(OT_EINVAL, "bad dtype");
             if (c->kind == OT_COST_RATES && !(c->scale > 0.0 && std::isfinite(c->scale)))
                 return e->fail(OT_EINVAL, "rates need scale > 0");
+            if (c->ld != 0 && c->ld < c->J) return e->fail(OT_EINVAL, "row stride below J");
             break;
         case OT_COST_GEOMETRY:
             if (c->mem != OT_MEM_DEVICE) return e->fail(OT_EINVAL, "batched geometry must be in device memory");
@@ -553,9 +571,10 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         const int J = (int)c->J;
         const int parts_cap = (int)parts_of(I, 64);  // the finest layout the tuner may choose
         const int parts = (int)parts_of(I, rpp);
-        const bool ref = c->kind == OT_COST_DENSE && c->mem == OT_MEM_DEVICE && c->dtype == OT_F32 && J % 4 == 0 &&
+        const int64_t lds = c->ld ? c->ld : J;
+        const bool ref = c->kind == OT_COST_DENSE && c->mem == OT_MEM_DEVICE && c->dtype == OT_F32 && lds % 4 == 0 &&
                          ((uintptr_t)c->data % 16) == 0;
-        const int64_t ld = ref ? J : (J + 3) / 4 * 4;
+        const int64_t ld = ref ? lds : (J + 3) / 4 * 4;
         if (free_slots.empty() || items_running + n_items + parts > cap_items) {
             if (strict) return fail(OT_ENOMEM, "batch exceeds %d slots / %d work items", cap_slots, cap_items);
             break;
@@ -564,8 +583,8 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         // cost; released once the conversion is queued (stream order)
         const size_t esz = c->dtype == OT_F64 ? 8 : 4;
         size_t stage_b = 0;
-        if (!ref && c->kind != OT_COST_GEOMETRY && c->mem == OT_MEM_HOST) stage_b = esz * (size_t)I * J;
-        if (c->kind == OT_COST_GEOMETRY && ld != J) stage_b = sizeof(float) * (size_t)I * J;
+        if (!ref && c->kind != OT_COST_GEOMETRY && c->mem == OT_MEM_HOST) stage_b = esz * (size_t)(I * lds);
+        if (c->kind == OT_COST_GEOMETRY) stage_b = (2 * sizeof(double) + sizeof(int)) * (size_t)I;
         char* stage = stage_b ? pool.alloc(stage_b) : nullptr;
         char* mem = (stage_b && !stage) ? nullptr : pool.alloc(slot_bytes(I, J, ld, parts_cap, !ref));
         if (!mem) {

@@ -4,10 +4,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
 #include "../../include/ot_assoc.h"
+#include "cost_sources.h"
 #include "device_common.h"
 
 namespace otk_host {
@@ -16,6 +18,19 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
 };
 }  // namespace otk_host
+
+// Constants of the geometry cost functor (relative gains, log2-domain
+// shadowing, median-normalised cost scale) from the public descriptor.
+inline otk::GeoConst geo_const(const ot_geometry& g, double scale) {
+    otk::GeoConst k{};
+    k.alpha_half = 0.5 * g.pathloss_exp;
+    k.shadow_c = g.shadow_sigma_db * std::log2(10.0) / 10.0;
+    k.dmin2 = g.min_dist_m * g.min_dist_m;
+    k.cscale = std::log(2.0) / (g.bandwidth_hz * scale);
+    k.n0n = g.noise_w / (g.tx_power_w * g.ref_gain);
+    k.key = g.shadow_key;
+    return k;
+}
 
 struct BatchEngine;
 void batch_engine_destroy(BatchEngine* e);

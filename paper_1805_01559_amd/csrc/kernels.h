@@ -647,10 +647,12 @@ __global__ __launch_bounds__(512) void k_plan(int64_t I, int J, int nch, const d
 // ------------------------------------------------------------- validation --
 // Flags a non-finite dense cost, or a rate that is not finite and positive.
 template <typename T, bool RATES>
-__global__ void k_validate(const T* x, int64_t n, int* bad) {
+__global__ void k_validate(const T* x, int64_t I, int J, int64_t ld, int* bad) {
     int flag = 0;
+    const int64_t n = I * J;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-        const double v = (double)x[q];
+        const int64_t i = q / J;
+        const double v = (double)x[i * ld + (q - i * J)];
         if (RATES ? !(v > 0.0 && isfinite(v)) : !isfinite(v)) flag = 1;
     }
     if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
@@ -724,14 +726,14 @@ __global__ __launch_bounds__(256) void k_geo_prepass(GeoSrc src, int64_t I, int 
 
 // Materialised FP32 cost: the FP64 functor rounded once to FP32.
 template <class Src>
-__global__ void k_materialize(int64_t I, int J, float* C, Src src) {
+__global__ void k_materialize(int64_t I, int J, int64_t ld, float* C, Src src) {
     extern __shared__ double sm[];
     src.stage(sm, J);
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int64_t i = (int64_t)blockIdx.x * nw + w; i < I; i += (int64_t)gridDim.x * nw) {
         auto row = src.row(i);
-        for (int j = lane; j < J; j += 64) C[i * J + j] = (float)src.at64(row, i, j, sm);
+        for (int j = lane; j < ld; j += 64) C[i * ld + j] = j < J ? (float)src.at64(row, i, j, sm) : __builtin_huge_valf();
     }
 }
 

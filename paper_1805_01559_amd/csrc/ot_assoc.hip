@@ -71,11 +71,16 @@ struct Shape {
     int64_t rpb = 1;
 };
 
+// Vector width of the row loads: 16-byte loads need a row stride that is a
+// multiple of the width and an aligned base (then a vector that straddles J
+// stays inside its row and its entries past J are masked).
 template <class Src>
-int vec_for(int64_t J, const void* d) {
+int vec_for(int64_t ld, const void* d) {
     if (Src::kVecWide == 1) return 1;
-    return (J % Src::kVecWide == 0 && ((uintptr_t)d % 16) == 0) ? Src::kVecWide : 1;
+    return (ld % Src::kVecWide == 0 && ((uintptr_t)d % 16) == 0) ? Src::kVecWide : 1;
 }
+
+inline int64_t ld_of(const ot_cost_desc& c) { return c.ld ? c.ld : c.J; }
 
 template <class Src>
 constexpr int max_rb(bool p64) {
@@ -324,6 +329,8 @@ ot_status validate_desc(ot_assoc* h, const ot_cost_desc* c) {
         return fail(h, OT_EINVAL, "instance %lld x %lld outside 1..%lld x 1..%lld", (long long)c->I, (long long)c->J,
                     (long long)h->I_max, (long long)h->J_max);
     if (c->mem != OT_MEM_HOST && c->mem != OT_MEM_DEVICE) return fail(h, OT_EINVAL, "bad memory space");
+    if ((c->kind == OT_COST_DENSE || c->kind == OT_COST_RATES) && c->ld != 0 && c->ld < c->J)
+        return fail(h, OT_EINVAL, "row stride ld = %lld is below J = %lld", (long long)c->ld, (long long)c->J);
     switch (c->kind) {
         case OT_COST_DENSE:
         case OT_COST_RATES:
@@ -360,42 +367,35 @@ ot_status ensure_stage(ot_assoc* h, size_t bytes) {
     return OT_OK;
 }
 
-GeoConst geo_const(const ot_geometry& g, double scale) {
-    GeoConst k{};
-    k.alpha_half = 0.5 * g.pathloss_exp;
-    k.shadow_c = g.shadow_sigma_db * std::log2(10.0) / 10.0;
-    k.dmin2 = g.min_dist_m * g.min_dist_m;
-    k.cscale = std::log(2.0) / (g.bandwidth_hz * scale);
-    k.n0n = g.noise_w / (g.tx_power_w * g.ref_gain);
-    k.key = g.shadow_key;
-    return k;
-}
 
 // Brings the cost of `c` onto the device: host matrices are staged, device
 // matrices are referenced, geometry is copied and its per-device set-up pass
 // runs. Afterwards the handle can rebuild the source without the caller.
 ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, bool validate_values) {
-    const int64_t I = c->I, J = c->J, n = I * J;
+    const int64_t I = c->I, J = c->J, ld = ld_of(*c), n = I * J;
     h->retained = false;
     h->last = *c;
     if (c->kind != OT_COST_GEOMETRY) {
         const size_t esz = c->dtype == OT_F32 ? 4 : 8;
         const void* data = c->data;
         if (c->mem == OT_MEM_HOST) {
-            ot_status st = ensure_stage(h, (size_t)n * esz);
+            // the padded rows travel whole (I x ld), so the stride is kept
+            const size_t bytes = (size_t)(I * ld) * esz;
+            ot_status st = ensure_stage(h, bytes);
             if (st) return st;
-            HIPCHK(h, hipMemcpyAsync(h->stage, data, (size_t)n * esz, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(h->stage, data, bytes, hipMemcpyHostToDevice, h->stream));
             data = h->stage;
         }
         if (validate_values) {
             HIPCHK(h, hipMemsetAsync(h->bad, 0, sizeof(int), h->stream));
             const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+            const int Ji = (int)J;
             if (c->dtype == OT_F32) {
-                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<float, false>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, n, h->bad);
-                else hipLaunchKernelGGL((k_validate<float, true>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, n, h->bad);
+                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<float, false>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, I, Ji, ld, h->bad);
+                else hipLaunchKernelGGL((k_validate<float, true>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, I, Ji, ld, h->bad);
             } else {
-                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<double, false>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, n, h->bad);
-                else hipLaunchKernelGGL((k_validate<double, true>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, n, h->bad);
+                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<double, false>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, I, Ji, ld, h->bad);
+                else hipLaunchKernelGGL((k_validate<double, true>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, I, Ji, ld, h->bad);
             }
             int bad = 0;
             HIPCHK(h, hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -447,7 +447,7 @@ ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, bool validate_values) 
 template <class F>
 ot_status with_retained(ot_assoc* h, F&& fn) {
     const ot_cost_desc& c = h->last;
-    const int64_t J = c.J;
+    const int64_t J = ld_of(c);  // row stride
     if (c.kind == OT_COST_DENSE) {
         if (c.dtype == OT_F32) { DenseSrc<float> s{}; s.C = (const float*)h->cost_dev; s.ld = J; return fn(s, h->cost_dev); }
         DenseSrc<double> s{}; s.C = (const double*)h->cost_dev; s.ld = J; return fn(s, h->cost_dev);
@@ -615,7 +615,7 @@ struct Solver {
 template <class Src>
 ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, int J, double tol, int32_t max_iter,
                      Ctl& c, int& result_iter) {
-    const int vec = vec_for<Src>(J, data);
+    const int vec = vec_for<Src>(ld_of(h->last), data);
     Solver S{h, I, J, make_shape<Src>(h, I, J, vec, false), make_shape<Src>(h, I, J, vec, true), h->opt.use_graphs != 0};
     fit_grid<Src, false>(h, I, S.shape);
     fit_grid<Src, true>(h, I, S.shape64);
@@ -876,7 +876,7 @@ ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
     }
     ot_status st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
         using S = std::decay_t<decltype(src)>;
-        const Shape s = row64(make_shape<S>(h, I, J, vec_for<S>(J, data)), J);
+        const Shape s = row64(make_shape<S>(h, I, J, vec_for<S>(ld_of(h->last), data)), J);
         bool ok = dtype == OT_F32 ? launch_plan<S, float>(s, I, (int)J, h->f[h->res_par], h->g[h->res_par], h->prm, (float*)dst, src, h->stream)
                                   : launch_plan<S, double>(s, I, (int)J, h->f[h->res_par], h->g[h->res_par], h->prm, (double*)dst, src, h->stream);
         if (!ok) return fail(h, OT_EINVAL, "no plan kernel for this shape");
@@ -986,7 +986,7 @@ ot_status ot_assoc_materialize_cost(ot_assoc* h, const ot_cost_desc* cost, float
         using S = std::decay_t<decltype(src)>;
         const size_t lds = sizeof(double) * S::kStageDoubles * (size_t)J + 8;
         const int grid = (int)std::min<int64_t>(4096, (I + 7) / 8);
-        hipLaunchKernelGGL(k_materialize<S>, dim3(grid), dim3(512), lds, h->stream, I, (int)J, C_dev, src);
+        hipLaunchKernelGGL(k_materialize<S>, dim3(grid), dim3(512), lds, h->stream, I, (int)J, (int64_t)J, C_dev, src);
         HIPCHK(h, hipStreamSynchronize(h->stream));
         return OT_OK;
     });
@@ -1022,7 +1022,7 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
         hipMemcpyAsync(h->ctl, &h->ctl_h[0], sizeof(Ctl), hipMemcpyHostToDevice, h->stream);
         st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
             using S = std::decay_t<decltype(src)>;
-            const int vec = vec_for<S>(J, data);
+            const int vec = vec_for<S>(ld_of(h->last), data);
             Solver sv{h, I, (int)J, make_shape<S>(h, I, J, vec, false), make_shape<S>(h, I, J, vec, true), false};
             fit_grid<S, false>(h, I, sv.shape);
             fit_grid<S, true>(h, I, sv.shape64);

@@ -46,7 +46,7 @@ class ot_geometry(ct.Structure):
 
 class ot_cost_desc(ct.Structure):
     _fields_ = [("kind", ct.c_int), ("I", ct.c_int64), ("J", ct.c_int64), ("mem", ct.c_int), ("dtype", ct.c_int),
-                ("data", ct.c_void_p), ("scale", ct.c_double), ("geom", ot_geometry)]
+                ("data", ct.c_void_p), ("scale", ct.c_double), ("geom", ot_geometry), ("ld", ct.c_int64)]
 
 
 class ot_assoc_options(ct.Structure):
@@ -331,12 +331,17 @@ def geometry_desc(dev_xy, rrh_xy, radio: dict, shadow_key: int, scale: float = 1
     return d, (kd, kr)
 
 
-def matrix_desc(M, kind=OT_COST_DENSE, scale: float = 1.0):
+def matrix_desc(M, kind=OT_COST_DENSE, scale: float = 1.0, J=None):
+    """Descriptor of a dense cost (or rate) matrix. With J given, M is an
+    (I, ld) row-padded buffer of which the first J columns are the instance."""
     dt = np.float32 if (str(getattr(M, "dtype", "")) in ("float32", "torch.float32")) else np.float64
     p, m, keep = _ptr_mem(M, dt)
     d = ot_cost_desc()
     d.kind, d.mem, d.dtype = kind, m, (OT_F32 if dt == np.float32 else OT_F64)
-    d.I, d.J = int(M.shape[0]), int(M.shape[1])
+    d.I, d.J = int(M.shape[0]), int(M.shape[1] if J is None else J)
+    d.ld = 0 if J is None else int(M.shape[1])
+    if d.J > int(M.shape[1]):
+        raise ValueError("J exceeds the buffer's row length")
     d.data, d.scale = p, float(scale)
     return d, (keep,)
 

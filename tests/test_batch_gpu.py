@@ -223,3 +223,28 @@ def test_batch_constant_cost_closed_form(A):
         for k in range(3):
             P = s.batch_plan(k)
             assert np.allclose(P, np.outer(aa[k], bb[k]), rtol=1e-8, atol=0)
+
+
+def test_batch_row_padded_inputs_in_place(A, oracle_lib, inst):
+    announce("batch of row-padded device matrices (ld % 4 == 0, NaN padding) referenced in place")
+    import torch
+    dev = torch.device("cuda:0")
+    picks = [0, 3, 4, 5]
+    costs, aa, bb, keep = [], [], [], []
+    for k in picks:
+        x = inst[k]
+        I, J = x["C32"].shape
+        ld = (J + 3) // 4 * 4 + 4
+        buf = np.full((I, ld), np.nan, np.float32)
+        buf[:, :J] = x["C32"]
+        t = torch.from_numpy(buf).to(dev)
+        keep.append(t)
+        costs.append(A.matrix_desc(t, A.OT_COST_DENSE, J=J))
+        aa.append(torch.from_numpy(x["L"].a).to(dev))
+        bb.append(torch.from_numpy(x["L"].b).to(dev))
+    with A.Solver(16, 16) as s:
+        st, res = s.solve_batch(costs, aa, bb, EPS, TOL, 2000)
+        assert st == A.OT_OK, [r.status for r in res]
+        for q, k in enumerate(picks):
+            f, g = s.batch_potentials(q)
+            check(oracle_lib, inst[k], f, g, res[q])

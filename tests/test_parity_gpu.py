@@ -301,3 +301,28 @@ def test_cran_20000x400_dense_and_geometry(A, oracle_lib, cran_cfg, eps, torch_m
         f, g = s.potentials()
     ref, ref_stats = oracle_ref(oracle_lib, C64, L.a, L.b, eps)
     check_against(oracle_lib, C64, L.a, L.b, eps, 1e-8, f, g, res, ref_stats, ref)
+
+
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_dense_row_padded_matrix(A, oracle_lib, torch_mod, where):
+    announce(f"row-padded FP32 matrix (ld = J + 5, NaN padding) in {where} memory")
+    L = S.make_layout(1500, 130, 1000.0, seed=77)
+    C64, _ = oracle_lib.cost(L)
+    C32 = C64.astype(np.float32)
+    I, J = C32.shape
+    for ld in (J + 2, J + 6):  # ld % 4 == 0 (vector loads) and not
+        buf = np.full((I, ld), np.nan, np.float32)
+        buf[:, :J] = C32
+        M = buf if where == "host" else torch_mod.from_numpy(buf).to("cuda:0")
+        a = L.a if where == "host" else torch_mod.from_numpy(L.a).to("cuda:0")
+        b = L.b if where == "host" else torch_mod.from_numpy(L.b).to("cuda:0")
+        d, keep = A.matrix_desc(M, A.OT_COST_DENSE, J=J)
+        with A.Solver(I, J) as s:
+            st, res = s.solve(d, keep, a, b, 0.05, 1e-9, 2000)
+            assert st == A.OT_OK
+            f, g = s.potentials()
+            P = s.plan()
+        Cq = C32.astype(np.float64)
+        ref, ref_stats = oracle_ref(oracle_lib, Cq, L.a, L.b, 0.05)
+        check_against(oracle_lib, Cq, L.a, L.b, 0.05, 1e-9, f, g, res, ref_stats, ref)
+        assert np.allclose(P, oracle_lib.plan(Cq, f, g, 0.05), rtol=1e-12, atol=1e-300)
