@@ -81,6 +81,167 @@ def cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale_gpu):
     return base, acc
 
 
+def pad_cols(t, J):
+    """(I, ld) FP32 device buffer, ld = J rounded up to 4, holding t in its first J columns."""
+    import torch
+    I = t.shape[0]
+    ld = (J + 3) // 4 * 4
+    buf = torch.full((I, ld), float("inf"), dtype=torch.float32, device=t.device)
+    buf[:, :J] = t
+    return buf
+
+
+def leg_batch(args, A, S, torch, dev):
+    """256 uneven instances (log-uniform I in [500, 20000], J in [20, 400],
+    1 km square, seeds 3000 + k) solved in one batch, eps 0.05, tol 1e-6; the
+    same instances one at a time through the plain single-instance path."""
+    n = args.batch
+    Ls = S.batch_layouts(n, 3000)
+    one = A.Solver(20000, 400)
+    mats, aa, bb, descs = [], [], [], []
+    for L in Ls:
+        xy = torch.from_numpy(L.dev_xy).to(dev)
+        rxy = torch.from_numpy(L.rrh_xy).to(dev)
+        d, keep = A.geometry_desc(xy, rxy, L.radio, L.shadow_key, 1.0)
+        d.scale = one.cost_median(d)
+        C = torch.empty((L.I, L.J), dtype=torch.float32, device=dev)
+        one.materialize_cost(d, C)
+        buf = pad_cols(C, L.J)
+        mats.append(buf)
+        descs.append(A.matrix_desc(buf, A.OT_COST_DENSE, J=L.J))
+        aa.append(torch.from_numpy(L.a).to(dev))
+        bb.append(torch.from_numpy(L.b).to(dev))
+    torch.cuda.synchronize()
+    cells = sum(L.I * L.J for L in Ls)
+    log(f"batch set-up: {n} instances, {cells:.3e} cells, {sum(m.numel() for m in mats) * 4 / 1e9:.2f} GB")
+    eps, tol = 0.05, 1e-6
+    bs = A.Solver(16, 16)
+    for _ in range(max(1, args.warmup)):
+        bs.solve_batch(descs, aa, bb, eps, tol, 2000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    K = max(1, args.steps // 2)
+    for _ in range(K):
+        st, res = bs.solve_batch(descs, aa, bb, eps, tol, 2000)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / K
+    iters = np.array([r.iterations for r in res])
+    viol = np.array([r.marginal_violation for r in res])
+    cell_it = sum(L.I * L.J * r.iterations for L, r in zip(Ls, res))
+    log(f"batch: {t_batch * 1e3:.2f} ms for {n} solves = {n / t_batch:.0f} solves/s, iterations "
+        f"{iters.min()}..{iters.max()} (mean {iters.mean():.1f}), max violation {viol.max():.2e}")
+    # the plain path, one instance at a time, same matrices
+    times = []
+    for d, a, b in zip(descs, aa, bb):
+        with A.Solver(d[0].I, d[0].J) as s1:
+            s1.solve(d[0], d[1], a, b, eps, tol, 2000)  # warm-up (graph capture)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s1.solve(d[0], d[1], a, b, eps, tol, 2000)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+    t_plain = float(np.sum(times))
+    log(f"plain one at a time: {t_plain * 1e3:.1f} ms = {n / t_plain:.0f} solves/s; batch speed-up {t_plain / t_batch:.1f}x")
+    out = {"workload": f"{n} uneven instances, I~LogU[500,20000], J~LogU[20,400], 1 km, eps={eps}, tol={tol}, "
+                       "dense FP32 costs resident in HBM",
+           "ms_per_batch": t_batch * 1e3, "solves_per_s": n / t_batch, "cells": cells,
+           "cells_per_s": cell_it / t_batch, "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),
+           "max_marginal_violation": float(viol.max()), "status_ok": int(sum(r.status == 0 for r in res)),
+           "plain_ms_total": t_plain * 1e3, "plain_solves_per_s": n / t_plain, "speedup_vs_plain": t_plain / t_batch,
+           "plain_p50_ms": float(np.percentile(times, 50) * 1e3), "plain_p99_ms": float(np.percentile(times, 99) * 1e3)}
+    bs.close()
+    one.close()
+    return out
+
+
+def leg_serve(args, A, S, torch, dev):
+    """Request stream: Poisson arrivals (seed 4000) of association solves for
+    `layouts` layouts x 10 snapshots (5 m drift per step), sizes as the batch,
+    eps 0.02, tol 1e-6, warm starts per layout; open loop at `rate` req/s,
+    then all requests at once (saturated)."""
+    n_lay, n_snap = args.serve_layouts, 10
+    sizes = S.batch_sizes(n_lay, 4100)
+    Ls = [S.make_layout(I, J, 1000.0, seed=4100 + k) for k, (I, J) in enumerate(sizes)]
+    one = A.Solver(20000, 400)
+    reqs = []  # (layout, snapshot, desc, keep, a, b)
+    scales = []
+    for k, L in enumerate(Ls):
+        rxy = torch.from_numpy(L.rrh_xy).to(dev)
+        a = torch.from_numpy(L.a).to(dev)
+        b = torch.from_numpy(L.b).to(dev)
+        pos = S.drift_positions(L, n_snap, 5.0, seed=4200 + k)
+        xy0 = torch.from_numpy(pos[0]).to(dev)
+        d0, _ = A.geometry_desc(xy0, rxy, L.radio, L.shadow_key, 1.0)
+        scale = one.cost_median(d0)
+        scales.append(scale)
+        for t in range(n_snap):
+            xy = torch.from_numpy(pos[t]).to(dev)
+            d, keep = A.geometry_desc(xy, rxy, L.radio, L.shadow_key, scale)
+            reqs.append((k, t, d, (keep, xy, rxy), a, b))
+    one.close()
+    # arrival order: snapshot-major (every layout's snapshot t before t + 1)
+    order = sorted(range(len(reqs)), key=lambda q: (reqs[q][1], reqs[q][0]))
+    arr = S.poisson_arrivals(args.rate, len(order), seed=4000)
+    torch.cuda.synchronize()
+    eps, tol = 0.02, 1e-6
+
+    def run(open_loop):
+        lat, done, warm = [], 0, 0
+        with A.Server() as srv:
+            t0 = srv.now()
+            nxt = 0
+            arrival = {}
+            iters = []
+            while done < len(order):
+                now = srv.now() - t0
+                while nxt < len(order) and (not open_loop or arr[nxt] <= now):
+                    k, t, d, keep, a, b = reqs[order[nxt]]
+                    tk = srv.submit((d, keep), a, b, eps, tol, 2000, layout_key=k + 1, user_tag=order[nxt])
+                    arrival[tk] = t0 + (arr[nxt] if open_loop else 0.0)
+                    nxt += 1
+                q, r, _, _ = srv.counts()
+                if r == 0 and q == 0 and nxt < len(order):
+                    time.sleep(max(0.0, min(1e-3, arr[nxt] - now)))
+                    continue
+                for c in srv.progress():
+                    lat.append(c.t_done - arrival[c.ticket])
+                    iters.append(c.result.iterations)
+                    warm += c.warm
+                    if c.result.status != 0:
+                        log(f"request {c.user_tag}: status {c.result.status}")
+                    done += 1
+            span = srv.now() - t0
+        lat = np.array(lat)
+        return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                    mean_ms=float(lat.mean() * 1e3), solves_per_s=len(order) / span, seconds=span,
+                    warm_started=warm, iterations_mean=float(np.mean(iters)))
+
+    ol = run(True)
+    log(f"serve open loop {args.rate}/s: p50 {ol['p50_ms']:.2f} ms, p99 {ol['p99_ms']:.2f} ms, "
+        f"{ol['warm_started']} warm, {ol['iterations_mean']:.1f} iterations mean")
+    sat = run(False)
+    log(f"serve saturated: {sat['solves_per_s']:.0f} solves/s, p50 {sat['p50_ms']:.1f} ms, p99 {sat['p99_ms']:.1f} ms")
+    # the plain path alone on the first snapshot of every layout (cold)
+    times = []
+    for q in [i for i in order if reqs[i][1] == 0]:
+        k, t, d, keep, a, b = reqs[q]
+        with A.Solver(d.I, d.J) as s1:
+            s1.solve(d, keep, a, b, eps, tol, 2000)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s1.solve(d, keep, a, b, eps, tol, 2000)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+    times = np.array(times)
+    plain = dict(solves_per_s=len(times) / times.sum(), p50_ms=float(np.percentile(times, 50) * 1e3),
+                 p99_ms=float(np.percentile(times, 99) * 1e3))
+    log(f"plain alone: {plain['solves_per_s']:.0f} solves/s, p50 {plain['p50_ms']:.2f} ms")
+    return {"workload": f"Poisson {args.rate}/s, {n_lay} layouts x {n_snap} snapshots (5 m drift), sizes as the "
+                        f"batch, eps={eps}, tol={tol}, geometry costs built at admission, warm starts per layout",
+            "open_loop": ol, "saturated": sat, "plain_alone_cold": plain,
+            "speedup_saturated_vs_plain": sat["solves_per_s"] / plain["solves_per_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +251,11 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=200)
+    ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0 skips it)")
+    ap.add_argument("--serve-layouts", type=int, default=200, help="layouts of the serving leg (0 skips it)")
+    ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the serving leg (requests/s)")
+    ap.add_argument("--only", choices=["all", "main", "batch", "serve"], default="all",
+                    help="run one leg (for profiling): main = the 20000x400 solve and its sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU execution is not part of this build",
@@ -170,24 +336,26 @@ def main():
     del src_buf, dst_buf
     log(f"copy ceiling: {copy_gbps:.0f} GB/s")
 
-    # the same sweep above the 256 MB last-level cache: 200000 x 400 FP32
-    # (320 MB) materialised from a 15 km layout with 16 hot spots
-    LB = S.make_layout(200000, 400, 15000.0, hot_spots=16, hot_share=0.4, seed=2400)
-    big = A.Solver(LB.I, LB.J)
-    xyb = torch.from_numpy(LB.dev_xy).to(dev)
-    rxyb = torch.from_numpy(LB.rrh_xy).to(dev)
-    ab = torch.from_numpy(LB.a).to(dev)
-    bb = torch.from_numpy(LB.b).to(dev)
-    dB, keepB = A.geometry_desc(xyb, rxyb, LB.radio, LB.shadow_key, 1.0)
-    dB.scale = big.cost_median(dB)
-    CB = torch.empty((LB.I, LB.J), dtype=torch.float32, device=dev)
-    big.materialize_cost(dB, CB)
-    _, resB = big.solve_dense(CB, ab, bb, eps, tol, 2000)
-    ms_big = big.time_sweep(max(20, args.sweep_reps // 4), fp64=False)
-    gbps_big = 4.0 * LB.I * LB.J / (ms_big * 1e-3) / 1e9
-    log(f"320 MB sweep: {ms_big * 1e3:.2f} us = {gbps_big:.0f} GB/s ({resB.iterations} iterations to converge)")
-    big.close()
-    del CB
+    ms_big, gbps_big, resB = None, None, None
+    if args.only == "all":
+        # the same sweep above the 256 MB last-level cache: 200000 x 400 FP32
+        # (320 MB) materialised from a 15 km layout with 16 hot spots
+        LB = S.make_layout(200000, 400, 15000.0, hot_spots=16, hot_share=0.4, seed=2400)
+        big = A.Solver(LB.I, LB.J)
+        xyb = torch.from_numpy(LB.dev_xy).to(dev)
+        rxyb = torch.from_numpy(LB.rrh_xy).to(dev)
+        ab = torch.from_numpy(LB.a).to(dev)
+        bb = torch.from_numpy(LB.b).to(dev)
+        dB, keepB = A.geometry_desc(xyb, rxyb, LB.radio, LB.shadow_key, 1.0)
+        dB.scale = big.cost_median(dB)
+        CB = torch.empty((LB.I, LB.J), dtype=torch.float32, device=dev)
+        big.materialize_cost(dB, CB)
+        _, resB = big.solve_dense(CB, ab, bb, eps, tol, 2000)
+        ms_big = big.time_sweep(max(20, args.sweep_reps // 4), fp64=False)
+        gbps_big = 4.0 * LB.I * LB.J / (ms_big * 1e-3) / 1e9
+        log(f"320 MB sweep: {ms_big * 1e3:.2f} us = {gbps_big:.0f} GB/s ({resB.iterations} iterations to converge)")
+        big.close()
+        del CB
 
     cells = I * J
     alg_bytes = 4.0 * cells  # one FP32 read of C per iteration
@@ -218,16 +386,21 @@ def main():
                      "kernel": "k_iter<DenseSrc<float>, fp32 exp> (fused row update + column partials)",
                      "avg_launch_us": ms_sweep * 1e3},
         "copy_gbps": copy_gbps,
-        "sweep_above_llc": {"workload": "200000x400 dense FP32 (320 MB), same kernel", "sweep_us": ms_big * 1e3,
-                            "achieved_gbps": gbps_big, "frac": gbps_big / HBM_PEAK_GBS,
-                            "iterations": resB.iterations, "marginal_violation": resB.marginal_violation},
+        "sweep_above_llc": None if resB is None else {
+            "workload": "200000x400 dense FP32 (320 MB), same kernel", "sweep_us": ms_big * 1e3,
+            "achieved_gbps": gbps_big, "frac": gbps_big / HBM_PEAK_GBS,
+            "iterations": resB.iterations, "marginal_violation": resB.marginal_violation},
         "fp64_sweep_us": ms_sweep64 * 1e3,
         "on_the_fly": {"ms_per_solve": t_geo * 1e3, "cells_per_s": cells * res_g.iterations / t_geo,
                        "iterations": res_g.iterations, "fp64_iterations": res_g.fp64_iterations,
                        "sweep_us": ms_sweep_geo * 1e3, "cells_per_s_sweep": cells / (ms_sweep_geo * 1e-3),
                        "marginal_violation": res_g.marginal_violation},
     }
-    if not args.no_cpu_baseline:
+    if args.only in ("all", "batch") and args.batch > 0:
+        out["batched"] = leg_batch(args, A, S, torch, dev)
+    if args.only in ("all", "serve") and args.serve_layouts > 0:
+        out["serving"] = leg_serve(args, A, S, torch, dev)
+    if not args.no_cpu_baseline and args.only == "all":
         log("cpu baseline (FP64 oracle on host cores) ...")
         cb, acc = cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale)
         out["cpu_baseline"] = cb

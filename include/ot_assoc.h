@@ -217,7 +217,7 @@ const char *ot_assoc_last_error(const ot_assoc *h);
  * iteration counts cost only their own work.
  *
  * Every cost is held as a padded FP32 row-major matrix: a DENSE FP32 matrix in
- * device memory whose row stride (ld, else J) is a multiple of 4 and whose
+ * device memory whose J and row stride (ld, else J) are multiples of 4 and whose
  * base is 16-byte aligned is referenced in place (keep it valid until the
  * next batch on the handle); other DENSE / RATES inputs (host or device, FP32
  * or FP64) are converted, GEOMETRY inputs (device memory; positions read at

@@ -194,18 +194,20 @@ struct BatchEngine {
     Ctl* ctl = nullptr;
     BList L[2]{};
     char* lists_mem = nullptr;
-    BItem* adm_items = nullptr;  // admission staging (device)
-    int* adm_insts = nullptr;
-    // pinned host
+    // admission staging: one block per admission (jobs, pad jobs, host
+    // marginals), pinned on the host and mirrored on the device; two sets
+    // used in turn, so an admission waits only for the one before last
+    char* blob_h[2] = {nullptr, nullptr};
+    char* blob_d[2] = {nullptr, nullptr};
+    size_t blob_cap[2] = {0, 0};
+    int* relay_h = nullptr;  // relayout: slots and item bases
+    int* relay_d = nullptr;
     Ctl* snap[2] = {nullptr, nullptr};
-    BItem* adm_items_h = nullptr;
-    int* adm_insts_h = nullptr;
-    BInst* tab_h = nullptr;  // staging of table entries
-    Ctl* ctl_init_h = nullptr;
-    hipEvent_t ev_snap[2] = {nullptr, nullptr}, ev_adm = nullptr;
-    bool adm_pending = false;
-    char* hstage = nullptr;  // marginals and constants of the pending admission
-    size_t hstage_cap = 0;
+    hipEvent_t ev_snap[2] = {nullptr, nullptr}, ev_adm[2] = {nullptr, nullptr};
+    bool adm_pending[2] = {false, false};
+    int adm_set = 0;  // staging set of the next admission
+    ot_status wait_staging(int set);
+    ot_status ensure_blob(int set, size_t bytes);
 
     std::vector<Slot> slots;
     std::vector<int> free_slots;
@@ -237,7 +239,7 @@ struct BatchEngine {
     ot_status prepare_kernels();
     ot_status capture(int widx);
     ot_status admit(const std::vector<AdmitReq>& reqs, std::vector<int>& out_slots, bool strict);
-    ot_status upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage);
+    ot_status upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage, PadJob* pad);
     ot_status launch_chunk();
     ot_status collect(bool wait, std::vector<int>& finished);
     ot_status drain_snapshot(std::vector<int>* finished);
@@ -271,13 +273,13 @@ BatchEngine::~BatchEngine() {
     if (stream) hipStreamSynchronize(stream);
     for (auto g : graph)
         if (g) hipGraphExecDestroy(g);
-    void* dev_bufs[] = {tab, ctl, lists_mem, adm_items, adm_insts};
+    void* dev_bufs[] = {tab, ctl, lists_mem, blob_d[0], blob_d[1], relay_d};
     for (void* p : dev_bufs)
         if (p) hipFree(p);
-    void* host_bufs[] = {snap[0], snap[1], adm_items_h, adm_insts_h, tab_h, ctl_init_h, hstage};
+    void* host_bufs[] = {snap[0], snap[1], blob_h[0], blob_h[1], relay_h};
     for (void* p : host_bufs)
         if (p) hipHostFree(p);
-    hipEvent_t evs[] = {ev_snap[0], ev_snap[1], ev_adm};
+    hipEvent_t evs[] = {ev_snap[0], ev_snap[1], ev_adm[0], ev_adm[1]};
     for (auto e : evs)
         if (e) hipEventDestroy(e);
     if (helper) ot_assoc_destroy(helper);
@@ -315,15 +317,11 @@ ot_status BatchEngine::init(int dev, hipStream_t st, int slots_cap, int items_ca
         L[g].cnt = (int*)(p + 2 * item_bytes + inst_bytes);
     }
     ECHK(this, hipMemsetAsync(lists_mem, 0, 2 * gen_bytes, stream));
-    ECHK(this, hipMalloc(&adm_items, sizeof(BItem) * (size_t)cap_items));
-    ECHK(this, hipMalloc(&adm_insts, sizeof(int) * cap_slots));
+    for (int q = 0; q < 2; ++q) ECHK(this, hipEventCreateWithFlags(&ev_adm[q], hipEventDisableTiming));
+    ECHK(this, hipHostMalloc(&relay_h, sizeof(int) * 2 * cap_slots));
+    ECHK(this, hipMalloc(&relay_d, sizeof(int) * 2 * cap_slots));
     for (auto& s : snap) ECHK(this, hipHostMalloc(&s, sizeof(Ctl) * cap_slots));
-    ECHK(this, hipHostMalloc(&adm_items_h, sizeof(BItem) * (size_t)cap_items));
-    ECHK(this, hipHostMalloc(&adm_insts_h, sizeof(int) * cap_slots));
-    ECHK(this, hipHostMalloc(&tab_h, sizeof(BInst) * cap_slots));
-    ECHK(this, hipHostMalloc(&ctl_init_h, sizeof(Ctl) * cap_slots));
     for (auto& e : ev_snap) ECHK(this, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    ECHK(this, hipEventCreateWithFlags(&ev_adm, hipEventDisableTiming));
     slots.assign(cap_slots, Slot{});
     free_slots.clear();
     for (int q = cap_slots - 1; q >= 0; --q) free_slots.push_back(q);
@@ -336,7 +334,7 @@ ot_status BatchEngine::init(int dev, hipStream_t st, int slots_cap, int items_ca
 static size_t bsweep_lds(bool p64, int w) {
     const size_t ncols = 512;
     const size_t a = sizeof(double) * (ncols + ncols / 2);
-    const size_t red = (p64 ? 8 : 4) * (size_t)w * 4 * 256;  // LPR 16: R = 4 rows, 256 columns
+    const size_t red = (p64 ? 8 : 4) * (size_t)w * 4 * 256;  // LPR 16: R = 4 rows, up to 256 columns
     const size_t red32 = (p64 ? 8 : 4) * (size_t)w * 2 * 512;  // LPR 32: R = 2 rows, 512 columns
     const size_t chk = sizeof(double) * (size_t)(w / 2) * 2 * 64 * 4;
     return std::max({a, red, red32, chk});
@@ -374,9 +372,15 @@ ot_status BatchEngine::capture(int wi) {
     for (int t = 0; t < kChunk; ++t) {
         const BList& in = L[t & 1];
         const BList& out = L[(t + 1) & 1];
-        if (wi == 0) hipLaunchKernelGGL((k_bsweep<false, 4>), dim3(grid32[0]), dim3(256), lds32[0], stream, tab, in, out);
-        else hipLaunchKernelGGL((k_bsweep<false, 8>), dim3(grid32[1]), dim3(512), lds32[1], stream, tab, in, out);
-        hipLaunchKernelGGL((k_bsweep<true, 8>), dim3(grid64), dim3(512), lds64, stream, tab, in, out);
+        const BInst* T = tab;
+        if (wi == 0)
+            hipLaunchKernelGGL((k_bsweep<false, 4>), dim3(grid32[0]), dim3(256), lds32[0], stream, T,
+                               (const BItem*)in.it32, (const int*)in.cnt, out.cnt);
+        else
+            hipLaunchKernelGGL((k_bsweep<false, 8>), dim3(grid32[1]), dim3(512), lds32[1], stream, T,
+                               (const BItem*)in.it32, (const int*)in.cnt, out.cnt);
+        hipLaunchKernelGGL((k_bsweep<true, 8>), dim3(grid64), dim3(512), lds64, stream, T, (const BItem*)in.it64,
+                           (const int*)in.cnt, out.cnt);
         hipLaunchKernelGGL(k_bcombine, dim3(gridc), dim3(1024), 0, stream, tab, in, out, P);
     }
     hipError_t e1 = hipStreamEndCapture(stream, &g);
@@ -401,12 +405,12 @@ static size_t slot_bytes(int64_t I, int J, int64_t ld, int parts_cap, bool own_c
 
 static int64_t parts_of(int64_t I, int64_t rpp) { return (I + rpp - 1) / rpp; }
 
-ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage) {
+ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage, PadJob* pad) {
     const int64_t I = s.I;
     const int J = s.J;
     const int64_t ld = s.ld;
     float* dst = (float*)C_mem;
-    const unsigned grid = (unsigned)std::min<int64_t>(4096, (I * ld + 255) / 256);
+    pad->src = nullptr;
     if (c->kind == OT_COST_GEOMETRY) {
         double scale = c->scale;
         if (!(scale > 0.0)) {
@@ -451,6 +455,7 @@ ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, 
         ECHK(this, hipGetLastError());
         return OT_OK;
     }
+    // dense or rate matrices: a padded-copy job, run for the whole admission
     const size_t esz = c->dtype == OT_F32 ? 4 : 8;
     const int64_t lds = c->ld ? c->ld : J;
     const void* src = c->data;
@@ -458,41 +463,18 @@ ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, 
         ECHK(this, hipMemcpyAsync(stage, c->data, esz * (size_t)(I * lds), hipMemcpyHostToDevice, stream));
         src = stage;
     }
-    const double inv = c->kind == OT_COST_RATES ? 1.0 / c->scale : 1.0;
-    if (c->kind == OT_COST_DENSE) {
-        if (c->dtype == OT_F32)
-            hipLaunchKernelGGL((k_bpad<float, 0>), dim3(grid), dim3(256), 0, stream, (const float*)src, I, J, lds, dst, ld, inv);
-        else
-            hipLaunchKernelGGL((k_bpad<double, 0>), dim3(grid), dim3(256), 0, stream, (const double*)src, I, J, lds, dst, ld, inv);
-    } else {
-        if (c->dtype == OT_F32)
-            hipLaunchKernelGGL((k_bpad<float, 1>), dim3(grid), dim3(256), 0, stream, (const float*)src, I, J, lds, dst, ld, inv);
-        else
-            hipLaunchKernelGGL((k_bpad<double, 1>), dim3(grid), dim3(256), 0, stream, (const double*)src, I, J, lds, dst, ld, inv);
-    }
+    pad->src = src;
+    pad->dst = dst;
+    pad->I = I;
+    pad->lds = lds;
+    pad->ld = ld;
+    pad->inv_scale = c->kind == OT_COST_RATES ? 1.0 / c->scale : 1.0;
+    pad->J = J;
+    pad->kind = c->kind == OT_COST_RATES ? 1 : 0;
+    pad->f64 = c->dtype == OT_F64 ? 1 : 0;
     return OT_OK;
 }
 
-static ot_status read_host(BatchEngine* e, const double* p, int64_t n, ot_mem mem, std::vector<double>& out) {
-    out.resize((size_t)n);
-    if (mem == OT_MEM_HOST) {
-        std::memcpy(out.data(), p, sizeof(double) * n);
-        return OT_OK;
-    }
-    ECHK(e, hipMemcpyAsync(out.data(), p, sizeof(double) * n, hipMemcpyDeviceToHost, e->stream));
-    ECHK(e, hipStreamSynchronize(e->stream));
-    return OT_OK;
-}
-
-static double ksum(const std::vector<double>& v) {
-    double s = 0.0, c = 0.0;
-    for (double x : v) {
-        const double t = s + x;
-        c += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
-        s = t;
-    }
-    return s + c;
-}
 
 static ot_status check_desc(BatchEngine* e, const ot_cost_desc* c) {
     if (!c) return e->fail(OT_EINVAL, "cost descriptor is NULL");
@@ -521,13 +503,13 @@ static ot_status check_desc(BatchEngine* e, const ot_cost_desc* c) {
 
 // Admits the requests in order. strict: every request must fit now (else
 // OT_ENOMEM and nothing is admitted); otherwise admits the longest prefix
-// that fits and reports the admitted slots.
+// that fits and reports the admitted slots. Settings are checked here,
+// marginal values on the device, so admission never waits on the GPU beyond
+// the staging set of the admission before last.
 ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>& out_slots, bool strict) {
     out_slots.clear();
     if (reqs.empty()) return OT_OK;
     ECHK(this, hipSetDevice(device));
-    // validate everything first
-    std::vector<std::vector<double>> ah(reqs.size()), bh(reqs.size());
     for (size_t q = 0; q < reqs.size(); ++q) {
         const AdmitReq& r = reqs[q];
         if (ot_status st = check_desc(this, r.cost)) return st;
@@ -535,36 +517,33 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         if (!(r.eps > 0.0) || !std::isfinite(r.eps)) return fail(OT_EINVAL, "eps must be positive and finite");
         if (!(r.tol >= 0.0) || !std::isfinite(r.tol)) return fail(OT_EINVAL, "tol must be >= 0");
         if (r.max_iter < 1) return fail(OT_EINVAL, "max_iter must be >= 1");
-        const ot_mem m = r.cost->kind == OT_COST_GEOMETRY ? OT_MEM_DEVICE : r.cost->mem;
-        if (ot_status st = read_host(this, r.a, r.cost->I, m, ah[q])) return st;
-        if (ot_status st = read_host(this, r.b, r.cost->J, m, bh[q])) return st;
-        for (double v : ah[q])
-            if (!(v > 0.0) || !std::isfinite(v)) return fail(OT_EINVAL, "instance %zu: a must be positive and finite", q);
-        for (double v : bh[q])
-            if (!(v > 0.0) || !std::isfinite(v)) return fail(OT_EINVAL, "instance %zu: b must be positive and finite", q);
-        const double sa = ksum(ah[q]), sb = ksum(bh[q]);
-        if (std::fabs(sa - sb) > 1e-12 * sa) return fail(OT_EINVAL, "instance %zu: unbalanced marginals", q);
     }
-    // the staging buffers of the previous admission must have been consumed
-    if (adm_pending) {
-        ECHK(this, hipEventSynchronize(ev_adm));
-        adm_pending = false;
-    }
-    // pinned staging of the marginals and solve constants (async copies)
-    size_t hbytes = 0;
-    for (auto& r : reqs) hbytes += sizeof(double) * (r.cost->I + r.cost->J) + sizeof(SolveParams);
-    if (hbytes > hstage_cap) {
-        if (hstage) hipHostFree(hstage);
-        hstage = nullptr;
-        hstage_cap = 0;
-        ECHK(this, hipHostMalloc(&hstage, hbytes));
-        hstage_cap = hbytes;
-    }
-    char* hp = hstage;
-    int n_items = 0;
-    int n_insts = 0;
+    const int set = adm_set;
+    if (ot_status st = wait_staging(set)) return st;
+    // staging block: [AdmJob x n][PadJob x n][host marginals]
+    const size_t n = reqs.size();
+    const size_t jobs_b = align_up(sizeof(AdmJob) * n), pads_b = align_up(sizeof(PadJob) * n);
+    size_t marg_b = 0;
+    for (auto& r : reqs)
+        if (r.cost->kind != OT_COST_GEOMETRY && r.cost->mem == OT_MEM_HOST)
+            marg_b += align_up(sizeof(double) * r.cost->I) + align_up(sizeof(double) * r.cost->J);
+    if (ot_status st = ensure_blob(set, jobs_b + pads_b + marg_b)) return st;
+    AdmJob* jobs_h = (AdmJob*)blob_h[set];
+    PadJob* pads_h = (PadJob*)(blob_h[set] + jobs_b);
+    char* marg_h = blob_h[set] + jobs_b + pads_b;
+    char* marg_d = blob_d[set] + jobs_b + pads_b;
+    int n_items = 0, n_insts = 0, n_pads = 0;
+    std::vector<char*> stages;
+    auto undo = [&]() {
+        for (char* x : stages) pool.release(x);
+        for (int k : out_slots) {
+            slots[k].finished = true;  // never counted as running
+            release(k);
+        }
+        out_slots.clear();
+    };
     const int64_t rpp = rpp_rows;
-    for (size_t q = 0; q < reqs.size(); ++q) {
+    for (size_t q = 0; q < n; ++q) {
         const AdmitReq& r = reqs[q];
         const ot_cost_desc* c = r.cost;
         const int64_t I = c->I;
@@ -572,15 +551,18 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         const int parts_cap = (int)parts_of(I, 64);  // the finest layout the tuner may choose
         const int parts = (int)parts_of(I, rpp);
         const int64_t lds = c->ld ? c->ld : J;
-        const bool ref = c->kind == OT_COST_DENSE && c->mem == OT_MEM_DEVICE && c->dtype == OT_F32 && lds % 4 == 0 &&
-                         ((uintptr_t)c->data % 16) == 0;
+        const bool ref = c->kind == OT_COST_DENSE && c->mem == OT_MEM_DEVICE && c->dtype == OT_F32 && J % 4 == 0 &&
+                         lds % 4 == 0 && ((uintptr_t)c->data % 16) == 0;
         const int64_t ld = ref ? lds : (J + 3) / 4 * 4;
         if (free_slots.empty() || items_running + n_items + parts > cap_items) {
-            if (strict) return fail(OT_ENOMEM, "batch exceeds %d slots / %d work items", cap_slots, cap_items);
+            if (strict) {
+                undo();
+                return fail(OT_ENOMEM, "batch exceeds %d slots / %d work items", cap_slots, cap_items);
+            }
             break;
         }
-        // staging for host inputs and for padding a materialised geometry
-        // cost; released once the conversion is queued (stream order)
+        // staging for host cost matrices and for the geometry set-up pass;
+        // released once the work reading it is queued (stream order)
         const size_t esz = c->dtype == OT_F64 ? 8 : 4;
         size_t stage_b = 0;
         if (!ref && c->kind != OT_COST_GEOMETRY && c->mem == OT_MEM_HOST) stage_b = esz * (size_t)(I * lds);
@@ -590,32 +572,31 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         if (!mem) {
             if (stage) pool.release(stage);
             if (strict) {
-                for (int k : out_slots) release(k);
-                out_slots.clear();
+                undo();
                 return fail(OT_ENOMEM, "batch exceeds the device memory budget (%.3g GB)", pool.budget / 1e9);
             }
             break;
         }
+        if (stage) stages.push_back(stage);
         const int k = free_slots.back();
         free_slots.pop_back();
         hi_slot = std::max(hi_slot, k + 1);
-        Slot& s = slots[k];
-        s = Slot{};
-        s.live = true;
-        s.I = I;
-        s.J = J;
-        s.ld = ld;
-        s.parts_cap = parts_cap;
-        s.mem = mem;
-        s.eps = r.eps;
-        s.mass = ksum(ah[q]);
+        Slot& sl = slots[k];
+        sl = Slot{};
+        sl.live = true;
+        sl.I = I;
+        sl.J = J;
+        sl.ld = ld;
+        sl.parts_cap = parts_cap;
+        sl.mem = mem;
+        sl.eps = r.eps;
         char* p = mem;
         auto carve = [&](size_t bytes) {
             char* x = p;
             p += align_up(bytes);
             return x;
         };
-        BInst& d = s.d;
+        BInst& d = sl.d;
         char* C_mem = ref ? nullptr : carve(sizeof(float) * (size_t)I * ld);
         d.C = ref ? (const float*)c->data : (const float*)C_mem;
         d.ld = ld;
@@ -626,10 +607,8 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         d.nchk = (J + 255) / 256;
         d.parts = parts;
         d.rpp = rpp;
-        double* a_d = (double*)carve(sizeof(double) * I);
-        double* b_d = (double*)carve(sizeof(double) * J);
-        d.a = a_d;
-        d.b = b_d;
+        d.a = (double*)carve(sizeof(double) * I);
+        d.b = (double*)carve(sizeof(double) * J);
         d.f[0] = (double*)carve(sizeof(double) * I);
         d.f[1] = (double*)carve(sizeof(double) * I);
         d.g[0] = (double*)carve(sizeof(double) * J);
@@ -637,68 +616,94 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         d.col_part = (double*)carve(sizeof(double) * (size_t)parts_cap * J);
         d.res_part = (double*)carve(sizeof(double) * parts_cap);
         d.stat_part = (double*)carve(sizeof(double) * (size_t)parts_cap * 5);
-        s.prm = (SolveParams*)carve(sizeof(SolveParams));
+        sl.prm = (SolveParams*)carve(sizeof(SolveParams));
         d.ctl = ctl + k;
         d.kk = std::log2(std::exp(1.0)) / r.eps;
         d.eps = r.eps;
+        out_slots.push_back(k);
         if (!ref) {
-            ot_status st = upload_cost(s, c, C_mem, stage);
-            if (stage) pool.release(stage);
+            PadJob pj{};
+            ot_status st = upload_cost(sl, c, C_mem, stage, &pj);
             if (st) {
-                release(k);
-                for (int kk : out_slots) release(kk);
-                out_slots.clear();
+                undo();
                 return st;
             }
+            if (pj.src) pads_h[n_pads++] = pj;
         }
-        std::memcpy(hp, ah[q].data(), sizeof(double) * I);
-        ECHK(this, hipMemcpyAsync(a_d, hp, sizeof(double) * I, hipMemcpyHostToDevice, stream));
-        hp += sizeof(double) * I;
-        std::memcpy(hp, bh[q].data(), sizeof(double) * J);
-        ECHK(this, hipMemcpyAsync(b_d, hp, sizeof(double) * J, hipMemcpyHostToDevice, stream));
-        hp += sizeof(double) * J;
-        const bool warm = r.f0 && r.g0;
-        if (warm) {
-            ECHK(this, hipMemcpyAsync(d.f[0], r.f0, sizeof(double) * I, hipMemcpyDeviceToDevice, stream));
-            ECHK(this, hipMemcpyAsync(d.g[0], r.g0, sizeof(double) * J, hipMemcpyDeviceToDevice, stream));
+        AdmJob& J1 = jobs_h[n_insts];
+        J1 = AdmJob{};
+        J1.d = d;
+        J1.sp = SolveParams{d.kk, d.eps};
+        J1.prm_dst = sl.prm;
+        if (c->kind != OT_COST_GEOMETRY && c->mem == OT_MEM_HOST) {
+            std::memcpy(marg_h, r.a, sizeof(double) * I);
+            J1.a_src = (const double*)marg_d;
+            marg_h += align_up(sizeof(double) * I);
+            marg_d += align_up(sizeof(double) * I);
+            std::memcpy(marg_h, r.b, sizeof(double) * J);
+            J1.b_src = (const double*)marg_d;
+            marg_h += align_up(sizeof(double) * J);
+            marg_d += align_up(sizeof(double) * J);
         } else {
-            ECHK(this, hipMemsetAsync(d.g[0], 0, sizeof(double) * J, stream));
+            J1.a_src = r.a;
+            J1.b_src = r.b;
         }
-        const SolveParams sp{d.kk, d.eps};
-        Ctl ci{};
+        const bool warm = r.f0 && r.g0;
+        J1.f0 = warm ? r.f0 : nullptr;
+        J1.g0 = warm ? r.g0 : nullptr;
+        Ctl& ci = J1.ci;
         ci.has_prev = warm ? 1 : 0;
         ci.max_iter = r.max_iter;
         ci.tol = r.tol;
-        ci.mass = s.mass;
         ci.r_last = __builtin_huge_val();
         for (double& x : ci.r_hist) x = __builtin_huge_val();
         ci.phase = kPhFast;
-        // stage the table entry, control block and solve constants
-        tab_h[k] = d;
-        ctl_init_h[k] = ci;
-        ECHK(this, hipMemcpyAsync(tab + k, tab_h + k, sizeof(BInst), hipMemcpyHostToDevice, stream));
-        ECHK(this, hipMemcpyAsync(ctl + k, ctl_init_h + k, sizeof(Ctl), hipMemcpyHostToDevice, stream));
-        std::memcpy(&s.fin, &ci, sizeof ci);
-        std::memcpy(hp, &sp, sizeof sp);
-        ECHK(this, hipMemcpyAsync(s.prm, hp, sizeof sp, hipMemcpyHostToDevice, stream));
-        hp += sizeof sp;
-        for (int pq = 0; pq < parts; ++pq) adm_items_h[n_items + pq] = BItem{k, pq, warm ? kItPrev : 0, 0};
+        sl.fin = ci;
+        J1.slot = k;
+        J1.item_base = n_items;
+        J1.inst_pos = n_insts;
         n_items += parts;
-        adm_insts_h[n_insts++] = k;
-        s.t_admit = now_s();
-        s.adm_seq = seq;
-        items_running += parts;
-        out_slots.push_back(k);
+        ++n_insts;
+        sl.t_admit = now_s();
+        sl.adm_seq = seq;
     }
     if (n_insts) {
-        ECHK(this, hipMemcpyAsync(adm_items, adm_items_h, sizeof(BItem) * n_items, hipMemcpyHostToDevice, stream));
-        ECHK(this, hipMemcpyAsync(adm_insts, adm_insts_h, sizeof(int) * n_insts, hipMemcpyHostToDevice, stream));
-        hipLaunchKernelGGL(k_badmit, dim3(1), dim3(256), 0, stream, L[0], (const BItem*)adm_items, n_items,
-                           (const int*)adm_insts, n_insts);
+        const size_t used = (size_t)(marg_h - blob_h[set]);
+        ECHK(this, hipMemcpyAsync(blob_d[set], blob_h[set], used, hipMemcpyHostToDevice, stream));
+        if (n_pads)
+            hipLaunchKernelGGL(k_bpad_jobs, dim3(64, n_pads), dim3(256), 0, stream,
+                               (const PadJob*)(blob_d[set] + jobs_b));
+        hipLaunchKernelGGL(k_badmit_jobs, dim3(n_insts), dim3(256), 0, stream, (const AdmJob*)blob_d[set], tab, ctl,
+                           L[0]);
+        hipLaunchKernelGGL(k_bcount, dim3(1), dim3(64), 0, stream, L[0], n_items, n_insts);
         ECHK(this, hipGetLastError());
-        ECHK(this, hipEventRecord(ev_adm, stream));
-        adm_pending = true;
+        ECHK(this, hipEventRecord(ev_adm[set], stream));
+        adm_pending[set] = true;
+        adm_set ^= 1;
         n_live_running += n_insts;
+        items_running += n_items;
+    }
+    for (char* x : stages) pool.release(x);
+    return OT_OK;
+}
+
+ot_status BatchEngine::ensure_blob(int set, size_t bytes) {
+    if (blob_cap[set] >= bytes) return OT_OK;
+    if (blob_h[set]) hipHostFree(blob_h[set]);
+    if (blob_d[set]) hipFree(blob_d[set]);
+    blob_h[set] = blob_d[set] = nullptr;
+    blob_cap[set] = 0;
+    const size_t cap = std::max(bytes, (size_t)1 << 20);
+    ECHK(this, hipHostMalloc(&blob_h[set], cap));
+    ECHK(this, hipMalloc(&blob_d[set], cap));
+    blob_cap[set] = cap;
+    return OT_OK;
+}
+
+ot_status BatchEngine::wait_staging(int set) {
+    if (adm_pending[set]) {
+        ECHK(this, hipEventSynchronize(ev_adm[set]));
+        adm_pending[set] = false;
     }
     return OT_OK;
 }
@@ -769,31 +774,27 @@ ot_status BatchEngine::drain_snapshot(std::vector<int>* finished) {
 // Rebuilds the parts of the given (not yet started) instances for another
 // rows-per-part value and re-queues their first sweep items.
 ot_status BatchEngine::relayout(const std::vector<int>& ks, int w, int64_t rpp) {
-    if (adm_pending) {  // the staging below is still being read by the admission's copies
-        ECHK(this, hipEventSynchronize(ev_adm));
-        adm_pending = false;
-    }
+    for (int q = 0; q < 2; ++q)  // the relayout staging is reused only after admissions have landed
+        if (ot_status st = wait_staging(q)) return st;
     waves = w;
     rpp_rows = rpp;
     int n_items = 0;
-    for (int k : ks) {
-        Slot& s = slots[k];
+    const int n = (int)ks.size();
+    for (int q = 0; q < n; ++q) {
+        Slot& s = slots[ks[q]];
         items_running -= s.d.parts;
         s.d.rpp = rpp;
         s.d.parts = (int)parts_of(s.I, rpp);
         items_running += s.d.parts;
-        tab_h[k] = s.d;
-        ECHK(this, hipMemcpyAsync(tab + k, tab_h + k, sizeof(BInst), hipMemcpyHostToDevice, stream));
-        const int fl = ctl_init_h[k].has_prev ? kItPrev : 0;
-        for (int pq = 0; pq < s.d.parts; ++pq) adm_items_h[n_items + pq] = BItem{k, pq, fl, 0};
+        relay_h[q] = ks[q];
+        relay_h[n + q] = n_items;
         n_items += s.d.parts;
     }
-    for (size_t q = 0; q < ks.size(); ++q) adm_insts_h[q] = ks[q];
-    ECHK(this, hipMemcpyAsync(adm_items, adm_items_h, sizeof(BItem) * n_items, hipMemcpyHostToDevice, stream));
-    ECHK(this, hipMemcpyAsync(adm_insts, adm_insts_h, sizeof(int) * ks.size(), hipMemcpyHostToDevice, stream));
+    ECHK(this, hipMemcpyAsync(relay_d, relay_h, sizeof(int) * 2 * n, hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(k_bclear, dim3(1), dim3(64), 0, stream, L[0]);
-    hipLaunchKernelGGL(k_badmit, dim3(1), dim3(256), 0, stream, L[0], (const BItem*)adm_items, n_items,
-                       (const int*)adm_insts, (int)ks.size());
+    hipLaunchKernelGGL(k_brelayout, dim3(n), dim3(256), 0, stream, tab, (const int*)relay_d,
+                       (const int*)(relay_d + n), rpp, L[0]);
+    hipLaunchKernelGGL(k_bcount, dim3(1), dim3(64), 0, stream, L[0], n_items, n);
     ECHK(this, hipGetLastError());
     ECHK(this, hipStreamSynchronize(stream));
     return OT_OK;
@@ -823,8 +824,13 @@ ot_status BatchEngine::tune(const std::vector<int>& ks) {
             if ((st = relayout(ks, w, rpp))) break;
             const int wi = w == 4 ? 0 : 1;
             auto launch = [&]() {
-                if (wi == 0) hipLaunchKernelGGL((k_bsweep<false, 4>), dim3(grid32[0]), dim3(256), lds32[0], stream, tab, L[0], L[1]);
-                else hipLaunchKernelGGL((k_bsweep<false, 8>), dim3(grid32[1]), dim3(512), lds32[1], stream, tab, L[0], L[1]);
+                const BInst* T = tab;
+                if (wi == 0)
+                    hipLaunchKernelGGL((k_bsweep<false, 4>), dim3(grid32[0]), dim3(256), lds32[0], stream, T,
+                                       (const BItem*)L[0].it32, (const int*)L[0].cnt, L[1].cnt);
+                else
+                    hipLaunchKernelGGL((k_bsweep<false, 8>), dim3(grid32[1]), dim3(512), lds32[1], stream, T,
+                                       (const BItem*)L[0].it32, (const int*)L[0].cnt, L[1].cnt);
             };
             launch();  // warm-up
             hipEventRecord(e0, stream);
@@ -847,7 +853,8 @@ ot_status BatchEngine::tune(const std::vector<int>& ks) {
 static void fill_result(const Slot& s, ot_assoc_result* r) {
     const Ctl& c = s.fin;
     ot_status rs = OT_OK;
-    if (c.numeric_bad || !std::isfinite(c.chk_violation)) rs = OT_ENUMERIC;
+    if (c.numeric_bad == 2) rs = OT_EINVAL;  // marginals rejected on the device
+    else if (c.numeric_bad || !std::isfinite(c.chk_violation)) rs = OT_ENUMERIC;
     else if (!(c.chk_violation < c.tol)) rs = OT_WARN_MAXITER;
     r->iterations = c.result_iter;
     r->fp64_iterations = c.fp64_iters;
@@ -981,6 +988,24 @@ ot_status ot_assoc_solve_batch(ot_assoc* h, int n, const ot_cost_desc* costs, co
     hipEventCreate(&e1);
     std::vector<int> ks;
     ot_status st = e->admit(reqs, ks, true);
+    if (!st) {
+        // marginals were checked on the device: one wait for all of them
+        std::vector<Ctl> cs(ks.size());
+        for (size_t q = 0; q < ks.size() && !st; ++q)
+            if (hipMemcpyAsync(&cs[q], e->ctl + ks[q], sizeof(Ctl), hipMemcpyDeviceToHost, e->stream) != hipSuccess)
+                st = e->fail(OT_EDEVICE, "control block read failed");
+        if (!st && hipStreamSynchronize(e->stream) != hipSuccess) st = e->fail(OT_EDEVICE, "admission failed");
+        for (size_t q = 0; q < ks.size() && !st; ++q)
+            if (cs[q].numeric_bad == 2)
+                st = e->fail(OT_EINVAL, "instance %zu: marginals must be positive, finite and balanced", q);
+        if (st) {
+            h->err = e->err;
+            for (int k : ks) e->release(k);
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return st;
+        }
+    }
     if (!st && h->opt.batch_tune) st = e->tune(ks);
     if (!st && !h->opt.batch_tune) st = e->relayout(ks, 8, 128);
     if (!st) {

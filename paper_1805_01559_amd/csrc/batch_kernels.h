@@ -70,7 +70,10 @@ struct BParams {
     double stall_below;
 };
 
-// Column classes: (lanes per row, column chunks of 4 FP32 values per lane).
+// Column classes: (lanes per row, column chunks of 4 FP32 values per lane):
+// (16, 1), (16, 2), (16, 4), (32, 4) for J up to 64, 128, 256, 512. The one
+// kernel that holds every class stays within the register budget of
+// 3 waves per SIMD.
 __host__ __device__ constexpr int batch_class(int J) { return J <= 64 ? 0 : J <= 128 ? 1 : J <= 256 ? 2 : 3; }
 __host__ __device__ constexpr int batch_class_lpr(int cls) { return cls == 3 ? 32 : 16; }
 __host__ __device__ constexpr int batch_class_nch(int cls) { return cls == 0 ? 1 : cls == 1 ? 2 : 4; }
@@ -105,12 +108,15 @@ __device__ __forceinline__ void batch_sweep_item(const BInst& d, const BItem& it
 // Persistent sweep over the FP32 (P64 = false) or FP64 (P64 = true) list.
 // The FP32 kernel also clears the counters of the next generation, which
 // nothing reads or writes before the combine kernel of this iteration.
+// (the table, the list and its counter are read-only here and marked so:
+// their uniform loads then go through the scalar unit into SGPRs)
 template <bool P64, int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) void k_bsweep(const BInst* tab, BList in, BList out) {
+__global__ __launch_bounds__(WAVES * kWave) void k_bsweep(const BInst* __restrict__ tab,
+                                                          const BItem* __restrict__ items,
+                                                          const int* __restrict__ cnt_in, int* __restrict__ cnt_out) {
     extern __shared__ double sm[];
-    if (!P64 && blockIdx.x == 0 && threadIdx.x < 3) out.cnt[threadIdx.x] = 0;
-    const int n = in.cnt[P64 ? 1 : 0];
-    const BItem* items = P64 ? in.it64 : in.it32;
+    if (!P64 && blockIdx.x == 0 && threadIdx.x < 3) cnt_out[threadIdx.x] = 0;
+    const int n = cnt_in[P64 ? 1 : 0];
     for (int q = blockIdx.x; q < n; q += gridDim.x) {
         const BItem it = items[q];
         const BInst& d = tab[it.inst];
@@ -150,6 +156,7 @@ __global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, B
         const BInst& d = tab[k];
         Ctl* ctl = d.ctl;
         const int phase = ctl->phase;
+        if (phase == kPhDone) continue;  // rejected at admission: no work, no next items (uniform)
         const bool check = phase == kPhCheck;
         const int J = d.J, parts = d.parts;
         const int pin = check ? (ctl->check_iter & 1) : (ctl->iter & 1);
@@ -273,20 +280,110 @@ __global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, B
     }
 }
 
-// Appends admitted instances (their first FP32 sweep items) to a list
-// generation that no kernel is using (stream order puts it between chunks).
-__global__ __launch_bounds__(256) void k_badmit(BList l, const BItem* items, int n_items, const int* insts,
-                                                 int n_insts) {
-    __shared__ int s_bi, s_bk;
-    if (threadIdx.x == 0) {
-        s_bi = l.cnt[0];
-        s_bk = l.cnt[2];
-        l.cnt[0] = s_bi + n_items;
-        l.cnt[2] = s_bk + n_insts;
-    }
+// Everything one admitted instance needs on the device, staged by the host
+// in one block for the whole admission.
+struct AdmJob {
+    BInst d;
+    Ctl ci;
+    SolveParams sp;
+    SolveParams* prm_dst;
+    const double* a_src;  // marginals to copy into d.a / d.b
+    const double* b_src;
+    const double* f0;  // warm start (with g0) or null
+    const double* g0;
+    int slot;
+    int item_base;  // offset of its items among this admission's items
+    int inst_pos;   // position among this admission's instances
+    int pad_;
+};
+
+// One workgroup per admitted instance: copies and checks its marginals
+// (a_i > 0 and b_j > 0 finite, |sum a - sum b| <= 1e-12 sum a), sets up its
+// starting potentials, writes its table entry, control block (mass = sum a;
+// an instance that fails the checks is marked done with numeric_bad = 2
+// before any work runs) and constants, and appends its first sweep items to a
+// list generation that no kernel is using. The list counters move afterwards
+// (k_bcount), so every workgroup reads the same base.
+__global__ __launch_bounds__(256) void k_badmit_jobs(const AdmJob* __restrict__ jobs, BInst* tab, Ctl* ctls,
+                                                     BList l) {
+    const AdmJob& J = jobs[blockIdx.x];
+    const BInst& d = J.d;
+    double* a = const_cast<double*>(d.a);
+    double* b = const_cast<double*>(d.b);
+    __shared__ double red[4][2];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
     __syncthreads();
-    for (int q = threadIdx.x; q < n_items; q += blockDim.x) l.it32[s_bi + q] = items[q];
-    for (int q = threadIdx.x; q < n_insts; q += blockDim.x) l.inst[s_bk + q] = insts[q];
+    double sa = 0.0, sb = 0.0;
+    int flag = 0;
+    for (int64_t i = threadIdx.x; i < d.I; i += blockDim.x) {
+        const double v = J.a_src[i];
+        a[i] = v;
+        flag |= !(v > 0.0 && isfinite(v));
+        sa += v;
+        if (J.f0) d.f[0][i] = J.f0[i];
+    }
+    for (int j = threadIdx.x; j < d.J; j += blockDim.x) {
+        const double v = J.b_src[j];
+        b[j] = v;
+        flag |= !(v > 0.0 && isfinite(v));
+        sb += v;
+        d.g[0][j] = J.g0 ? J.g0[j] : 0.0;
+    }
+    if (flag) bad = 1;
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[w][0] = sa;
+        red[w][1] = sb;
+    }
+    const int base = l.cnt[0] + J.item_base;
+    const int flags = J.f0 ? kItPrev : 0;
+    for (int p = threadIdx.x; p < d.parts; p += blockDim.x) l.it32[base + p] = BItem{J.slot, p, flags, 0};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double ta = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+        const double tb = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+        Ctl c = J.ci;
+        c.mass = ta;
+        if (bad || !(fabs(ta - tb) <= 1e-12 * ta)) {
+            c.numeric_bad = 2;
+            c.done = 1;
+            c.phase = kPhDone;
+            c.result_iter = 0;
+            c.chk_violation = __builtin_nan("");
+        }
+        ctls[J.slot] = c;
+        tab[J.slot] = d;
+        *J.prm_dst = J.sp;
+        l.inst[l.cnt[2] + J.inst_pos] = J.slot;
+    }
+}
+
+// Advances the counters of a list generation after appends.
+__global__ void k_bcount(BList l, int n_items, int n_insts) {
+    if (threadIdx.x == 0) {
+        l.cnt[0] += n_items;
+        l.cnt[2] += n_insts;
+    }
+}
+
+// Re-partitions instances that have not started (rows per part rpp) and
+// queues their first sweep items in an emptied list generation.
+__global__ __launch_bounds__(256) void k_brelayout(BInst* tab, const int* __restrict__ slots,
+                                                   const int* __restrict__ bases, int64_t rpp, BList l) {
+    const int k = slots[blockIdx.x];
+    const int64_t I = tab[k].I;
+    const int parts = (int)((I + rpp - 1) / rpp);
+    const int flags = tab[k].ctl->has_prev ? kItPrev : 0;
+    for (int p = threadIdx.x; p < parts; p += blockDim.x) l.it32[bases[blockIdx.x] + p] = BItem{k, p, flags, 0};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        tab[k].rpp = rpp;
+        tab[k].parts = parts;
+        l.inst[blockIdx.x] = k;
+    }
 }
 
 // Clears a list generation (all three counters).
@@ -294,31 +391,32 @@ __global__ void k_bclear(BList l) {
     if (threadIdx.x < 3) l.cnt[threadIdx.x] = 0;
 }
 
-// Padded FP32 copy of a cost source: dst[i ld + j] = cost(i, j) for j < J,
-// +inf for J <= j < ld. KIND 0: dense C; 1: rates, c = inv_scale / R.
-template <typename T, int KIND>
-__global__ void k_bpad(const T* src, int64_t I, int J, int64_t lds, float* dst, int64_t ld, double inv_scale) {
-    const int64_t n = I * ld;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / ld;
-        const int j = (int)(e - i * ld);
-        float v = __builtin_huge_valf();
-        if (j < J) {
-            const double x = (double)src[i * lds + j];
-            v = KIND == 0 ? (float)x : (float)((1.0 / x) * inv_scale);
-        }
-        dst[e] = v;
-    }
-}
+// Batched padded copies of cost sources (one job per blockIdx.y):
+// dst[i ld + j] = cost(i, j) for j < J, +inf for J <= j < ld. kind 0: dense C;
+// 1: rates, c = inv_scale / R.
+struct PadJob {
+    const void* src;
+    float* dst;
+    int64_t I, lds, ld;
+    double inv_scale;
+    int J;
+    int kind;
+    int f64;
+    int pad_;
+};
 
-// Non-finite or non-positive entry detection for batch inputs (bad = 1).
-template <typename T, bool POS>
-__global__ void k_bvalidate(const T* x, int64_t I, int J, int64_t lds, int* bad) {
-    const int64_t n = I * J;
+__global__ void k_bpad_jobs(const PadJob* __restrict__ jobs) {
+    const PadJob& P = jobs[blockIdx.y];
+    const int64_t n = P.I * P.ld;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / J;
-        const double v = (double)x[i * lds + (e - i * J)];
-        if (!isfinite(v) || (POS && !(v > 0.0))) *bad = 1;
+        const int64_t i = e / P.ld;
+        const int j = (int)(e - i * P.ld);
+        float v = __builtin_huge_valf();
+        if (j < P.J) {
+            const double x = P.f64 ? ((const double*)P.src)[i * P.lds + j] : (double)((const float*)P.src)[i * P.lds + j];
+            v = P.kind == 0 ? (float)x : (float)((1.0 / x) * P.inv_scale);
+        }
+        P.dst[e] = v;
     }
 }
 

@@ -52,18 +52,13 @@ struct DenseSrc {
 #pragma unroll
             for (int v = 0; v < VEC; ++v) x.v[v] = (T)__builtin_huge_val();
         } else if constexpr (VEC == 4 && sizeof(T) == 4) {
-            // (the row stride is a multiple of VEC, so a vector that straddles
-            // J stays inside the row; its entries past J are masked)
+            // (vector loads are only used when J is a multiple of VEC, so a
+            // vector is either inside the row or wholly past J)
             float4 y = *reinterpret_cast<const float4*>(r.p + col0);
             x.v[0] = y.x; x.v[1] = y.y; x.v[2] = y.z; x.v[3] = y.w;
-            if (col0 + VEC > J)
-#pragma unroll
-                for (int v = 1; v < VEC; ++v)
-                    if (col0 + v >= J) x.v[v] = (T)__builtin_huge_val();
         } else if constexpr (VEC == 2 && sizeof(T) == 8) {
             double2 y = *reinterpret_cast<const double2*>(r.p + col0);
             x.v[0] = y.x; x.v[1] = y.y;
-            if (col0 + 1 >= J) x.v[1] = (T)__builtin_huge_val();
         } else {
 #pragma unroll
             for (int v = 0; v < VEC; ++v) x.v[v] = (col0 + v < J) ? r.p[col0 + v] : (T)__builtin_huge_val();
@@ -111,14 +106,9 @@ struct RatesSrc {
         } else if constexpr (VEC == 4 && sizeof(T) == 4) {
             float4 y = *reinterpret_cast<const float4*>(r.p + col0);
             x.v[0] = y.x; x.v[1] = y.y; x.v[2] = y.z; x.v[3] = y.w;
-            if (col0 + VEC > J)
-#pragma unroll
-                for (int v = 1; v < VEC; ++v)
-                    if (col0 + v >= J) x.v[v] = (T)0;
         } else if constexpr (VEC == 2 && sizeof(T) == 8) {
             double2 y = *reinterpret_cast<const double2*>(r.p + col0);
             x.v[0] = y.x; x.v[1] = y.y;
-            if (col0 + 1 >= J) x.v[1] = (T)0;
         } else {
 #pragma unroll
             for (int v = 0; v < VEC; ++v) x.v[v] = (col0 + v < J) ? r.p[col0 + v] : (T)0;

@@ -71,13 +71,14 @@ struct Shape {
     int64_t rpb = 1;
 };
 
-// Vector width of the row loads: 16-byte loads need a row stride that is a
-// multiple of the width and an aligned base (then a vector that straddles J
-// stays inside its row and its entries past J are masked).
+// Vector width of the row loads: 16-byte loads need J and the row stride to
+// be multiples of the width and an aligned base, so that no vector straddles
+// J (padding entries are never read as costs).
 template <class Src>
-int vec_for(int64_t ld, const void* d) {
+int vec_for(int64_t J, int64_t ld, const void* d) {
     if (Src::kVecWide == 1) return 1;
-    return (ld % Src::kVecWide == 0 && ((uintptr_t)d % 16) == 0) ? Src::kVecWide : 1;
+    const int w = Src::kVecWide;
+    return (J % w == 0 && ld % w == 0 && ((uintptr_t)d % 16) == 0) ? w : 1;
 }
 
 inline int64_t ld_of(const ot_cost_desc& c) { return c.ld ? c.ld : c.J; }
@@ -615,7 +616,7 @@ struct Solver {
 template <class Src>
 ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, int J, double tol, int32_t max_iter,
                      Ctl& c, int& result_iter) {
-    const int vec = vec_for<Src>(ld_of(h->last), data);
+    const int vec = vec_for<Src>(J, ld_of(h->last), data);
     Solver S{h, I, J, make_shape<Src>(h, I, J, vec, false), make_shape<Src>(h, I, J, vec, true), h->opt.use_graphs != 0};
     fit_grid<Src, false>(h, I, S.shape);
     fit_grid<Src, true>(h, I, S.shape64);
@@ -876,7 +877,7 @@ ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
     }
     ot_status st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
         using S = std::decay_t<decltype(src)>;
-        const Shape s = row64(make_shape<S>(h, I, J, vec_for<S>(ld_of(h->last), data)), J);
+        const Shape s = row64(make_shape<S>(h, I, J, vec_for<S>(J, ld_of(h->last), data)), J);
         bool ok = dtype == OT_F32 ? launch_plan<S, float>(s, I, (int)J, h->f[h->res_par], h->g[h->res_par], h->prm, (float*)dst, src, h->stream)
                                   : launch_plan<S, double>(s, I, (int)J, h->f[h->res_par], h->g[h->res_par], h->prm, (double*)dst, src, h->stream);
         if (!ok) return fail(h, OT_EINVAL, "no plan kernel for this shape");
@@ -1022,7 +1023,7 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
         hipMemcpyAsync(h->ctl, &h->ctl_h[0], sizeof(Ctl), hipMemcpyHostToDevice, h->stream);
         st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
             using S = std::decay_t<decltype(src)>;
-            const int vec = vec_for<S>(ld_of(h->last), data);
+            const int vec = vec_for<S>(J, ld_of(h->last), data);
             Solver sv{h, I, (int)J, make_shape<S>(h, I, J, vec, false), make_shape<S>(h, I, J, vec, true), false};
             fit_grid<S, false>(h, I, sv.shape);
             fit_grid<S, true>(h, I, sv.shape64);

@@ -226,10 +226,10 @@ def test_batch_constant_cost_closed_form(A):
 
 
 def test_batch_row_padded_inputs_in_place(A, oracle_lib, inst):
-    announce("batch of row-padded device matrices (ld % 4 == 0, NaN padding) referenced in place")
+    announce("batch of row-padded device matrices (NaN padding): J % 4 == 0 in place, others copied")
     import torch
     dev = torch.device("cuda:0")
-    picks = [0, 3, 4, 5]
+    picks = [0, 2, 3, 4, 5]
     costs, aa, bb, keep = [], [], [], []
     for k in picks:
         x = inst[k]
