@@ -125,10 +125,12 @@ def leg_batch(args, A, S, torch, dev):
         st, res = bs.solve_batch(descs, aa, bb, eps, tol, 2000)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / K
+    cfg_w, cfg_rpp = bs.batch_config()
     iters = np.array([r.iterations for r in res])
     viol = np.array([r.marginal_violation for r in res])
     cell_it = sum(L.I * L.J * r.iterations for L, r in zip(Ls, res))
-    log(f"batch: {t_batch * 1e3:.2f} ms for {n} solves = {n / t_batch:.0f} solves/s, iterations "
+    log(f"batch: {t_batch * 1e3:.2f} ms for {n} solves = {n / t_batch:.0f} solves/s (waves {cfg_w}, "
+        f"{cfg_rpp} rows per part), iterations "
         f"{iters.min()}..{iters.max()} (mean {iters.mean():.1f}), max violation {viol.max():.2e}")
     # the plain path, one instance at a time, same matrices
     times = []
@@ -145,6 +147,7 @@ def leg_batch(args, A, S, torch, dev):
     out = {"workload": f"{n} uneven instances, I~LogU[500,20000], J~LogU[20,400], 1 km, eps={eps}, tol={tol}, "
                        "dense FP32 costs resident in HBM",
            "ms_per_batch": t_batch * 1e3, "solves_per_s": n / t_batch, "cells": cells,
+           "tuned": {"waves": cfg_w, "rows_per_part": cfg_rpp},
            "cells_per_s": cell_it / t_batch, "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),
            "max_marginal_violation": float(viol.max()), "status_ok": int(sum(r.status == 0 for r in res)),
            "plain_ms_total": t_plain * 1e3, "plain_solves_per_s": n / t_plain, "speedup_vs_plain": t_plain / t_batch,

@@ -237,6 +237,11 @@ ot_status ot_assoc_solve_batch(ot_assoc *h, int n, const ot_cost_desc *costs, co
                                const double *const *b, const double *eps, double tol, int32_t max_iter,
                                ot_assoc_result *out);
 
+/* Launch configuration the last batch ran with (chosen by the autotuner when
+ * batch_tune is set): waves per FP32 sweep workgroup and rows per work item.
+ * OT_ESTATE before any batch. */
+ot_status ot_assoc_batch_config(ot_assoc *h, int *waves, int *rows_per_part);
+
 /* Potentials (f: I, g: J, FP64) of instance k of the last batch, into host or
  * device memory. OT_ESTATE before a batch, OT_EINVAL for a bad k. */
 ot_status ot_assoc_batch_potentials(ot_assoc *h, int k, double *f, double *g, ot_mem mem);

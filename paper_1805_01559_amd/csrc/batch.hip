@@ -617,6 +617,7 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         d.res_part = (double*)carve(sizeof(double) * parts_cap);
         d.stat_part = (double*)carve(sizeof(double) * (size_t)parts_cap * 5);
         sl.prm = (SolveParams*)carve(sizeof(SolveParams));
+        d.prm = sl.prm;
         d.ctl = ctl + k;
         d.kk = std::log2(std::exp(1.0)) / r.eps;
         d.eps = r.eps;
@@ -811,7 +812,14 @@ ot_status BatchEngine::tune(const std::vector<int>& ks) {
         key.append((const char*)dims, sizeof dims);
     }
     auto it = tuned.find(key);
-    if (it != tuned.end()) return relayout(ks, it->second.first, it->second.second);
+    if (it != tuned.end()) {
+        // admission already partitioned with the engine's current rows per part
+        if (it->second.second == rpp_rows) {
+            waves = it->second.first;
+            return OT_OK;
+        }
+        return relayout(ks, it->second.first, it->second.second);
+    }
     hipEvent_t e0, e1;
     ECHK(this, hipEventCreate(&e0));
     ECHK(this, hipEventCreate(&e1));
@@ -989,14 +997,13 @@ ot_status ot_assoc_solve_batch(ot_assoc* h, int n, const ot_cost_desc* costs, co
     std::vector<int> ks;
     ot_status st = e->admit(reqs, ks, true);
     if (!st) {
-        // marginals were checked on the device: one wait for all of them
-        std::vector<Ctl> cs(ks.size());
+        // marginals were checked on the device: one read-back for all of them
+        const int hi = *std::max_element(ks.begin(), ks.end()) + 1;
+        if (hipMemcpyAsync(e->snap[0], e->ctl, sizeof(Ctl) * hi, hipMemcpyDeviceToHost, e->stream) != hipSuccess ||
+            hipStreamSynchronize(e->stream) != hipSuccess)
+            st = e->fail(OT_EDEVICE, "admission failed");
         for (size_t q = 0; q < ks.size() && !st; ++q)
-            if (hipMemcpyAsync(&cs[q], e->ctl + ks[q], sizeof(Ctl), hipMemcpyDeviceToHost, e->stream) != hipSuccess)
-                st = e->fail(OT_EDEVICE, "control block read failed");
-        if (!st && hipStreamSynchronize(e->stream) != hipSuccess) st = e->fail(OT_EDEVICE, "admission failed");
-        for (size_t q = 0; q < ks.size() && !st; ++q)
-            if (cs[q].numeric_bad == 2)
+            if (e->snap[0][ks[q]].numeric_bad == 2)
                 st = e->fail(OT_EINVAL, "instance %zu: marginals must be positive, finite and balanced", q);
         if (st) {
             h->err = e->err;
@@ -1035,6 +1042,18 @@ ot_status ot_assoc_solve_batch(ot_assoc* h, int n, const ot_cost_desc* costs, co
     e->tab_order = ks;
     if (worst < 0) h->err = "an instance of the batch failed numerically";
     return worst;
+}
+
+ot_status ot_assoc_batch_config(ot_assoc* h, int* waves, int* rows_per_part) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!h->batch) {
+        h->err = "no batch has run on this handle";
+        return OT_ESTATE;
+    }
+    if (waves) *waves = h->batch->waves;
+    if (rows_per_part) *rows_per_part = (int)h->batch->rpp_rows;
+    return OT_OK;
 }
 
 ot_status ot_assoc_batch_potentials(ot_assoc* h, int k, double* f, double* g, ot_mem mem) {

@@ -49,6 +49,7 @@ struct BInst {
     double* res_part;   // parts
     double* stat_part;  // parts x 5
     Ctl* ctl;
+    const SolveParams* prm;  // kk, eps in device memory
     double kk, eps;
 };
 
@@ -79,7 +80,7 @@ __host__ __device__ constexpr int batch_class_lpr(int cls) { return cls == 3 ? 3
 __host__ __device__ constexpr int batch_class_nch(int cls) { return cls == 0 ? 1 : cls == 1 ? 2 : 4; }
 
 template <bool P64, int WAVES>
-__device__ __forceinline__ void batch_sweep_item(const BInst& d, const BItem& it, double* sm) {
+__device__ __forceinline__ void batch_sweep_item(const BInst& d, const BItem& it) {
     const int pin = (it.flags & kItPar) ? 1 : 0;
     SweepJob job;
     job.r0 = (int64_t)it.part * d.rpp;
@@ -87,21 +88,22 @@ __device__ __forceinline__ void batch_sweep_item(const BInst& d, const BItem& it
     job.J = d.J;
     job.nch = d.nch;
     job.has_prev = (it.flags & kItPrev) ? 1 : 0;
-    job.kk = d.kk;
-    job.eps = d.eps;
+    job.prev_ctl = nullptr;
+    job.prm = d.prm;
     job.a = d.a;
     job.f_in = d.f[pin];
     job.f_out = d.f[pin ^ 1];
     job.g_in = d.g[pin];
-    job.col_out = d.col_part + (int64_t)it.part * d.J;
-    job.res_out = d.res_part + it.part;
+    job.col_part = d.col_part;
+    job.res_part = d.res_part;
+    job.part = it.part;
     const DenseSrc<float> src{d.C, d.ld};
     using S = DenseSrc<float>;
     switch (d.cls) {
-        case 0: sweep_rows<S, P64, 4, 1, 16, WAVES, 1>(job, src, sm, nullptr); break;
-        case 1: sweep_rows<S, P64, 4, 2, 16, WAVES, 1>(job, src, sm, nullptr); break;
-        case 2: sweep_rows<S, P64, 4, 4, 16, WAVES, 1>(job, src, sm, nullptr); break;
-        default: sweep_rows<S, P64, 4, 4, 32, WAVES, 1>(job, src, sm, nullptr); break;
+        case 0: sweep_rows<S, P64, 4, 1, 16, WAVES, 1>(job, src, nullptr); break;
+        case 1: sweep_rows<S, P64, 4, 2, 16, WAVES, 1>(job, src, nullptr); break;
+        case 2: sweep_rows<S, P64, 4, 4, 16, WAVES, 1>(job, src, nullptr); break;
+        default: sweep_rows<S, P64, 4, 4, 32, WAVES, 1>(job, src, nullptr); break;
     }
 }
 
@@ -114,7 +116,6 @@ template <bool P64, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void k_bsweep(const BInst* __restrict__ tab,
                                                           const BItem* __restrict__ items,
                                                           const int* __restrict__ cnt_in, int* __restrict__ cnt_out) {
-    extern __shared__ double sm[];
     if (!P64 && blockIdx.x == 0 && threadIdx.x < 3) cnt_out[threadIdx.x] = 0;
     const int n = cnt_in[P64 ? 1 : 0];
     for (int q = blockIdx.x; q < n; q += gridDim.x) {
@@ -134,11 +135,11 @@ __global__ __launch_bounds__(WAVES * kWave) void k_bsweep(const BInst* __restric
                 cj.g = d.g[par];
                 cj.col_out = d.col_part + (int64_t)it.part * d.J;
                 cj.stat_out = d.stat_part + (int64_t)it.part * 5;
-                check_rows<DenseSrc<float>, 4, 2, WAVES>(cj, DenseSrc<float>{d.C, d.ld}, sm);
+                check_rows<DenseSrc<float>, 4, 2, WAVES>(cj, DenseSrc<float>{d.C, d.ld});
                 continue;
             }
         }
-        batch_sweep_item<P64, WAVES>(d, it, sm);
+        batch_sweep_item<P64, WAVES>(d, it);
     }
 }
 
@@ -167,8 +168,18 @@ __global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, B
         for (int j0 = 0; j0 < J; j0 += 64) {
             const int j = j0 + c;
             double s = 0.0;
-            if (j < J)
-                for (int p = r; p < parts; p += 16) s += d.col_part[(int64_t)p * J + j];
+            if (j < J) {
+                // eight independent loads in flight, summed in a fixed order
+                const double* cp = d.col_part + j;
+                int p = r;
+                for (; p + 7 * 16 < parts; p += 8 * 16) {
+                    double x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) x[u] = cp[(int64_t)(p + u * 16) * J];
+                    s += ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
+                }
+                for (; p < parts; p += 16) s += cp[(int64_t)p * J];
+            }
             red[r][c] = s;
             __syncthreads();
             if (tid < 64 && j < J) {
@@ -241,7 +252,11 @@ __global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, B
                     next = 2;
                 } else if (ctl->stop) {
                     ctl->stop = 0;
-                    if (phase == kPhFast && P.polish_iters > 0 && ctl->iter < ctl->max_iter) {
+                    // polish only when the FP32 sweeps stalled short of tol; a
+                    // residual that met a tol above the FP32 noise threshold
+                    // goes straight to the exact check
+                    const bool met = ctl->r_last < ctl->tol && ctl->tol >= P.stall_below;
+                    if (phase == kPhFast && P.polish_iters > 0 && ctl->iter < ctl->max_iter && !met) {
                         ctl->phase = kPhPolish;
                         ctl->polish_left = P.polish_iters;
                         next = 1;

@@ -147,14 +147,16 @@ struct SweepJob {
     int64_t r0, r1;
     int J;
     int nch;
-    int has_prev;
-    double kk, eps;
+    int has_prev;               // used when prev_ctl is null
+    const Ctl* prev_ctl;        // else has_prev is read from here
+    const SolveParams* prm;     // kk, eps (read after the first loads are issued)
     const double* a;
     const double* f_in;
     double* f_out;
     const double* g_in;
-    double* col_out;  // J partial column sums of the half-iterate
-    double* res_out;  // one partial row residual of the previous iterate
+    double* col_part;  // rows of J partial column sums of the half-iterate ...
+    double* res_part;  // ... and partial row residuals of the previous iterate
+    int part;          // the row of both that this job writes
 };
 
 // The sweep of rows [r0, r1) by one workgroup. With stop_ctl set, the first
@@ -162,7 +164,10 @@ struct SweepJob {
 // nothing more if the chunk has been stopped. LDS is reused from the previous
 // call of a persistent workgroup only after a barrier.
 template <class Src, bool P64, int VEC, int NCH, int LPR, int WAVES, int RB>
-__device__ __forceinline__ void sweep_rows(const SweepJob& A, const Src& src, double* sm, const Ctl* stop_ctl) {
+__device__ __forceinline__ void sweep_rows(const SweepJob& A, const Src& src, const Ctl* stop_ctl) {
+    // (the dynamic LDS is named here rather than passed in: a pointer
+    // parameter loses its address space and turns LDS accesses into flat ones)
+    extern __shared__ double sm[];
     constexpr int R = kWave / LPR;
     const int J = A.J, nch = A.nch;
     const int ncols = nch * LPR * VEC;
@@ -193,9 +198,11 @@ __device__ __forceinline__ void sweep_rows(const SweepJob& A, const Src& src, do
     if (stop_ctl && (stop_ctl->stop | stop_ctl->done)) return;
 
     // 2. per-column state in LDS: staged source data, g kk in FP64 and FP32
-    const double kk = A.kk, eps = A.eps;
+    //    (scalars are loaded only now, so they hold no registers while the
+    //    first loads are in flight)
+    const double kk = A.prm->kk, eps = A.prm->eps;
     const float kk32 = (float)kk;
-    const int has_prev = A.has_prev;
+    const int has_prev = A.prev_ctl ? A.prev_ctl->has_prev : A.has_prev;
     __syncthreads();  // LDS may still be read by this workgroup's previous job
     src.stage(sm, J);
     double* gs64 = sm + Src::kStageDoubles * ncols;
@@ -322,39 +329,49 @@ __device__ __forceinline__ void sweep_rows(const SweepJob& A, const Src& src, do
     __shared__ double wres[WAVES];
     if (lane == 0) wres[w] = res;
     __syncthreads();
+    // (output addresses are formed only here: live registers are scarce)
+    double* out = A.col_part + (int64_t)A.part * J;
     for (int c = threadIdx.x; c < J; c += blockDim.x) {
         double t = 0.0;
 #pragma unroll 8
         for (int k = 0; k < WAVES * R; ++k) t += (double)red[k * ncols + c];
-        A.col_out[c] = t;
+        out[c] = t;
     }
     if (threadIdx.x == 0) {
         double r = 0.0;
         for (int q = 0; q < WAVES; ++q) r += wres[q];
-        *A.res_out = r;
+        A.res_part[A.part] = r;
     }
 }
+
+// Occupancy the register allocator is asked to keep (waves per SIMD): the
+// FP32-exponential dense sweeps with at most 16 columns per lane fit in 128
+// registers (4 waves per SIMD) without spills; left to itself the allocator
+// sometimes settles a little above 128 and loses a quarter of the occupancy.
+template <class Src, bool P64, int VEC, int NCH, int RB>
+constexpr int sweep_waves_per_eu() { return (!P64 && Src::kTag == 1 && NCH * RB * VEC <= 16) ? 4 : 1; }
 
 // One Sinkhorn sweep of a single instance: workgroup b owns rows
 // [b rows_per_block, (b + 1) rows_per_block).
 template <class Src, bool P64, int VEC, int NCH, int LPR, int WAVES, int RB>
-__global__ __launch_bounds__(WAVES * kWave) void k_iter(IterArgs A, Src src) {
-    extern __shared__ double sm[];
+__global__ __launch_bounds__(WAVES * kWave)
+__attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<Src, P64, VEC, NCH, RB>(), 8))) void k_iter(IterArgs A, Src src) {
     SweepJob job;
     job.r0 = (int64_t)blockIdx.x * A.rows_per_block;
     job.r1 = min(A.I, job.r0 + A.rows_per_block);
     job.J = A.J;
     job.nch = A.nch;
-    job.has_prev = A.ctl->has_prev;
-    job.kk = A.prm->kk;
-    job.eps = A.prm->eps;
+    job.has_prev = 0;
+    job.prev_ctl = A.ctl;
+    job.prm = A.prm;
     job.a = A.a;
     job.f_in = A.f_in;
     job.f_out = A.f_out;
     job.g_in = A.g_in;
-    job.col_out = A.col_part + (int64_t)blockIdx.x * A.J;
-    job.res_out = A.res_part + blockIdx.x;
-    sweep_rows<Src, P64, VEC, NCH, LPR, WAVES, RB>(job, src, sm, A.ctl);
+    job.col_part = A.col_part;
+    job.res_part = A.res_part;
+    job.part = blockIdx.x;
+    sweep_rows<Src, P64, VEC, NCH, LPR, WAVES, RB>(job, src, A.ctl);
 }
 
 // -------------------------------------------------------- column combine --
@@ -455,7 +472,8 @@ struct CheckJob {
 };
 
 template <class Src, int VEC, int NCH, int WAVES>
-__device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src, double* sm) {
+__device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
+    extern __shared__ double sm[];
     const double kk = A.kk;
     const int J = A.J, nch = A.nch;
     const int ncols = nch * kWave * VEC;
@@ -537,7 +555,6 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src, do
 
 template <class Src, int VEC, int NCH, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
-    extern __shared__ double sm[];
     CheckJob job;
     job.r0 = (int64_t)blockIdx.x * A.rows_per_block;
     job.r1 = min(A.I, job.r0 + A.rows_per_block);
@@ -549,7 +566,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
     job.g = A.g;
     job.col_out = A.col_part + (int64_t)blockIdx.x * A.J;
     job.stat_out = A.stat_part + (int64_t)blockIdx.x * 5;
-    check_rows<Src, VEC, NCH, WAVES>(job, src, sm);
+    check_rows<Src, VEC, NCH, WAVES>(job, src);
 }
 
 // Column sums of the check: per column |colsum_j - b_j| and g_j b_j, summed

@@ -628,7 +628,10 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
     const double stall_below = 1e-7;  // FP32 sweeps are not trusted below this
     if (h->opt.precision == OT_PREC_FP32) {
         if ((st = S.run_phase<Src, false>(src, kModeFast, chunk, stall_below, c))) return st;
-        if (!c.done && c.iter < max_iter) {
+        // polish only when the FP32 sweeps stalled short of tol; a residual
+        // that met a tol above the FP32 noise threshold goes to the check
+        const bool met = c.r_last < tol && tol >= stall_below;
+        if (!c.done && c.iter < max_iter && !met) {
             const int np = std::max(0, std::min(h->opt.polish_iters, max_iter - c.iter));
             if (np > 0) {
                 hipLaunchKernelGGL(k_ctl_resume, dim3(1), dim3(64), 0, h->stream, h->ctl);

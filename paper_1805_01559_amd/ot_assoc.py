@@ -31,7 +31,8 @@ OT_PREC_FP32, OT_PREC_FP64 = 0, 1
 EXPORTS = [
     "ot_assoc_default_options", "ot_assoc_create", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
     "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep",
-    "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_potentials",
+    "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_config",
+    "ot_assoc_batch_potentials",
     "ot_assoc_batch_plan", "ot_serve_default_options", "ot_serve_create", "ot_serve_submit", "ot_serve_progress",
     "ot_serve_counts", "ot_serve_potentials", "ot_serve_now", "ot_serve_last_error", "ot_serve_destroy",
 ]
@@ -110,6 +111,7 @@ def lib():
         PP = ct.POINTER(ct.c_void_p)
         L.ot_assoc_solve_batch.argtypes = [vp, ct.c_int, ct.POINTER(ot_cost_desc), PP, PP, ct.POINTER(d), d,
                                            ct.c_int32, ct.POINTER(ot_assoc_result)]
+        L.ot_assoc_batch_config.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
         L.ot_assoc_batch_potentials.argtypes = [vp, ct.c_int, vp, vp, ct.c_int]
         L.ot_assoc_batch_plan.argtypes = [vp, ct.c_int, vp, ct.c_int, ct.c_int]
         L.ot_serve_default_options.argtypes = [ct.POINTER(ot_serve_options)]
@@ -216,6 +218,12 @@ def ot_assoc_solve_batch(h, descs, a_ptrs, b_ptrs, eps, tol, max_iter):
     st = lib().ot_assoc_solve_batch(h, n, D, A, B, E, float(tol), int(max_iter), R)
     _check(h, st)
     return st, list(R)
+
+
+def ot_assoc_batch_config(h):
+    w, r = ct.c_int(), ct.c_int()
+    _check(h, lib().ot_assoc_batch_config(h, ct.byref(w), ct.byref(r)))
+    return w.value, r.value
 
 
 def ot_assoc_batch_potentials(h, k, f_ptr, g_ptr, mem):
@@ -467,6 +475,10 @@ class Solver:
         self._batch_dims = [(d.I, d.J) for d in descs]
         del keep
         return st, res
+
+    def batch_config(self):
+        """(waves per FP32 sweep workgroup, rows per work item) of the last batch."""
+        return ot_assoc_batch_config(self.h)
 
     def batch_potentials(self, k):
         I, J = self._batch_dims[k]
