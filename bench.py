@@ -32,7 +32,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale_gpu):
+def cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale_gpu, snap_As=None):
     """The FP64 oracle timed on this host's cores, and the GPU's errors against
     it on the same instance: the GPU re-solves with the oracle's median scale
     (an input the oracle defines; nothing flows from the GPU to the oracle)."""
@@ -78,6 +78,20 @@ def cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale_gpu):
     _, res = solver.solve_geometry(xy, rxy, L.radio, L.shadow_key, scale, a, b, eps, tol, 2000)
     f, g = solver.potentials()
     acc["on_the_fly"] = errors(C64, f, g, res)
+    if snap_As is not None:
+        # BF16 snapshot path: two snapshots against the oracle's own solves
+        # (the snapshot leg ran before the re-solves above, its state is kept)
+        snap = []
+        for q in (0, 1):
+            fq, gq = solver.snapshot_potentials(q)
+            aq = snap_As[q]
+            ref = O.sinkhorn(C64, aq, L.b, 0.02, 1e-10, 4000)
+            rs = O.plan_stats(C64, aq, L.b, ref.f, ref.g, 0.02)
+            st = O.plan_stats(C64, aq, L.b, fq, gq, 0.02)
+            snap.append(dict(snapshot=q, marginal_violation=st["marginal_violation"],
+                             objective_rel_err=abs(st["objective"] - rs["objective"]) / abs(rs["objective"]),
+                             plan_l1=float(np.abs(O.plan(C64, fq, gq, 0.02) - O.plan(C64, ref.f, ref.g, 0.02)).sum())))
+        acc["snapshots_bf16"] = snap
     return base, acc
 
 
@@ -155,6 +169,52 @@ def leg_batch(args, A, S, torch, dev):
     bs.close()
     one.close()
     return out
+
+
+def leg_snapshots(args, A, S, torch, dev, solver, C, L):
+    """One 20000 x 400 layout (the main workload's cost, resident in HBM) and
+    B = 64 traffic snapshots (lambda resampled, seeds 3500 + s), eps 0.02,
+    tol 1e-6, solved together through BF16 GEMMs on the matrix cores; the
+    plain single-instance path on the first 8 snapshots beside it."""
+    B, eps, tol = 64, 0.02, 1e-6
+    As = S.snapshot_marginals(L.I, B, seed=3500)
+    Ad = torch.from_numpy(As).to(dev)
+    bd = torch.from_numpy(L.b).to(dev)
+    for _ in range(max(1, args.warmup)):
+        solver.solve_snapshots(C, Ad, bd, eps, tol, 2000)
+    torch.cuda.synchronize()
+    K = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        st, res = solver.solve_snapshots(C, Ad, bd, eps, tol, 2000)
+    torch.cuda.synchronize()
+    t_snap = (time.perf_counter() - t0) / K
+    iters = res[0].iterations
+    viol = [r.marginal_violation for r in res]
+    gemm_s = res[0].seconds  # device time of the GEMM iteration
+    flops = 2 * 2 * L.I * L.J * B * 2 * iters  # two GEMMs, hi + lo operand halves
+    log(f"snapshots: {t_snap * 1e3:.2f} ms for {B} = {B / t_snap:.0f} snapshot solves/s; {iters} iterations in "
+        f"{gemm_s * 1e3:.2f} ms ({flops / gemm_s / 1e12:.1f} TFLOP/s); violation max {max(viol):.2e}")
+    times = []
+    ad1 = [torch.from_numpy(As[q]).to(dev) for q in range(8)]
+    with A.Solver(L.I, L.J) as s1:
+        s1.solve_dense(C, ad1[0], bd, eps, tol, 2000)
+        for q in range(8):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s1.solve_dense(C, ad1[q], bd, eps, tol, 2000)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+    t_plain = float(np.mean(times))
+    log(f"plain per snapshot: {t_plain * 1e3:.2f} ms = {1 / t_plain:.0f} solves/s; snapshot speed-up "
+        f"{B / t_snap * t_plain:.1f}x")
+    return {"workload": f"cran_20000x400 cost, B={B} snapshots (lambda resampled), eps={eps}, tol={tol} on the BF16 "
+                        "problem, K and K^T in BF16, u / v split hi + lo, FP32 accumulation",
+            "ms_per_64": t_snap * 1e3, "snapshot_solves_per_s": B / t_snap, "iterations": iters,
+            "gemm_ms": gemm_s * 1e3, "mfma_tflops": flops / gemm_s / 1e12,
+            "mfma_frac_bf16_dense_peak": flops / gemm_s / 2.5e15,
+            "max_marginal_violation_fp64_check": max(viol),
+            "plain_ms_per_solve": t_plain * 1e3, "speedup_vs_plain": B / t_snap * t_plain}, As
 
 
 def leg_serve(args, A, S, torch, dev):
@@ -257,7 +317,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0 skips it)")
     ap.add_argument("--serve-layouts", type=int, default=200, help="layouts of the serving leg (0 skips it)")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the serving leg (requests/s)")
-    ap.add_argument("--only", choices=["all", "main", "batch", "serve"], default="all",
+    ap.add_argument("--only", choices=["all", "main", "batch", "serve", "snapshots"], default="all",
                     help="run one leg (for profiling): main = the 20000x400 solve and its sweep")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -399,13 +459,16 @@ def main():
                        "sweep_us": ms_sweep_geo * 1e3, "cells_per_s_sweep": cells / (ms_sweep_geo * 1e-3),
                        "marginal_violation": res_g.marginal_violation},
     }
+    snap_As = None
+    if args.only in ("all", "snapshots"):
+        out["snapshots"], snap_As = leg_snapshots(args, A, S, torch, dev, solver, C, L)
     if args.only in ("all", "batch") and args.batch > 0:
         out["batched"] = leg_batch(args, A, S, torch, dev)
     if args.only in ("all", "serve") and args.serve_layouts > 0:
         out["serving"] = leg_serve(args, A, S, torch, dev)
     if not args.no_cpu_baseline and args.only == "all":
         log("cpu baseline (FP64 oracle on host cores) ...")
-        cb, acc = cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale)
+        cb, acc = cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale, snap_As)
         out["cpu_baseline"] = cb
         out["accuracy_vs_oracle"] = acc
     solver.close()

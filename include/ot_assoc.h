@@ -250,6 +250,31 @@ ot_status ot_assoc_batch_potentials(ot_assoc *h, int k, double *f, double *g, ot
  * (eq. (7)) with the FP32 cost the batch used, I x J row-major, FP32 or FP64. */
 ot_status ot_assoc_batch_plan(ot_assoc *h, int k, void *pi, ot_mem mem, ot_dtype dtype);
 
+/* -------------------------------------------------------- traffic snapshots
+ * B (1..64) traffic snapshots of one layout: marginals a_s (row s of A, B x I
+ * row-major) over one cost C and one RRH marginal b, each the problem of
+ * eq. (5). Solved together in the scaling form of the Sinkhorn iteration
+ * (Sec. III-B): a reference solve of the mean snapshot (single-instance path)
+ * gives potentials (fbar, gbar) that stabilise the kernel
+ * K = exp((fbar + gbar - C) / eps), held in BF16; the half-steps
+ * u_s = a_s / (K v_s) and v_s = b / (K^T u_s) of all snapshots are two GEMMs
+ * on the matrix cores (BF16 operands, u and v split into high and low BF16
+ * parts, FP32 accumulation). The iteration stops when every snapshot's column
+ * residual of the BF16 problem is below tol (relative to sum a_s) or after
+ * max_iter iterations. out[s] reports the common iteration count and the
+ * exact FP64 check of snapshot s's potentials fbar + eps ln u_s,
+ * gbar + eps ln v_s against C (for RATES / GEOMETRY, its FP32 materialised
+ * form): the violation reflects the BF16 kernel (about 1e-3), not tol.
+ * A and b live in cost->mem (GEOMETRY: device). Afterwards the handle's
+ * single-instance state (ot_assoc_plan / ot_assoc_potentials) is the
+ * reference solve. Errors: OT_EINVAL for bad arguments or marginals,
+ * OT_ENOMEM, OT_EDEVICE. */
+ot_status ot_assoc_solve_snapshots(ot_assoc *h, const ot_cost_desc *cost, int B, const double *A, const double *b,
+                                   double eps, double tol, int32_t max_iter, ot_assoc_result *out);
+
+/* Potentials of snapshot s of the last snapshot solve (f: I, g: J, FP64). */
+ot_status ot_assoc_snapshot_potentials(ot_assoc *h, int s, double *f, double *g, ot_mem mem);
+
 /* ------------------------------------------------------------------ serving
  * A request server over the batched engine: requests (one association solve
  * per scheduling instant) are queued on submit and admitted, oldest first, as

@@ -23,7 +23,7 @@ FLAGS = [
 
 
 def sources():
-    return [os.path.join(CSRC, f) for f in ("ot_assoc.hip", "batch.hip")]
+    return [os.path.join(CSRC, f) for f in ("ot_assoc.hip", "batch.hip", "snapshots.hip")]
 
 
 def _compile(src: str, obj: str, inc: str):

@@ -34,6 +34,8 @@ inline otk::GeoConst geo_const(const ot_geometry& g, double scale) {
 
 struct BatchEngine;
 void batch_engine_destroy(BatchEngine* e);
+struct SnapState;
+void snap_state_destroy(SnapState* s);
 
 struct ot_assoc {
     int device = 0;
@@ -72,4 +74,5 @@ struct ot_assoc {
     bool retained = false;     // the handle still holds the cost of the last solve
     std::string err;
     BatchEngine* batch = nullptr;  // engine of ot_assoc_solve_batch, created on first use
+    SnapState* snap = nullptr;     // buffers and results of the last snapshot solve
 };

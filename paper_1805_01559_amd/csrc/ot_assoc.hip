@@ -695,6 +695,7 @@ void ot_assoc_destroy(ot_assoc* h) {
     for (auto e : evs)
         if (e) hipEventDestroy(e);
     if (h->batch) batch_engine_destroy(h->batch);
+    if (h->snap) snap_state_destroy(h->snap);
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
     delete h;
 }
@@ -925,6 +926,7 @@ ot_status ot_assoc_set_potentials(ot_assoc* h, const double* f, const double* g,
     h->solved = false;
     return OT_OK;
 }
+
 
 ot_status ot_assoc_cost_median(ot_assoc* h, const ot_cost_desc* cost, double* median_out) {
     if (!h) return OT_EINVAL;

@@ -1,0 +1,385 @@
+// Kernels of the snapshot solve: B traffic snapshots (device marginals a_s,
+// one per snapshot) over one cost matrix C and one RRH marginal b, solved
+// together in the scaling form of the Sinkhorn iteration (Sec. III-B),
+//   u_s = a_s / (K v_s),   v_s = b / (K^T u_s),   pi_s = diag(u_s) K diag(v_s),
+// with the kernel stabilised by the potentials (fbar, gbar) of a reference
+// solve: K_ij = exp((fbar_i + gbar_j - C_ij) / eps), so that u and v stay near
+// 1 and the potentials of snapshot s are fbar + eps ln u_s, gbar + eps ln v_s.
+// Stacking the snapshots as columns turns both half-steps into GEMMs with a
+// K-dimension of J and I respectively:
+//   P = K V   (I x J) . (J x B)        Q = K^T U   (J x I) . (I x B)
+// run on the matrix cores (v_mfma_f32_16x16x32_bf16): K is held in BF16 (and
+// its transpose, so both GEMMs read their A operand along contiguous memory),
+// U and V are split into BF16 high and low parts (x = hi + lo, so the scaling
+// vectors keep about 16 bits), and every product accumulates in FP32.
+//
+// MFMA 16x16x32 lane layout (lane l of the 64-lane wavefront):
+//   A (16 x 32): row l % 16, k = 8 (l / 16) .. 8 (l / 16) + 7
+//   B (32 x 16): col l % 16, k = 8 (l / 16) .. 8 (l / 16) + 7
+//   D (16 x 16): col l % 16, rows 4 (l / 16) .. 4 (l / 16) + 3
+#pragma once
+
+#include "kernels.h"
+
+namespace otk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSnapB = 64;     // snapshots per GEMM (4 column tiles of 16)
+constexpr int kSnapNT = kSnapB / 16;
+
+// Round-to-nearest-even FP32 -> BF16 (bit pattern).
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+    const unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// Device state of a snapshot solve.
+struct SnapArgs {
+    int64_t I, Ip;   // rows; rows padded to a multiple of 32 (K-dimension of Q)
+    int J, Jp;       // columns; padded to a multiple of 32 (K-dimension of P)
+    int B;           // live snapshots (<= kSnapB)
+    int splits;      // K-splits of the column GEMM
+    int64_t rows_per_split;  // multiple of 32
+    const unsigned short* K;   // Ip x Jp BF16, zero padded
+    const unsigned short* Kt;  // Jp x Ip BF16, zero padded
+    const double* A;           // kSnapB x I marginals a_s (rows >= B unused)
+    const double* b;           // J
+    float* U;                  // kSnapB x Ip
+    unsigned short* Uh;        // kSnapB x Ip, BF16 high part of U
+    unsigned short* Ul;        // kSnapB x Ip, BF16 low part
+    float* V;                  // kSnapB x Jp
+    unsigned short* Vh;        // kSnapB x Jp
+    unsigned short* Vl;        // kSnapB x Jp
+    float* Qpart;              // splits x kSnapB x Jp
+    double* res;               // kSnapB x kResParts: column residual of the last combined iterate
+    double* mass;              // kSnapB: sum a_s
+    int* ctl;                  // [0] iterations done, [1] stop, [2] max_iter, [3] result iteration
+    double tol;
+};
+
+// Builds the stabilised kernel in BF16 and its transpose, through a 32 x 32
+// LDS tile: K_ij = exp2((fbar_i + gbar_j - C_ij) log2(e) / eps), zero outside
+// I x J.
+__global__ __launch_bounds__(256) void k_snap_build(const float* C, int64_t ldc, int64_t I, int J, int64_t Ip, int Jp,
+                                                    const double* fbar, const double* gbar, double kk,
+                                                    unsigned short* K, unsigned short* Kt) {
+    __shared__ unsigned short t[32][33];
+    const int64_t i0 = (int64_t)blockIdx.y * 32;
+    const int j0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = i0 + r;
+        const int j = j0 + tx;
+        float v = 0.0f;
+        if (i < I && j < J) v = (float)exp2((fbar[i] + gbar[j] - (double)C[i * ldc + j]) * kk);
+        const unsigned short h = bf16_bits(v);
+        K[i * Jp + j] = h;
+        t[r][tx] = h;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) Kt[(int64_t)(j0 + r) * Ip + i0 + tx] = t[tx][r];
+}
+
+// Splits x (FP32) into BF16 high and low parts.
+__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
+    hi = bf16_bits(x);
+    lo = bf16_bits(x - bf16_value(hi));
+}
+
+// Sets the scaling vectors of a cold start: v = 1 on live (s, j), 0 elsewhere.
+__global__ void k_snap_init(SnapArgs S) {
+    const int64_t n = (int64_t)kSnapB * S.Jp;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(e / S.Jp), j = (int)(e - (int64_t)s * S.Jp);
+        const float v = (s < S.B && j < S.J) ? 1.0f : 0.0f;
+        unsigned short hi, lo;
+        split_bf16(v, hi, lo);
+        S.V[e] = v;
+        S.Vh[e] = hi;
+        S.Vl[e] = lo;
+    }
+    if (blockIdx.x == 0)
+        for (int q = threadIdx.x; q < kSnapB * 4; q += blockDim.x) S.res[q] = __builtin_huge_val();
+}
+
+__device__ __forceinline__ bf16x8 load8(const unsigned short* p) {
+    return *reinterpret_cast<const bf16x8*>(p);
+}
+
+// Stop decision, taken identically by every workgroup of the row pass from
+// the residuals of the last combine (kResParts column quarters per snapshot,
+// summed in a fixed order): all live snapshots met tol, or the iteration cap.
+constexpr int kResParts = 4;
+__device__ __forceinline__ double snap_residual(const SnapArgs& S, int s) {
+    const double* r = S.res + (int64_t)s * kResParts;
+    return ((r[0] + r[1]) + (r[2] + r[3])) / S.mass[s];
+}
+__device__ __forceinline__ bool snap_stop(const SnapArgs& S) {
+    if (S.ctl[1]) return true;
+    double r = 0.0;
+    for (int s = 0; s < S.B; ++s) r = fmax(r, snap_residual(S, s));
+    return (r < S.tol) || (S.ctl[0] >= S.ctl[2]);
+}
+
+// One wave's share of a 16 x kSnapB output tile: K-steps k0 = kbeg, kbeg +
+// kstride, ... < kend of A (16 rows, row stride lda) times the hi and lo
+// parts of B^T (kSnapB rows, row stride ldb). The next step's fragments are
+// loaded before the current step's products are issued.
+__device__ __forceinline__ void snap_tile(const unsigned short* arow, int64_t lda, const unsigned short* bh,
+                                          const unsigned short* bl, int64_t ldb, int64_t kbeg, int64_t kend,
+                                          int64_t kstride, int lane, f32x4 (&acc)[kSnapNT]) {
+    const int m = lane & 15, kq = (lane >> 4) * 8;
+    (void)lda;
+#pragma unroll
+    for (int t = 0; t < kSnapNT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (kbeg >= kend) return;
+    bf16x8 a, h[kSnapNT], l[kSnapNT];
+    auto fetch = [&](int64_t k0) {
+        a = load8(arow + k0 + kq);
+#pragma unroll
+        for (int t = 0; t < kSnapNT; ++t) {
+            const int64_t o = (int64_t)(t * 16 + m) * ldb + k0 + kq;
+            h[t] = load8(bh + o);
+            l[t] = load8(bl + o);
+        }
+    };
+    fetch(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kstride) {
+        const bf16x8 ca = a;
+        bf16x8 ch[kSnapNT], cl[kSnapNT];
+#pragma unroll
+        for (int t = 0; t < kSnapNT; ++t) {
+            ch[t] = h[t];
+            cl[t] = l[t];
+        }
+        if (k0 + kstride < kend) fetch(k0 + kstride);
+#pragma unroll
+        for (int t = 0; t < kSnapNT; ++t) {
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, ch[t], acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, cl[t], acc[t], 0, 0, 0);
+        }
+    }
+}
+
+// Sums the four waves' partial tiles through LDS, in wave order; wave 0
+// returns with the total.
+__device__ __forceinline__ void snap_reduce4(f32x4 (&acc)[kSnapNT], int w, int lane) {
+    __shared__ f32x4 red[3][kSnapNT][64];
+    if (w > 0)
+#pragma unroll
+        for (int t = 0; t < kSnapNT; ++t) red[w - 1][t][lane] = acc[t];
+    __syncthreads();
+    if (w == 0)
+#pragma unroll
+        for (int t = 0; t < kSnapNT; ++t) acc[t] = ((acc[t] + red[0][t][lane]) + red[1][t][lane]) + red[2][t][lane];
+}
+
+// Row half-step: P = K V for a 16-row tile per workgroup (the four waves take
+// every fourth K-step and are summed in LDS), then u = a / P (0 on padded
+// rows and snapshots), stored as FP32 and as BF16 hi / lo.
+__global__ __launch_bounds__(256) void k_snap_rows(SnapArgs S) {
+    if (snap_stop(S)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && !S.ctl[1]) {
+            S.ctl[1] = 1;
+            S.ctl[3] = S.ctl[0];
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * 16;
+    const int m = lane & 15;
+    f32x4 acc[kSnapNT];
+    snap_tile(S.K + (i0 + m) * S.Jp, S.Jp, S.Vh, S.Vl, S.Jp, (int64_t)w * 32, S.Jp, 128, lane, acc);
+    snap_reduce4(acc, w, lane);
+    if (w != 0) return;
+    // D: column = snapshot t * 16 + m, rows i0 + 4 (lane / 16) + q
+    const int64_t ib = i0 + (lane >> 4) * 4;
+#pragma unroll
+    for (int t = 0; t < kSnapNT; ++t) {
+        const int s = t * 16 + m;
+        float u[4];
+        unsigned short hi[4], lo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = ib + q;
+            u[q] = (s < S.B && i < S.I) ? (float)(S.A[(int64_t)s * S.I + i] / (double)acc[t][q]) : 0.0f;
+            split_bf16(u[q], hi[q], lo[q]);
+        }
+        const int64_t o = (int64_t)s * S.Ip + ib;
+        *reinterpret_cast<float4*>(S.U + o) = make_float4(u[0], u[1], u[2], u[3]);
+        *reinterpret_cast<ushort4*>(S.Uh + o) = make_ushort4(hi[0], hi[1], hi[2], hi[3]);
+        *reinterpret_cast<ushort4*>(S.Ul + o) = make_ushort4(lo[0], lo[1], lo[2], lo[3]);
+    }
+}
+
+// Column half-step, split along i: Qpart[split] = K^T[j-tile, rows of split] U
+// for one 16-column tile per workgroup (the four waves take every fourth
+// K-step and are summed in LDS).
+__global__ __launch_bounds__(256) void k_snap_cols(SnapArgs S) {
+    if (S.ctl[1]) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int jt = blockIdx.x, split = blockIdx.y;
+    const int m = lane & 15;
+    const int64_t r0 = (int64_t)split * S.rows_per_split;
+    const int64_t r1 = min(S.Ip, r0 + S.rows_per_split);
+    f32x4 acc[kSnapNT];
+    snap_tile(S.Kt + (int64_t)(jt * 16 + m) * S.Ip, S.Ip, S.Uh, S.Ul, S.Ip, r0 + (int64_t)w * 32, r1, 128, lane, acc);
+    snap_reduce4(acc, w, lane);
+    if (w != 0) return;
+    const int jb = jt * 16 + (lane >> 4) * 4;
+#pragma unroll
+    for (int t = 0; t < kSnapNT; ++t) {
+        const int s = t * 16 + m;
+        float* o = S.Qpart + ((int64_t)split * kSnapB + s) * S.Jp + jb;
+        *reinterpret_cast<float4*>(o) = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+    }
+}
+
+// Column combine, workgroup (s, quarter): for its quarter of the columns,
+// Q = sum of the splits (fixed order, FP64), the column residual of the
+// iterate (u, v_old) and v = b / Q.
+__global__ __launch_bounds__(256) void k_snap_combine(SnapArgs S) {
+    if (S.ctl[1]) return;
+    const int s = blockIdx.x, quarter = blockIdx.y;
+    const int jq = (S.Jp / 4 + 63) / 64 * 64;  // columns per quarter
+    __shared__ double red[4];
+    double r = 0.0;
+    const int jend = min(S.Jp, (quarter + 1) * jq);
+    for (int j = quarter * jq + threadIdx.x; j < jend; j += blockDim.x) {
+        const int64_t e = (int64_t)s * S.Jp + j;
+        float v = 0.0f;
+        if (s < S.B && j < S.J) {
+            const float* qp = S.Qpart + (int64_t)s * S.Jp + j;
+            const int64_t step = (int64_t)kSnapB * S.Jp;
+            double q = 0.0;
+            int p = 0;
+            for (; p + 8 <= S.splits; p += 8) {
+                float x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = qp[(p + u) * step];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) q += (double)x[u];
+            }
+            for (; p < S.splits; ++p) q += (double)qp[p * step];
+            r += fabs((double)S.V[e] * q - S.b[j]);
+            v = (float)(S.b[j] / q);
+        }
+        unsigned short hi, lo;
+        split_bf16(v, hi, lo);
+        S.V[e] = v;
+        S.Vh[e] = hi;
+        S.Vl[e] = lo;
+    }
+    r = wave_sum(r);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S.res[(int64_t)s * kResParts + quarter] = (red[0] + red[1]) + (red[2] + red[3]);
+        if (s == 0 && quarter == 0) S.ctl[0] += 1;
+    }
+}
+
+// Snapshot marginals on the device: abar_i = mean over s of A[s][i], and a
+// flag when any entry is not positive and finite.
+__global__ void k_snap_mean(const double* A, int B, int64_t I, double* abar, int* bad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += (int64_t)gridDim.x * blockDim.x) {
+        double t = 0.0;
+        int f = 0;
+        for (int s = 0; s < B; ++s) {
+            const double v = A[(int64_t)s * I + i];
+            f |= !(v > 0.0 && isfinite(v));
+            t += v;
+        }
+        abar[i] = t / B;
+        if (f) *bad = 1;
+    }
+}
+
+// mass[s] = sum_i A[s][i] (fixed order), one workgroup per snapshot; 1 for
+// padded snapshots.
+__global__ __launch_bounds__(256) void k_snap_mass(const double* A, int B, int64_t I, double* mass) {
+    const int s = blockIdx.x;
+    __shared__ double red[4];
+    double t = 0.0;
+    if (s < B)
+        for (int64_t i = threadIdx.x; i < I; i += blockDim.x) t += A[(int64_t)s * I + i];
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) mass[s] = s < B ? (red[0] + red[1]) + (red[2] + red[3]) : 1.0;
+}
+
+// Potentials of every live snapshot: F[s] = fbar + eps ln u_s (I),
+// G[s] = gbar + eps ln v_s (J), FP64.
+__global__ void k_snap_all_potentials(SnapArgs S, const double* fbar, const double* gbar, double eps, double* F,
+                                      double* G) {
+    const int s = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S.I; i += (int64_t)gridDim.x * blockDim.x)
+        F[(int64_t)s * S.I + i] = fbar[i] + eps * log((double)S.U[(int64_t)s * S.Ip + i]);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < S.J; j += (int64_t)gridDim.x * blockDim.x)
+        G[(int64_t)s * S.J + j] = gbar[j] + eps * log((double)S.V[(int64_t)s * S.Jp + j]);
+}
+
+// Exact FP64 check of every snapshot in one launch: workgroup (chunk, s)
+// takes rows [chunk rpc, (chunk + 1) rpc) of snapshot s and writes its column
+// partials and five row statistics (check_rows).
+template <int NCH>
+__global__ __launch_bounds__(512) void k_snap_check(const float* C, int64_t ldc, int64_t I, int J, int64_t rpc,
+                                                    const double* A, const double* F, const double* G, double kk,
+                                                    double* col_part, double* stat_part) {
+    const int s = blockIdx.y, chunk = blockIdx.x, nchunk = gridDim.x;
+    CheckJob cj;
+    cj.r0 = (int64_t)chunk * rpc;
+    cj.r1 = min(I, cj.r0 + rpc);
+    cj.J = J;
+    cj.nch = (J + 63) / 64;
+    cj.kk = kk;
+    cj.a = A + (int64_t)s * I;
+    cj.f = F + (int64_t)s * I;
+    cj.g = G + (int64_t)s * J;
+    cj.col_out = col_part + ((int64_t)s * nchunk + chunk) * J;
+    cj.stat_out = stat_part + ((int64_t)s * nchunk + chunk) * 5;
+    check_rows<DenseSrc<float>, 1, NCH, 8>(cj, DenseSrc<float>{C, ldc});
+}
+
+// Per snapshot: column sums of the check, the statistics, into out[s * 8]:
+// violation, <C, pi>, reg. objective, dual, mass, row residual, col residual.
+__global__ __launch_bounds__(256) void k_snap_check_finish(int nchunk, int J, const double* b, const double* G,
+                                                           const double* col_part, const double* stat_part,
+                                                           const double* mass, double eps, double* out) {
+    const int s = blockIdx.x;
+    __shared__ double red[4][7];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int j = threadIdx.x; j < J; j += blockDim.x) {
+        double cs = 0.0;
+        for (int c = 0; c < nchunk; ++c) cs += col_part[((int64_t)s * nchunk + c) * J + j];
+        v[5] += fabs(cs - b[j]);
+        v[6] += G[(int64_t)s * J + j] * b[j];
+    }
+    for (int c = threadIdx.x; c < nchunk; c += blockDim.x)
+        for (int u = 0; u < 5; ++u) v[u] += stat_part[((int64_t)s * nchunk + c) * 5 + u];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int u = 0; u < 7; ++u) {
+        const double t = wave_sum(v[u]);
+        if (lane == 0) red[w][u] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[7];
+        for (int u = 0; u < 7; ++u) t[u] = (red[0][u] + red[1][u]) + (red[2][u] + red[3][u]);
+        double* o = out + (int64_t)s * 8;
+        o[0] = (t[0] + t[5]) / mass[s];
+        o[1] = t[1];
+        o[2] = t[1] + eps * t[2];
+        o[3] = t[4] + t[6] - eps * t[3];
+        o[4] = t[3];
+        o[5] = t[0];
+        o[6] = t[5];
+    }
+}
+
+}  // namespace otk

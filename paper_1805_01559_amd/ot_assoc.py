@@ -32,7 +32,7 @@ EXPORTS = [
     "ot_assoc_default_options", "ot_assoc_create", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
     "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep",
     "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_config",
-    "ot_assoc_batch_potentials",
+    "ot_assoc_batch_potentials", "ot_assoc_solve_snapshots", "ot_assoc_snapshot_potentials",
     "ot_assoc_batch_plan", "ot_serve_default_options", "ot_serve_create", "ot_serve_submit", "ot_serve_progress",
     "ot_serve_counts", "ot_serve_potentials", "ot_serve_now", "ot_serve_last_error", "ot_serve_destroy",
 ]
@@ -113,6 +113,9 @@ def lib():
                                            ct.c_int32, ct.POINTER(ot_assoc_result)]
         L.ot_assoc_batch_config.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
         L.ot_assoc_batch_potentials.argtypes = [vp, ct.c_int, vp, vp, ct.c_int]
+        L.ot_assoc_solve_snapshots.argtypes = [vp, ct.POINTER(ot_cost_desc), ct.c_int, vp, vp, d, d, ct.c_int32,
+                                               ct.POINTER(ot_assoc_result)]
+        L.ot_assoc_snapshot_potentials.argtypes = [vp, ct.c_int, vp, vp, ct.c_int]
         L.ot_assoc_batch_plan.argtypes = [vp, ct.c_int, vp, ct.c_int, ct.c_int]
         L.ot_serve_default_options.argtypes = [ct.POINTER(ot_serve_options)]
         L.ot_serve_create.argtypes = [ct.POINTER(vp), ct.POINTER(ot_serve_options)]
@@ -232,6 +235,18 @@ def ot_assoc_batch_potentials(h, k, f_ptr, g_ptr, mem):
 
 def ot_assoc_batch_plan(h, k, pi_ptr, mem, dtype):
     return _check(h, lib().ot_assoc_batch_plan(h, int(k), pi_ptr, mem, dtype))
+
+
+def ot_assoc_solve_snapshots(h, desc, B, A_ptr, b_ptr, eps, tol, max_iter):
+    R = (ot_assoc_result * B)()
+    st = lib().ot_assoc_solve_snapshots(h, ct.byref(desc), int(B), A_ptr, b_ptr, float(eps), float(tol),
+                                        int(max_iter), R)
+    _check(h, st)
+    return st, list(R)
+
+
+def ot_assoc_snapshot_potentials(h, s, f_ptr, g_ptr, mem):
+    return _check(h, lib().ot_assoc_snapshot_potentials(h, int(s), f_ptr, g_ptr, mem))
 
 
 def ot_serve_default_options() -> ot_serve_options:
@@ -368,6 +383,7 @@ class Solver:
         self.h = ot_assoc_create(I_max, J_max, o)
         self.I_max, self.J_max = I_max, J_max
         self._I = self._J = None
+        self._snap_dims = None
 
     def close(self):
         h = getattr(self, "h", None)
@@ -475,6 +491,31 @@ class Solver:
         self._batch_dims = [(d.I, d.J) for d in descs]
         del keep
         return st, res
+
+    # ---------------------------------------------------------- snapshots --
+    def solve_snapshots(self, cost, A, b, eps, tol=1e-6, max_iter=2000):
+        """B traffic snapshots (rows of A, B x I) over one cost: a matrix or a
+        (desc, keep) pair; A and b in the cost's memory space."""
+        d, keep = cost if isinstance(cost, tuple) else matrix_desc(cost, OT_COST_DENSE)
+        pa, ma, ka = _ptr_mem(A, np.float64)
+        pb, mb, kb = _ptr_mem(b, np.float64)
+        want = OT_MEM_DEVICE if d.kind == OT_COST_GEOMETRY else d.mem
+        if ma != want or mb != want:
+            raise ValueError("snapshots and b must be in the cost's memory space")
+        st, res = ot_assoc_solve_snapshots(self.h, d, int(A.shape[0]), pa, pb, eps, tol, max_iter)
+        self._snap_dims = (d.I, d.J, int(A.shape[0]))
+        self._I, self._J = d.I, d.J
+        del keep, ka, kb
+        return st, res
+
+    def snapshot_potentials(self, s):
+        if self._snap_dims is None:  # let the library report the state error
+            ot_assoc_snapshot_potentials(self.h, s, None, None, OT_MEM_HOST)
+        I, J, _ = self._snap_dims
+        f = np.empty(I)
+        g = np.empty(J)
+        ot_assoc_snapshot_potentials(self.h, s, f.ctypes.data, g.ctypes.data, OT_MEM_HOST)
+        return f, g
 
     def batch_config(self):
         """(waves per FP32 sweep workgroup, rows per work item) of the last batch."""

@@ -1,0 +1,129 @@
+"""GPU tests of the snapshot solve (ot_assoc_solve_snapshots): B traffic
+snapshots over one cost through BF16 GEMMs on the matrix cores, against the
+FP64 oracle solving every snapshot on its own.
+
+Bar of the BF16 path: the marginal violation of each snapshot's plan and the
+relative error of its transport cost against the oracle's converged solution
+both within 1e-3 (the BF16 kernel carries a relative rounding of 2^-9 per
+entry; u and v keep about 16 bits through their high / low split). The
+library's own exact check must agree with the oracle's recomputation from the
+same potentials.
+"""
+
+import numpy as np
+import pytest
+
+import scenario as S
+
+pytestmark = pytest.mark.gpu
+
+BF16_BAR = 1e-3
+
+
+@pytest.fixture(scope="module")
+def A():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_01559_amd import ot_assoc
+    ot_assoc.lib()
+    return ot_assoc
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def oracle_case(O, I, J, B, seed, eps):
+    L = S.make_layout(I, J, 1000.0, seed=seed)
+    C32 = O.cost(L)[0].astype(np.float32)
+    Cq = C32.astype(np.float64)
+    As = S.snapshot_marginals(I, B, seed=seed + 1)
+    return L, C32, Cq, As
+
+
+def check_snapshot(O, Cq, a, b, eps, f, g, res):
+    chk = O.plan_stats(Cq, a, b, f, g, eps)
+    ref = O.sinkhorn(Cq, a, b, eps, 1e-11, 20000)
+    rst = O.plan_stats(Cq, a, b, ref.f, ref.g, eps)
+    assert chk["marginal_violation"] < BF16_BAR, chk["marginal_violation"]
+    rel = abs(chk["objective"] - rst["objective"]) / abs(rst["objective"])
+    assert rel < BF16_BAR, rel
+    # the library's exact FP64 check of the same potentials
+    assert abs(res.marginal_violation - chk["marginal_violation"]) <= 1e-9 + 1e-6 * chk["marginal_violation"]
+    assert abs(res.objective - chk["objective"]) <= 1e-9 * abs(chk["objective"])
+    return chk["marginal_violation"], rel
+
+
+@pytest.mark.parametrize("I,J,B", [(1500, 60, 8), (1001, 37, 1), (2048, 130, 17)])
+def test_snapshots_against_oracle(A, oracle_lib, I, J, B):
+    announce(f"snapshots {I}x{J}, B={B}")
+    eps = 0.05
+    L, C32, Cq, As = oracle_case(oracle_lib, I, J, B, 7000 + I, eps)
+    with A.Solver(I, J) as s:
+        st, res = s.solve_snapshots(C32, As, L.b, eps, 1e-6, 3000)
+        assert st == A.OT_OK, [r.status for r in res]
+        for q in range(B):
+            f, g = s.snapshot_potentials(q)
+            check_snapshot(oracle_lib, Cq, As[q], L.b, eps, f, g, res[q])
+        # the handle's single-instance state is the reference solve of the
+        # mean snapshot (solved to 1e-6: it only conditions the kernel)
+        f0, g0 = s.potentials()
+        st0 = oracle_lib.plan_stats(Cq, As.mean(axis=0), L.b, f0, g0, eps)
+        assert st0["marginal_violation"] < 1e-6
+
+
+def test_snapshots_64_sampled(A, oracle_lib):
+    announce("64 snapshots of a 4000 x 200 layout, every 9th checked against the oracle")
+    eps = 0.05
+    L, C32, Cq, As = oracle_case(oracle_lib, 4000, 200, 64, 7300, eps)
+    import torch
+    dev = torch.device("cuda:0")
+    Cd = torch.from_numpy(C32).to(dev)
+    Ad = torch.from_numpy(As).to(dev)
+    bd = torch.from_numpy(L.b).to(dev)
+    with A.Solver(4000, 200) as s:
+        st, res = s.solve_snapshots(Cd, Ad, bd, eps, 1e-6, 3000)
+        assert st == A.OT_OK
+        for r in res:
+            assert r.marginal_violation < BF16_BAR
+        for q in range(0, 64, 9):
+            f, g = s.snapshot_potentials(q)
+            check_snapshot(oracle_lib, Cq, As[q], L.b, eps, f, g, res[q])
+
+
+def test_snapshots_constant_cost_closed_form(A):
+    announce("snapshots of a constant cost: pi_s = a_s b^T / sum(a_s)")
+    I, J, B = 300, 40, 5
+    rng = np.random.default_rng(3)
+    As = rng.random((B, I)) + 0.2
+    As /= As.sum(axis=1, keepdims=True)
+    b = rng.random(J) + 0.2
+    b /= b.sum()
+    C = np.full((I, J), 0.5, np.float32)
+    with A.Solver(I, J) as s:
+        st, res = s.solve_snapshots(C, As, b, 0.05, 1e-7, 2000)
+        assert st == A.OT_OK
+        for q in range(B):
+            f, g = s.snapshot_potentials(q)
+            P = np.exp((f[:, None] + g[None, :] - 0.5) / 0.05)
+            assert np.abs(P - np.outer(As[q], b)).sum() < BF16_BAR
+
+
+def test_snapshots_errors(A):
+    announce("snapshot argument errors")
+    I, J = 100, 10
+    C = np.ones((I, J), np.float32)
+    b = np.full(J, 0.1)
+    with A.Solver(I, J) as s:
+        for As in (np.full((0, I), 1.0 / I), np.full((65, I), 1.0 / I)):
+            with pytest.raises((A.OTError, ValueError)):
+                s.solve_snapshots(C, As, b, 0.05, 1e-6, 100)
+        bad = np.full((2, I), 1.0 / I)
+        bad[1, 3] = -1.0
+        with pytest.raises(A.OTError) as e:
+            s.solve_snapshots(C, bad, b, 0.05, 1e-6, 100)
+        assert e.value.status == A.OT_EINVAL
+        with pytest.raises(A.OTError) as e:
+            s.snapshot_potentials(0)
+        assert e.value.status == A.OT_ESTATE
