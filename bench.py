@@ -423,6 +423,19 @@ def main():
     cells = I * J
     alg_bytes = 4.0 * cells  # one FP32 read of C per iteration
     achieved = alg_bytes / (ms_sweep * 1e-3) / 1e9
+    # HBM traffic of the same kernel from the committed counter summary, only
+    # while the kernel's sources are the ones the counters were taken on
+    traffic, traffic_note = None, "no counter summary"
+    tpath = os.path.join(ROOT, "profiles", "k_iter_dense_cran_20000x400_traffic.json")
+    if os.path.exists(tpath):
+        from paper_1805_01559_amd import profiling
+        t = json.load(open(tpath))
+        if t.get("source_hash") == profiling.sweep_source_hash():
+            traffic = t["hbm_bytes"] / (ms_sweep * 1e-3) / 1e9
+            traffic_note = (f"{t['hbm_bytes']:.4g} B per launch from FETCH_SIZE + WRITE_SIZE (copy-calibrated), "
+                            f"{t['ratio']:.3f} x the algorithmic bytes")
+        else:
+            traffic_note = "kernel sources changed since the counters were taken"
     out = {
         "metric": METRIC,
         "value": cells * res_d.iterations / t_dense,
@@ -445,7 +458,8 @@ def main():
         "marginal_violation": res_d.marginal_violation,
         "objective": res_d.objective,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
+                     "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel": "k_iter<DenseSrc<float>, fp32 exp> (fused row update + column partials)",
                      "avg_launch_us": ms_sweep * 1e3},
         "copy_gbps": copy_gbps,

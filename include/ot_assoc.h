@@ -247,7 +247,8 @@ ot_status ot_assoc_batch_config(ot_assoc *h, int *waves, int *rows_per_part);
 ot_status ot_assoc_batch_potentials(ot_assoc *h, int k, double *f, double *g, ot_mem mem);
 
 /* Plan of instance k of the last batch, pi_ij = exp((f_i + g_j - C_ij) / eps)
- * (eq. (7)) with the FP32 cost the batch used, I x J row-major, FP32 or FP64. */
+ * (the KKT form of Sec. III-B) with the FP32 cost the batch used, I x J
+ * row-major, FP32 or FP64. */
 ot_status ot_assoc_batch_plan(ot_assoc *h, int k, void *pi, ot_mem mem, ot_dtype dtype);
 
 /* -------------------------------------------------------- traffic snapshots

@@ -1,0 +1,110 @@
+"""Summaries of rocprofv3 output (CSV) for the association kernels.
+
+    python -m paper_1805_01559_amd.profiling stats <dir> [--top N]
+    python -m paper_1805_01559_amd.profiling traffic <fetch_dir> <write_dir> <kernel-substring> \
+        --bytes <algorithmic bytes per launch> [--copy-bytes 536870912]
+
+`stats` prints the kernel table of a `--kernel-trace --stats` run.
+`traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs into HBM bytes
+per launch of one kernel. Both counters are in KiB per dispatch; each is
+scaled by what it reads for the largest plain device copy in the same run
+(a copy of known size: it reads and writes `--copy-bytes / 2` each), so that
+the figure is in bytes the copy would have moved. The kernel's figure is the
+median over its dispatches, which drops the launches of a chunk that stop at
+once. Also prints a JSON line that bench.py can pick up.
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sweep_source_hash() -> str:
+    """Hash of the sources that define the single-instance sweep kernel: a
+    traffic figure taken from counters is valid only for this hash."""
+    h = hashlib.sha256()
+    for f in ("kernels.h", "cost_sources.h", "device_common.h"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d: str, suffix: str) -> str:
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def stats(d: str, top: int = 15) -> str:
+    rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
+    out = ["| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 110:
+            name = name[:107] + "..."
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def _counter(d: str):
+    return list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+
+
+def traffic(fetch_dir: str, write_dir: str, kernel: str, alg_bytes: float, copy_bytes: float) -> dict:
+    res = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter(d) if r["Counter_Name"] == name]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        cal_kib = max(copies) if copies else None
+        vals = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
+        if not vals or not cal_kib:
+            raise SystemExit(f"{name}: no dispatches of '{kernel}' or no copy calibration in {d}")
+        factor = (copy_bytes / 2) / (cal_kib * 1024.0)
+        res[name] = dict(median_kib=statistics.median(vals), dispatches=len(vals), copy_kib=cal_kib,
+                         factor=factor, bytes=statistics.median(vals) * 1024.0 * factor)
+    total = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
+    return dict(kernel=kernel, algorithmic_bytes=alg_bytes, hbm_bytes=total, ratio=total / alg_bytes,
+                fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"], source_hash=sweep_source_hash())
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("dir")
+    a.add_argument("--top", type=int, default=15)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("kernel")
+    b.add_argument("--bytes", type=float, required=True)
+    b.add_argument("--copy-bytes", type=float, default=float(2 * (256 << 20)))
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        print(stats(args.dir, args.top))
+    else:
+        t = traffic(args.fetch_dir, args.write_dir, args.kernel, args.bytes, args.copy_bytes)
+        f, w = t["fetch"], t["write"]
+        print(f"kernel: {t['kernel']}")
+        print(f"FETCH_SIZE median {f['median_kib']:.1f} KiB over {f['dispatches']} dispatches; copy reads "
+              f"{f['copy_kib']:.1f} KiB for 256 MiB -> factor {f['factor']:.4f}")
+        print(f"WRITE_SIZE median {w['median_kib']:.1f} KiB; copy writes {w['copy_kib']:.1f} KiB -> factor "
+              f"{w['factor']:.4f}")
+        print(f"HBM bytes per launch {t['hbm_bytes']:.4g} vs algorithmic {t['algorithmic_bytes']:.4g} "
+              f"(ratio {t['ratio']:.3f})")
+        print(json.dumps(t))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
