@@ -119,19 +119,27 @@ typedef struct {
     int sweep_lanes;    /* 0 = choose automatically; else 16, 32 or 64 lanes per row */
     int batch_tune;     /* ot_assoc_solve_batch: 1 (default) times the (waves, rows per part)
                            candidates once per batch shape and keeps the fastest; 0 uses 8, 128 */
+    int persistent;     /* ot_assoc_solve, FP32 precision: 1 (default) runs the FP32 phase as one
+                           cooperative launch that keeps the cost in LDS when the instance fits
+                           (about I * J <= 9.8e6 cells on 256 CUs; dense FP32, FP32 rates or
+                           geometry costs); 0 always uses graph-captured chunks of launches */
 } ot_assoc_options;
 
 typedef struct {
     int32_t iterations;      /* full (row + column) iterations of the returned iterate */
     int32_t fp64_iterations; /* FP64 sweeps run by the solve (polish and exact phases) */
     int32_t status;          /* ot_status of the solve */
-    int32_t reserved;
+    int32_t flags;           /* OT_RESULT_* bits */
     double marginal_violation; /* (sum_i |rowsum_i - a_i| + sum_j |colsum_j - b_j|) / sum(a), FP64 */
     double objective;          /* <C, pi> (transport cost) */
     double reg_objective;      /* <C, pi> + eps sum pi (log pi - 1), eq. (5) */
     double dual_objective;     /* <f, a> + <g, b> - eps sum pi */
     double seconds;            /* device time of the solve (HIP events) */
 } ot_assoc_result;
+
+/* ot_assoc_result.flags: the FP32 phase ran as one cooperative launch with the
+   cost held in LDS (ot_assoc_options.persistent). */
+#define OT_RESULT_PERSISTENT 1
 
 /* Fills *opt with the defaults listed above (device 0, default stream). */
 ot_status ot_assoc_default_options(ot_assoc_options *opt);

@@ -867,7 +867,7 @@ static void fill_result(const Slot& s, ot_assoc_result* r) {
     r->iterations = c.result_iter;
     r->fp64_iterations = c.fp64_iters;
     r->status = rs;
-    r->reserved = 0;
+    r->flags = 0;
     r->marginal_violation = c.chk_violation;
     r->objective = c.chk_objective;
     r->reg_objective = c.chk_reg_objective;

@@ -146,6 +146,11 @@ struct Ctl {
     int32_t polish_left;   // FP64 polish sweeps still to run
     int32_t check_iter;    // iterate the pending check examines
     int32_t exact_done;    // 1: the next check ends the solve whatever it finds
+    // single solves: inputs rejected on the device (bits: 1 a, 2 b, 4 sum a != sum b,
+    // 8 cost or positions), and a cooperative launch whose grid barrier gave up
+    int32_t input_bad;
+    int32_t sync_fail;
+    double mass_b;         // sum(b)
 };
 
 }  // namespace otk

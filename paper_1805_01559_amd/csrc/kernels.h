@@ -662,9 +662,11 @@ __global__ __launch_bounds__(512) void k_plan(int64_t I, int J, int nch, const d
 }
 
 // ------------------------------------------------------------- validation --
-// Flags a non-finite dense cost, or a rate that is not finite and positive.
+// Flags a non-finite dense cost, or a rate that is not finite and positive:
+// ORs `bit` into *bad and, when ctl is given, ends the solve on the device
+// (done and stop) so that a solve needs no host round trip for the check.
 template <typename T, bool RATES>
-__global__ void k_validate(const T* x, int64_t I, int J, int64_t ld, int* bad) {
+__global__ void k_validate(const T* x, int64_t I, int J, int64_t ld, int* bad, int bit, Ctl* ctl) {
     int flag = 0;
     const int64_t n = I * J;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
@@ -672,14 +674,26 @@ __global__ void k_validate(const T* x, int64_t I, int J, int64_t ld, int* bad) {
         const double v = (double)x[i * ld + (q - i * J)];
         if (RATES ? !(v > 0.0 && isfinite(v)) : !isfinite(v)) flag = 1;
     }
-    if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+    if (__any(flag) && (threadIdx.x & 63) == 0) {
+        atomicOr(bad, bit);
+        if (ctl) {
+            ctl->done = 1;
+            ctl->stop = 1;
+        }
+    }
 }
 
-static __global__ void k_validate_xy(const float* xy, int64_t n, int* bad) {
+static __global__ void k_validate_xy(const float* xy, int64_t n, int* bad, int bit, Ctl* ctl) {
     int flag = 0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
         if (!isfinite(xy[q])) flag = 1;
-    if (__any(flag) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+    if (__any(flag) && (threadIdx.x & 63) == 0) {
+        atomicOr(bad, bit);
+        if (ctl) {
+            ctl->done = 1;
+            ctl->stop = 1;
+        }
+    }
 }
 
 // Clears the stop flag between phases (kept as a kernel so that it may sit in

@@ -1,14 +1,19 @@
 // Host runtime and C ABI of the association solver (include/ot_assoc.h).
 //
 // A solve runs three phases on one HIP stream:
-//   fast    FP32-exponential sweeps, captured in HIP graphs CHUNK iterations at
-//           a time; the combine kernel stops the chunk on the device when the
-//           residual meets tol or stalls at the FP32 noise floor;
+//   fast    FP32-exponential sweeps until the residual meets tol or stalls at
+//           the FP32 noise floor. When the instance's FP32 cost fits in the
+//           LDS of the GPU this is ONE cooperative launch (persist_kernels.h)
+//           that keeps the cost on chip; otherwise the sweeps are captured in
+//           HIP graphs CHUNK iterations at a time, and the combine kernel
+//           stops the chunk on the device;
 //   polish  a few FP64 sweeps, then an exact FP64 check of the iterate;
 //   exact   (only if the check misses tol) FP64 sweeps until an FP64 iterate
 //           meets tol, then the check again.
-// The host reads a small control block once per chunk, one chunk behind the
-// device, so there is no host round trip per iteration.
+// Inputs are checked on the device (the verdict travels in the control
+// block). With the cooperative launch a solve has a single host wait before
+// the exact phase; the chunked form reads the control block once per chunk,
+// one chunk behind the device, so there is no host round trip per iteration.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +27,7 @@
 #include "../../include/ot_assoc.h"
 #include "handle.h"
 #include "kernels.h"
+#include "persist_kernels.h"
 
 using namespace otk;
 
@@ -372,7 +378,17 @@ ot_status ensure_stage(ot_assoc* h, size_t bytes) {
 // Brings the cost of `c` onto the device: host matrices are staged, device
 // matrices are referenced, geometry is copied and its per-device set-up pass
 // runs. Afterwards the handle can rebuild the source without the caller.
-ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, bool validate_values) {
+// Value checks of the cost: kCheckNone, kCheckNow (the host waits for the
+// verdict) or kCheckDeferred (the verdict goes into the control block, bit 8
+// of input_bad, and ends the solve on the device).
+enum { kCheckNone = 0, kCheckNow = 1, kCheckDeferred = 2 };
+
+ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, int check) {
+    const bool validate_values = check != kCheckNone;
+    const bool now = check == kCheckNow;
+    int* bad = now ? h->bad : &h->ctl->input_bad;
+    const int bit = now ? 1 : 8;
+    Ctl* ectl = now ? nullptr : h->ctl;
     const int64_t I = c->I, J = c->J, ld = ld_of(*c), n = I * J;
     h->retained = false;
     h->last = *c;
@@ -388,20 +404,22 @@ ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, bool validate_values) 
             data = h->stage;
         }
         if (validate_values) {
-            HIPCHK(h, hipMemsetAsync(h->bad, 0, sizeof(int), h->stream));
+            if (now) HIPCHK(h, hipMemsetAsync(h->bad, 0, sizeof(int), h->stream));
             const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
             const int Ji = (int)J;
             if (c->dtype == OT_F32) {
-                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<float, false>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, I, Ji, ld, h->bad);
-                else hipLaunchKernelGGL((k_validate<float, true>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, I, Ji, ld, h->bad);
+                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<float, false>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, I, Ji, ld, bad, bit, ectl);
+                else hipLaunchKernelGGL((k_validate<float, true>), dim3(grid), dim3(256), 0, h->stream, (const float*)data, I, Ji, ld, bad, bit, ectl);
             } else {
-                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<double, false>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, I, Ji, ld, h->bad);
-                else hipLaunchKernelGGL((k_validate<double, true>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, I, Ji, ld, h->bad);
+                if (c->kind == OT_COST_DENSE) hipLaunchKernelGGL((k_validate<double, false>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, I, Ji, ld, bad, bit, ectl);
+                else hipLaunchKernelGGL((k_validate<double, true>), dim3(grid), dim3(256), 0, h->stream, (const double*)data, I, Ji, ld, bad, bit, ectl);
             }
-            int bad = 0;
-            HIPCHK(h, hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(h, hipStreamSynchronize(h->stream));
-            if (bad)
+            int hbad = 0;
+            if (now) {
+                HIPCHK(h, hipMemcpyAsync(&hbad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(h, hipStreamSynchronize(h->stream));
+            }
+            if (hbad)
                 return fail(h, OT_EINVAL, c->kind == OT_COST_DENSE ? "cost matrix has non-finite entries"
                                                                   : "rate matrix has entries that are not finite and positive");
         }
@@ -414,13 +432,15 @@ ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, bool validate_values) 
     st = copy_in(h, h->xy_rrh, c->geom.rrh_xy, sizeof(float) * 2 * (size_t)J, c->mem);
     if (st) return st;
     if (validate_values) {
-        HIPCHK(h, hipMemsetAsync(h->bad, 0, sizeof(int), h->stream));
-        hipLaunchKernelGGL(k_validate_xy, dim3((unsigned)std::min<int64_t>(1024, (2 * I + 255) / 256)), dim3(256), 0, h->stream, h->xy_dev, 2 * I, h->bad);
-        hipLaunchKernelGGL(k_validate_xy, dim3((unsigned)std::min<int64_t>(1024, (2 * J + 255) / 256)), dim3(256), 0, h->stream, h->xy_rrh, 2 * J, h->bad);
-        int bad = 0;
-        HIPCHK(h, hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        if (bad) return fail(h, OT_EINVAL, "geometry positions have non-finite entries");
+        if (now) HIPCHK(h, hipMemsetAsync(h->bad, 0, sizeof(int), h->stream));
+        hipLaunchKernelGGL(k_validate_xy, dim3((unsigned)std::min<int64_t>(1024, (2 * I + 255) / 256)), dim3(256), 0, h->stream, h->xy_dev, 2 * I, bad, bit, ectl);
+        hipLaunchKernelGGL(k_validate_xy, dim3((unsigned)std::min<int64_t>(1024, (2 * J + 255) / 256)), dim3(256), 0, h->stream, h->xy_rrh, 2 * J, bad, bit, ectl);
+        int hbad = 0;
+        if (now) {
+            HIPCHK(h, hipMemcpyAsync(&hbad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+        }
+        if (hbad) return fail(h, OT_EINVAL, "geometry positions have non-finite entries");
     }
     GeoSrc s{};
     s.dev_xy = h->xy_dev;
@@ -611,6 +631,102 @@ struct Solver {
     }
 };
 
+// ------------------------------------------------------ cooperative phase --
+// Shape of the LDS-resident FP32 phase: one workgroup of kPersistWaves waves
+// per CU, rows per workgroup a whole number of wave steps, lanes per row by J.
+constexpr int kPersistWaves = 8;
+
+struct PersistPlan {
+    int lpr = 0, nch = 0, rpw = 0, nb = 0, Jp = 0, cpw = 0;
+    size_t lds = 0;
+};
+
+// Sources whose fast-sweep cost is an FP32 value (dense FP32, FP32 rates, the
+// FP32 geometry functor): the tile holds exactly what the streaming sweeps
+// compute per cell.
+template <class Src>
+constexpr bool persist_source() { return Src::kTag == 1 || Src::kTag == 3 || Src::kTag == 5; }
+
+template <class Src>
+bool persist_plan(const ot_assoc* h, int64_t I, int J, PersistPlan& p) {
+    if (!persist_source<Src>() || h->num_cu < 1 || h->lds_max < 1 || I < 1) return false;
+    if (J <= 128) { p.lpr = 16; }
+    else if (J <= 512) { p.lpr = 32; }
+    else if (J <= kMaxJ) { p.lpr = 64; }
+    else return false;
+    const int slots = kPersistWaves * (64 / p.lpr);  // rows per wave step of the workgroup
+    const int64_t per = (int64_t)h->num_cu * slots;
+    const int64_t steps = (I + per - 1) / per;
+    p.nch = (J + 4 * p.lpr - 1) / (4 * p.lpr);
+    p.rpw = (int)(steps * slots);
+    p.nb = (int)((I + p.rpw - 1) / p.rpw);
+    p.Jp = (J + 3) & ~3;
+    p.cpw = (J + p.nb - 1) / p.nb;
+    p.lds = persist_lds_bytes(p.rpw, J, p.Jp, kPersistWaves);
+    // (a little LDS stays for the kernel's static arrays)
+    return p.nb <= h->num_cu && p.nb <= kMaxNb && p.lds + 2048 <= (size_t)h->lds_max;
+}
+
+template <class Src>
+const void* persist_kernel(int lpr) {
+    if (lpr == 16) return (const void*)k_persist<Src, 4, 2, 16, kPersistWaves>;
+    if (lpr == 32) return (const void*)k_persist<Src, 4, 4, 32, kPersistWaves>;
+    return (const void*)k_persist<Src, 4, 8, 64, kPersistWaves>;
+}
+
+// Issues the cooperative FP32 phase. `launched` is false (and nothing is
+// issued) when the runtime refuses the co-resident grid; the caller then
+// runs the chunked launches instead.
+template <class Src>
+ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const PersistPlan& p, double stall_below,
+                      bool& launched) {
+    launched = false;
+    const void* kern = persist_kernel<Src>(p.lpr);
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return OT_OK;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPersistWaves * 64, p.lds) != hipSuccess ||
+        (int64_t)per_cu * h->num_cu < p.nb) {
+        (void)hipGetLastError();
+        return OT_OK;
+    }
+    PersistArgs A{};
+    A.I = I;
+    A.J = J;
+    A.Jp = p.Jp;
+    A.rpw = p.rpw;
+    A.cpw = p.cpw;
+    A.nch = p.nch;
+    A.max_spin = 1 << 20;  // polls of at least ~1 us each: ~1 s before a barrier gives up
+    A.stall_below = stall_below;
+    A.a = h->a;
+    A.b = h->b;
+    A.f[0] = h->f[0];
+    A.f[1] = h->f[1];
+    A.g[0] = h->g[0];
+    A.g[1] = h->g[1];
+    A.part = h->col_part;
+    A.rpart = h->res_part;
+    A.gx = h->gx;
+    A.sync = h->sync;
+    A.ctl = h->ctl;
+    A.prm = h->prm;
+    hipLaunchKernelGGL(k_sync_clear, dim3(1), dim3(256), 0, h->stream, h->sync, h->ctl);
+    Src sv = src;
+    void* args[] = {(void*)&A, (void*)&sv};
+    const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)p.nb), dim3(kPersistWaves * 64), args,
+                                                    (unsigned)p.lds, h->stream);
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        (void)hipGetLastError();
+        return OT_OK;
+    }
+    HIPCHK(h, e);
+    launched = true;
+    return OT_OK;
+}
+
 // The three phases of a solve. `c` enters with the initial control state and
 // leaves with the final one; result_iter names the returned iterate.
 template <class Src>
@@ -626,7 +742,29 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
     chunk += chunk & 1;  // even: every chunk starts on the same buffer parity
     ot_status st;
     const double stall_below = 1e-7;  // FP32 sweeps are not trusted below this
-    if (h->opt.precision == OT_PREC_FP32) {
+    bool checked = false;
+    PersistPlan pp;
+    bool persisted = false;
+    if (h->opt.precision == OT_PREC_FP32 && h->opt.persistent && persist_plan<Src>(h, I, J, pp))
+        if ((st = run_persist<Src>(h, src, I, J, pp, stall_below, persisted))) return st;
+    h->last_persistent = persisted;
+    if (persisted) {
+        // polish decided on the device, then the check: one host wait
+        const int np = std::max(0, h->opt.polish_iters);
+        const unsigned gb = (unsigned)std::min<int64_t>(64, (std::max<int64_t>(I, J) + 255) / 256);
+        hipLaunchKernelGGL(k_polish_gate, dim3(gb), dim3(256), 0, h->stream, h->ctl, h->f[0], h->f[1], h->g[0],
+                           h->g[1], I, J, tol, stall_below, np);
+        if (np > 0 && (st = S.issue_chunk<Src, true>(src, 0, np, kModePolish, 0.0))) return st;
+        if ((st = S.run_check<Src>(src, np, c))) return st;
+        checked = true;
+        // the iterate sits in the buffers of parity np & 1; restore the
+        // convention that iterate k lives in buffers k & 1
+        const int k = c.done ? c.result_iter : c.iter;
+        if (((k ^ np) & 1) != 0) {
+            HIPCHK(h, hipMemcpyAsync(h->f[k & 1], h->f[np & 1], sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(h->g[k & 1], h->g[np & 1], sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
+        }
+    } else if (h->opt.precision == OT_PREC_FP32) {
         if ((st = S.run_phase<Src, false>(src, kModeFast, chunk, stall_below, c))) return st;
         // polish only when the FP32 sweeps stalled short of tol; a residual
         // that met a tol above the FP32 noise threshold goes to the check
@@ -641,11 +779,15 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
             }
         }
     }
-    if (c.done) {  // numeric failure in the fast phase
+    if (c.done) {  // inputs rejected, or a numeric failure in the fast phase
         result_iter = c.result_iter;
         return OT_OK;
     }
-    if ((st = S.run_check<Src>(src, c.iter, c))) return st;
+    if (!checked && (st = S.run_check<Src>(src, c.iter, c))) return st;
+    if (c.done) {  // inputs rejected (seen first by the check of an FP64-precision solve)
+        result_iter = c.result_iter;
+        return OT_OK;
+    }
     result_iter = c.iter;
     if (!(c.chk_violation < tol) && c.iter < max_iter) {
         if ((st = S.run_phase<Src, true>(src, kModeExact, chunk, 0.0, c))) return st;
@@ -676,6 +818,7 @@ ot_status ot_assoc_default_options(ot_assoc_options* opt) {
     opt->chunk = 8;
     opt->use_graphs = 1;
     opt->batch_tune = 1;
+    opt->persistent = 1;
     return OT_OK;
 }
 
@@ -686,7 +829,7 @@ void ot_assoc_destroy(ot_assoc* h) {
     hipSetDevice(h->device);
     for (auto& e : h->graphs) hipGraphExecDestroy(e.exec);
     void* bufs[] = {h->a, h->b, h->f[0], h->f[1], h->g[0], h->g[1], h->col_part, h->res_part, h->stat_part,
-                    h->cpart, h->ctl, h->prm, h->bad, h->hist,
+                    h->cpart, h->ctl, h->prm, h->bad, h->hist, h->sync, h->gx,
                     h->xy_dev, h->xy_rrh, h->s_all, h->s_ex, h->j1, h->stage};
     for (void* p : bufs)
         if (p) hipFree(p);
@@ -726,6 +869,9 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     ot_assoc* h = new ot_assoc();
     h->device = o.device;
     if (hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, o.device) != hipSuccess) h->num_cu = 0;
+    if (hipDeviceGetAttribute(&h->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, o.device) != hipSuccess) h->lds_max = 0;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, o.device) != hipSuccess || !coop) h->lds_max = 0;
     h->stream = (hipStream_t)o.stream;
     h->opt = o;
     h->I_max = I_max;
@@ -747,6 +893,8 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     if (e == hipSuccess) e = al((void**)&h->prm, sizeof(SolveParams));
     if (e == hipSuccess) e = al((void**)&h->bad, sizeof(int));
     if (e == hipSuccess) e = al((void**)&h->hist, sizeof(unsigned long long) * 2048);
+    if (e == hipSuccess) e = al((void**)&h->sync, sizeof(uint32_t) * kSyncWords);
+    if (e == hipSuccess) e = al((void**)&h->gx, J8);
     if (e == hipSuccess) e = al((void**)&h->xy_dev, sizeof(float) * 2 * (size_t)I_max);
     if (e == hipSuccess) e = al((void**)&h->xy_rrh, sizeof(float) * 2 * (size_t)J_max);
     if (e == hipSuccess) e = al((void**)&h->s_all, I8);
@@ -785,44 +933,48 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
     if (warm_start && !(h->have_pot && h->I == I && h->J == J))
         return fail(h, OT_ESTATE, "warm start needs potentials of a %lld x %lld instance", (long long)I, (long long)J);
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
-    std::vector<double> ah, bh;
-    if ((st = read_vec(h, a, I, cost->mem, ah)) || (st = read_vec(h, b, J, cost->mem, bh))) return st;
-    for (double v : ah)
-        if (!(v > 0.0) || !std::isfinite(v)) return fail(h, OT_EINVAL, "device marginal a must be positive and finite");
-    for (double v : bh)
-        if (!(v > 0.0) || !std::isfinite(v)) return fail(h, OT_EINVAL, "RRH marginal b must be positive and finite");
-    const double sa = ksum(ah), sb = ksum(bh);
-    if (std::fabs(sa - sb) > 1e-12 * sa) return fail(h, OT_EINVAL, "marginals are unbalanced: sum a = %.17g, sum b = %.17g", sa, sb);
-
+    // marginals, constants and the initial control block are set up and
+    // checked on the device (no host round trip before the first sweep)
     const int res_par_prev = h->res_par;
     HIPCHK(h, hipEventRecord(h->ev_start, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->a, ah.data(), sizeof(double) * I, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->b, bh.data(), sizeof(double) * J, hipMemcpyHostToDevice, h->stream));
-    if (warm_start) {
-        if (res_par_prev != 0) {
-            HIPCHK(h, hipMemcpyAsync(h->f[0], h->f[1], sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
-            HIPCHK(h, hipMemcpyAsync(h->g[0], h->g[1], sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
-        }
-    } else {
-        HIPCHK(h, hipMemsetAsync(h->g[0], 0, sizeof(double) * J, h->stream));
+    const double* a_src = a;
+    const double* b_src = b;
+    if (cost->mem == OT_MEM_HOST) {
+        HIPCHK(h, hipMemcpyAsync(h->a, a, sizeof(double) * I, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->b, b, sizeof(double) * J, hipMemcpyHostToDevice, h->stream));
+        a_src = h->a;
+        b_src = h->b;
     }
-    SolveParams p{std::log2(std::exp(1.0)) / eps, eps};
-    HIPCHK(h, hipMemcpyAsync(h->prm, &p, sizeof p, hipMemcpyHostToDevice, h->stream));
+    if (warm_start && res_par_prev != 0) {
+        HIPCHK(h, hipMemcpyAsync(h->f[0], h->f[1], sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->g[0], h->g[1], sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
+    }
     Ctl c{};
     c.has_prev = warm_start ? 1 : 0;
     c.last_fp64 = 0;
     c.max_iter = max_iter;
     c.tol = tol;
-    c.mass = sa;
     c.r_last = __builtin_huge_val();
     for (double& r : c.r_hist) r = __builtin_huge_val();
-    std::memcpy(&h->ctl_h[0], &c, sizeof c);
-    HIPCHK(h, hipMemcpyAsync(h->ctl, &h->ctl_h[0], sizeof(Ctl), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));  // ctl_h[0] is reused as the initial-state mirror below
+    InitArgs ia{};
+    ia.I = I;
+    ia.J = (int)J;
+    ia.cold = warm_start ? 0 : 1;
+    ia.a_src = a_src;
+    ia.b_src = b_src;
+    ia.a = h->a;
+    ia.b = h->b;
+    ia.g0 = h->g[0];
+    ia.prm_out = h->prm;
+    ia.ctl_out = h->ctl;
+    ia.prm = SolveParams{std::log2(std::exp(1.0)) / eps, eps};
+    ia.ctl = c;
+    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(1024), 0, h->stream, ia);
+    HIPCHK(h, hipGetLastError());
 
     Ctl fin = c;
     int result_iter = 0;
-    st = upload_cost(h, cost, true);
+    st = upload_cost(h, cost, kCheckDeferred);
     if (!st)
         st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
             return solve_with(h, src, data, I, (int)J, tol, max_iter, fin, result_iter);
@@ -839,6 +991,24 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
     hipEventElapsedTime(&ms, h->ev_start, h->ev_stop);
     HIPCHK(h, hipGetLastError());
 
+    if (fin.input_bad) {  // rejected on the device: the handle keeps no result
+        h->solved = false;
+        h->have_pot = false;
+        h->retained = false;
+        const int fb = fin.input_bad;
+        if (fb & 1) return fail(h, OT_EINVAL, "device marginal a must be positive and finite");
+        if (fb & 2) return fail(h, OT_EINVAL, "RRH marginal b must be positive and finite");
+        if (fb & 4)
+            return fail(h, OT_EINVAL, "marginals are unbalanced: sum a = %.17g, sum b = %.17g", fin.mass, fin.mass_b);
+        if (cost->kind == OT_COST_GEOMETRY) return fail(h, OT_EINVAL, "geometry positions have non-finite entries");
+        return fail(h, OT_EINVAL, cost->kind == OT_COST_DENSE ? "cost matrix has non-finite entries"
+                                                              : "rate matrix has entries that are not finite and positive");
+    }
+    if (fin.sync_fail) {
+        h->solved = false;
+        h->have_pot = false;
+        return fail(h, OT_EDEVICE, "a grid barrier of the cooperative FP32 phase gave up waiting");
+    }
     h->I = I;
     h->J = J;
     h->eps = eps;
@@ -852,7 +1022,7 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
         out->iterations = result_iter;
         out->fp64_iterations = fin.fp64_iters;
         out->status = rs;
-        out->reserved = 0;
+        out->flags = h->last_persistent ? OT_RESULT_PERSISTENT : 0;
         out->marginal_violation = fin.chk_violation;
         out->objective = fin.chk_objective;
         out->reg_objective = fin.chk_reg_objective;
@@ -944,7 +1114,7 @@ ot_status ot_assoc_cost_median(ot_assoc* h, const ot_cost_desc* cost, double* me
     uint32_t prefix = 0;
     std::vector<unsigned long long> hh(2048);
     h->solved = false;  // the handle's retained cost is replaced below
-    st = upload_cost(h, &c, true);
+    st = upload_cost(h, &c, kCheckNow);
     if (st) return st;
     st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
         using S = std::decay_t<decltype(src)>;
@@ -986,7 +1156,7 @@ ot_status ot_assoc_materialize_cost(ot_assoc* h, const ot_cost_desc* cost, float
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
     const int64_t I = cost->I, J = cost->J;
     h->solved = false;  // the handle's retained cost is replaced below
-    st = upload_cost(h, cost, true);
+    st = upload_cost(h, cost, kCheckNow);
     if (st) return st;
     st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
         using S = std::decay_t<decltype(src)>;

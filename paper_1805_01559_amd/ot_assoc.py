@@ -26,6 +26,7 @@ OT_COST_DENSE, OT_COST_RATES, OT_COST_GEOMETRY = 0, 1, 2
 OT_MEM_HOST, OT_MEM_DEVICE = 0, 1
 OT_F32, OT_F64 = 0, 1
 OT_PREC_FP32, OT_PREC_FP64 = 0, 1
+OT_RESULT_PERSISTENT = 1
 
 # every symbol include/ot_assoc.h declares
 EXPORTS = [
@@ -53,16 +54,17 @@ class ot_cost_desc(ct.Structure):
 class ot_assoc_options(ct.Structure):
     _fields_ = [("device", ct.c_int), ("stream", ct.c_void_p), ("precision", ct.c_int), ("polish_iters", ct.c_int),
                 ("chunk", ct.c_int), ("use_graphs", ct.c_int), ("sweep_blocks", ct.c_int), ("sweep_waves", ct.c_int),
-                ("sweep_rows", ct.c_int), ("sweep_lanes", ct.c_int), ("batch_tune", ct.c_int)]
+                ("sweep_rows", ct.c_int), ("sweep_lanes", ct.c_int), ("batch_tune", ct.c_int),
+                ("persistent", ct.c_int)]
 
 
 class ot_assoc_result(ct.Structure):
     _fields_ = [("iterations", ct.c_int32), ("fp64_iterations", ct.c_int32), ("status", ct.c_int32),
-                ("reserved", ct.c_int32), ("marginal_violation", ct.c_double), ("objective", ct.c_double),
+                ("flags", ct.c_int32), ("marginal_violation", ct.c_double), ("objective", ct.c_double),
                 ("reg_objective", ct.c_double), ("dual_objective", ct.c_double), ("seconds", ct.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ot_serve_options(ct.Structure):

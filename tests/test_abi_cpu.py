@@ -44,7 +44,7 @@ def test_struct_layouts_match_the_header(tmp_path):
               "offsetof(ot_assoc_options, batch_tune)", "sizeof(ot_serve_options)",
               "offsetof(ot_serve_options, keep_layouts)", "sizeof(ot_request)", "offsetof(ot_request, layout_key)",
               "offsetof(ot_request, user_tag)", "sizeof(ot_completion)", "offsetof(ot_completion, result)",
-              "offsetof(ot_completion, t_done)"]
+              "offsetof(ot_completion, t_done)", "offsetof(ot_assoc_options, persistent)"]
     fmt = " ".join(["%zu"] * len(fields))
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ot_assoc.h"\n'
                    'int main(void){printf("' + fmt + '\\n", ' + ", ".join(fields) + ');return 0;}\n')
@@ -55,14 +55,14 @@ def test_struct_layouts_match_the_header(tmp_path):
             A.ot_cost_desc.geom.offset, A.ot_assoc_result.seconds.offset, A.ot_assoc_options.batch_tune.offset,
             ct.sizeof(A.ot_serve_options), A.ot_serve_options.keep_layouts.offset, ct.sizeof(A.ot_request),
             A.ot_request.layout_key.offset, A.ot_request.user_tag.offset, ct.sizeof(A.ot_completion),
-            A.ot_completion.result.offset, A.ot_completion.t_done.offset]
+            A.ot_completion.result.offset, A.ot_completion.t_done.offset, A.ot_assoc_options.persistent.offset]
     assert got == want
 
 
 def test_default_options(lib):
     o = A.ot_assoc_default_options()
-    assert (o.device, o.precision, o.polish_iters, o.chunk, o.use_graphs, o.batch_tune) == \
-        (0, A.OT_PREC_FP32, 1, 8, 1, 1)
+    assert (o.device, o.precision, o.polish_iters, o.chunk, o.use_graphs, o.batch_tune, o.persistent) == \
+        (0, A.OT_PREC_FP32, 1, 8, 1, 1, 1)
     s = A.ot_serve_default_options()
     assert (s.polish_iters, s.sweep_waves, s.rows_per_part, s.max_slots, s.budget_bytes) == (1, 8, 128, 0, 0.0)
 

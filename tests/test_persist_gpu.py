@@ -1,0 +1,192 @@
+"""GPU tests of the cooperative FP32 phase (ot_assoc_options.persistent): one
+launch that keeps the instance's FP32 cost in LDS and exchanges the column
+partials between workgroups through agent-scope atomics and grid barriers.
+
+Every case is solved with the cooperative launch and with the chunked graph
+launches, and both are held to the same bar against the FP64 oracle as the
+other parity tests (marginal violation < tol as reported and as recomputed by
+the oracle; transport cost within 1e-6 relative of the oracle's converged
+solution; plan L1 distance <= 1e-6). The result flag says which path ran;
+the LDS capacity boundary is tested on both sides.
+"""
+
+import numpy as np
+import pytest
+
+import scenario as S
+
+pytestmark = pytest.mark.gpu
+
+OBJ_RTOL = 1e-6
+PLAN_L1 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def A():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_01559_amd import ot_assoc
+    ot_assoc.lib()
+    return ot_assoc
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def check(O, C, a, b, eps, tol, f, g, res, ref):
+    chk = O.plan_stats(C, a, b, f, g, eps)
+    rst = O.plan_stats(C, a, b, ref.f, ref.g, eps)
+    assert res.marginal_violation < tol, res.marginal_violation
+    assert chk["marginal_violation"] < tol * 1.05, chk["marginal_violation"]
+    assert abs(chk["objective"] - rst["objective"]) <= OBJ_RTOL * abs(rst["objective"])
+    assert abs(res.objective - chk["objective"]) <= 1e-9 * abs(chk["objective"])
+    l1 = np.abs(O.plan(C, f, g, eps) - O.plan(C, ref.f, ref.g, eps)).sum()
+    assert l1 <= PLAN_L1, l1
+
+
+def random_case(I, J, seed):
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0.0, 1.0, size=(I, J)).astype(np.float32)
+    a = rng.uniform(0.5, 1.5, I)
+    a /= a.sum()
+    b = rng.uniform(0.5, 1.5, J)
+    b = b / b.sum() * a.sum()
+    return C, a, b
+
+
+def solve_both(A, I, J, fn):
+    out = {}
+    for pers in (1, 0):
+        with A.Solver(I, J, persistent=pers) as s:
+            st, res = fn(s)
+            f, g = s.potentials()
+            out[pers] = (st, res, f, g)
+    return out
+
+
+@pytest.mark.parametrize("I,J", [(1, 1), (2, 3), (50, 7), (1000, 50), (4097, 130), (6000, 400), (3000, 513), (900, 2048)])
+def test_dense_both_paths(A, oracle_lib, I, J):
+    announce(f"dense random {I}x{J}, cooperative and chunked")
+    C, a, b = random_case(I, J, 77 * I + J)
+    Cd = C.astype(np.float64)
+    eps, tol = 0.05, 1e-8
+    ref = oracle_lib.sinkhorn(Cd, a, b, eps, 1e-12, 20000)
+    out = solve_both(A, I, J, lambda s: s.solve_dense(C, a, b, eps, tol, 2000))
+    for pers, (st, res, f, g) in out.items():
+        assert st == A.OT_OK, (pers, st)
+        assert bool(res.flags & A.OT_RESULT_PERSISTENT) == bool(pers), (pers, res.flags)
+        check(oracle_lib, Cd, a, b, eps, tol, f, g, res, ref)
+    # the two paths run the same iteration; only summation orders differ
+    assert abs(out[1][1].iterations - out[0][1].iterations) <= 2
+
+
+def test_lds_capacity_boundary(A):
+    """20480 x 400 is the largest FP32 instance of 400 RRHs whose rows fit in
+    the LDS of 256 CUs (80 rows of 1600 bytes per workgroup); one more device
+    needs 96-row blocks, which do not fit, and the solve falls back to the
+    chunked launches."""
+    announce("LDS capacity boundary at J=400")
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    if props.multi_processor_count != 256:
+        pytest.skip("boundary computed for 256 CUs")
+    for I, expect in ((20480, 1), (20481, 0)):
+        C, a, b = random_case(I, 400, I)
+        with A.Solver(I, 400) as s:
+            st, res = s.solve_dense(C, a, b, 0.05, 1e-8, 2000)
+            assert st == A.OT_OK and res.marginal_violation < 1e-8
+            assert (res.flags & A.OT_RESULT_PERSISTENT) == expect, (I, res.flags)
+
+
+def test_cran_20000x400_cooperative(A, oracle_lib):
+    announce("cran_20000x400 dense, cooperative path against the oracle")
+    L = S.preset_layout("cran_20000x400")
+    C64, scale = oracle_lib.cost(L)
+    C32 = C64.astype(np.float32)
+    Cd = C32.astype(np.float64)
+    eps, tol = 0.02, 1e-8
+    ref = oracle_lib.sinkhorn(Cd, L.a, L.b, eps, 1e-11, 20000)
+    with A.Solver(L.I, L.J) as s:
+        st, res = s.solve_dense(C32, L.a, L.b, eps, tol, 2000)
+        assert st == A.OT_OK and res.flags & A.OT_RESULT_PERSISTENT
+        f, g = s.potentials()
+    check(oracle_lib, Cd, L.a, L.b, eps, tol, f, g, res, ref)
+
+
+def test_geometry_and_rates_both_paths(A, oracle_lib):
+    announce("geometry 3000x150 and FP32 rates, cooperative and chunked")
+    L = S.make_layout(3000, 150, 2000.0, hot_spots=2, hot_share=0.4, seed=5150)
+    C64, scale = oracle_lib.cost(L)
+    eps, tol = 0.05, 1e-8
+    ref = oracle_lib.sinkhorn(C64, L.a, L.b, eps, 1e-12, 20000)
+    out = solve_both(A, L.I, L.J, lambda s: s.solve_geometry(L.dev_xy, L.rrh_xy, L.radio, L.shadow_key, scale,
+                                                              L.a, L.b, eps, tol, 2000))
+    for pers, (st, res, f, g) in out.items():
+        assert st == A.OT_OK
+        assert bool(res.flags & A.OT_RESULT_PERSISTENT) == bool(pers)
+        check(oracle_lib, C64, L.a, L.b, eps, tol, f, g, res, ref)
+    # rates: C = (1 / R) / scale with R given in FP32
+    R = (1.0 / (C64 * scale)).astype(np.float32)
+    Cr = (1.0 / R.astype(np.float64)) / scale
+    ref_r = oracle_lib.sinkhorn(Cr, L.a, L.b, eps, 1e-12, 20000)
+    out = solve_both(A, L.I, L.J, lambda s: s.solve_rates(R, scale, L.a, L.b, eps, tol, 2000))
+    for pers, (st, res, f, g) in out.items():
+        assert st == A.OT_OK
+        assert bool(res.flags & A.OT_RESULT_PERSISTENT) == bool(pers)
+        check(oracle_lib, Cr, L.a, L.b, eps, tol, f, g, res, ref_r)
+
+
+def test_fp64_costs_take_the_chunked_path(A, oracle_lib):
+    announce("FP64 dense cost: no cooperative launch")
+    C, a, b = random_case(2000, 60, 9)
+    Cd = C.astype(np.float64) + 1e-3 * np.arange(60)[None, :]
+    ref = oracle_lib.sinkhorn(Cd, a, b, 0.05, 1e-12, 20000)
+    with A.Solver(2000, 60) as s:
+        st, res = s.solve_dense(Cd, a, b, 0.05, 1e-8, 2000)
+        assert st == A.OT_OK and not (res.flags & A.OT_RESULT_PERSISTENT)
+        f, g = s.potentials()
+    check(oracle_lib, Cd, a, b, 0.05, 1e-8, f, g, res, ref)
+
+
+def test_cooperative_max_iter_warm_start_and_determinism(A, oracle_lib):
+    announce("cooperative path: max_iter stop, warm start, bitwise determinism")
+    C, a, b = random_case(5000, 200, 21)
+    Cd = C.astype(np.float64)
+    eps = 0.05
+    with A.Solver(5000, 200) as s:
+        st, res = s.solve_dense(C, a, b, eps, 1e-12, 3)
+        assert st == A.OT_WARN_MAXITER and res.iterations == 3 and res.flags & A.OT_RESULT_PERSISTENT
+        st, r1 = s.solve_dense(C, a, b, eps, 1e-9, 2000)
+        f1, g1 = s.potentials()
+        st, r2 = s.solve_dense(C, a, b, eps, 1e-9, 2000)
+        f2, g2 = s.potentials()
+        assert np.array_equal(f1, f2) and np.array_equal(g1, g2) and r1.iterations == r2.iterations
+        st, r3 = s.solve_dense(C, a, b, eps, 1e-9, 2000, warm_start=True)
+        assert st == A.OT_OK and r3.iterations <= max(6, r1.iterations // 4)
+        assert r3.flags & A.OT_RESULT_PERSISTENT
+        f3, g3 = s.potentials()
+    ref = oracle_lib.sinkhorn(Cd, a, b, eps, 1e-12, 20000)
+    check(oracle_lib, Cd, a, b, eps, 1e-9, f3, g3, r3, ref)
+
+
+def test_cooperative_rejects_bad_inputs(A):
+    announce("cooperative path: inputs rejected on the device")
+    C, a, b = random_case(3000, 100, 4)
+    with A.Solver(3000, 100) as s:
+        bad = C.copy()
+        bad[1234, 56] = np.nan
+        with pytest.raises(A.OTError) as e:
+            s.solve_dense(bad, a, b, 0.05, 1e-8, 100)
+        assert e.value.status == A.OT_EINVAL and "non-finite" in str(e.value)
+        a2 = a.copy()
+        a2[7] = -a2[7]
+        with pytest.raises(A.OTError) as e:
+            s.solve_dense(C, a2, b, 0.05, 1e-8, 100)
+        assert e.value.status == A.OT_EINVAL and "marginal a" in str(e.value)
+        with pytest.raises(A.OTError) as e:
+            s.solve_dense(C, a, b * 1.5, 0.05, 1e-8, 100)
+        assert e.value.status == A.OT_EINVAL and "unbalanced" in str(e.value)
+        st, res = s.solve_dense(C, a, b, 0.05, 1e-8, 2000)
+        assert st == A.OT_OK and res.flags & A.OT_RESULT_PERSISTENT
