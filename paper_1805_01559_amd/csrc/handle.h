@@ -53,8 +53,7 @@ struct ot_assoc {
     otk::SolveParams* prm = nullptr;
     int* bad = nullptr;
     unsigned long long* hist = nullptr;
-    uint32_t* sync = nullptr;  // barrier words of the cooperative launch
-    double* gx = nullptr;      // J_max: the new g of each iteration of the cooperative launch
+    double* xch = nullptr;     // exchange block of the cooperative FP32 phase
     int lds_max = 0;           // LDS bytes a workgroup may allocate
     bool last_persistent = false;  // the last solve's FP32 phase was one cooperative launch
     float* xy_dev = nullptr;  // I_max x 2

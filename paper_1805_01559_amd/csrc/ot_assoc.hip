@@ -633,11 +633,12 @@ struct Solver {
 
 // ------------------------------------------------------ cooperative phase --
 // Shape of the LDS-resident FP32 phase: one workgroup of kPersistWaves waves
-// per CU, rows per workgroup a whole number of wave steps, lanes per row by J.
+// per CU, rows per workgroup a whole number of wave steps; lanes per row and
+// cells per lane by J (column q LPR + sub of a row belongs to lane sub).
 constexpr int kPersistWaves = 8;
 
 struct PersistPlan {
-    int lpr = 0, nch = 0, rpw = 0, nb = 0, Jp = 0, cpw = 0;
+    int lpr = 0, cpl = 0, ncl = 0, rpw = 0, nb = 0, Jp = 0, cpw = 0;
     size_t lds = 0;
 };
 
@@ -649,29 +650,44 @@ constexpr bool persist_source() { return Src::kTag == 1 || Src::kTag == 3 || Src
 
 template <class Src>
 bool persist_plan(const ot_assoc* h, int64_t I, int J, PersistPlan& p) {
-    if (!persist_source<Src>() || h->num_cu < 1 || h->lds_max < 1 || I < 1) return false;
-    if (J <= 128) { p.lpr = 16; }
-    else if (J <= 512) { p.lpr = 32; }
-    else if (J <= kMaxJ) { p.lpr = 64; }
-    else return false;
+    if (!persist_source<Src>() || h->num_cu < 1 || h->lds_max < 1 || I < 1 || !h->xch) return false;
+    // cells per lane: the smallest instantiated width that covers the row
+    if (J <= 512) {
+        p.lpr = 32;
+        const int n = (J + 31) / 32;
+        p.cpl = n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : n <= 13 ? 13 : 16;
+    } else if (J <= kMaxJ) {
+        p.lpr = 64;
+        p.cpl = J <= 1024 ? 16 : 32;
+    } else {
+        return false;
+    }
     const int slots = kPersistWaves * (64 / p.lpr);  // rows per wave step of the workgroup
     const int64_t per = (int64_t)h->num_cu * slots;
     const int64_t steps = (I + per - 1) / per;
-    p.nch = (J + 4 * p.lpr - 1) / (4 * p.lpr);
+    p.ncl = (J + p.lpr - 1) / p.lpr;
+    p.Jp = p.ncl * p.lpr;
     p.rpw = (int)(steps * slots);
     p.nb = (int)((I + p.rpw - 1) / p.rpw);
-    p.Jp = (J + 3) & ~3;
     p.cpw = (J + p.nb - 1) / p.nb;
     p.lds = persist_lds_bytes(p.rpw, J, p.Jp, kPersistWaves);
     // (a little LDS stays for the kernel's static arrays)
-    return p.nb <= h->num_cu && p.nb <= kMaxNb && p.lds + 2048 <= (size_t)h->lds_max;
+    return p.nb <= h->num_cu && p.nb <= kMaxCoopGroups && p.lds + 2048 <= (size_t)h->lds_max;
 }
 
 template <class Src>
-const void* persist_kernel(int lpr) {
-    if (lpr == 16) return (const void*)k_persist<Src, 4, 2, 16, kPersistWaves>;
-    if (lpr == 32) return (const void*)k_persist<Src, 4, 4, 32, kPersistWaves>;
-    return (const void*)k_persist<Src, 4, 8, 64, kPersistWaves>;
+const void* persist_kernel(int lpr, int cpl) {
+    if (lpr == 32) {
+        switch (cpl) {
+            case 2: return (const void*)k_persist<Src, 2, 32, kPersistWaves>;
+            case 4: return (const void*)k_persist<Src, 4, 32, kPersistWaves>;
+            case 8: return (const void*)k_persist<Src, 8, 32, kPersistWaves>;
+            case 13: return (const void*)k_persist<Src, 13, 32, kPersistWaves>;
+            default: return (const void*)k_persist<Src, 16, 32, kPersistWaves>;
+        }
+    }
+    if (cpl == 16) return (const void*)k_persist<Src, 16, 64, kPersistWaves>;
+    return (const void*)k_persist<Src, 32, 64, kPersistWaves>;
 }
 
 // Issues the cooperative FP32 phase. `launched` is false (and nothing is
@@ -681,7 +697,7 @@ template <class Src>
 ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const PersistPlan& p, double stall_below,
                       bool& launched) {
     launched = false;
-    const void* kern = persist_kernel<Src>(p.lpr);
+    const void* kern = persist_kernel<Src>(p.lpr, p.cpl);
     if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) != hipSuccess) {
         (void)hipGetLastError();
         return OT_OK;
@@ -696,10 +712,10 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
     A.I = I;
     A.J = J;
     A.Jp = p.Jp;
+    A.ncl = p.ncl;
     A.rpw = p.rpw;
     A.cpw = p.cpw;
-    A.nch = p.nch;
-    A.max_spin = 1 << 20;  // polls of at least ~1 us each: ~1 s before a barrier gives up
+    A.max_spin = 1 << 20;  // polls of at least ~1 us each: ~1 s before a wait gives up
     A.stall_below = stall_below;
     A.a = h->a;
     A.b = h->b;
@@ -707,13 +723,12 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
     A.f[1] = h->f[1];
     A.g[0] = h->g[0];
     A.g[1] = h->g[1];
-    A.part = h->col_part;
-    A.rpart = h->res_part;
-    A.gx = h->gx;
-    A.sync = h->sync;
+    A.xch = h->xch;
     A.ctl = h->ctl;
     A.prm = h->prm;
-    hipLaunchKernelGGL(k_sync_clear, dim3(1), dim3(256), 0, h->stream, h->sync, h->ctl);
+    const size_t nx = persist_exchange_doubles(p.nb, J);
+    hipLaunchKernelGGL(k_xch_clear, dim3((unsigned)std::min<size_t>(512, (nx + 255) / 256)), dim3(256), 0, h->stream,
+                       h->xch, nx, h->ctl);
     Src sv = src;
     void* args[] = {(void*)&A, (void*)&sv};
     const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)p.nb), dim3(kPersistWaves * 64), args,
@@ -829,7 +844,7 @@ void ot_assoc_destroy(ot_assoc* h) {
     hipSetDevice(h->device);
     for (auto& e : h->graphs) hipGraphExecDestroy(e.exec);
     void* bufs[] = {h->a, h->b, h->f[0], h->f[1], h->g[0], h->g[1], h->col_part, h->res_part, h->stat_part,
-                    h->cpart, h->ctl, h->prm, h->bad, h->hist, h->sync, h->gx,
+                    h->cpart, h->ctl, h->prm, h->bad, h->hist, h->xch,
                     h->xy_dev, h->xy_rrh, h->s_all, h->s_ex, h->j1, h->stage};
     for (void* p : bufs)
         if (p) hipFree(p);
@@ -893,8 +908,7 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     if (e == hipSuccess) e = al((void**)&h->prm, sizeof(SolveParams));
     if (e == hipSuccess) e = al((void**)&h->bad, sizeof(int));
     if (e == hipSuccess) e = al((void**)&h->hist, sizeof(unsigned long long) * 2048);
-    if (e == hipSuccess) e = al((void**)&h->sync, sizeof(uint32_t) * kSyncWords);
-    if (e == hipSuccess) e = al((void**)&h->gx, J8);
+    if (e == hipSuccess) e = al((void**)&h->xch, sizeof(double) * persist_exchange_doubles(kMaxCoopGroups, (int)J_max));
     if (e == hipSuccess) e = al((void**)&h->xy_dev, sizeof(float) * 2 * (size_t)I_max);
     if (e == hipSuccess) e = al((void**)&h->xy_rrh, sizeof(float) * 2 * (size_t)J_max);
     if (e == hipSuccess) e = al((void**)&h->s_all, I8);

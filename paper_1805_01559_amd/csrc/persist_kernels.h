@@ -4,31 +4,43 @@
 // block of rows, fills its LDS with their costs once (read from the matrix,
 // or regenerated from positions), and then runs Sinkhorn iterations
 // (Sec. III-B, the alternating row and column updates of the dual
-// potentials) until the device-side stop rule fires:
+// potentials) until the device-side stop rule fires. Iteration k:
 //
-//   1. row update of its rows from the LDS tile: f_i, the row residual of the
-//      previous iterate and the column partials of the half-iterate, exactly
-//      as in the streaming sweep (FP32 exponentials, FP64 arguments and sums);
-//   2. the partials go to a global exchange block; grid barrier;
-//   3. workgroup w combines columns [w cpw, (w + 1) cpw) over all workgroups
-//      in a fixed order and writes the new g_j; workgroup 0 also sums the
-//      residual and takes the stop decision; grid barrier;
-//   4. every workgroup reads the new g and the decision.
+//   1. row update of the workgroup's rows from the LDS tile: f_i, the row
+//      residual of the previous iterate and the column partials of the
+//      half-iterate (FP32 exponentials, FP64 arguments, FP64 sums across
+//      lanes, rows and workgroups), published to an exchange buffer;
+//   2. workgroup w owns columns [w cpw, (w + 1) cpw): it collects their
+//      partials from every workgroup, sums them in a fixed order and
+//      publishes the new g_j; workgroup 0 also sums the residuals and
+//      publishes the stop decision;
+//   3. every workgroup collects the new g and the decision.
 //
-// Only the O(I + J) potentials and the O(nb J) partials move per iteration;
-// the I x J cost is read from HBM once per launch instead of once per
-// iteration, and the two kernel boundaries per iteration of the chunked
-// launches become two grid barriers.
+// Only O(I + J) potentials and O(nb J) partials move per iteration; the
+// I x J cost is read once per launch instead of once per iteration.
 //
-// Cross-workgroup data never goes through a memory fence: on this GPU the L2
-// of an XCD is not coherent with the other XCDs' L2s, and an agent-scope
-// release writes its whole L2 back. Every exchanged value is instead stored
-// and loaded with agent-scope relaxed atomics (stores that write through the
-// L2, loads that are served at the device's coherence point); each thread
-// waits for its own stores to complete before its workgroup signals arrival,
-// and arrival and release go through agent-scope atomic counters. Every wait
-// is bounded: a workgroup that polls too long sets an abort word that
-// releases all others, and the launch ends with its control block marked.
+// Exchange without fences or barriers. On this GPU the L2 of an XCD is not
+// coherent with the other XCDs' L2s, and an agent-scope release writes a
+// whole L2 back; so every exchanged value is stored and loaded with
+// agent-scope relaxed atomics (stores that write through the L2, loads served
+// at the device's coherence point), and a reader simply polls each slot
+// until it no longer holds kEmpty, a signalling-NaN bit pattern that no
+// arithmetic produces (results that are NaN are quiet NaNs). Slots are
+// emptied again by their single reader before they are reused:
+//   * partials (2 buffers by iteration parity): the owner of column j
+//     empties its column after reading it; the producer writes it again two
+//     iterations later, after it has read a g that the owner published
+//     after the emptying stores had completed;
+//   * new g (3 buffers by iteration mod 3): at iteration k the owner of
+//     column j empties slot (k + 2) mod 3, whose value (iteration k - 1)
+//     every workgroup has read by then, and readers poll that slot only at
+//     iteration k + 2;
+//   * the decision word carries its iteration number and is never emptied.
+// "Completed" is made explicit: each owner waits for all its memory
+// operations (s_waitcnt vmcnt(0)) before it starts collecting an iteration.
+// Every poll is bounded: a workgroup that waits too long sets an abort word
+// that releases every other poller, and the launch ends with its control
+// block marked.
 #pragma once
 
 #include "kernels.h"
@@ -42,78 +54,93 @@ __device__ __forceinline__ void put_agent(double* p, double v) {
 __device__ __forceinline__ double get_agent(const double* p) {
     return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void put_agent(uint32_t* p, uint32_t v) {
+__device__ __forceinline__ void put_agent(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t get_agent(const uint32_t* p) {
-    return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t get_agent(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Words of the barrier block (uint32), each on a 256-byte line of its own:
-// [0] top counter, then one arrival counter and one release word per group,
-// then the abort word and the stop-decision / numeric-failure pair.
-constexpr int kSyncGroups = 16;
-constexpr int kSyncLine = 64;
-constexpr int kSyncArrive = kSyncLine;
-constexpr int kSyncRelease = kSyncLine * (1 + kSyncGroups);
-constexpr int kSyncAbort = kSyncLine * (1 + 2 * kSyncGroups);
-constexpr int kSyncDec = kSyncAbort + kSyncLine;  // stop decision; the next word flags a numeric failure
-constexpr int kSyncBad = kSyncDec + 1;
-constexpr int kSyncWords = kSyncDec + kSyncLine;
+constexpr uint64_t kEmpty = 0x7FF4000000000BADull;  // signalling NaN with a payload
+__device__ __forceinline__ bool is_empty(double x) { return (uint64_t)__double_as_longlong(x) == kEmpty; }
 
-// Grid barrier number `round` (1, 2, ... within a launch; the words start at
-// zero). Workgroup b arrives on the counter of group b mod G; the last
-// arrival of a group bumps the top counter, and the last group to arrive
-// writes the round into every group's release word, which the group polls.
-// Returns false once any workgroup has given up (poll bound or abort word).
-__device__ bool grid_sync(uint32_t* sync, uint32_t round, int max_spin) {
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's exchange stores have completed
-    __syncthreads();
-    __shared__ int s_ok;
-    if (threadIdx.x == 0) {
-        const int G = min((int)gridDim.x, kSyncGroups);
-        const int grp = (int)(blockIdx.x % (unsigned)G);
-        const uint32_t gsize = (gridDim.x - (unsigned)grp + (unsigned)G - 1) / (unsigned)G;
-        const uint32_t old = __hip_atomic_fetch_add(sync + kSyncArrive + kSyncLine * grp, 1u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 == gsize * round) {
-            const uint32_t top = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (top + 1 == (uint32_t)G * round)
-                for (int q = 0; q < G; ++q) put_agent(sync + kSyncRelease + kSyncLine * q, round);
-        }
-        int ok = 1, n = 0;
-        while (get_agent(sync + kSyncRelease + kSyncLine * grp) < round) {
-            if ((++n & 31) == 0 && (get_agent(sync + kSyncAbort) != 0u || n > max_spin)) {
-                put_agent(sync + kSyncAbort, 1u);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        s_ok = ok;
+constexpr int kPollLoads = 4;                   // exchange slots per lane in one poll
+constexpr int kMaxCoopGroups = kPollLoads * kWave;  // workgroups a column owner can collect from
+
+// Layout of the exchange block (doubles):
+//   part  [2][J][nb]   column partials by iteration parity (a column's
+//                      partials are contiguous for its owner)
+//   rpart [2][nb]      row-residual partials by parity
+//   gx    [3][J]       new g by iteration mod 3
+//   dec   [2]          (iteration << 2) | stop, as uint64, by parity
+//   abort [1]          uint64, nonzero once a poll gave up
+__host__ __device__ inline size_t persist_exchange_doubles(int nb, int J) {
+    return (size_t)2 * nb * J + (size_t)2 * nb + (size_t)3 * J + 3;
+}
+
+// Polls up to U slots per lane of one wave, slot u of lane l at
+// base[(u 64 + l) stride] for u 64 + l < n, until none is empty (all loads
+// of a round are in flight together); absent slots read 0. Returns false if
+// the wait gave up (bound reached or abort word set).
+template <int U>
+__device__ bool poll_slots(const double* base, int64_t stride, int n, double (&x)[U], uint64_t* abort_word,
+                           int max_spin) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int p = u * kWave + lane;
+        x[u] = p < n ? get_agent(base + (int64_t)p * stride) : 0.0;
     }
-    __syncthreads();
-    return s_ok != 0;
+    int spin = 0;
+    for (;;) {
+        bool pend = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) pend |= is_empty(x[u]);
+        if (!__any(pend)) return true;
+        if ((++spin & 31) == 0 && (get_agent(abort_word) != 0 || spin > max_spin)) {
+            put_agent(abort_word, (uint64_t)1);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = u * kWave + lane;
+            if (is_empty(x[u])) x[u] = get_agent(base + (int64_t)p * stride);
+        }
+    }
+}
+constexpr int kGPollLoads = 8;  // new-g slots per lane in one poll (512 columns)
+
+// Single-slot poll (one value per thread).
+__device__ bool poll_one(const double* p, double& x, uint64_t* abort_word, int max_spin) {
+    x = get_agent(p);
+    int spin = 0;
+    while (is_empty(x)) {
+        if ((++spin & 31) == 0 && (get_agent(abort_word) != 0 || spin > max_spin)) {
+            put_agent(abort_word, (uint64_t)1);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        x = get_agent(p);
+    }
+    return true;
 }
 
 // ------------------------------------------------------- persistent solve --
 struct PersistArgs {
     int64_t I;
     int J;
-    int Jp;   // LDS row stride of the cost tile (J rounded up to 4; padding reads +inf)
+    int Jp;   // LDS row stride of the cost tile (ncl * LPR; padding reads +inf)
+    int ncl;  // cells per lane of a row: column q LPR + sub for q < ncl (<= CPL)
     int rpw;  // rows per workgroup: a whole number of wave steps
     int cpw;  // columns per workgroup in the combine step
-    int nch;  // column chunks of LPR * VEC used (<= NCH)
     int max_spin;
     double stall_below;
     const double* a;
     const double* b;
     double* f[2];  // iterate k lives in f[k & 1], g[k & 1]
     double* g[2];
-    double* part;   // gridDim.x x J column partials
-    double* rpart;  // gridDim.x row-residual partials
-    double* gx;     // J: the new g of each iteration
-    uint32_t* sync;
+    double* xch;   // exchange block (persist_exchange_doubles)
     Ctl* ctl;
     const SolveParams* prm;
 };
@@ -121,30 +148,43 @@ struct PersistArgs {
 // Dynamic LDS of k_persist in bytes (the layout the kernel carves).
 __host__ __device__ inline size_t persist_lds_bytes(int rpw, int J, int Jp, int waves) {
     const size_t Jr2 = (size_t)((J + 1) & ~1), Jr4 = (size_t)((J + 3) & ~3);
-    return (size_t)rpw * Jp * 4 + Jr2 * 8 + 3 * (size_t)rpw * 8 + (size_t)waves * Jr4 * 4;
+    return (size_t)rpw * Jp * 4 + Jr2 * 8 + 4 * (size_t)rpw * 8 + (size_t)waves * Jr4 * 4;
 }
 
-template <class Src, int VEC, int NCH, int LPR, int WAVES>
+// Lane layout: a row is handled by LPR lanes (32 or 64); lane `sub` owns
+// columns q LPR + sub, q < CPL, so consecutive lanes read consecutive LDS
+// words. Every cell is processed without a branch (branches around LDS reads
+// would serialise their latencies): cells q >= ncl re-read the row's last
+// chunk and get g = -inf, i.e. a zero term. A wave advances R = 64 / LPR
+// rows per step.
+template <class Src, int CPL, int LPR, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src src) {
     extern __shared__ double sm[];
     constexpr int R = kWave / LPR;
     constexpr int T = WAVES * kWave;
-    constexpr int kPartLoads = 4;  // exchange loads in flight per lane
-    const int J = A.J, Jp = A.Jp, rpw = A.rpw, nch = A.nch;
+    const int J = A.J, Jp = A.Jp, rpw = A.rpw, ncl = A.ncl;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int sub = lane % LPR, rg = lane / LPR;
-    const int64_t r0 = (int64_t)blockIdx.x * rpw;
+    const int nb = (int)gridDim.x, blk = (int)blockIdx.x;
+    const int64_t r0 = (int64_t)blk * rpw;
     const int nrows = (int)max((int64_t)0, min((int64_t)rpw, A.I - r0));
     const int Jr2 = (J + 1) & ~1, Jr4 = (J + 3) & ~3;
     float* tile = reinterpret_cast<float*>(sm);
     double* graw = reinterpret_cast<double*>(tile + (size_t)rpw * Jp);
-    double* fl = graw + Jr2;
-    double* al = fl + rpw;
-    double* lal = al + rpw;
-    float* red = reinterpret_cast<float*>(lal + rpw);
+    double* fl = graw + Jr2;   // f_i of the current iterate
+    double* al = fl + rpw;     // a_i
+    double* lal = al + rpw;    // ln a_i
+    double* lse = lal + rpw;   // log2 sum_j 2^(g_j kk - C_ij kk) of the last row update
+    float* red = reinterpret_cast<float*>(lse + rpw);
     __shared__ Ctl cs;  // workgroup 0: the control block for the whole launch
     __shared__ double wres[WAVES];
     __shared__ uint32_t s_dec;
+
+    double* part = A.xch;
+    double* rpart = part + (size_t)2 * nb * J;
+    double* gx = rpart + (size_t)2 * nb;
+    uint64_t* dec = reinterpret_cast<uint64_t*>(gx + (size_t)3 * J);
+    uint64_t* abort_word = dec + 2;
 
     Ctl* ctl = A.ctl;
     if (ctl->stop | ctl->done) return;  // the same words for every workgroup
@@ -175,8 +215,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             for (int j = lane; j < Jp; j += kWave) trow[j] = __builtin_huge_valf();
         }
     }
-    // 2. the rows' a_i, ln a_i and current f_i; the current g; ln b_j of the
-    //    columns this workgroup combines (one per wave)
+    // 2. the rows' a_i, ln a_i and current f_i; the current g
     const double* f_in = A.f[k0 & 1];
     for (int lr = threadIdx.x; lr < rpw; lr += T) {
         const bool ok = lr < nrows;
@@ -184,53 +223,49 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
         al[lr] = ai;
         lal[lr] = ok ? log(ai) : 0.0;
         fl[lr] = (ok && has_prev) ? f_in[r0 + lr] : 0.0;
+        lse[lr] = 0.0;
     }
     const double* g_in = A.g[k0 & 1];
     for (int j = threadIdx.x; j < J; j += T) graw[j] = g_in[j];
-    if (blockIdx.x == 0 && threadIdx.x == 0) cs = *ctl;
+    if (blk == 0 && threadIdx.x == 0) cs = *ctl;
     __syncthreads();
 
-    // g_j kk of this lane's columns, FP64 and FP32 (-inf past J)
-    double gk[NCH][VEC];
-    float gk32[NCH][VEC];
+    // g_j kk of this lane's columns (-inf past J)
+    double gk[CPL];
     auto load_g = [&]() {
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                const int col = (ch * LPR + sub) * VEC + v;
-                const double x = (ch < nch && col < J) ? graw[col] * kk : -pinf64();
-                gk[ch][v] = x;
-                gk32[ch][v] = (float)x;
-            }
+        for (int q = 0; q < CPL; ++q) {
+            const int j = q * LPR + sub;
+            gk[q] = (q < ncl && j < J) ? graw[j] * kk : -pinf64();
+        }
     };
     load_g();
 
     const int steps = rpw / (WAVES * R);
-    const int nb = (int)gridDim.x;
-    uint32_t round = 0;
     int k = k0;
     bool ok = true;
+    bool exact_shift = true;  // first row update of the launch: shift by the row maximum
     for (;;) {
         ++k;
+        const int P = k & 1;
         // ---- 1. row update from the LDS tile
-        float acc[NCH][VEC];
+        float acc[CPL];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[ch][v] = 0.0f;
+        for (int q = 0; q < CPL; ++q) acc[q] = 0.0f;
         double res = 0.0;
-        // Row outputs (f_i and the residual term) need only (m_i, S_i): lane L
-        // keeps those of the wave's L-th row since the last flush, and a flush
-        // finishes up to 64 rows at once, so the FP64 logarithm and expm1 run
-        // once per 64 rows instead of once per row.
+        // Row outputs (f_i, the next shift and the residual term) need only
+        // (shift, S_i): lane L keeps those of the wave's L-th row since the
+        // last flush, and a flush finishes up to 64 rows at once, so the FP64
+        // logarithm and expm1 run once per 64 rows instead of once per row.
         double stash_m = 0.0, stash_S = 1.0;
         int stash_lr = -1, nstash = 0;
         auto flush = [&]() {
             if (lane < nstash && stash_lr < nrows) {
-                const double fi = eps * (lal[stash_lr] - kLn2 * (stash_m + log2(stash_S)));
+                const double L2 = stash_m + log2(stash_S);
+                const double fi = eps * (lal[stash_lr] - kLn2 * L2);
                 if (has_prev) res += al[stash_lr] * fabs(expm1((fl[stash_lr] - fi) * inv_eps));
                 fl[stash_lr] = fi;
+                lse[stash_lr] = L2;
             }
             nstash = 0;
         };
@@ -238,51 +273,52 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             const int lr0 = (st * WAVES + w) * R;
             const int lr = lr0 + rg;
             const bool vrow = lr < nrows;
-            const float* trow = tile + (size_t)lr * Jp;
-            float cv[NCH][VEC];
+            const float* trow = tile + (size_t)lr * Jp + sub;
+            float cv[CPL];
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                const int col0 = (ch * LPR + sub) * VEC;
-                if (ch < nch && col0 < J) {
-                    if constexpr (VEC == 4) {
-                        const float4 y = *reinterpret_cast<const float4*>(trow + col0);
-                        cv[ch][0] = y.x; cv[ch][1] = y.y; cv[ch][2] = y.z; cv[ch][3] = y.w;
-                    } else {
+            for (int q = 0; q < CPL; ++q) cv[q] = trow[min(q, ncl - 1) * LPR];
+            // shift: the row's previous log-sum-exp (any value near the row
+            // maximum keeps the FP32 exponentials in range), or the maximum
+            double m = lse[lr];
+            float ev[CPL];
+            float s = 0.0f, s2 = 0.0f;  // even and odd cells: two shorter add chains
+            bool redo = exact_shift;
+            if (!redo) {
 #pragma unroll
-                        for (int v = 0; v < VEC; ++v) cv[ch][v] = trow[col0 + v];
-                    }
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) cv[ch][v] = __builtin_huge_valf();
+                for (int q = 0; q < CPL; ++q) {
+                    const double t = fma((double)cv[q], -kk, gk[q]) - m;
+                    const float e = exp2_f32((float)t);
+                    ev[q] = e;
+                    if (q & 1) s2 += e;
+                    else s += e;
                 }
             }
-            // row maximum (an FP32 estimate: it only sets the shift)
-            float mx = -__builtin_huge_valf();
+            double S = group_sum<LPR>((double)(s + s2));
+            // a sum far from 1 means the shift drifted too far from the row
+            // maximum for FP32 exponentials: redo the wave's rows with the maximum
+            redo = __any(redo || (vrow && !(S >= 0x1p-100 && S <= 0x1p100)));
+            if (redo) {
+                float mx = -__builtin_huge_valf();
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
+                for (int q = 0; q < CPL; ++q) mx = fmaxf(mx, fmaf(cv[q], -kk32, (float)gk[q]));
+                m = fmax((double)group_max<LPR>(mx), -1e300);
+                s = 0.0f;
+                s2 = 0.0f;
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) mx = fmaxf(mx, fmaf(cv[ch][v], -kk32, gk32[ch][v]));
-            const double m = fmax((double)group_max<LPR>(mx), -1e300);
-            // exponentials (FP64 arguments) and the row sum
-            float ev[NCH][VEC];
-            float s = 0.0f;
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    const double t = fma((double)cv[ch][v], -kk, gk[ch][v]) - m;
+                for (int q = 0; q < CPL; ++q) {
+                    const double t = fma((double)cv[q], -kk, gk[q]) - m;
                     const float e = exp2_f32((float)t);
-                    ev[ch][v] = e;
-                    s += e;
+                    ev[q] = e;
+                    if (q & 1) s2 += e;
+                    else s += e;
                 }
-            const double S = group_sum<LPR>((double)s);
+                S = group_sum<LPR>((double)(s + s2));
+            }
             // column partials of the half-iterate plan, pi_ij = e_ij a_i / S_i
             const float wq = vrow ? (float)al[lr] * __builtin_amdgcn_rcpf((float)S) : 0.0f;
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[ch][v] = fmaf(ev[ch][v], wq, acc[ch][v]);
-            // hand (m, S) of each row group to lane nstash + group
+            for (int q = 0; q < CPL; ++q) acc[q] = fmaf(ev[q], wq, acc[q]);
+            // hand (shift, S) of each row group to lane nstash + group
             const int src_lane = (lane - nstash) * LPR;
             const int sl = (src_lane < 0 || src_lane >= kWave) ? 0 : src_lane;
             const double mm = __shfl(m, sl, kWave);
@@ -296,97 +332,128 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             if (nstash == kWave) flush();
         }
         flush();
-        // ---- 2. the workgroup's partials: fold the row groups of a wave
-        //         (lanes sub + LPR q share columns), then the waves in FP64
+        exact_shift = false;
+        // ---- the workgroup's partials: fold the row groups of a wave (lanes
+        //      sub + LPR r share columns), then the waves in FP64, published
 #pragma unroll
         for (int o = LPR; o < kWave; o <<= 1)
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[ch][v] += __shfl_xor(acc[ch][v], o, kWave);
+            for (int q = 0; q < CPL; ++q) acc[q] += __shfl_xor(acc[q], o, kWave);
         res = wave_sum(res);
         if (lane == 0) wres[w] = res;
         if (rg == 0) {
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    const int col = (ch * LPR + sub) * VEC + v;
-                    if (ch < nch && col < J) red[w * Jr4 + col] = acc[ch][v];
-                }
+            for (int q = 0; q < CPL; ++q) {
+                const int j = q * LPR + sub;
+                if (q < ncl && j < J) red[w * Jr4 + j] = acc[q];
+            }
         }
+        // earlier emptying stores of this workgroup have completed (they were
+        // issued an iteration ago, so this costs nothing; waiting after the
+        // partial stores below would add their latency)
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        double* prow = A.part + (size_t)blockIdx.x * J;
+        double* pcol = part + (size_t)P * J * nb + blk;
         for (int c = threadIdx.x; c < J; c += T) {
             double t = 0.0;
 #pragma unroll
             for (int q = 0; q < WAVES; ++q) t += (double)red[q * Jr4 + c];
-            put_agent(prow + c, t);
+            put_agent(pcol + (size_t)c * nb, t);
         }
         if (threadIdx.x == 0) {
             double r = 0.0;
 #pragma unroll
             for (int q = 0; q < WAVES; ++q) r += wres[q];
-            put_agent(A.rpart + blockIdx.x, r);
+            put_agent(rpart + (size_t)P * nb + blk, r);
         }
-        if (!(ok = grid_sync(A.sync, ++round, A.max_spin))) break;
 
-        // ---- 3. column update of this workgroup's columns, one wave per
-        //         column; the partials are summed lane-strided in a fixed order
-        //         with kPartLoads loads in flight per lane
+        // ---- 2. column update of the owned columns, one wave per column
+        bool fail = false;
         for (int q = w; q < A.cpw; q += WAVES) {
-            const int j = (int)blockIdx.x * A.cpw + q;
+            const int j = blk * A.cpw + q;
             if (j >= J) break;
+            const double bj = A.b[j];
+            double x[kPollLoads];
+            const double* col = part + ((size_t)P * J + j) * nb;
+            if (!poll_slots(col, 1, nb, x, abort_word, A.max_spin)) { fail = true; break; }
             double s = 0.0;
-            for (int p0 = 0; p0 < nb; p0 += kWave * kPartLoads) {
-                double x[kPartLoads];
 #pragma unroll
-                for (int u = 0; u < kPartLoads; ++u) {
-                    const int p = p0 + u * kWave + lane;
-                    x[u] = p < nb ? get_agent(A.part + (size_t)p * J + j) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < kPartLoads; ++u) s += x[u];
-            }
+            for (int u = 0; u < kPollLoads; ++u) s += x[u];
             const double csum = wave_sum(s);
             if (lane == 0) {
-                const double gn = graw[j] + eps * (log(A.b[j]) - log(csum));
-                put_agent(A.gx + j, gn);
-                if (!isfinite(gn)) put_agent(A.sync + kSyncBad, 1u);
+                put_agent(gx + (size_t)(k % 3) * J + j, graw[j] + eps * (log(bj) - log(csum)));
+                put_agent(gx + (size_t)((k + 2) % 3) * J + j, __longlong_as_double((long long)kEmpty));
+            }
+            // (emptied after g is published: the slots are reused two iterations on)
+#pragma unroll
+            for (int u = 0; u < kPollLoads; ++u) {
+                const int p = u * kWave + lane;
+                if (p < nb) put_agent(const_cast<double*>(col) + p, __longlong_as_double((long long)kEmpty));
             }
         }
-        if (blockIdx.x == 0 && w == 0) {  // residual of iterate k - 1 and the stop rule
-            double r = 0.0;
-            for (int p0 = 0; p0 < nb; p0 += kWave * kPartLoads) {
-                double x[kPartLoads];
+        if (blk == 0 && w == WAVES - 1 && !fail) {  // residual of iterate k - 1 and the stop rule
+            double x[kPollLoads];
+            const double* rp = rpart + (size_t)P * nb;
+            if (!poll_slots(rp, 1, nb, x, abort_word, A.max_spin)) {
+                fail = true;
+            } else {
+                double r = 0.0;
 #pragma unroll
-                for (int u = 0; u < kPartLoads; ++u) {
-                    const int p = p0 + u * kWave + lane;
-                    x[u] = p < nb ? get_agent(A.rpart + p) : 0.0;
+                for (int u = 0; u < kPollLoads; ++u) r += x[u];
+#pragma unroll
+                for (int u = 0; u < kPollLoads; ++u) {
+                    const int p = u * kWave + lane;
+                    if (p < nb) put_agent(const_cast<double*>(rp) + p, __longlong_as_double((long long)kEmpty));
+                }
+                r = wave_sum(r);
+                if (lane == 0) {
+                    bookkeep(&cs, r, kModeFast, A.stall_below);
+                    put_agent(dec + P, ((uint64_t)k << 2) | (uint64_t)((cs.stop | cs.done) ? 1 : 0));
+                }
+            }
+        }
+
+        __syncthreads();  // the combine above still reads the old g from LDS
+
+        // ---- 3. the new g and the decision
+        bool bad = false;
+        if (!fail && w == 0) {  // (one wave polls: fewer requests in flight at the coherence point)
+            const double* gk_new = gx + (size_t)(k % 3) * J;
+            for (int j0 = 0; j0 < J; j0 += kGPollLoads * kWave) {
+                double x[kGPollLoads];
+                if (!poll_slots(gk_new + j0, 1, min(J - j0, kGPollLoads * kWave), x, abort_word, A.max_spin)) {
+                    fail = true;
+                    break;
                 }
 #pragma unroll
-                for (int u = 0; u < kPartLoads; ++u) r += x[u];
-            }
-            r = wave_sum(r);
-            if (lane == 0) {
-                bookkeep(&cs, r, kModeFast, A.stall_below);
-                put_agent(A.sync + kSyncDec, (cs.stop | cs.done) ? 1u : 0u);
+                for (int u = 0; u < kGPollLoads; ++u) {
+                    const int j = j0 + u * kWave + lane;
+                    if (j < J) {
+                        graw[j] = x[u];
+                        bad |= !isfinite(x[u]);
+                    }
+                }
             }
         }
-        if (!(ok = grid_sync(A.sync, ++round, A.max_spin))) break;
-
-        // ---- 4. the new g and the decision (one load of the word pair)
-        for (int j = threadIdx.x; j < J; j += T) graw[j] = get_agent(A.gx + j);
-        if (threadIdx.x == 0) {
-            const uint64_t pair = __hip_atomic_load(reinterpret_cast<uint64_t*>(A.sync + kSyncDec), __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-            s_dec = (uint32_t)pair | ((uint32_t)(pair >> 32) << 1);
+        if (threadIdx.x == (WAVES > 1 ? kWave : 0) && !fail) {  // the decision, polled by another wave
+            uint64_t d = get_agent(dec + P);
+            int spin = 0;
+            while ((d >> 2) != (uint64_t)k) {
+                if ((++spin & 31) == 0 && (get_agent(abort_word) != 0 || spin > A.max_spin)) {
+                    put_agent(abort_word, (uint64_t)1);
+                    fail = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                d = get_agent(dec + P);
+            }
+            s_dec = (uint32_t)(d & 3);
         }
-        __syncthreads();
-        const uint32_t dec = s_dec;
+        if (__syncthreads_or(fail)) { ok = false; break; }
+        const bool bad_any = __syncthreads_or(bad);
         has_prev = 1;
-        if (dec) {
-            if ((dec & 2u) && blockIdx.x == 0 && threadIdx.x == 0) {
+        if (s_dec || bad_any) {
+            if (bad_any && blk == 0 && threadIdx.x == 0) {
                 cs.numeric_bad = 1;
                 cs.done = 1;
                 cs.stop = 1;
@@ -401,12 +468,12 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     if (ok) {
         double* fo = A.f[k & 1];
         for (int lr = threadIdx.x; lr < nrows; lr += T) fo[r0 + lr] = fl[lr];
-        if (blockIdx.x == 0) {
+        if (blk == 0) {
             double* go = A.g[k & 1];
             for (int j = threadIdx.x; j < J; j += T) go[j] = graw[j];
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         if (!ok) {
             cs.sync_fail = 1;
             cs.done = 1;
@@ -417,10 +484,14 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     }
 }
 
-// Zeroes the barrier block and clears the stop flag before a persistent launch.
-static __global__ void k_sync_clear(uint32_t* sync, Ctl* ctl) {
-    for (int q = threadIdx.x; q < kSyncWords; q += blockDim.x) sync[q] = 0u;
-    if (threadIdx.x == 0) ctl->stop = 0;
+// Empties the exchange block and clears the stop flag before a persistent
+// launch (grid-stride; any grid).
+static __global__ void k_xch_clear(double* xch, size_t n_slots, Ctl* ctl) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t n = n_slots - 3;  // the decision and abort words start at zero
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_slots; q += stride)
+        xch[q] = q < n ? __longlong_as_double((long long)kEmpty) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->stop = 0;
 }
 
 // Between the FP32 phase and the FP64 polish, decided on the device: the
@@ -483,11 +554,24 @@ static __global__ __launch_bounds__(1024) void k_solve_init(InitArgs A) {
     __syncthreads();
     double sa = 0.0, ca = 0.0, sb = 0.0, cb = 0.0;
     int bad = 0;
-    for (int64_t i = threadIdx.x; i < A.I; i += blockDim.x) {
-        const double v = A.a_src[i];
-        if (!(v > 0.0) || !isfinite(v)) bad |= 1;
-        if (A.a != A.a_src) A.a[i] = v;
-        two_sum_add(sa, ca, v);
+    // (eight loads in flight per thread, then their terms in index order)
+    const int64_t n8 = (int64_t)blockDim.x * 8;
+    for (int64_t i0 = threadIdx.x; i0 < A.I; i0 += n8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x;
+            v[u] = i < A.I ? A.a_src[i] : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x;
+            if (i < A.I) {
+                if (!(v[u] > 0.0) || !isfinite(v[u])) bad |= 1;
+                if (A.a != A.a_src) A.a[i] = v[u];
+                two_sum_add(sa, ca, v[u]);
+            }
+        }
     }
     for (int j = threadIdx.x; j < A.J; j += blockDim.x) {
         const double v = A.b_src[j];

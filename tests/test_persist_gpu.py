@@ -1,6 +1,7 @@
 """GPU tests of the cooperative FP32 phase (ot_assoc_options.persistent): one
 launch that keeps the instance's FP32 cost in LDS and exchanges the column
-partials between workgroups through agent-scope atomics and grid barriers.
+partials and the new g between workgroups through polled exchange slots
+(agent-scope atomic loads and stores).
 
 Every case is solved with the cooperative launch and with the chunked graph
 launches, and both are held to the same bar against the FP64 oracle as the
@@ -78,8 +79,10 @@ def test_dense_both_paths(A, oracle_lib, I, J):
         assert st == A.OT_OK, (pers, st)
         assert bool(res.flags & A.OT_RESULT_PERSISTENT) == bool(pers), (pers, res.flags)
         check(oracle_lib, Cd, a, b, eps, tol, f, g, res, ref)
-    # the two paths run the same iteration; only summation orders differ
-    assert abs(out[1][1].iterations - out[0][1].iterations) <= 2
+    # the two paths run the same iteration with different summation orders
+    # and row shifts; the FP32 phase ends where its residual stalls at the
+    # FP32 noise floor, which moves by a few iterations with the rounding
+    assert abs(out[1][1].iterations - out[0][1].iterations) <= 4
 
 
 def test_lds_capacity_boundary(A):
