@@ -26,6 +26,15 @@ import numpy as np  # noqa: E402
 
 METRIC = "Sinkhorn cells/s + HBM GB/s at 20000x400; batched solves/s + p99 at fixed error"
 HBM_PEAK_GBS = 8000.0
+# ALU roofline of the cooperative FP32 sweep (derivation in the design doc): per
+# cell and iteration 7 algorithmic flops (argument FMA 2, shift 1, row-sum
+# add 1, column-partial FMA 2, the exponential 1) issued as 7 full-rate VALU
+# slots plus one quarter-rate v_exp_f32 (4 slots); 256 CUs x 4 SIMDs x 16
+# lanes at 2.4 GHz issue 3.93e13 lane-slots per second.
+FLOP_PER_CELL = 7.0
+ALU_SLOTS_PER_CELL = 11.0
+LANES_PER_CLOCK = 256 * 4 * 16
+CLOCK_HZ = 2.4e9
 
 
 def log(msg):
@@ -375,6 +384,18 @@ def main():
     t_dense, res_d = timed(step_dense, args.steps, args.warmup)
     log(f"dense: {t_dense * 1e3:.3f} ms/solve, iters={res_d.iterations}, fp64={res_d.fp64_iterations}, "
         f"violation={res_d.marginal_violation:.3e}")
+    coop = None
+    if res_d.flags & A.OT_RESULT_PERSISTENT:
+        # the cooperative FP32 launch of each timed solve, HIP events on its stream
+        ms_list, it_list = [], []
+        for _ in range(args.steps):
+            step_dense()
+            ms_c, it_c = solver.fast_phase_time()
+            ms_list.append(ms_c)
+            it_list.append(it_c)
+        coop = (float(np.mean(ms_list)), float(np.mean(it_list)))
+        log(f"cooperative FP32 launch: {coop[0] * 1e3:.1f} us for {coop[1]:.1f} iterations "
+            f"({coop[0] * 1e3 / coop[1]:.2f} us per iteration)")
     ms_sweep = solver.time_sweep(args.sweep_reps, fp64=False)
     ms_sweep64 = solver.time_sweep(max(10, args.sweep_reps // 4), fp64=True)
     log(f"fused sweep: {ms_sweep * 1e3:.2f} us (fp32), {ms_sweep64 * 1e3:.2f} us (fp64)")
@@ -423,19 +444,50 @@ def main():
     cells = I * J
     alg_bytes = 4.0 * cells  # one FP32 read of C per iteration
     achieved = alg_bytes / (ms_sweep * 1e-3) / 1e9
-    # HBM traffic of the same kernel from the committed counter summary, only
-    # while the kernel's sources are the ones the counters were taken on
-    traffic, traffic_note = None, "no counter summary"
-    tpath = os.path.join(ROOT, "profiles", "k_iter_dense_cran_20000x400_traffic.json")
-    if os.path.exists(tpath):
+
+    def counter_traffic(name, seconds):
+        """HBM GB/s of a kernel from the committed counter summary (FETCH_SIZE +
+        WRITE_SIZE, copy-calibrated), only while the kernel's sources are the
+        ones the counters were taken on."""
         from paper_1805_01559_amd import profiling
+        tpath = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(tpath):
+            return None, "no counter summary"
         t = json.load(open(tpath))
-        if t.get("source_hash") == profiling.sweep_source_hash():
-            traffic = t["hbm_bytes"] / (ms_sweep * 1e-3) / 1e9
-            traffic_note = (f"{t['hbm_bytes']:.4g} B per launch from FETCH_SIZE + WRITE_SIZE (copy-calibrated), "
-                            f"{t['ratio']:.3f} x the algorithmic bytes")
-        else:
-            traffic_note = "kernel sources changed since the counters were taken"
+        if t.get("source_hash") != profiling.source_hash(t.get("sources", profiling.SWEEP_SOURCES)):
+            return None, "kernel sources changed since the counters were taken"
+        return (t["hbm_bytes"] / seconds / 1e9,
+                f"{t['hbm_bytes']:.4g} B per launch from FETCH_SIZE + WRITE_SIZE (copy-calibrated), "
+                f"{t['ratio']:.3f} x the algorithmic bytes")
+
+    traffic, traffic_note = counter_traffic("k_iter_dense_cran_20000x400_traffic.json", ms_sweep * 1e-3)
+    streaming = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
+                 "algorithmic_bytes_per_launch": alg_bytes,
+                 "kernel": "k_iter<DenseSrc<float>, fp32 exp> (streaming fused row update + column partials; "
+                           "the path of instances whose cost does not fit in LDS)",
+                 "avg_launch_us": ms_sweep * 1e3, "fp64_sweep_us": ms_sweep64 * 1e3}
+    if coop is not None:
+        # dominant kernel: the cooperative FP32 launch. Per cell and iteration
+        # it issues ALU_SLOTS_PER_CELL VALU issue slots (7 full-rate ops and one
+        # quarter-rate v_exp_f32) for FLOP_PER_CELL algorithmic flops; the ALU
+        # peak of that mix follows from the unit counts and the clock.
+        coop_s, coop_it = coop[0] * 1e-3, coop[1]
+        flops = FLOP_PER_CELL * cells * coop_it
+        achieved_alu = flops / coop_s / 1e12
+        peak_alu = FLOP_PER_CELL * LANES_PER_CLOCK * CLOCK_HZ / ALU_SLOTS_PER_CELL / 1e12
+        ctraffic, cnote = counter_traffic("k_persist_dense_cran_20000x400_traffic.json", coop_s)
+        roofline = {"bound": "alu", "achieved": achieved_alu, "peak": peak_alu, "unit": "TFLOP/s",
+                    "frac": achieved_alu / peak_alu, "traffic": ctraffic, "traffic_note": cnote,
+                    "kernel": "k_persist<DenseSrc<float>> (cooperative FP32 phase, cost held in LDS)",
+                    "avg_launch_us": coop[0] * 1e3, "iterations_per_launch": coop_it,
+                    "us_per_iteration": coop[0] * 1e3 / coop_it,
+                    "algorithmic_flop_per_launch": flops,
+                    "hbm_equivalent_gbps": alg_bytes * coop_it / coop_s / 1e9,
+                    "hbm_equivalent_note": "4 B per cell-iteration (a fused single read of C) per unit time, "
+                                           "against 8000 GB/s; the cost itself is read from HBM once per launch"}
+    else:
+        roofline = streaming
     out = {
         "metric": METRIC,
         "value": cells * res_d.iterations / t_dense,
@@ -455,19 +507,16 @@ def main():
         "iterations": res_d.iterations,
         "fp64_iterations": res_d.fp64_iterations,
         "hbm_gbps_sweep": achieved,
+        "cooperative": res_d.flags & A.OT_RESULT_PERSISTENT != 0,
         "marginal_violation": res_d.marginal_violation,
         "objective": res_d.objective,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel": "k_iter<DenseSrc<float>, fp32 exp> (fused row update + column partials)",
-                     "avg_launch_us": ms_sweep * 1e3},
+        "roofline": roofline,
+        "streaming_sweep": streaming,
         "copy_gbps": copy_gbps,
         "sweep_above_llc": None if resB is None else {
             "workload": "200000x400 dense FP32 (320 MB), same kernel", "sweep_us": ms_big * 1e3,
             "achieved_gbps": gbps_big, "frac": gbps_big / HBM_PEAK_GBS,
             "iterations": resB.iterations, "marginal_violation": resB.marginal_violation},
-        "fp64_sweep_us": ms_sweep64 * 1e3,
         "on_the_fly": {"ms_per_solve": t_geo * 1e3, "cells_per_s": cells * res_g.iterations / t_geo,
                        "iterations": res_g.iterations, "fp64_iterations": res_g.fp64_iterations,
                        "sweep_us": ms_sweep_geo * 1e3, "cells_per_s_sweep": cells / (ms_sweep_geo * 1e-3),

@@ -206,6 +206,14 @@ ot_status ot_assoc_materialize_cost(ot_assoc *h, const ot_cost_desc *cost, float
  * Errors: OT_ESTATE before a successful solve, OT_EINVAL for bad reps. */
 ot_status ot_assoc_time_sweep(ot_assoc *h, int32_t reps, int fp64, double *ms_per_launch);
 
+/* (instrumentation) Device duration, in milliseconds, of the cooperative
+ * launch that ran the FP32 phase of the last successful solve (HIP events on
+ * the handle's stream right around that one launch: the LDS fill and every
+ * FP32 iteration), and the number of FP32 iterations it ran.
+ * Errors: OT_ESTATE if the last solve did not use the cooperative launch
+ * (see ot_assoc_result.flags). */
+ot_status ot_assoc_fast_phase_time(ot_assoc *h, double *ms, int32_t *iterations);
+
 /* Frees the handle and its device workspace. NULL-safe. */
 void ot_assoc_destroy(ot_assoc *h);
 

@@ -56,6 +56,8 @@ struct ot_assoc {
     double* xch = nullptr;     // exchange block of the cooperative FP32 phase
     int lds_max = 0;           // LDS bytes a workgroup may allocate
     bool last_persistent = false;  // the last solve's FP32 phase was one cooperative launch
+    int last_fast_iters = 0;       // ... and the FP32 iterations it ran
+    hipEvent_t ev_coop[2] = {nullptr, nullptr};  // around that launch
     float* xy_dev = nullptr;  // I_max x 2
     float* xy_rrh = nullptr;  // J_max x 2
     double *s_all = nullptr, *s_ex = nullptr;

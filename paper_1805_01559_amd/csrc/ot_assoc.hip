@@ -731,6 +731,7 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
                        h->xch, nx, h->ctl);
     Src sv = src;
     void* args[] = {(void*)&A, (void*)&sv};
+    HIPCHK(h, hipEventRecord(h->ev_coop[0], h->stream));
     const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)p.nb), dim3(kPersistWaves * 64), args,
                                                     (unsigned)p.lds, h->stream);
     if (e == hipErrorCooperativeLaunchTooLarge) {
@@ -738,6 +739,7 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
         return OT_OK;
     }
     HIPCHK(h, e);
+    HIPCHK(h, hipEventRecord(h->ev_coop[1], h->stream));
     launched = true;
     return OT_OK;
 }
@@ -772,6 +774,7 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
         if (np > 0 && (st = S.issue_chunk<Src, true>(src, 0, np, kModePolish, 0.0))) return st;
         if ((st = S.run_check<Src>(src, np, c))) return st;
         checked = true;
+        h->last_fast_iters = c.iter - c.fp64_iters;  // (the solve starts at iteration 0)
         // the iterate sits in the buffers of parity np & 1; restore the
         // convention that iterate k lives in buffers k & 1
         const int k = c.done ? c.result_iter : c.iter;
@@ -849,7 +852,7 @@ void ot_assoc_destroy(ot_assoc* h) {
     for (void* p : bufs)
         if (p) hipFree(p);
     if (h->ctl_h) hipHostFree(h->ctl_h);
-    hipEvent_t evs[] = {h->ev_start, h->ev_stop, h->ev_slot[0], h->ev_slot[1]};
+    hipEvent_t evs[] = {h->ev_start, h->ev_stop, h->ev_slot[0], h->ev_slot[1], h->ev_coop[0], h->ev_coop[1]};
     for (auto e : evs)
         if (e) hipEventDestroy(e);
     if (h->batch) batch_engine_destroy(h->batch);
@@ -919,6 +922,8 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     if (e == hipSuccess) e = hipEventCreate(&h->ev_stop);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_slot[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_slot[1], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev_coop[0]);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev_coop[1]);
     if (e == hipSuccess && !h->stream) {  // graphs cannot be captured on the legacy default stream
         e = hipStreamCreate(&h->stream);
         h->own_stream = (e == hipSuccess);
@@ -1181,6 +1186,20 @@ ot_status ot_assoc_materialize_cost(ot_assoc* h, const ot_cost_desc* cost, float
         return OT_OK;
     });
     return st;
+}
+
+ot_status ot_assoc_fast_phase_time(ot_assoc* h, double* ms, int32_t* iterations) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!ms || !iterations) return fail(h, OT_EINVAL, "output pointer is NULL");
+    if (!h->solved || !h->last_persistent)
+        return fail(h, OT_ESTATE, "the last solve did not run the cooperative FP32 phase");
+    float t = 0.0f;
+    HIPCHK(h, hipEventSynchronize(h->ev_coop[1]));
+    HIPCHK(h, hipEventElapsedTime(&t, h->ev_coop[0], h->ev_coop[1]));
+    *ms = (double)t;
+    *iterations = h->last_fast_iters;
+    return OT_OK;
 }
 
 ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_per_launch) {

@@ -32,6 +32,7 @@ OT_RESULT_PERSISTENT = 1
 EXPORTS = [
     "ot_assoc_default_options", "ot_assoc_create", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
     "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep",
+    "ot_assoc_fast_phase_time",
     "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_config",
     "ot_assoc_batch_potentials", "ot_assoc_solve_snapshots", "ot_assoc_snapshot_potentials",
     "ot_assoc_batch_plan", "ot_serve_default_options", "ot_serve_create", "ot_serve_submit", "ot_serve_progress",
@@ -106,6 +107,7 @@ def lib():
         L.ot_assoc_cost_median.argtypes = [vp, ct.POINTER(ot_cost_desc), ct.POINTER(d)]
         L.ot_assoc_materialize_cost.argtypes = [vp, ct.POINTER(ot_cost_desc), vp]
         L.ot_assoc_time_sweep.argtypes = [vp, ct.c_int32, ct.c_int, ct.POINTER(d)]
+        L.ot_assoc_fast_phase_time.argtypes = [vp, ct.POINTER(d), ct.POINTER(ct.c_int32)]
         L.ot_assoc_destroy.argtypes = [vp]
         L.ot_assoc_destroy.restype = None
         L.ot_assoc_last_error.argtypes = [vp]
@@ -206,6 +208,13 @@ def ot_assoc_time_sweep(h, reps: int, fp64: bool = False) -> float:
     ms = ct.c_double()
     _check(h, lib().ot_assoc_time_sweep(h, int(reps), int(bool(fp64)), ct.byref(ms)))
     return ms.value
+
+
+def ot_assoc_fast_phase_time(h):
+    """(ms, iterations) of the last solve's cooperative FP32 launch."""
+    ms, it = ct.c_double(), ct.c_int32()
+    _check(h, lib().ot_assoc_fast_phase_time(h, ct.byref(ms), ct.byref(it)))
+    return ms.value, it.value
 
 
 def ot_assoc_destroy(h):
@@ -451,6 +460,9 @@ class Solver:
         g = np.ascontiguousarray(g, dtype=np.float64)
         ot_assoc_set_potentials(self.h, f.ctypes.data, g.ctypes.data, f.size, g.size, OT_MEM_HOST)
         self._I, self._J = f.size, g.size
+
+    def fast_phase_time(self):
+        return ot_assoc_fast_phase_time(self.h)
 
     def time_sweep(self, reps=50, fp64=False):
         """Average ms of one fused-sweep launch of the last solve's shape."""

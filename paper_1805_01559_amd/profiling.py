@@ -27,14 +27,22 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def sweep_source_hash() -> str:
-    """Hash of the sources that define the single-instance sweep kernel: a
-    traffic figure taken from counters is valid only for this hash."""
+SWEEP_SOURCES = ("kernels.h", "cost_sources.h", "device_common.h")
+COOP_SOURCES = ("persist_kernels.h", "kernels.h", "cost_sources.h", "device_common.h")
+
+
+def source_hash(files=SWEEP_SOURCES) -> str:
+    """Hash of the sources that define a kernel: a traffic figure taken from
+    counters is valid only for this hash."""
     h = hashlib.sha256()
-    for f in ("kernels.h", "cost_sources.h", "device_common.h"):
+    for f in files:
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def sweep_source_hash() -> str:
+    return source_hash(SWEEP_SOURCES)
 
 
 def _find(d: str, suffix: str) -> str:
@@ -61,7 +69,8 @@ def _counter(d: str):
     return list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
 
 
-def traffic(fetch_dir: str, write_dir: str, kernel: str, alg_bytes: float, copy_bytes: float) -> dict:
+def traffic(fetch_dir: str, write_dir: str, kernel: str, alg_bytes: float, copy_bytes: float,
+            sources=SWEEP_SOURCES) -> dict:
     res = {}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _counter(d) if r["Counter_Name"] == name]
@@ -75,7 +84,8 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, alg_bytes: float, copy_
                          factor=factor, bytes=statistics.median(vals) * 1024.0 * factor)
     total = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
     return dict(kernel=kernel, algorithmic_bytes=alg_bytes, hbm_bytes=total, ratio=total / alg_bytes,
-                fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"], source_hash=sweep_source_hash())
+                fetch=res["FETCH_SIZE"], write=res["WRITE_SIZE"], sources=list(sources),
+                source_hash=source_hash(sources))
 
 
 def main(argv=None):
@@ -90,11 +100,13 @@ def main(argv=None):
     b.add_argument("kernel")
     b.add_argument("--bytes", type=float, required=True)
     b.add_argument("--copy-bytes", type=float, default=float(2 * (256 << 20)))
+    b.add_argument("--coop", action="store_true", help="the kernel is the cooperative phase (persist_kernels.h)")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print(stats(args.dir, args.top))
     else:
-        t = traffic(args.fetch_dir, args.write_dir, args.kernel, args.bytes, args.copy_bytes)
+        t = traffic(args.fetch_dir, args.write_dir, args.kernel, args.bytes, args.copy_bytes,
+                    COOP_SOURCES if args.coop else SWEEP_SOURCES)
         f, w = t["fetch"], t["write"]
         print(f"kernel: {t['kernel']}")
         print(f"FETCH_SIZE median {f['median_kib']:.1f} KiB over {f['dispatches']} dispatches; copy reads "
