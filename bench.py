@@ -150,31 +150,44 @@ def leg_batch(args, A, S, torch, dev):
     t_batch = (time.perf_counter() - t0) / K
     cfg_w, cfg_rpp = bs.batch_config()
     iters = np.array([r.iterations for r in res])
+    fp64 = np.array([r.fp64_iterations for r in res])
     viol = np.array([r.marginal_violation for r in res])
     cell_it = sum(L.I * L.J * r.iterations for L, r in zip(Ls, res))
     log(f"batch: {t_batch * 1e3:.2f} ms for {n} solves = {n / t_batch:.0f} solves/s (waves {cfg_w}, "
         f"{cfg_rpp} rows per part), iterations "
-        f"{iters.min()}..{iters.max()} (mean {iters.mean():.1f}), max violation {viol.max():.2e}")
-    # the plain path, one instance at a time, same matrices
-    times = []
-    for d, a, b in zip(descs, aa, bb):
-        with A.Solver(d[0].I, d[0].J) as s1:
-            s1.solve(d[0], d[1], a, b, eps, tol, 2000)  # warm-up (graph capture)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            s1.solve(d[0], d[1], a, b, eps, tol, 2000)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t1)
+        f"{iters.min()}..{iters.max()} (mean {iters.mean():.1f}; FP64 mean {fp64.mean():.2f}, max {fp64.max()}), "
+        f"max violation {viol.max():.2e}")
+    # one instance at a time, same matrices: the plain streaming FP32 kernel
+    # (persistent = 0) and the library's default single path (one cooperative
+    # launch for instances that fit in LDS)
+    def one_at_a_time(persistent):
+        times = []
+        for d, a, b in zip(descs, aa, bb):
+            with A.Solver(d[0].I, d[0].J, persistent=persistent) as s1:
+                s1.solve(d[0], d[1], a, b, eps, tol, 2000)  # warm-up (graph capture)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                s1.solve(d[0], d[1], a, b, eps, tol, 2000)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t1)
+        return times
+    times = one_at_a_time(0)
     t_plain = float(np.sum(times))
-    log(f"plain one at a time: {t_plain * 1e3:.1f} ms = {n / t_plain:.0f} solves/s; batch speed-up {t_plain / t_batch:.1f}x")
+    times_single = one_at_a_time(1)
+    t_single = float(np.sum(times_single))
+    log(f"plain one at a time (streaming FP32 kernel): {t_plain * 1e3:.1f} ms = {n / t_plain:.0f} solves/s, batch "
+        f"speed-up {t_plain / t_batch:.1f}x; single default (cooperative when it fits): {t_single * 1e3:.1f} ms = "
+        f"{n / t_single:.0f} solves/s, batch speed-up {t_single / t_batch:.1f}x")
     out = {"workload": f"{n} uneven instances, I~LogU[500,20000], J~LogU[20,400], 1 km, eps={eps}, tol={tol}, "
                        "dense FP32 costs resident in HBM",
            "ms_per_batch": t_batch * 1e3, "solves_per_s": n / t_batch, "cells": cells,
            "tuned": {"waves": cfg_w, "rows_per_part": cfg_rpp},
            "cells_per_s": cell_it / t_batch, "iterations_mean": float(iters.mean()), "iterations_max": int(iters.max()),
+           "fp64_iterations_mean": float(fp64.mean()),
            "max_marginal_violation": float(viol.max()), "status_ok": int(sum(r.status == 0 for r in res)),
            "plain_ms_total": t_plain * 1e3, "plain_solves_per_s": n / t_plain, "speedup_vs_plain": t_plain / t_batch,
-           "plain_p50_ms": float(np.percentile(times, 50) * 1e3), "plain_p99_ms": float(np.percentile(times, 99) * 1e3)}
+           "plain_p50_ms": float(np.percentile(times, 50) * 1e3), "plain_p99_ms": float(np.percentile(times, 99) * 1e3),
+           "single_default_solves_per_s": n / t_single, "speedup_vs_single_default": t_single / t_batch}
     bs.close()
     one.close()
     return out
@@ -293,25 +306,34 @@ def leg_serve(args, A, S, torch, dev):
         f"{ol['warm_started']} warm, {ol['iterations_mean']:.1f} iterations mean")
     sat = run(False)
     log(f"serve saturated: {sat['solves_per_s']:.0f} solves/s, p50 {sat['p50_ms']:.1f} ms, p99 {sat['p99_ms']:.1f} ms")
-    # the plain path alone on the first snapshot of every layout (cold)
-    times = []
-    for q in [i for i in order if reqs[i][1] == 0]:
-        k, t, d, keep, a, b = reqs[q]
-        with A.Solver(d.I, d.J) as s1:
-            s1.solve(d, keep, a, b, eps, tol, 2000)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            s1.solve(d, keep, a, b, eps, tol, 2000)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t1)
-    times = np.array(times)
-    plain = dict(solves_per_s=len(times) / times.sum(), p50_ms=float(np.percentile(times, 50) * 1e3),
-                 p99_ms=float(np.percentile(times, 99) * 1e3))
-    log(f"plain alone: {plain['solves_per_s']:.0f} solves/s, p50 {plain['p50_ms']:.2f} ms")
+    # the single-instance path alone on the first snapshot of every layout
+    # (cold): the plain streaming FP32 kernel (persistent = 0), and the
+    # library's default, which runs instances that fit in LDS as one
+    # cooperative launch
+    def alone(persistent):
+        times = []
+        for q in [i for i in order if reqs[i][1] == 0]:
+            k, t, d, keep, a, b = reqs[q]
+            with A.Solver(d.I, d.J, persistent=persistent) as s1:
+                s1.solve(d, keep, a, b, eps, tol, 2000)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                s1.solve(d, keep, a, b, eps, tol, 2000)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t1)
+        times = np.array(times)
+        return dict(solves_per_s=len(times) / times.sum(), p50_ms=float(np.percentile(times, 50) * 1e3),
+                    p99_ms=float(np.percentile(times, 99) * 1e3))
+    plain = alone(0)
+    single = alone(1)
+    log(f"plain alone (streaming FP32 kernel): {plain['solves_per_s']:.0f} solves/s, p50 {plain['p50_ms']:.2f} ms; "
+        f"single default (cooperative when it fits): {single['solves_per_s']:.0f} solves/s, "
+        f"p50 {single['p50_ms']:.2f} ms")
     return {"workload": f"Poisson {args.rate}/s, {n_lay} layouts x {n_snap} snapshots (5 m drift), sizes as the "
                         f"batch, eps={eps}, tol={tol}, geometry costs built at admission, warm starts per layout",
-            "open_loop": ol, "saturated": sat, "plain_alone_cold": plain,
-            "speedup_saturated_vs_plain": sat["solves_per_s"] / plain["solves_per_s"]}
+            "open_loop": ol, "saturated": sat, "plain_alone_cold": plain, "single_default_alone_cold": single,
+            "speedup_saturated_vs_plain": sat["solves_per_s"] / plain["solves_per_s"],
+            "speedup_saturated_vs_single_default": sat["solves_per_s"] / single["solves_per_s"]}
 
 
 def main():

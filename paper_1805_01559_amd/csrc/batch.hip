@@ -37,6 +37,7 @@ using namespace otk;
 namespace {
 
 constexpr int kChunk = 8;  // iterations per captured chunk (even: list generations alternate)
+constexpr double kBatchStallBelow = 1e-7;  // FP32 sweeps are not trusted below this residual
 constexpr size_t kAlign = 256;
 
 double now_s() {
@@ -366,7 +367,7 @@ ot_status BatchEngine::prepare_kernels() {
 
 ot_status BatchEngine::capture(int wi) {
     if (graph[wi]) return OT_OK;
-    BParams P{polish_iters, 1e-7};
+    BParams P{polish_iters, kBatchStallBelow};
     hipGraph_t g = nullptr;
     ECHK(this, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     for (int t = 0; t < kChunk; ++t) {
@@ -656,6 +657,10 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         ci.has_prev = warm ? 1 : 0;
         ci.max_iter = r.max_iter;
         ci.tol = r.tol;
+        // (no margin here: a batched instance whose check misses tol continues
+        // with FP64 sweeps on the device, which costs less than the longer
+        // FP32 tail a margin would add to the whole batch)
+        ci.tol_fast = r.tol;
         ci.r_last = __builtin_huge_val();
         for (double& x : ci.r_hist) x = __builtin_huge_val();
         ci.phase = kPhFast;

@@ -128,14 +128,21 @@ __global__ __launch_bounds__(WAVES * kWave) void k_bsweep(const BInst* __restric
                 cj.r0 = (int64_t)it.part * d.rpp;
                 cj.r1 = min(d.I, cj.r0 + d.rpp);
                 cj.J = d.J;
-                cj.nch = d.nchk;
+                cj.nch = d.nch;
                 cj.kk = d.kk;
                 cj.a = d.a;
                 cj.f = d.f[par];
                 cj.g = d.g[par];
                 cj.col_out = d.col_part + (int64_t)it.part * d.J;
                 cj.stat_out = d.stat_part + (int64_t)it.part * 5;
-                check_rows<DenseSrc<float>, 4, 2, WAVES>(cj, DenseSrc<float>{d.C, d.ld});
+                const DenseSrc<float> src{d.C, d.ld};
+                using S = DenseSrc<float>;
+                switch (d.cls) {  // the sweeps' lane layout of the instance's column class
+                    case 0: check_rows_g<S, 4, 1, 16, WAVES>(cj, src); break;
+                    case 1: check_rows_g<S, 4, 2, 16, WAVES>(cj, src); break;
+                    case 2: check_rows_g<S, 4, 4, 16, WAVES>(cj, src); break;
+                    default: check_rows_g<S, 4, 4, 32, WAVES>(cj, src); break;
+                }
                 continue;
             }
         }
@@ -255,7 +262,7 @@ __global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, B
                     // polish only when the FP32 sweeps stalled short of tol; a
                     // residual that met a tol above the FP32 noise threshold
                     // goes straight to the exact check
-                    const bool met = ctl->r_last < ctl->tol && ctl->tol >= P.stall_below;
+                    const bool met = ctl->r_last < ctl->tol_fast && ctl->tol >= P.stall_below;
                     if (phase == kPhFast && P.polish_iters > 0 && ctl->iter < ctl->max_iter && !met) {
                         ctl->phase = kPhPolish;
                         ctl->polish_left = P.polish_iters;

@@ -151,6 +151,17 @@ struct Ctl {
     int32_t input_bad;
     int32_t sync_fail;
     double mass_b;         // sum(b)
+    // target of the FP32 phase. Single solves: tol / 4 when that is above
+    // the FP32 noise threshold (the exact check that follows measures the row
+    // AND column residual of the next iterate; a margin lets it pass the first
+    // time instead of sending the solve into an FP64 phase with host round
+    // trips), else tol. Batched instances: tol.
+    double tol_fast;
 };
+
+// The FP32 phase's residual target for a solve to `tol`.
+__host__ __device__ inline double fast_target(double tol, double stall_below) {
+    return tol * 0.25 >= stall_below ? tol * 0.25 : tol;
+}
 
 }  // namespace otk

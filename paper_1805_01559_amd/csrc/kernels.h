@@ -115,7 +115,8 @@ __device__ __forceinline__ void bookkeep(Ctl* c, double rsum, int mode, double s
         const bool stall = (nfin >= 1) && isfinite(r) && (r < stall_below) && (r > 0.95 * mn);
         for (int q = 3; q > 0; --q) c->r_hist[q] = c->r_hist[q - 1];
         c->r_hist[0] = r;
-        if (r < c->tol || stall || k >= c->max_iter) c->stop = 1;
+        const double target = c->tol_fast > 0.0 ? c->tol_fast : c->tol;
+        if (r < target || stall || k >= c->max_iter) c->stop = 1;
     } else {
         c->fp64_iters += 1;
         c->last_fp64 = 1;
@@ -545,6 +546,128 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
                     const int col = (ch * kWave + lane) * VEC + v;
                     if (col < J) out[col] = acc[ch][v];
                 }
+        if (lane < 5) {
+            double r = 0.0;
+            for (int q = 0; q < WAVES; ++q) r += wst[q][lane];
+            A.stat_out[lane] = r;
+        }
+    }
+}
+
+// The same check with the lane layout of the sweeps: LPR (16 or 32) lanes
+// per row, R = 64 / LPR rows per wave step, lane `sub` owning columns
+// (ch LPR + sub) VEC + v. For short rows (tens of RRHs) this keeps the lanes
+// busy where one row per wavefront would leave most of them idle. Every sum
+// runs in a fixed order.
+template <class Src, int VEC, int NCH, int LPR, int WAVES>
+__device__ __forceinline__ void check_rows_g(const CheckJob& A, const Src& src) {
+    extern __shared__ double sm[];
+    constexpr int R = kWave / LPR;
+    const double kk = A.kk;
+    const int J = A.J, nch = A.nch;
+    const int ncols = nch * LPR * VEC;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int sub = lane % LPR, rg = lane / LPR;
+    __syncthreads();  // LDS may still be read by this workgroup's previous job
+    src.stage(sm, J);
+    double gsr[NCH][VEC];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int col = (ch * LPR + sub) * VEC + v;
+            gsr[ch][v] = (ch < nch && col < J) ? A.g[col] * kk : -pinf64();
+        }
+    __syncthreads();
+    double acc[NCH][VEC];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[ch][v] = 0.0;
+    double st[5] = {0, 0, 0, 0, 0};  // rowres, cost, ent, mass, fa (first lane of each row group)
+    for (int64_t base = A.r0 + (int64_t)w * R; base < A.r1; base += (int64_t)WAVES * R) {
+        const int64_t i = base + rg;
+        const bool vrow = i < A.r1;
+        auto row = src.row(vrow ? i : A.r0);
+        const double fi = vrow ? A.f[i] : 0.0;
+        const double fk = fi * kk;
+        double rs = 0.0, cost = 0.0, ent = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            if (ch < nch) {
+                const int col0 = (ch * LPR + sub) * VEC;
+                double c[VEC];
+                src.template get<true, VEC>(row, i, col0, vrow ? J : 0, sm, c);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    if (vrow && col0 + v < J) {
+                        const double t = fk + fma(c[v], -kk, gsr[ch][v]);  // log2 pi_ij
+                        const double p = exp2(t);
+                        rs += p;
+                        cost = fma(c[v], p, cost);
+                        ent = fma(p, t * kLn2 - 1.0, ent);
+                        acc[ch][v] += p;
+                    }
+                }
+            }
+        }
+        rs = group_sum<LPR>(rs);
+        cost = group_sum<LPR>(cost);
+        ent = group_sum<LPR>(ent);
+        if (sub == 0 && vrow) {
+            const double ai = A.a[i];
+            st[0] += fabs(rs - ai);
+            st[1] += cost;
+            st[2] += ent;
+            st[3] += rs;
+            st[4] += fi * ai;
+        }
+    }
+    // the row groups of a wave share columns: fold them, then the waves
+#pragma unroll
+    for (int o = LPR; o < kWave; o <<= 1)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[ch][v] += __shfl_xor(acc[ch][v], o, kWave);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) st[q] = wave_sum(st[q]);
+    __syncthreads();
+    double* red = sm;
+#pragma unroll
+    for (int half = WAVES / 2; half >= 1; half >>= 1) {
+        if (w >= half && w < 2 * half && rg == 0) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) red[(w - half) * ncols + (ch * LPR + sub) * VEC + v] = acc[ch][v];
+        }
+        __syncthreads();
+        if (w < half && rg == 0) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) acc[ch][v] += red[w * ncols + (ch * LPR + sub) * VEC + v];
+        }
+        __syncthreads();
+    }
+    __shared__ double wst[WAVES][5];
+    if (lane == 0)
+        for (int q = 0; q < 5; ++q) wst[w][q] = st[q];
+    __syncthreads();
+    if (w == 0) {
+        if (rg == 0) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        const int col = (ch * LPR + sub) * VEC + v;
+                        if (col < J) A.col_out[col] = acc[ch][v];
+                    }
+        }
         if (lane < 5) {
             double r = 0.0;
             for (int q = 0; q < WAVES; ++q) r += wst[q][lane];

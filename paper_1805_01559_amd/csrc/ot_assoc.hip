@@ -786,7 +786,7 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
         if ((st = S.run_phase<Src, false>(src, kModeFast, chunk, stall_below, c))) return st;
         // polish only when the FP32 sweeps stalled short of tol; a residual
         // that met a tol above the FP32 noise threshold goes to the check
-        const bool met = c.r_last < tol && tol >= stall_below;
+        const bool met = c.r_last < c.tol_fast && tol >= stall_below;
         if (!c.done && c.iter < max_iter && !met) {
             const int np = std::max(0, std::min(h->opt.polish_iters, max_iter - c.iter));
             if (np > 0) {
@@ -973,6 +973,7 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
     c.last_fp64 = 0;
     c.max_iter = max_iter;
     c.tol = tol;
+    c.tol_fast = fast_target(tol, 1e-7);
     c.r_last = __builtin_huge_val();
     for (double& r : c.r_hist) r = __builtin_huge_val();
     InitArgs ia{};

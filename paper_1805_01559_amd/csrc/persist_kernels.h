@@ -504,7 +504,7 @@ static __global__ void k_xch_clear(double* xch, size_t n_slots, Ctl* ctl) {
 static __global__ void k_polish_gate(Ctl* ctl, double* f0, double* f1, double* g0, double* g1, int64_t I, int J,
                                      double tol, double stall_below, int np) {
     const int it = ctl->iter;
-    const bool met = ctl->r_last < tol && tol >= stall_below;
+    const bool met = ctl->r_last < ctl->tol_fast && tol >= stall_below;
     const bool skip = ctl->done || np <= 0 || it >= ctl->max_iter || met;
     const int want = skip ? (np & 1) : 0;
     if ((it & 1) != want) {
