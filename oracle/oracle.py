@@ -17,7 +17,12 @@ What it computes (paper sections in parentheses):
 * ``brute_force_ot``: the unregularised OT of eqs. (2)-(4) on tiny square
   instances with uniform marginals, by enumeration of permutations;
 * ``maxsinr_traffic`` and ``lemma1_lower_bound``: the maxSINR rule and the
-  RRH traffic it induces (Sec. IV), and the total-load bound behind Lemma 1.
+  RRH traffic it induces (Sec. IV), and the total-load bound behind Lemma 1;
+* ``rrh_loads`` and ``evaluate``: the RRH load rho_j, the mean number of jobs
+  E[N_j] = rho_j / (1 - rho_j) under processor sharing and the devices'
+  average completion times (Sec. II-B);
+* ``adaptive_sinkhorn``: the Adaptive Sinkhorn Association of Sec. IV
+  (Alg. 2), with the readings stated at the function.
 """
 
 from __future__ import annotations
@@ -237,3 +242,84 @@ def entropy(x) -> float:
     x = np.asarray(x, dtype=np.float64)
     x = x[x > 0]
     return float(-(x * np.log(x)).sum())
+
+
+# ------------------------------------------------------ loads (Sec. II-B) --
+
+def rrh_loads(C, f, g, eps) -> np.ndarray:
+    """Per-RRH load of the transport plan x = exp((f + g - C)/eps):
+    sum_i C_ij x_ij. With C = 1/(mu R) scaled by a constant and the
+    association pi_ij = x_ij / a_i (Lemma 1's pi* = x* / lambda), this is
+    Sec. II-B's rho_j = sum_i lambda_i pi_ij / (mu R_ij) up to the factor
+    sum(lambda) scale / mu. Column sums are compensated (osum)."""
+    C = _c64(C)
+    P = plan(C, f, g, eps)
+    return np.array([osum(C[:, j] * P[:, j]) for j in range(C.shape[1])])
+
+
+def evaluate(C, f, g, eps, a, kappa, tau) -> dict:
+    """Association quality of the plan x = exp((f + g - C)/eps) with row sums
+    a (Sec. II-B), for a cost C = (1/R) / scale:
+      rho_j   = kappa sum_i C_ij x_ij             (kappa = sum(lambda) scale / mu)
+      E[N_j]  = rho_j / (1 - rho_j) if rho_j < 1, else inf   (processor sharing)
+      T_i     = (tau / a_i) sum_j C_ij x_ij / (1 - rho_j)    (tau = scale / mu),
+    the average completion time of device i (sum over its associations of
+    pi_ij / (mu R_ij (1 - rho_j)) with pi_ij = x_ij / a_i); inf if it uses an
+    overloaded RRH. Returns rho, EN, T (per device), T_mean and the objective
+    of eq. (1), sum_i T_i."""
+    C, a = _c64(C), _c64(a)
+    P = plan(C, f, g, eps)
+    rho = kappa * np.array([osum(C[:, j] * P[:, j]) for j in range(C.shape[1])])
+    over = rho >= 1.0
+    EN = np.where(over, np.inf, rho / np.where(over, 1.0, 1.0 - rho))
+    T = np.empty(C.shape[0])
+    for i in range(C.shape[0]):
+        if np.any(over & (P[i] > 0)):
+            T[i] = np.inf
+        else:
+            T[i] = tau / a[i] * osum(C[i] * P[i] / (1.0 - rho))
+    return dict(rho=rho, EN=EN, T=T, T_mean=osum(T) / T.size if np.all(np.isfinite(T)) else np.inf,
+                objective=osum(T) if np.all(np.isfinite(T)) else np.inf)
+
+
+# ------------------------------------------- Adaptive Sinkhorn (Alg. 2) --
+
+def adaptive_sinkhorn(C, a, eps, tol, max_iter, delta=None, max_outer=100) -> dict:
+    """Adaptive Sinkhorn Association (Sec. IV, Alg. 2) on cost C (load per
+    unit traffic) with device traffic a:
+      q <- sum(a) / J for every RRH;
+      repeat: x <- Sinkhorn(C, a, q, eps); j* <- argmax_j rho_j(x);
+              q_j* <- q_j* - delta, q_j <- q_j + delta / (J - 1) for j != j*.
+    Readings (the paper leaves them open): delta = 0.01 sum(a) / J; each
+    Sinkhorn solve runs to the total residual tol; j* is the lowest index
+    among equal loads; the loop ends when the maximum load of a new solve
+    does not fall below the best one so far, when q_j* - delta would not stay
+    positive, or after max_outer solves; the returned association is the one
+    with the lowest maximum load (the last one that lowered it), with the q it
+    was solved for. J = 1 has nothing to rebalance: one solve.
+    Returns q, f, g, max_load, loads, solves (Sinkhorn solves run), outer
+    (the index of the returned solve) and the per-solve history of (j*, max load)."""
+    C, a = _c64(C), _c64(a)
+    J = C.shape[1]
+    mass = osum(a)
+    d = 0.01 * mass / J if delta is None else float(delta)
+    q = np.full(J, mass / J)
+    best, hist = None, []
+    for k in range(max_outer):
+        r = sinkhorn(C, a, q, eps, tol, max_iter)
+        loads = rrh_loads(C, r.f, r.g, eps)
+        js = int(np.argmax(loads))
+        mx = float(loads[js])
+        hist.append((js, mx))
+        if best is not None and not mx < best["max_load"]:
+            break
+        best = dict(q=q.copy(), f=r.f, g=r.g, max_load=mx, loads=loads, outer=k, iters=r.iters)
+        if J < 2 or not q[js] - d > 0.0:
+            break
+        step = d / (J - 1)
+        nq = q + step
+        nq[js] = q[js] - d
+        q = nq
+    best["solves"] = len(hist)
+    best["history"] = hist
+    return best
