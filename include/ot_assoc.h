@@ -196,6 +196,77 @@ ot_status ot_assoc_cost_median(ot_assoc *h, const ot_cost_desc *cost, double *me
  * cost that the geometry sweeps regenerate on the fly. */
 ot_status ot_assoc_materialize_cost(ot_assoc *h, const ot_cost_desc *cost, float *C_dev);
 
+/* ------------------------------------------------ association quality --
+ * Loads and completion times of Sec. II-B, the maxSINR rule of Sec. II-A /
+ * IV and the Adaptive Sinkhorn Association of Sec. IV (Alg. 2). The cost is
+ * read as the load per unit traffic, C_ij = (1/R_ij) / scale (cost choice
+ * (ii) of Sec. IV): then the transport plan x of a solve with row sums
+ * a_i = lambda_i / sum(lambda) gives the association pi_ij = x_ij / a_i and
+ *   rho_j = sum_i lambda_i pi_ij / (mu R_ij) = kappa load_j,
+ *   load_j = sum_i C_ij x_ij,  kappa = sum(lambda) scale / mu,
+ * with 1/mu the mean job size. */
+
+/* Per-RRH load of the last successful solve's plan: load_j = sum_i C_ij x_ij
+ * in FP64 (the FP64 cost, x = exp((f + g - C)/eps)). loads: J doubles in
+ * `mem`. Errors: OT_ESTATE before a successful solve (or after a call that
+ * replaced the handle's cost). */
+ot_status ot_assoc_rrh_loads(ot_assoc *h, double *loads, ot_mem mem);
+
+typedef struct {
+    double max_rho;             /* max_j rho_j */
+    double mean_completion;     /* (1/I) sum_i T_i in the unit of tau; +inf if a device uses an RRH with rho >= 1 */
+    double objective;           /* sum_i T_i, the objective of eq. (1); +inf as above */
+    int32_t overloaded_rrhs;    /* RRHs with rho_j >= 1 */
+    int32_t devices_overloaded; /* devices with a positive share on such an RRH */
+} ot_eval_result;
+
+/* Association quality of the last successful solve (Sec. II-B):
+ *   rho_j = kappa load_j;  E[N_j] = rho_j / (1 - rho_j) (mean number of jobs
+ *   under processor sharing; +inf when rho_j >= 1);
+ *   T_i = (tau / a_i) sum_j C_ij x_ij / (1 - rho_j), the average completion
+ *   time of device i (tau = scale / mu for C = (1/R) / scale).
+ * rho and EN: J doubles in `mem` (either may be NULL); out is required.
+ * Errors: OT_EINVAL (kappa or tau not positive and finite, out NULL),
+ * OT_ESTATE before a successful solve. */
+ot_status ot_assoc_evaluate(ot_assoc *h, double kappa, double tau, double *rho, double *EN, ot_mem mem,
+                            ot_eval_result *out);
+
+/* maxSINR rule: every device to the RRH of lowest cost, i.e. highest rate
+ * (lowest index on ties; decided on the FP64 cost), and the traffic it
+ * induces, Lambda_j = sum of a_i over the devices associated to j (the RRH
+ * marginal q of Lemma 1). a: I doubles; assoc: I int32 (may be NULL);
+ * Lambda: J doubles; all in cost->mem. Replaces the handle's retained cost:
+ * a later ot_assoc_plan / loads / evaluate needs a new solve.
+ * Errors: as ot_assoc_solve for the descriptor and a (values checked). */
+ot_status ot_assoc_maxsinr(ot_assoc *h, const ot_cost_desc *cost, const double *a, int32_t *assoc, double *Lambda);
+
+typedef struct {
+    int32_t solves;          /* Sinkhorn solves run */
+    int32_t best;            /* index (from 0) of the returned solve */
+    int32_t iterations;      /* Sinkhorn iterations over all solves */
+    int32_t status;          /* ot_status of the returned solve */
+    double max_load;         /* max_j load_j of the returned solve */
+    double first_max_load;   /* max_j load_j of the first solve (q_j = sum(a) / J) */
+    double delta;            /* the step used */
+} ot_adaptive_result;
+
+/* Adaptive Sinkhorn Association (Sec. IV, Alg. 2): starting from q_j =
+ * sum(a) / J, solve (eps, tol, max_iter as ot_assoc_solve), find the RRH of
+ * highest load j* (lowest index on ties), move delta of its traffic to the
+ * others (q_j* -= delta, q_j += delta / (J - 1)), and repeat. Readings of
+ * the paper's open points: delta <= 0 selects 0.01 sum(a) / J; the loop
+ * stops when a solve's maximum load does not fall below the best one so far,
+ * when q_j* - delta would not stay positive, or after max_outer solves; the
+ * result is the solve with the lowest maximum load, whose potentials and
+ * plan the handle then holds (ot_assoc_plan / potentials / loads /
+ * evaluate), solved for the returned q. Solves after the first warm-start
+ * from the previous one. q: J doubles on the HOST (output); jstar: max_outer
+ * int32 on the host, the j* picked after each solve (may be NULL).
+ * Errors: as ot_assoc_solve; OT_EINVAL for max_outer < 1 or q / out NULL. */
+ot_status ot_assoc_adaptive(ot_assoc *h, const ot_cost_desc *cost, const double *a, double eps, double tol,
+                            int32_t max_iter, double delta, int32_t max_outer, double *q, int32_t *jstar,
+                            ot_adaptive_result *out);
+
 /* (instrumentation) Average device duration, in milliseconds, of one launch
  * of the fused sweep kernel that the last successful solve used (same cost,
  * shape and launch configuration; FP32 exponentials if fp64 == 0, else FP64).

@@ -28,6 +28,7 @@
 #include "handle.h"
 #include "kernels.h"
 #include "persist_kernels.h"
+#include "assoc_kernels.h"
 
 using namespace otk;
 
@@ -821,6 +822,72 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
     return OT_OK;
 }
 
+// ------------------------------------------------- association quality --
+// Workgroups and rows per workgroup of the load passes.
+inline void load_grid(const ot_assoc* h, int64_t I, int& nb, int64_t& rpb) {
+    const int want = std::max(1, std::min(kMaxNb, 4 * std::max(1, h->num_cu)));
+    rpb = std::max<int64_t>(1, (I + want - 1) / want);
+    nb = (int)((I + rpb - 1) / rpb);
+}
+
+template <class Src, int NCH>
+void launch_loads_t(ot_assoc* h, const LoadArgs& A, const Src& src, int nb) {
+    auto kern = k_loads<Src, 1, NCH, 8>;
+    const size_t ncols = (size_t)NCH * 64;
+    const size_t lds = sizeof(double) * std::max((size_t)Src::kStageDoubles * ncols, (size_t)4 * ncols) + 64;
+    set_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(512), lds, h->stream, A, src);
+}
+
+// One pass of k_loads over the retained cost (load pass when rho is null).
+ot_status run_loads(ot_assoc* h, const double* rho, int& nb_out) {
+    const int64_t I = h->I;
+    const int J = (int)h->J;
+    int nb;
+    int64_t rpb;
+    load_grid(h, I, nb, rpb);
+    nb_out = nb;
+    LoadArgs A{};
+    A.I = I;
+    A.J = J;
+    A.nch = (J + 63) / 64;
+    A.rows_per_block = rpb;
+    A.kk = std::log2(std::exp(1.0)) / h->eps;
+    A.a = h->a;
+    A.f = h->f[h->res_par];
+    A.g = h->g[h->res_par];
+    A.rho = rho;
+    A.col_part = h->col_part;
+    A.row_part = h->stat_part;
+    ot_status st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
+        using S = std::decay_t<decltype(src)>;
+        if (J <= 512) launch_loads_t<S, 8>(h, A, src, nb);
+        else launch_loads_t<S, 32>(h, A, src, nb);
+        return OT_OK;
+    });
+    if (st) return st;
+    HIPCHK(h, hipGetLastError());
+    return OT_OK;
+}
+
+// load_j (scale 1) or rho_j = kappa load_j and E[N_j] into device buffers.
+ot_status device_loads(ot_assoc* h, double scale, double* out_dev, double* en_dev) {
+    int nb = 0;
+    ot_status st = run_loads(h, nullptr, nb);
+    if (st) return st;
+    const int J = (int)h->J;
+    hipLaunchKernelGGL(k_cols_fin, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, h->stream,
+                       (const double*)h->col_part, nb, J, scale, out_dev, en_dev);
+    HIPCHK(h, hipGetLastError());
+    return OT_OK;
+}
+
+ot_status copy_out(ot_assoc* h, void* dst, const void* src_dev, size_t bytes, ot_mem mem) {
+    HIPCHK(h, hipMemcpyAsync(dst, src_dev, bytes, mem == OT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                             h->stream));
+    return OT_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI ==
@@ -1264,6 +1331,207 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
     hipFree(fs);
     hipFree(gs);
     return st;
+}
+
+
+ot_status ot_assoc_rrh_loads(ot_assoc* h, double* loads, ot_mem mem) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!loads) return fail(h, OT_EINVAL, "loads is NULL");
+    if (mem != OT_MEM_HOST && mem != OT_MEM_DEVICE) return fail(h, OT_EINVAL, "bad memory space");
+    if (!h->solved || !h->retained) return fail(h, OT_ESTATE, "no successful solve to take loads from");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    double* out = h->xch;  // (scratch between solves)
+    ot_status st = device_loads(h, 1.0, out, nullptr);
+    if (!st) st = copy_out(h, loads, out, sizeof(double) * (size_t)h->J, mem);
+    if (st) return st;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return OT_OK;
+}
+
+ot_status ot_assoc_evaluate(ot_assoc* h, double kappa, double tau, double* rho, double* EN, ot_mem mem,
+                            ot_eval_result* out) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!out) return fail(h, OT_EINVAL, "out is NULL");
+    if (!(kappa > 0.0) || !std::isfinite(kappa) || !(tau > 0.0) || !std::isfinite(tau))
+        return fail(h, OT_EINVAL, "kappa and tau must be positive and finite");
+    if (mem != OT_MEM_HOST && mem != OT_MEM_DEVICE) return fail(h, OT_EINVAL, "bad memory space");
+    if (!h->solved || !h->retained) return fail(h, OT_ESTATE, "no successful solve to evaluate");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const int J = (int)h->J;
+    double* rho_d = h->xch;
+    double* en_d = h->xch + J;
+    double* tot_d = h->xch + 2 * (size_t)J;
+    ot_status st = device_loads(h, kappa, rho_d, en_d);
+    if (st) return st;
+    int nb = 0;
+    if ((st = run_loads(h, rho_d, nb))) return st;
+    hipLaunchKernelGGL(k_rows_fin, dim3(1), dim3(64), 0, h->stream, (const double*)h->stat_part, nb, tot_d);
+    std::vector<double> hr((size_t)J + 2);
+    HIPCHK(h, hipMemcpyAsync(hr.data(), rho_d, sizeof(double) * J, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(hr.data() + J, tot_d, sizeof(double) * 2, hipMemcpyDeviceToHost, h->stream));
+    if (rho && (st = copy_out(h, rho, rho_d, sizeof(double) * J, mem))) return st;
+    if (EN && (st = copy_out(h, EN, en_d, sizeof(double) * J, mem))) return st;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    ot_eval_result r{};
+    r.max_rho = 0.0;
+    for (int j = 0; j < J; ++j) {
+        r.max_rho = std::max(r.max_rho, hr[j]);
+        if (hr[j] >= 1.0) r.overloaded_rrhs += 1;
+    }
+    r.devices_overloaded = (int32_t)hr[J + 1];
+    const bool finite = r.devices_overloaded == 0;
+    r.objective = finite ? tau * hr[J] : __builtin_huge_val();
+    r.mean_completion = finite ? r.objective / (double)h->I : __builtin_huge_val();
+    *out = r;
+    return OT_OK;
+}
+
+ot_status ot_assoc_maxsinr(ot_assoc* h, const ot_cost_desc* cost, const double* a, int32_t* assoc, double* Lambda) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    ot_status st = validate_desc(h, cost);
+    if (st) return st;
+    if (!a || !Lambda) return fail(h, OT_EINVAL, "a or Lambda is NULL");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const int64_t I = cost->I;
+    const int J = (int)cost->J;
+    std::vector<double> ah;
+    if ((st = read_vec(h, a, I, cost->mem, ah))) return st;
+    for (double v : ah)
+        if (!(v >= 0.0) || !std::isfinite(v)) return fail(h, OT_EINVAL, "device traffic a must be non-negative and finite");
+    h->solved = false;  // the handle's retained cost is replaced below
+    HIPCHK(h, hipMemcpyAsync(h->a, ah.data(), sizeof(double) * I, hipMemcpyHostToDevice, h->stream));
+    if ((st = upload_cost(h, cost, kCheckNow))) return st;
+    // rows per workgroup: a multiple of the 64-row chunk, at most kMaxNb workgroups
+    int64_t rpb = std::max<int64_t>(kMaxsinrRows, (I + kMaxNb - 1) / kMaxNb);
+    rpb = (rpb + kMaxsinrRows - 1) / kMaxsinrRows * kMaxsinrRows;
+    const int nb = (int)((I + rpb - 1) / rpb);
+    int32_t* assoc_d = nullptr;
+    if (assoc && cost->mem == OT_MEM_DEVICE) assoc_d = assoc;
+    else if (assoc) {
+        HIPCHK(h, hipMalloc(&assoc_d, sizeof(int32_t) * (size_t)std::max<int64_t>(I, 1)));
+    }
+    st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
+        using S = std::decay_t<decltype(src)>;
+        const size_t lds = sizeof(double) * (size_t)S::kStageDoubles * (size_t)J + 8;
+        hipLaunchKernelGGL(k_maxsinr<S>, dim3((unsigned)nb), dim3(256), lds, h->stream, I, J, rpb,
+                           (const double*)h->a, src, assoc_d, h->col_part);
+        return OT_OK;
+    });
+    if (!st) {
+        double* lam_d = h->xch;
+        hipLaunchKernelGGL(k_cols_fin, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, h->stream,
+                           (const double*)h->col_part, nb, J, 1.0, lam_d, (double*)nullptr);
+        st = copy_out(h, Lambda, lam_d, sizeof(double) * J, cost->mem);
+        if (!st && assoc && assoc_d != assoc)
+            st = copy_out(h, assoc, assoc_d, sizeof(int32_t) * (size_t)I, OT_MEM_HOST);
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (assoc_d && assoc_d != assoc) hipFree(assoc_d);
+    if (st) return st;
+    if (e != hipSuccess) return fail(h, OT_EDEVICE, "maxSINR kernels failed: %s", hipGetErrorString(e));
+    return OT_OK;
+}
+
+ot_status ot_assoc_adaptive(ot_assoc* h, const ot_cost_desc* cost, const double* a, double eps, double tol,
+                            int32_t max_iter, double delta, int32_t max_outer, double* q, int32_t* jstar,
+                            ot_adaptive_result* out) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    ot_status st = validate_desc(h, cost);
+    if (st) return st;
+    if (!a || !q || !out) return fail(h, OT_EINVAL, "a, q or out is NULL");
+    if (max_outer < 1) return fail(h, OT_EINVAL, "max_outer must be >= 1");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const int64_t I = cost->I;
+    const int J = (int)cost->J;
+    std::vector<double> ah;
+    if ((st = read_vec(h, a, I, cost->mem, ah))) return st;
+    const double mass = ksum(ah);
+    const double d = delta > 0.0 ? delta : 0.01 * mass / J;
+    // device copies reused by every solve: a, q, the best potentials; a
+    // host-memory matrix is staged once and then referenced
+    double *a_d = nullptr, *q_d = nullptr, *fb = nullptr, *gb = nullptr;
+    auto release = [&]() {
+        hipFree(a_d);
+        hipFree(q_d);
+        hipFree(fb);
+        hipFree(gb);
+    };
+    if (hipMalloc(&a_d, sizeof(double) * I) != hipSuccess || hipMalloc(&q_d, sizeof(double) * J) != hipSuccess ||
+        hipMalloc(&fb, sizeof(double) * I) != hipSuccess || hipMalloc(&gb, sizeof(double) * J) != hipSuccess) {
+        release();
+        return fail(h, OT_ENOMEM, "adaptive: workspace allocation failed");
+    }
+    ot_cost_desc dc = *cost;
+    auto failed = [&](ot_status s) {
+        release();
+        return s;
+    };
+    if (hipMemcpy(a_d, ah.data(), sizeof(double) * I, hipMemcpyHostToDevice) != hipSuccess)
+        return failed(fail(h, OT_EDEVICE, "adaptive: copy of a failed"));
+    if (cost->mem == OT_MEM_HOST && cost->kind != OT_COST_GEOMETRY) {
+        const size_t esz = cost->dtype == OT_F32 ? 4 : 8;
+        const size_t bytes = (size_t)(I * ld_of(*cost)) * esz;
+        if ((st = ensure_stage(h, bytes))) return failed(st);
+        if (hipMemcpy(h->stage, cost->data, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return failed(fail(h, OT_EDEVICE, "adaptive: staging of the cost failed"));
+        dc.data = h->stage;
+        dc.mem = OT_MEM_DEVICE;
+    } else if (cost->mem == OT_MEM_HOST) {
+        return failed(fail(h, OT_EINVAL, "adaptive: pass geometry positions in device memory"));
+    }
+    std::vector<double> qv((size_t)J, mass / J), best_q, loads((size_t)J);
+    int best = -1, solves = 0, iters = 0;
+    double best_max = 0.0, first_max = 0.0;
+    ot_assoc_result best_res{};
+    for (int k = 0; k < max_outer; ++k) {
+        if (hipMemcpy(q_d, qv.data(), sizeof(double) * J, hipMemcpyHostToDevice) != hipSuccess)
+            return failed(fail(h, OT_EDEVICE, "adaptive: copy of q failed"));
+        ot_assoc_result res{};
+        st = ot_assoc_solve(h, &dc, a_d, q_d, eps, tol, max_iter, k > 0 ? 1 : 0, &res);
+        if (st < 0) return failed(st);
+        ++solves;
+        iters += res.iterations;
+        if ((st = ot_assoc_rrh_loads(h, loads.data(), OT_MEM_HOST))) return failed(st);
+        int js = 0;
+        for (int j = 1; j < J; ++j)
+            if (loads[j] > loads[js]) js = j;
+        const double mx = loads[js];
+        if (jstar) jstar[k] = js;
+        if (k == 0) first_max = mx;
+        if (best >= 0 && !(mx < best_max)) break;
+        best = k;
+        best_max = mx;
+        best_q = qv;
+        best_res = res;
+        HIPCHK(h, hipMemcpyAsync(fb, h->f[h->res_par], sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(gb, h->g[h->res_par], sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
+        if (J < 2 || !(qv[js] - d > 0.0)) break;
+        const double step = d / (J - 1);
+        std::vector<double> nq((size_t)J);
+        for (int j = 0; j < J; ++j) nq[j] = qv[j] + step;
+        nq[js] = qv[js] - d;
+        qv.swap(nq);
+    }
+    // the handle holds the best solve's potentials (same instance and eps)
+    HIPCHK(h, hipMemcpyAsync(h->f[h->res_par], fb, sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->g[h->res_par], gb, sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    release();
+    std::memcpy(q, best_q.data(), sizeof(double) * J);
+    ot_adaptive_result r{};
+    r.solves = solves;
+    r.best = best;
+    r.iterations = iters;
+    r.status = best_res.status;
+    r.max_load = best_max;
+    r.first_max_load = first_max;
+    r.delta = d;
+    *out = r;
+    return (ot_status)best_res.status;
 }
 
 }  // extern "C"

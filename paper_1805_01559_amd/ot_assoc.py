@@ -32,7 +32,7 @@ OT_RESULT_PERSISTENT = 1
 EXPORTS = [
     "ot_assoc_default_options", "ot_assoc_create", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
     "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep",
-    "ot_assoc_fast_phase_time",
+    "ot_assoc_fast_phase_time", "ot_assoc_rrh_loads", "ot_assoc_evaluate", "ot_assoc_maxsinr", "ot_assoc_adaptive",
     "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_config",
     "ot_assoc_batch_potentials", "ot_assoc_solve_snapshots", "ot_assoc_snapshot_potentials",
     "ot_assoc_batch_plan", "ot_serve_default_options", "ot_serve_create", "ot_serve_submit", "ot_serve_progress",
@@ -66,6 +66,16 @@ class ot_assoc_result(ct.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ot_eval_result(ct.Structure):
+    _fields_ = [("max_rho", ct.c_double), ("mean_completion", ct.c_double), ("objective", ct.c_double),
+                ("overloaded_rrhs", ct.c_int32), ("devices_overloaded", ct.c_int32)]
+
+
+class ot_adaptive_result(ct.Structure):
+    _fields_ = [("solves", ct.c_int32), ("best", ct.c_int32), ("iterations", ct.c_int32), ("status", ct.c_int32),
+                ("max_load", ct.c_double), ("first_max_load", ct.c_double), ("delta", ct.c_double)]
 
 
 class ot_serve_options(ct.Structure):
@@ -108,6 +118,11 @@ def lib():
         L.ot_assoc_materialize_cost.argtypes = [vp, ct.POINTER(ot_cost_desc), vp]
         L.ot_assoc_time_sweep.argtypes = [vp, ct.c_int32, ct.c_int, ct.POINTER(d)]
         L.ot_assoc_fast_phase_time.argtypes = [vp, ct.POINTER(d), ct.POINTER(ct.c_int32)]
+        L.ot_assoc_rrh_loads.argtypes = [vp, vp, ct.c_int]
+        L.ot_assoc_evaluate.argtypes = [vp, d, d, vp, vp, ct.c_int, ct.POINTER(ot_eval_result)]
+        L.ot_assoc_maxsinr.argtypes = [vp, ct.POINTER(ot_cost_desc), vp, vp, vp]
+        L.ot_assoc_adaptive.argtypes = [vp, ct.POINTER(ot_cost_desc), vp, d, d, ct.c_int32, d, ct.c_int32, vp, vp,
+                                        ct.POINTER(ot_adaptive_result)]
         L.ot_assoc_destroy.argtypes = [vp]
         L.ot_assoc_destroy.restype = None
         L.ot_assoc_last_error.argtypes = [vp]
@@ -422,6 +437,57 @@ class Solver:
         self._I, self._J = desc.I, desc.J
         del keep, ka, kb
         return st, res
+
+    # ---- association quality (Sec. II-B), maxSINR (Sec. IV), Alg. 2 ----
+    def rrh_loads(self):
+        """load_j = sum_i C_ij x_ij of the last solve's plan (J doubles, host)."""
+        out = np.empty(self._J, np.float64)
+        _check(self.h, lib().ot_assoc_rrh_loads(self.h, out.ctypes.data, OT_MEM_HOST))
+        return out
+
+    def evaluate(self, kappa, tau):
+        """(rho, E[N], ot_eval_result) of the last solve: rho = kappa load,
+        E[N] = rho / (1 - rho), device completion times with tau."""
+        rho = np.empty(self._J, np.float64)
+        en = np.empty(self._J, np.float64)
+        r = ot_eval_result()
+        _check(self.h, lib().ot_assoc_evaluate(self.h, float(kappa), float(tau), rho.ctypes.data, en.ctypes.data,
+                                               OT_MEM_HOST, ct.byref(r)))
+        return rho, en, r
+
+    def maxsinr(self, desc, keep, a):
+        """(association per device, Lambda per RRH) of the maxSINR rule; a in
+        the cost's memory space; host numpy results."""
+        pa, ma, ka = _ptr_mem(a, np.float64)
+        if ma != desc.mem:
+            raise ValueError("a must be in the cost's memory space")
+        if desc.mem == OT_MEM_HOST:
+            assoc = np.empty(desc.I, np.int32)
+            lam = np.empty(desc.J, np.float64)
+            _check(self.h, lib().ot_assoc_maxsinr(self.h, ct.byref(desc), pa, assoc.ctypes.data, lam.ctypes.data))
+            return assoc, lam
+        import torch
+        assoc = torch.empty(desc.I, dtype=torch.int32, device=a.device)
+        lam = torch.empty(desc.J, dtype=torch.float64, device=a.device)
+        _check(self.h, lib().ot_assoc_maxsinr(self.h, ct.byref(desc), pa, assoc.data_ptr(), lam.data_ptr()))
+        del keep, ka
+        return assoc.cpu().numpy(), lam.cpu().numpy()
+
+    def adaptive(self, desc, keep, a, eps, tol=1e-8, max_iter=2000, delta=0.0, max_outer=100):
+        """Adaptive Sinkhorn Association (Alg. 2). Returns (status, q, j* per
+        solve, ot_adaptive_result); the handle then holds the best solve."""
+        pa, ma, ka = _ptr_mem(a, np.float64)
+        if ma != desc.mem:
+            raise ValueError("a must be in the cost's memory space")
+        q = np.empty(desc.J, np.float64)
+        js = np.full(max_outer, -1, np.int32)
+        r = ot_adaptive_result()
+        st = lib().ot_assoc_adaptive(self.h, ct.byref(desc), pa, float(eps), float(tol), int(max_iter), float(delta),
+                                     int(max_outer), q.ctypes.data, js.ctypes.data, ct.byref(r))
+        _check(self.h, st)
+        self._I, self._J = desc.I, desc.J
+        del keep, ka
+        return st, q, js[: r.solves], r
 
     def solve_dense(self, C, a, b, eps, tol=1e-8, max_iter=2000, warm_start=False):
         d, keep = matrix_desc(C, OT_COST_DENSE)

@@ -44,7 +44,9 @@ def test_struct_layouts_match_the_header(tmp_path):
               "offsetof(ot_assoc_options, batch_tune)", "sizeof(ot_serve_options)",
               "offsetof(ot_serve_options, keep_layouts)", "sizeof(ot_request)", "offsetof(ot_request, layout_key)",
               "offsetof(ot_request, user_tag)", "sizeof(ot_completion)", "offsetof(ot_completion, result)",
-              "offsetof(ot_completion, t_done)", "offsetof(ot_assoc_options, persistent)"]
+              "offsetof(ot_completion, t_done)", "offsetof(ot_assoc_options, persistent)",
+              "sizeof(ot_eval_result)", "offsetof(ot_eval_result, devices_overloaded)",
+              "sizeof(ot_adaptive_result)", "offsetof(ot_adaptive_result, delta)"]
     fmt = " ".join(["%zu"] * len(fields))
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ot_assoc.h"\n'
                    'int main(void){printf("' + fmt + '\\n", ' + ", ".join(fields) + ');return 0;}\n')
@@ -55,7 +57,9 @@ def test_struct_layouts_match_the_header(tmp_path):
             A.ot_cost_desc.geom.offset, A.ot_assoc_result.seconds.offset, A.ot_assoc_options.batch_tune.offset,
             ct.sizeof(A.ot_serve_options), A.ot_serve_options.keep_layouts.offset, ct.sizeof(A.ot_request),
             A.ot_request.layout_key.offset, A.ot_request.user_tag.offset, ct.sizeof(A.ot_completion),
-            A.ot_completion.result.offset, A.ot_completion.t_done.offset, A.ot_assoc_options.persistent.offset]
+            A.ot_completion.result.offset, A.ot_completion.t_done.offset, A.ot_assoc_options.persistent.offset,
+            ct.sizeof(A.ot_eval_result), A.ot_eval_result.devices_overloaded.offset,
+            ct.sizeof(A.ot_adaptive_result), A.ot_adaptive_result.delta.offset]
     assert got == want
 
 
