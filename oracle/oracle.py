@@ -10,6 +10,8 @@ What it computes (paper sections in parentheses):
   interference from all other RRHs (Sec. II-A);
 * ``cost``: C_ij = (1/R_ij) / median(1/R), the load-per-unit-traffic cost of
   Sec. IV choice (ii), median-normalised;
+* ``distance_cost``: C_ij = ||x_i - X_j|| / scale, the Euclidean cost of
+  Sec. IV choice (i) (scale = 1 is the paper's form);
 * ``sinkhorn``: FP64 log-domain Sinkhorn (Sec. III-B, Sinkhorn algorithm),
   stopping on the total absolute marginal residual (Sec. III, "Sinkhorn vs LP");
 * ``plan`` / ``plan_stats``: pi = exp((f + g - C)/eps) (the KKT form of
@@ -147,6 +149,22 @@ def cost_rows(layout, rows, scale: float) -> np.ndarray:
     if not scale > 0:
         raise ValueError("cost_rows needs the scale")
     return (1.0 / rates_rows(layout, rows)) / scale
+
+
+def distance_cost(layout, scale: float = 1.0):
+    """Returns (C, scale) with C_ij = ||x_i - X_j|| / scale, the distance
+    between device i and RRH j (Sec. IV, cost choice (i)). The positions are
+    the layout's FP32 coordinates, taken exactly into FP64; the distance is
+    the plain FP64 square root of the summed squared differences. scale <= 0
+    means: the lower median of the distances."""
+    dev = np.asarray(layout.dev_xy, dtype=np.float32).astype(np.float64)
+    rrh = np.asarray(layout.rrh_xy, dtype=np.float32).astype(np.float64)
+    dx = dev[:, 0][:, None] - rrh[:, 0][None, :]
+    dy = dev[:, 1][:, None] - rrh[:, 1][None, :]
+    D = np.sqrt(dx * dx + dy * dy)
+    if not scale > 0:
+        scale = lower_median(D)
+    return D / scale, float(scale)
 
 
 class SinkhornResult:
