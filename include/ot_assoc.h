@@ -61,7 +61,12 @@ typedef enum {
     OT_ESTATE = -5       /* call made in the wrong state (e.g. plan before solve) */
 } ot_status;
 
-typedef enum { OT_COST_DENSE = 0, OT_COST_RATES = 1, OT_COST_GEOMETRY = 2 } ot_cost_kind;
+/* Cost kinds: DENSE (a matrix C_ij), RATES (a matrix R_ij, C = (1/R) / scale:
+ * the load per unit traffic of Sec. IV, choice (ii)), GEOMETRY (the same cost
+ * regenerated from positions with the downlink model below) and EUCLID
+ * (C_ij = ||x_i - X_j|| / scale from the positions in `geom`, metres: Sec. IV
+ * choice (i); the radio fields of `geom` are not used). */
+typedef enum { OT_COST_DENSE = 0, OT_COST_RATES = 1, OT_COST_GEOMETRY = 2, OT_COST_EUCLID = 3 } ot_cost_kind;
 typedef enum { OT_MEM_HOST = 0, OT_MEM_DEVICE = 1 } ot_mem;
 typedef enum { OT_F32 = 0, OT_F64 = 1 } ot_dtype;
 
@@ -100,8 +105,8 @@ typedef struct {
     ot_mem mem;
     ot_dtype dtype;   /* element type of `data` (DENSE / RATES) */
     const void *data; /* DENSE: C_ij; RATES: R_ij > 0 */
-    double scale;     /* RATES / GEOMETRY: C_ij = (1 / R_ij) / scale, scale > 0 */
-    ot_geometry geom; /* GEOMETRY only */
+    double scale;     /* RATES / GEOMETRY: C_ij = (1 / R_ij) / scale; EUCLID: C_ij = ||x_i - X_j|| / scale; scale > 0 */
+    ot_geometry geom; /* GEOMETRY (all fields) and EUCLID (dev_xy, rrh_xy only) */
     int64_t ld;       /* DENSE / RATES: row stride of `data` in elements (0 = J, else >= J;
                          the padding entries are never used as costs) */
 } ot_cost_desc;
@@ -160,7 +165,7 @@ ot_status ot_assoc_create(ot_assoc **h, int64_t I_max, int64_t J_max, const ot_a
  *   otherwise from g = 0 (the all-ones column scaling of the algorithm).
  * Validation (OT_EINVAL, nothing written): 1 <= I <= I_max, 1 <= J <= J_max;
  * a_i > 0, b_j > 0, all finite; |sum a - sum b| <= 1e-12 sum a; eps > 0 and
- * finite; tol >= 0; max_iter >= 1; scale > 0 for RATES / GEOMETRY; geometry
+ * finite; tol >= 0; max_iter >= 1; scale > 0 for RATES / GEOMETRY / EUCLID; geometry
  * constants positive (noise_w >= 0, shadow_sigma_db >= 0). Dense costs and
  * rates are checked on the device (non-finite C or R <= 0 give OT_EINVAL).
  * Returns OT_OK, OT_WARN_MAXITER (result valid, tol not met) or an error.
@@ -185,13 +190,14 @@ ot_status ot_assoc_potentials(ot_assoc *h, double *f, double *g, ot_mem mem);
 ot_status ot_assoc_set_potentials(ot_assoc *h, const double *f, const double *g, int64_t I, int64_t J, ot_mem mem);
 
 /* Lower median (element floor((IJ - 1) / 2) in sorted order) of the I*J
- * values 1/R_ij of a RATES or GEOMETRY descriptor, computed on the device in
- * FP32 by radix selection over the regenerated values; the normalisation of
- * the cost C = (1/R)/median. The descriptor's `scale` is ignored.
+ * values 1/R_ij of a RATES or GEOMETRY descriptor (of the distances
+ * ||x_i - X_j|| of an EUCLID one), computed on the device in FP32 by radix
+ * selection over the regenerated values; the normalisation of the cost
+ * C = (1/R)/median. The descriptor's `scale` is ignored.
  * Errors: OT_EINVAL (bad descriptor or sizes), OT_EDEVICE. */
 ot_status ot_assoc_cost_median(ot_assoc *h, const ot_cost_desc *cost, double *median_out);
 
-/* Writes the FP32 cost C_ij of a RATES or GEOMETRY descriptor into the
+/* Writes the FP32 cost C_ij of a RATES, GEOMETRY or EUCLID descriptor into the
  * caller's device buffer C (I x J row-major): the materialised form of the
  * cost that the geometry sweeps regenerate on the fly. */
 ot_status ot_assoc_materialize_cost(ot_assoc *h, const ot_cost_desc *cost, float *C_dev);
@@ -307,11 +313,12 @@ const char *ot_assoc_last_error(const ot_assoc *h);
  * device memory whose J and row stride (ld, else J) are multiples of 4 and whose
  * base is 16-byte aligned is referenced in place (keep it valid until the
  * next batch on the handle); other DENSE / RATES inputs (host or device, FP32
- * or FP64) are converted, GEOMETRY inputs (device memory; positions read at
- * admission) are materialised (scale <= 0 takes the median of 1/R, which
+ * or FP64) are converted, GEOMETRY and EUCLID inputs (device memory; positions
+ * read at admission) are materialised (scale <= 0 takes the median of 1/R, or
+ * of the distances, which
  * waits on the host). Cost values are not screened: a non-finite cost ends
  * that instance with OT_ENUMERIC. 1 <= J <= 512; a[k] and b[k] live in costs[k].mem
- * (GEOMETRY: device memory). eps[k] > 0 per instance; tol and max_iter are
+ * (GEOMETRY, EUCLID: device memory). eps[k] > 0 per instance; tol and max_iter are
  * shared. out[k] (may be NULL) receives instance k's result; `seconds` is the
  * device time of the whole batch.
  *
@@ -344,16 +351,18 @@ ot_status ot_assoc_batch_plan(ot_assoc *h, int k, void *pi, ot_mem mem, ot_dtype
  * eq. (5). Solved together in the scaling form of the Sinkhorn iteration
  * (Sec. III-B): a reference solve of the mean snapshot (single-instance path)
  * gives potentials (fbar, gbar) that stabilise the kernel
- * K = exp((fbar + gbar - C) / eps), held in BF16; the half-steps
- * u_s = a_s / (K v_s) and v_s = b / (K^T u_s) of all snapshots are two GEMMs
- * on the matrix cores (BF16 operands, u and v split into high and low BF16
- * parts, FP32 accumulation). The iteration stops when every snapshot's column
+ * K = exp((fbar + gbar - C) / eps); the half-steps u_s = a_s / (K v_s) and
+ * v_s = b / (K^T u_s) of all snapshots are two GEMMs on the matrix cores
+ * with BF16 operands: K, u and v each split into high and low BF16 parts
+ * (about 16 significant bits), three products per step (hi.hi, hi.lo,
+ * lo.hi), FP32 accumulation. The iteration stops when every snapshot's column
  * residual of the BF16 problem is below tol (relative to sum a_s) or after
  * max_iter iterations. out[s] reports the common iteration count and the
  * exact FP64 check of snapshot s's potentials fbar + eps ln u_s,
- * gbar + eps ln v_s against C (for RATES / GEOMETRY, its FP32 materialised
- * form): the violation reflects the BF16 kernel (about 1e-3), not tol.
- * A and b live in cost->mem (GEOMETRY: device). Afterwards the handle's
+ * gbar + eps ln v_s against C (for RATES / GEOMETRY / EUCLID, its FP32 materialised
+ * form): the violation reflects the split-BF16 arithmetic and FP32
+ * accumulation (well below 1e-3), not tol.
+ * A and b live in cost->mem (GEOMETRY, EUCLID: device). Afterwards the handle's
  * single-instance state (ot_assoc_plan / ot_assoc_potentials) is the
  * reference solve. Errors: OT_EINVAL for bad arguments or marginals,
  * OT_ENOMEM, OT_EDEVICE. */
@@ -393,7 +402,7 @@ typedef struct {
 
 typedef struct {
     ot_cost_desc cost;     /* as for ot_assoc_solve_batch */
-    const double *a, *b;   /* marginals, in cost.mem (GEOMETRY: device memory) */
+    const double *a, *b;   /* marginals, in cost.mem (GEOMETRY, EUCLID: device memory) */
     double eps, tol;
     int32_t max_iter;
     int32_t reserved;

@@ -406,13 +406,19 @@ static size_t slot_bytes(int64_t I, int J, int64_t ld, int parts_cap, bool own_c
 
 static int64_t parts_of(int64_t I, int64_t rpp) { return (I + rpp - 1) / rpp; }
 
+// Costs regenerated from positions (geometry, distances): device memory only,
+// materialised into the slot's padded FP32 matrix at admission.
+static bool from_positions(const ot_cost_desc* c) {
+    return c->kind == OT_COST_GEOMETRY || c->kind == OT_COST_EUCLID;
+}
+
 ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage, PadJob* pad) {
     const int64_t I = s.I;
     const int J = s.J;
     const int64_t ld = s.ld;
     float* dst = (float*)C_mem;
     pad->src = nullptr;
-    if (c->kind == OT_COST_GEOMETRY) {
+    if (from_positions(c)) {
         double scale = c->scale;
         if (!(scale > 0.0)) {
             // the median of 1/R needs host read-backs: a handle of the
@@ -429,6 +435,17 @@ ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, 
             }
             ot_status st = ot_assoc_cost_median(helper, c, &scale);
             if (st) return fail(st, "cost median: %s", ot_assoc_last_error(helper));
+        }
+        const size_t lds = sizeof(double) * (size_t)J + 8;
+        const int mg = (int)std::min<int64_t>(4096, (I + 7) / 8);
+        if (c->kind == OT_COST_EUCLID) {  // distances: the padded FP32 matrix directly
+            EuclidSrc e{};
+            e.dev_xy = (const float*)c->geom.dev_xy;
+            e.rrh_xy = (const float*)c->geom.rrh_xy;
+            e.inv_scale = 1.0 / scale;
+            hipLaunchKernelGGL(k_materialize<EuclidSrc>, dim3(mg), dim3(512), lds, stream, I, J, ld, dst, e);
+            ECHK(this, hipGetLastError());
+            return OT_OK;
         }
         // per-device interference sums (the staging block), then the padded
         // FP32 matrix, both queued on the engine stream without a host wait;
@@ -450,8 +467,6 @@ ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, 
             case 3: case 4: hipLaunchKernelGGL(k_geo_prepass<4>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
             default: hipLaunchKernelGGL(k_geo_prepass<8>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
         }
-        const size_t lds = sizeof(double) * (size_t)J + 8;
-        const int mg = (int)std::min<int64_t>(4096, (I + 7) / 8);
         hipLaunchKernelGGL(k_materialize<GeoSrc>, dim3(mg), dim3(512), lds, stream, I, J, ld, dst, g);
         ECHK(this, hipGetLastError());
         return OT_OK;
@@ -493,8 +508,10 @@ static ot_status check_desc(BatchEngine* e, const ot_cost_desc* c) {
             if (c->ld != 0 && c->ld < c->J) return e->fail(OT_EINVAL, "row stride below J");
             break;
         case OT_COST_GEOMETRY:
-            if (c->mem != OT_MEM_DEVICE) return e->fail(OT_EINVAL, "batched geometry must be in device memory");
+        case OT_COST_EUCLID:
+            if (c->mem != OT_MEM_DEVICE) return e->fail(OT_EINVAL, "batched positions must be in device memory");
             if (!c->geom.dev_xy || !c->geom.rrh_xy) return e->fail(OT_EINVAL, "positions are NULL");
+            if (std::isinf(c->scale)) return e->fail(OT_EINVAL, "scale must be finite (<= 0: the median)");
             break;
         default:
             return e->fail(OT_EINVAL, "unknown cost kind");
@@ -526,7 +543,7 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
     const size_t jobs_b = align_up(sizeof(AdmJob) * n), pads_b = align_up(sizeof(PadJob) * n);
     size_t marg_b = 0;
     for (auto& r : reqs)
-        if (r.cost->kind != OT_COST_GEOMETRY && r.cost->mem == OT_MEM_HOST)
+        if (!from_positions(r.cost) && r.cost->mem == OT_MEM_HOST)
             marg_b += align_up(sizeof(double) * r.cost->I) + align_up(sizeof(double) * r.cost->J);
     if (ot_status st = ensure_blob(set, jobs_b + pads_b + marg_b)) return st;
     AdmJob* jobs_h = (AdmJob*)blob_h[set];
@@ -566,7 +583,7 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         // released once the work reading it is queued (stream order)
         const size_t esz = c->dtype == OT_F64 ? 8 : 4;
         size_t stage_b = 0;
-        if (!ref && c->kind != OT_COST_GEOMETRY && c->mem == OT_MEM_HOST) stage_b = esz * (size_t)(I * lds);
+        if (!ref && !from_positions(c) && c->mem == OT_MEM_HOST) stage_b = esz * (size_t)(I * lds);
         if (c->kind == OT_COST_GEOMETRY) stage_b = (2 * sizeof(double) + sizeof(int)) * (size_t)I;
         char* stage = stage_b ? pool.alloc(stage_b) : nullptr;
         char* mem = (stage_b && !stage) ? nullptr : pool.alloc(slot_bytes(I, J, ld, parts_cap, !ref));
@@ -637,7 +654,7 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         J1.d = d;
         J1.sp = SolveParams{d.kk, d.eps};
         J1.prm_dst = sl.prm;
-        if (c->kind != OT_COST_GEOMETRY && c->mem == OT_MEM_HOST) {
+        if (!from_positions(c) && c->mem == OT_MEM_HOST) {
             std::memcpy(marg_h, r.a, sizeof(double) * I);
             J1.a_src = (const double*)marg_d;
             marg_h += align_up(sizeof(double) * I);

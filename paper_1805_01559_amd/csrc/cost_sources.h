@@ -255,4 +255,61 @@ struct GeoSrc {
     }
 };
 
+// -------------------------------------------------------------- Euclidean --
+// C_ij = ||x_i - X_j|| / scale from device and RRH positions (Sec. IV, cost
+// choice (i)): one square root per cell, in FP32 for the fast sweeps and in
+// FP64 (from the same FP32 positions) for the polish, the check and the plan.
+struct EuclidSrc {
+    const float* dev_xy;  // I x 2
+    const float* rrh_xy;  // J x 2
+    double inv_scale;
+    static constexpr int kTag = 6;
+    static constexpr int kVecWide = 1;
+    static constexpr bool kCheap = false;    // keep the computed cost for the second pass
+    static constexpr int kStageDoubles = 1;  // (X_j, Y_j) as a float pair per column
+    __device__ void stage(double* sm, int ncols) const {
+        float2* xy = reinterpret_cast<float2*>(sm);
+        for (int c = threadIdx.x; c < ncols; c += blockDim.x) xy[c] = reinterpret_cast<const float2*>(rrh_xy)[c];
+    }
+    struct Row {
+        float x, y;
+    };
+    __device__ Row row(int64_t i) const {
+        const float2 p = reinterpret_cast<const float2*>(dev_xy)[i];
+        return Row{p.x, p.y};
+    }
+    __device__ __forceinline__ float cost32(const Row& r, float2 q) const {
+        const float dx = r.x - q.x, dy = r.y - q.y;
+        return __builtin_sqrtf(fmaf(dx, dx, dy * dy)) * (float)inv_scale;
+    }
+    __device__ __forceinline__ double cost64(const Row& r, float2 q) const {
+        const double dx = (double)r.x - (double)q.x, dy = (double)r.y - (double)q.y;
+        return sqrt(dx * dx + dy * dy) * inv_scale;
+    }
+    template <int VEC>
+    struct Raw {};
+    template <int VEC>
+    __device__ __forceinline__ Raw<VEC> load(const Row&, int, int) const { return Raw<VEC>{}; }
+    template <bool P64, int VEC>
+    __device__ __forceinline__ double cost(const Row& r, const Raw<VEC>&, int, int64_t, int j, const double* sm) const {
+        const float2 q = reinterpret_cast<const float2*>(sm)[j];
+        if constexpr (P64) return cost64(r, q);
+        else return (double)cost32(r, q);
+    }
+    template <bool P64, int VEC>
+    __device__ __forceinline__ void get(const Row& r, int64_t, int col0, int J, const double* sm, double (&c)[VEC]) const {
+        const float2* xy = reinterpret_cast<const float2*>(sm);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int j = col0 + v;
+            if (j >= J) { c[v] = pinf64(); continue; }
+            if constexpr (P64) c[v] = cost64(r, xy[j]);
+            else c[v] = (double)cost32(r, xy[j]);
+        }
+    }
+    __device__ __forceinline__ double at64(const Row& r, int64_t, int j, const double* sm) const {
+        return cost64(r, reinterpret_cast<const float2*>(sm)[j]);
+    }
+};
+
 }  // namespace otk

@@ -359,6 +359,11 @@ ot_status validate_desc(ot_assoc* h, const ot_cost_desc* c) {
                 return fail(h, OT_EINVAL, "geometry costs need a positive finite scale");
             break;
         }
+        case OT_COST_EUCLID:
+            if (!c->geom.dev_xy || !c->geom.rrh_xy) return fail(h, OT_EINVAL, "positions are NULL");
+            if (!(c->scale > 0.0 && std::isfinite(c->scale)))
+                return fail(h, OT_EINVAL, "distance costs need a positive finite scale");
+            break;
         default:
             return fail(h, OT_EINVAL, "unknown cost kind %d", (int)c->kind);
     }
@@ -377,8 +382,8 @@ ot_status ensure_stage(ot_assoc* h, size_t bytes) {
 
 
 // Brings the cost of `c` onto the device: host matrices are staged, device
-// matrices are referenced, geometry is copied and its per-device set-up pass
-// runs. Afterwards the handle can rebuild the source without the caller.
+// matrices are referenced, positions are copied (and, for the geometry cost,
+// its per-device set-up pass runs). Afterwards the handle can rebuild the source without the caller.
 // Value checks of the cost: kCheckNone, kCheckNow (the host waits for the
 // verdict) or kCheckDeferred (the verdict goes into the control block, bit 8
 // of input_bad, and ends the solve on the device).
@@ -393,7 +398,7 @@ ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, int check) {
     const int64_t I = c->I, J = c->J, ld = ld_of(*c), n = I * J;
     h->retained = false;
     h->last = *c;
-    if (c->kind != OT_COST_GEOMETRY) {
+    if (c->kind != OT_COST_GEOMETRY && c->kind != OT_COST_EUCLID) {
         const size_t esz = c->dtype == OT_F32 ? 4 : 8;
         const void* data = c->data;
         if (c->mem == OT_MEM_HOST) {
@@ -443,6 +448,11 @@ ot_status upload_cost(ot_assoc* h, const ot_cost_desc* c, int check) {
         }
         if (hbad) return fail(h, OT_EINVAL, "geometry positions have non-finite entries");
     }
+    if (c->kind == OT_COST_EUCLID) {  // distances need no per-device set-up
+        h->cost_dev = nullptr;
+        h->retained = true;
+        return OT_OK;
+    }
     GeoSrc s{};
     s.dev_xy = h->xy_dev;
     s.rrh_xy = h->xy_rrh;
@@ -477,6 +487,13 @@ ot_status with_retained(ot_assoc* h, F&& fn) {
     if (c.kind == OT_COST_RATES) {
         if (c.dtype == OT_F32) { RatesSrc<float> s{}; s.R = (const float*)h->cost_dev; s.ld = J; s.inv_scale = 1.0 / c.scale; return fn(s, h->cost_dev); }
         RatesSrc<double> s{}; s.R = (const double*)h->cost_dev; s.ld = J; s.inv_scale = 1.0 / c.scale; return fn(s, h->cost_dev);
+    }
+    if (c.kind == OT_COST_EUCLID) {
+        EuclidSrc s{};
+        s.dev_xy = h->xy_dev;
+        s.rrh_xy = h->xy_rrh;
+        s.inv_scale = 1.0 / c.scale;
+        return fn(s, (const void*)nullptr);
     }
     GeoSrc s{};
     s.dev_xy = h->xy_dev;
@@ -644,10 +661,10 @@ struct PersistPlan {
 };
 
 // Sources whose fast-sweep cost is an FP32 value (dense FP32, FP32 rates, the
-// FP32 geometry functor): the tile holds exactly what the streaming sweeps
-// compute per cell.
+// FP32 geometry and distance functors): the tile holds exactly what the
+// streaming sweeps compute per cell.
 template <class Src>
-constexpr bool persist_source() { return Src::kTag == 1 || Src::kTag == 3 || Src::kTag == 5; }
+constexpr bool persist_source() { return Src::kTag == 1 || Src::kTag == 3 || Src::kTag == 5 || Src::kTag == 6; }
 
 template <class Src>
 bool persist_plan(const ot_assoc* h, int64_t I, int J, PersistPlan& p) {
@@ -1087,7 +1104,8 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
         if (fb & 2) return fail(h, OT_EINVAL, "RRH marginal b must be positive and finite");
         if (fb & 4)
             return fail(h, OT_EINVAL, "marginals are unbalanced: sum a = %.17g, sum b = %.17g", fin.mass, fin.mass_b);
-        if (cost->kind == OT_COST_GEOMETRY) return fail(h, OT_EINVAL, "geometry positions have non-finite entries");
+        if (cost->kind == OT_COST_GEOMETRY || cost->kind == OT_COST_EUCLID)
+            return fail(h, OT_EINVAL, "geometry positions have non-finite entries");
         return fail(h, OT_EINVAL, cost->kind == OT_COST_DENSE ? "cost matrix has non-finite entries"
                                                               : "rate matrix has entries that are not finite and positive");
     }
@@ -1189,8 +1207,8 @@ ot_status ot_assoc_cost_median(ot_assoc* h, const ot_cost_desc* cost, double* me
     if (!h) return OT_EINVAL;
     h->err.clear();
     if (!median_out) return fail(h, OT_EINVAL, "median_out is NULL");
-    if (!cost || (cost->kind != OT_COST_RATES && cost->kind != OT_COST_GEOMETRY))
-        return fail(h, OT_EINVAL, "the median needs a RATES or GEOMETRY descriptor");
+    if (!cost || (cost->kind != OT_COST_RATES && cost->kind != OT_COST_GEOMETRY && cost->kind != OT_COST_EUCLID))
+        return fail(h, OT_EINVAL, "the median needs a RATES, GEOMETRY or EUCLID descriptor");
     ot_cost_desc c = *cost;
     c.scale = 1.0;  // C = 1/R
     ot_status st = validate_desc(h, &c);
@@ -1236,8 +1254,8 @@ ot_status ot_assoc_materialize_cost(ot_assoc* h, const ot_cost_desc* cost, float
     if (!h) return OT_EINVAL;
     h->err.clear();
     if (!C_dev) return fail(h, OT_EINVAL, "output buffer is NULL");
-    if (!cost || (cost->kind != OT_COST_RATES && cost->kind != OT_COST_GEOMETRY))
-        return fail(h, OT_EINVAL, "materialisation needs a RATES or GEOMETRY descriptor");
+    if (!cost || (cost->kind != OT_COST_RATES && cost->kind != OT_COST_GEOMETRY && cost->kind != OT_COST_EUCLID))
+        return fail(h, OT_EINVAL, "materialisation needs a RATES, GEOMETRY or EUCLID descriptor");
     ot_status st = validate_desc(h, cost);
     if (st) return st;
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
@@ -1472,7 +1490,8 @@ ot_status ot_assoc_adaptive(ot_assoc* h, const ot_cost_desc* cost, const double*
     };
     if (hipMemcpy(a_d, ah.data(), sizeof(double) * I, hipMemcpyHostToDevice) != hipSuccess)
         return failed(fail(h, OT_EDEVICE, "adaptive: copy of a failed"));
-    if (cost->mem == OT_MEM_HOST && cost->kind != OT_COST_GEOMETRY) {
+    const bool positions = cost->kind == OT_COST_GEOMETRY || cost->kind == OT_COST_EUCLID;
+    if (cost->mem == OT_MEM_HOST && !positions) {
         const size_t esz = cost->dtype == OT_F32 ? 4 : 8;
         const size_t bytes = (size_t)(I * ld_of(*cost)) * esz;
         if ((st = ensure_stage(h, bytes))) return failed(st);

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libot_assoc.so")
 OT_OK, OT_WARN_MAXITER, OT_EINVAL, OT_ENOMEM, OT_EDEVICE, OT_ENUMERIC, OT_ESTATE = 0, 1, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OT_OK", 1: "OT_WARN_MAXITER", -1: "OT_EINVAL", -2: "OT_ENOMEM", -3: "OT_EDEVICE",
                 -4: "OT_ENUMERIC", -5: "OT_ESTATE"}
-OT_COST_DENSE, OT_COST_RATES, OT_COST_GEOMETRY = 0, 1, 2
+OT_COST_DENSE, OT_COST_RATES, OT_COST_GEOMETRY, OT_COST_EUCLID = 0, 1, 2, 3
 OT_MEM_HOST, OT_MEM_DEVICE = 0, 1
 OT_F32, OT_F64 = 0, 1
 OT_PREC_FP32, OT_PREC_FP64 = 0, 1
@@ -380,6 +380,21 @@ def geometry_desc(dev_xy, rrh_xy, radio: dict, shadow_key: int, scale: float = 1
     return d, (kd, kr)
 
 
+def euclid_desc(dev_xy, rrh_xy, scale: float = 1.0):
+    """Descriptor of an on-the-fly distance cost C_ij = ||x_i - X_j|| / scale
+    (Sec. IV, cost choice (i))."""
+    pd, md, kd = _ptr_mem(dev_xy, np.float32)
+    pr, mr, kr = _ptr_mem(rrh_xy, np.float32)
+    if md != mr:
+        raise ValueError("device and RRH positions must live in the same memory space")
+    d = ot_cost_desc()
+    d.kind, d.mem, d.dtype = OT_COST_EUCLID, md, OT_F32
+    d.I, d.J = int(dev_xy.shape[0]), int(rrh_xy.shape[0])
+    d.scale = float(scale)
+    d.geom.dev_xy, d.geom.rrh_xy = pd, pr
+    return d, (kd, kr)
+
+
 def matrix_desc(M, kind=OT_COST_DENSE, scale: float = 1.0, J=None):
     """Descriptor of a dense cost (or rate) matrix. With J given, M is an
     (I, ld) row-padded buffer of which the first J columns are the instance."""
@@ -502,6 +517,10 @@ class Solver:
         d, keep = geometry_desc(dev_xy, rrh_xy, radio, shadow_key, scale)
         return self.solve(d, keep, a, b, eps, tol, max_iter, warm_start)
 
+    def solve_euclid(self, dev_xy, rrh_xy, scale, a, b, eps, tol=1e-8, max_iter=2000, warm_start=False):
+        d, keep = euclid_desc(dev_xy, rrh_xy, scale)
+        return self.solve(d, keep, a, b, eps, tol, max_iter, warm_start)
+
     def plan(self, out=None, dtype=np.float64):
         """The plan of the last solve: into `out` (numpy or torch), else a new numpy array."""
         if self._I is None:  # let the library report the state error
@@ -560,7 +579,7 @@ class Solver:
         for d, a, b in zip(descs, a_list, b_list):
             p1, m1, k1 = _ptr_mem(a, np.float64)
             p2, m2, k2 = _ptr_mem(b, np.float64)
-            want = OT_MEM_DEVICE if d.kind == OT_COST_GEOMETRY else d.mem
+            want = OT_MEM_DEVICE if d.kind in (OT_COST_GEOMETRY, OT_COST_EUCLID) else d.mem
             if m1 != want or m2 != want:
                 raise ValueError("marginals must be in the cost's memory space")
             pa.append(p1)
@@ -579,7 +598,7 @@ class Solver:
         d, keep = cost if isinstance(cost, tuple) else matrix_desc(cost, OT_COST_DENSE)
         pa, ma, ka = _ptr_mem(A, np.float64)
         pb, mb, kb = _ptr_mem(b, np.float64)
-        want = OT_MEM_DEVICE if d.kind == OT_COST_GEOMETRY else d.mem
+        want = OT_MEM_DEVICE if d.kind in (OT_COST_GEOMETRY, OT_COST_EUCLID) else d.mem
         if ma != want or mb != want:
             raise ValueError("snapshots and b must be in the cost's memory space")
         st, res = ot_assoc_solve_snapshots(self.h, d, int(A.shape[0]), pa, pb, eps, tol, max_iter)
@@ -653,7 +672,7 @@ class Server:
             d, kc = matrix_desc(cost, OT_COST_DENSE)
         p1, m1, k1 = _ptr_mem(a, np.float64)
         p2, m2, k2 = _ptr_mem(b, np.float64)
-        want = OT_MEM_DEVICE if d.kind == OT_COST_GEOMETRY else d.mem
+        want = OT_MEM_DEVICE if d.kind in (OT_COST_GEOMETRY, OT_COST_EUCLID) else d.mem
         if m1 != want or m2 != want:
             raise ValueError("marginals must be in the cost's memory space")
         r = ot_request()
