@@ -214,7 +214,9 @@ def leg_snapshots(args, A, S, torch, dev, solver, C, L):
     iters = res[0].iterations
     viol = [r.marginal_violation for r in res]
     gemm_s = res[0].seconds  # device time of the GEMM iteration
-    flops = 2 * 2 * L.I * L.J * B * 2 * iters  # two GEMMs, hi + lo operand halves
+    # executed MFMA work: two GEMMs per iteration, each three BF16 products
+    # (Kh Xh, Kh Xl, Kl Xh) of 2 I J B flop
+    flops = 2 * 3 * 2 * L.I * L.J * B * iters
     log(f"snapshots: {t_snap * 1e3:.2f} ms for {B} = {B / t_snap:.0f} snapshot solves/s; {iters} iterations in "
         f"{gemm_s * 1e3:.2f} ms ({flops / gemm_s / 1e12:.1f} TFLOP/s); violation max {max(viol):.2e}")
     times = []
@@ -231,7 +233,7 @@ def leg_snapshots(args, A, S, torch, dev, solver, C, L):
     log(f"plain per snapshot: {t_plain * 1e3:.2f} ms = {1 / t_plain:.0f} solves/s; snapshot speed-up "
         f"{B / t_snap * t_plain:.1f}x")
     return {"workload": f"cran_20000x400 cost, B={B} snapshots (lambda resampled), eps={eps}, tol={tol} on the BF16 "
-                        "problem, K and K^T in BF16, u / v split hi + lo, FP32 accumulation",
+                        "problem, K, u and v split into BF16 hi + lo (3 products per GEMM step), FP32 accumulation",
             "ms_per_64": t_snap * 1e3, "snapshot_solves_per_s": B / t_snap, "iterations": iters,
             "gemm_ms": gemm_s * 1e3, "mfma_tflops": flops / gemm_s / 1e12,
             "mfma_frac_bf16_dense_peak": flops / gemm_s / 2.5e15,

@@ -8,10 +8,13 @@
 // Stacking the snapshots as columns turns both half-steps into GEMMs with a
 // K-dimension of J and I respectively:
 //   P = K V   (I x J) . (J x B)        Q = K^T U   (J x I) . (I x B)
-// run on the matrix cores (v_mfma_f32_16x16x32_bf16): K is held in BF16 (and
-// its transpose, so both GEMMs read their A operand along contiguous memory),
-// U and V are split into BF16 high and low parts (x = hi + lo, so the scaling
-// vectors keep about 16 bits), and every product accumulates in FP32.
+// run on the matrix cores (v_mfma_f32_16x16x32_bf16). K (and its transpose,
+// so both GEMMs read their A operand along contiguous memory), U and V are
+// each split into BF16 high and low parts (x = hi + lo: about 16 significant
+// bits instead of BF16's 8, so that a plan concentrated on few RRHs per
+// device does not inherit the 2^-9 relative rounding of a single BF16 K
+// entry as its marginal error). A product is Kh Xh + Kh Xl + Kl Xh (the
+// Kl Xl term is below FP32 accumulation), every product accumulating in FP32.
 //
 // MFMA 16x16x32 lane layout (lane l of the 64-lane wavefront):
 //   A (16 x 32): row l % 16, k = 8 (l / 16) .. 8 (l / 16) + 7
@@ -44,8 +47,10 @@ struct SnapArgs {
     int B;           // live snapshots (<= kSnapB)
     int splits;      // K-splits of the column GEMM
     int64_t rows_per_split;  // multiple of 32
-    const unsigned short* K;   // Ip x Jp BF16, zero padded
-    const unsigned short* Kt;  // Jp x Ip BF16, zero padded
+    const unsigned short* K;   // Ip x Jp BF16 high part, zero padded
+    const unsigned short* Kt;  // Jp x Ip BF16 high part, zero padded
+    const unsigned short* Kl;  // Ip x Jp BF16 low part
+    const unsigned short* Ktl; // Jp x Ip BF16 low part
     const double* A;           // kSnapB x I marginals a_s (rows >= B unused)
     const double* b;           // J
     float* U;                  // kSnapB x Ip
@@ -61,13 +66,20 @@ struct SnapArgs {
     double tol;
 };
 
-// Builds the stabilised kernel in BF16 and its transpose, through a 32 x 32
-// LDS tile: K_ij = exp2((fbar_i + gbar_j - C_ij) log2(e) / eps), zero outside
-// I x J.
+// Splits x (FP32) into BF16 high and low parts.
+__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
+    hi = bf16_bits(x);
+    lo = bf16_bits(x - bf16_value(hi));
+}
+
+// Builds the stabilised kernel as BF16 high / low parts and their
+// transposes, through 32 x 32 LDS tiles: K_ij = exp2((fbar_i + gbar_j - C_ij)
+// log2(e) / eps) rounded to FP32, zero outside I x J.
 __global__ __launch_bounds__(256) void k_snap_build(const float* C, int64_t ldc, int64_t I, int J, int64_t Ip, int Jp,
                                                     const double* fbar, const double* gbar, double kk,
-                                                    unsigned short* K, unsigned short* Kt) {
-    __shared__ unsigned short t[32][33];
+                                                    unsigned short* K, unsigned short* Kt, unsigned short* Kl,
+                                                    unsigned short* Ktl) {
+    __shared__ unsigned short th[32][33], tl[32][33];
     const int64_t i0 = (int64_t)blockIdx.y * 32;
     const int j0 = blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
@@ -76,18 +88,19 @@ __global__ __launch_bounds__(256) void k_snap_build(const float* C, int64_t ldc,
         const int j = j0 + tx;
         float v = 0.0f;
         if (i < I && j < J) v = (float)exp2((fbar[i] + gbar[j] - (double)C[i * ldc + j]) * kk);
-        const unsigned short h = bf16_bits(v);
+        unsigned short h, l;
+        split_bf16(v, h, l);
         K[i * Jp + j] = h;
-        t[r][tx] = h;
+        Kl[i * Jp + j] = l;
+        th[r][tx] = h;
+        tl[r][tx] = l;
     }
     __syncthreads();
-    for (int r = ty; r < 32; r += 8) Kt[(int64_t)(j0 + r) * Ip + i0 + tx] = t[tx][r];
-}
-
-// Splits x (FP32) into BF16 high and low parts.
-__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
-    hi = bf16_bits(x);
-    lo = bf16_bits(x - bf16_value(hi));
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t o = (int64_t)(j0 + r) * Ip + i0 + tx;
+        Kt[o] = th[tx][r];
+        Ktl[o] = tl[tx][r];
+    }
 }
 
 // Sets the scaling vectors of a cold start: v = 1 on live (s, j), 0 elsewhere.
@@ -126,20 +139,22 @@ __device__ __forceinline__ bool snap_stop(const SnapArgs& S) {
 }
 
 // One wave's share of a 16 x kSnapB output tile: K-steps k0 = kbeg, kbeg +
-// kstride, ... < kend of A (16 rows, row stride lda) times the hi and lo
-// parts of B^T (kSnapB rows, row stride ldb). The next step's fragments are
-// loaded before the current step's products are issued.
-__device__ __forceinline__ void snap_tile(const unsigned short* arow, int64_t lda, const unsigned short* bh,
-                                          const unsigned short* bl, int64_t ldb, int64_t kbeg, int64_t kend,
-                                          int64_t kstride, int lane, f32x4 (&acc)[kSnapNT]) {
+// kstride, ... < kend of A = Ah + Al (16 rows each, the lane's row at ahrow /
+// alrow) times the hi and lo parts of B^T (kSnapB rows, row stride ldb). The
+// next step's fragments are loaded before the current step's products are
+// issued.
+__device__ __forceinline__ void snap_tile(const unsigned short* ahrow, const unsigned short* alrow,
+                                          const unsigned short* bh, const unsigned short* bl, int64_t ldb,
+                                          int64_t kbeg, int64_t kend, int64_t kstride, int lane,
+                                          f32x4 (&acc)[kSnapNT]) {
     const int m = lane & 15, kq = (lane >> 4) * 8;
-    (void)lda;
 #pragma unroll
     for (int t = 0; t < kSnapNT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (kbeg >= kend) return;
-    bf16x8 a, h[kSnapNT], l[kSnapNT];
+    bf16x8 a, al, h[kSnapNT], l[kSnapNT];
     auto fetch = [&](int64_t k0) {
-        a = load8(arow + k0 + kq);
+        a = load8(ahrow + k0 + kq);
+        al = load8(alrow + k0 + kq);
 #pragma unroll
         for (int t = 0; t < kSnapNT; ++t) {
             const int64_t o = (int64_t)(t * 16 + m) * ldb + k0 + kq;
@@ -149,7 +164,7 @@ __device__ __forceinline__ void snap_tile(const unsigned short* arow, int64_t ld
     };
     fetch(kbeg);
     for (int64_t k0 = kbeg; k0 < kend; k0 += kstride) {
-        const bf16x8 ca = a;
+        const bf16x8 ca = a, cal = al;
         bf16x8 ch[kSnapNT], cl[kSnapNT];
 #pragma unroll
         for (int t = 0; t < kSnapNT; ++t) {
@@ -161,6 +176,7 @@ __device__ __forceinline__ void snap_tile(const unsigned short* arow, int64_t ld
         for (int t = 0; t < kSnapNT; ++t) {
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, ch[t], acc[t], 0, 0, 0);
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, cl[t], acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cal, ch[t], acc[t], 0, 0, 0);
         }
     }
 }
@@ -193,7 +209,7 @@ __global__ __launch_bounds__(256) void k_snap_rows(SnapArgs S) {
     const int64_t i0 = (int64_t)blockIdx.x * 16;
     const int m = lane & 15;
     f32x4 acc[kSnapNT];
-    snap_tile(S.K + (i0 + m) * S.Jp, S.Jp, S.Vh, S.Vl, S.Jp, (int64_t)w * 32, S.Jp, 128, lane, acc);
+    snap_tile(S.K + (i0 + m) * S.Jp, S.Kl + (i0 + m) * S.Jp, S.Vh, S.Vl, S.Jp, (int64_t)w * 32, S.Jp, 128, lane, acc);
     snap_reduce4(acc, w, lane);
     if (w != 0) return;
     // D: column = snapshot t * 16 + m, rows i0 + 4 (lane / 16) + q
@@ -227,7 +243,8 @@ __global__ __launch_bounds__(256) void k_snap_cols(SnapArgs S) {
     const int64_t r0 = (int64_t)split * S.rows_per_split;
     const int64_t r1 = min(S.Ip, r0 + S.rows_per_split);
     f32x4 acc[kSnapNT];
-    snap_tile(S.Kt + (int64_t)(jt * 16 + m) * S.Ip, S.Ip, S.Uh, S.Ul, S.Ip, r0 + (int64_t)w * 32, r1, 128, lane, acc);
+    snap_tile(S.Kt + (int64_t)(jt * 16 + m) * S.Ip, S.Ktl + (int64_t)(jt * 16 + m) * S.Ip, S.Uh, S.Ul, S.Ip,
+              r0 + (int64_t)w * 32, r1, 128, lane, acc);
     snap_reduce4(acc, w, lane);
     if (w != 0) return;
     const int jb = jt * 16 + (lane >> 4) * 4;

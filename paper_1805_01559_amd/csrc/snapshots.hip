@@ -4,7 +4,8 @@
 //  1. the cost as an FP32 device matrix (materialised for rates / geometry);
 //  2. a reference solve of the mean snapshot through the single-instance path,
 //     whose potentials (fbar, gbar) stabilise the kernel;
-//  3. K = exp((fbar + gbar - C) / eps) in BF16, and its transpose;
+//  3. K = exp((fbar + gbar - C) / eps) as BF16 high / low parts, and their
+//     transposes;
 //  4. the scaling iteration of all snapshots at once on the matrix cores,
 //     CHUNK iterations per captured graph, stopping on the device when every
 //     snapshot's column residual (of the BF16 problem) meets tol;
@@ -120,6 +121,8 @@ ot_status snap_reserve(ot_assoc* h, SnapState* s, int64_t I, int J) {
     auto add = [&](void** p, size_t b) { parts.push_back({p, b}); };
     add((void**)&S.K, 2 * (size_t)Ip * Jp);
     add((void**)&S.Kt, 2 * (size_t)Jp * Ip);
+    add((void**)&S.Kl, 2 * (size_t)Ip * Jp);
+    add((void**)&S.Ktl, 2 * (size_t)Jp * Ip);
     add((void**)&S.A, 8 * (size_t)kSnapB * I);
     add((void**)&S.b, 8 * (size_t)J);
     add((void**)&S.U, 4 * (size_t)kSnapB * Ip);
@@ -214,7 +217,7 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
     S.tol = tol;
     // snapshot marginals into the device buffer, their mean, masses and a
     // validity flag on the device (one small read-back)
-    const ot_mem mem = cost->kind == OT_COST_GEOMETRY ? OT_MEM_DEVICE : cost->mem;
+    const ot_mem mem = (cost->kind == OT_COST_GEOMETRY || cost->kind == OT_COST_EUCLID) ? OT_MEM_DEVICE : cost->mem;
     const hipMemcpyKind kin = mem == OT_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     SCHK(hipMemcpyAsync((double*)S.A, A, sizeof(double) * (size_t)B * I, kin, h->stream));
     SCHK(hipMemcpyAsync(s->bdev, b, sizeof(double) * J, kin, h->stream));
@@ -237,7 +240,7 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
     if (cost->kind == OT_COST_DENSE && cost->mem == OT_MEM_DEVICE && cost->dtype == OT_F32) {
         C = (const float*)cost->data;
         ldc = cost->ld ? cost->ld : J;
-    } else if (cost->kind == OT_COST_GEOMETRY || cost->kind == OT_COST_RATES) {
+    } else if (cost->kind == OT_COST_GEOMETRY || cost->kind == OT_COST_RATES || cost->kind == OT_COST_EUCLID) {
         ot_status st = ot_assoc_materialize_cost(h, cost, s->Cconv);
         if (st) return st;
         C = s->Cconv;
@@ -276,11 +279,11 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
     ot_status st = ot_assoc_solve(h, &dd, s->abar, s->bdev, eps, 1e-6, std::max(2000, max_iter), 0, &ref);
     if (st < 0) return st;
     if ((st = ot_assoc_potentials(h, s->fbar, s->gbar, OT_MEM_DEVICE))) return st;
-    // 3. stabilised kernel in BF16 and its transpose
+    // 3. stabilised kernel as BF16 high / low parts and their transposes
     const double kk = std::log2(std::exp(1.0)) / eps;
     hipLaunchKernelGGL(k_snap_build, dim3((unsigned)(S.Jp / 32), (unsigned)(S.Ip / 32)), dim3(256), 0, h->stream, C, ldc,
                        I, J, S.Ip, S.Jp, (const double*)s->fbar, (const double*)s->gbar, kk, (unsigned short*)S.K,
-                       (unsigned short*)S.Kt);
+                       (unsigned short*)S.Kt, (unsigned short*)S.Kl, (unsigned short*)S.Ktl);
     // 4. the snapshot iteration
     SCHK(hipMemcpyAsync((double*)S.b, s->bdev, sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
     s->ctl_h[0] = 0;

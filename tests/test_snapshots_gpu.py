@@ -4,8 +4,11 @@ FP64 oracle solving every snapshot on its own.
 
 Bar of the BF16 path: the marginal violation of each snapshot's plan and the
 relative error of its transport cost against the oracle's converged solution
-both within 1e-3 (the BF16 kernel carries a relative rounding of 2^-9 per
-entry; u and v keep about 16 bits through their high / low split). The
+both within 1e-3, the BF16-path target. K, u and v are each split into high
+and low BF16 parts (about 16 significant bits); with a single BF16 K the
+2^-9 relative rounding of an entry would reach the marginals of plans
+concentrated on one RRH per device almost undamped (about 1.1e-3 was seen on
+a distance cost). The
 library's own exact check must agree with the oracle's recomputation from the
 same potentials.
 """
