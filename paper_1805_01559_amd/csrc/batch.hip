@@ -1140,6 +1140,9 @@ struct Pending {
     double t_submit;
 };
 
+// Requests admitted together per admission call of the serving loop.
+constexpr size_t kServeAdmitGroup = 64;
+
 struct ot_serve {
     BatchEngine eng;
     std::string err;
@@ -1263,63 +1266,78 @@ ot_status ot_serve_progress(ot_serve* s, ot_completion* out, int max_out, int* n
     if (n_out) *n_out = 0;
     BatchEngine& e = s->eng;
     if (hipSetDevice(e.device) != hipSuccess) return serve_fail(s, OT_EDEVICE, "hipSetDevice failed");
-    // 1. admission
+    // 1. admission, in groups from the head of the queue: one staging copy
+    // and one set of admission launches per group. A group whose admission
+    // fails is retried one request at a time, so that the error completes
+    // the request it belongs to.
+    size_t gmax = kServeAdmitGroup;
+    auto complete_with = [&](const Pending& p, ot_status st) {
+        ot_completion c{};
+        c.ticket = p.ticket;
+        c.user_tag = p.req.user_tag;
+        c.layout_key = p.req.layout_key;
+        c.t_submit = p.t_submit;
+        c.t_admit = c.t_done = now_s();
+        c.result.status = st;
+        s->done.push_back(c);
+    };
     while (!s->queue.empty()) {
-        Pending& p = s->queue.front();
-        AdmitReq ar;
-        ar.cost = &p.req.cost;
-        ar.a = p.req.a;
-        ar.b = p.req.b;
-        ar.eps = p.req.eps;
-        ar.tol = p.req.tol;
-        ar.max_iter = p.req.max_iter;
-        Resident* res = nullptr;
-        if (p.req.layout_key) {
-            auto it = s->resident.find(p.req.layout_key);
-            if (it != s->resident.end() && it->second.I == p.req.cost.I && it->second.J == p.req.cost.J) {
-                res = &it->second;
-                ar.f0 = res->f;
-                ar.g0 = res->g;
+        std::vector<AdmitReq> group;
+        std::vector<Resident*> gres;
+        for (size_t q = 0; q < s->queue.size() && group.size() < gmax; ++q) {
+            const Pending& p = s->queue[q];
+            AdmitReq ar;
+            ar.cost = &p.req.cost;
+            ar.a = p.req.a;
+            ar.b = p.req.b;
+            ar.eps = p.req.eps;
+            ar.tol = p.req.tol;
+            ar.max_iter = p.req.max_iter;
+            Resident* res = nullptr;
+            if (p.req.layout_key) {
+                auto it = s->resident.find(p.req.layout_key);
+                if (it != s->resident.end() && it->second.I == p.req.cost.I && it->second.J == p.req.cost.J) {
+                    res = &it->second;
+                    ar.f0 = res->f;
+                    ar.g0 = res->g;
+                }
             }
+            group.push_back(ar);
+            gres.push_back(res);
         }
         std::vector<int> ks;
-        ot_status st = e.admit({ar}, ks, false);
+        ot_status st = e.admit(group, ks, false);
         if (st) {
+            if (group.size() > 1) {
+                gmax = 1;
+                continue;
+            }
             // a request the engine rejects is completed with its error
-            ot_completion c{};
-            c.ticket = p.ticket;
-            c.user_tag = p.req.user_tag;
-            c.layout_key = p.req.layout_key;
-            c.t_submit = p.t_submit;
-            c.t_admit = c.t_done = now_s();
-            c.result.status = st;
-            s->done.push_back(c);
+            complete_with(s->queue.front(), st);
             s->queue.pop_front();
+            gmax = kServeAdmitGroup;
             continue;
         }
+        gmax = kServeAdmitGroup;
         if (ks.empty()) {
-            if (evict_one(s, p.req.layout_key)) continue;  // retry with more room
-            if (e.n_live_running > 0) break;                // wait for running requests to finish
-            ot_completion c{};  // it cannot fit even on an idle engine
-            c.ticket = p.ticket;
-            c.user_tag = p.req.user_tag;
-            c.layout_key = p.req.layout_key;
-            c.t_submit = p.t_submit;
-            c.t_admit = c.t_done = now_s();
-            c.result.status = OT_ENOMEM;
-            s->done.push_back(c);
+            if (evict_one(s, s->queue.front().req.layout_key)) continue;  // retry with more room
+            if (e.n_live_running > 0) break;                               // wait for running requests to finish
+            complete_with(s->queue.front(), OT_ENOMEM);  // it cannot fit even on an idle engine
             s->queue.pop_front();
             continue;
         }
-        Slot& sl = e.slots[ks[0]];
-        sl.ticket = p.ticket;
-        sl.user_tag = p.req.user_tag;
-        sl.layout_key = p.req.layout_key;
-        sl.t_submit = p.t_submit;
-        s->warm_of[ks[0]] = res ? 1 : 0;
-        if (res) res->last_use = ++s->tick;
-        s->running.push_back(ks[0]);
-        s->queue.pop_front();
+        for (size_t q = 0; q < ks.size(); ++q) {
+            const Pending& p = s->queue.front();
+            Slot& sl = e.slots[ks[q]];
+            sl.ticket = p.ticket;
+            sl.user_tag = p.req.user_tag;
+            sl.layout_key = p.req.layout_key;
+            sl.t_submit = p.t_submit;
+            s->warm_of[ks[q]] = gres[q] ? 1 : 0;
+            if (gres[q]) gres[q]->last_use = ++s->tick;
+            s->running.push_back(ks[q]);
+            s->queue.pop_front();
+        }
     }
     // 2. one chunk, and the snapshot behind the previous one
     std::vector<int> fin;

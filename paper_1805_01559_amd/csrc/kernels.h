@@ -878,7 +878,11 @@ __global__ __launch_bounds__(256) void k_geo_prepass(GeoSrc src, int64_t I, int 
     }
 }
 
-// Materialised FP32 cost: the FP64 functor rounded once to FP32.
+// Materialised FP32 cost: the FP64 functor rounded once to FP32. A lane
+// evaluates kMatCols columns of its row at once (columns past J on a clamped
+// index, their value discarded) so that the long dependent chains of the FP64
+// functors overlap within the lane.
+constexpr int kMatCols = 4;
 template <class Src>
 __global__ void k_materialize(int64_t I, int J, int64_t ld, float* C, Src src) {
     extern __shared__ double sm[];
@@ -887,7 +891,16 @@ __global__ void k_materialize(int64_t I, int J, int64_t ld, float* C, Src src) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int64_t i = (int64_t)blockIdx.x * nw + w; i < I; i += (int64_t)gridDim.x * nw) {
         auto row = src.row(i);
-        for (int j = lane; j < ld; j += 64) C[i * ld + j] = j < J ? (float)src.at64(row, i, j, sm) : __builtin_huge_valf();
+        for (int j0 = lane; j0 < ld; j0 += 64 * kMatCols) {
+            double v[kMatCols];
+#pragma unroll
+            for (int u = 0; u < kMatCols; ++u) v[u] = src.at64(row, i, min(j0 + 64 * u, J - 1), sm);
+#pragma unroll
+            for (int u = 0; u < kMatCols; ++u) {
+                const int j = j0 + 64 * u;
+                if (j < ld) C[i * ld + j] = j < J ? (float)v[u] : __builtin_huge_valf();
+            }
+        }
     }
 }
 
