@@ -240,7 +240,7 @@ struct BatchEngine {
     ot_status prepare_kernels();
     ot_status capture(int widx);
     ot_status admit(const std::vector<AdmitReq>& reqs, std::vector<int>& out_slots, bool strict);
-    ot_status upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage, PadJob* pad);
+    ot_status upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage, PadJob* pad, GeoJob* geo);
     ot_status launch_chunk();
     ot_status collect(bool wait, std::vector<int>& finished);
     ot_status drain_snapshot(std::vector<int>* finished);
@@ -412,12 +412,14 @@ static bool from_positions(const ot_cost_desc* c) {
     return c->kind == OT_COST_GEOMETRY || c->kind == OT_COST_EUCLID;
 }
 
-ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage, PadJob* pad) {
+ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, char* stage, PadJob* pad,
+                                   GeoJob* geo) {
     const int64_t I = s.I;
     const int J = s.J;
     const int64_t ld = s.ld;
     float* dst = (float*)C_mem;
     pad->src = nullptr;
+    geo->dst = nullptr;
     if (from_positions(c)) {
         double scale = c->scale;
         if (!(scale > 0.0)) {
@@ -436,39 +438,33 @@ ot_status BatchEngine::upload_cost(Slot& s, const ot_cost_desc* c, char* C_mem, 
             ot_status st = ot_assoc_cost_median(helper, c, &scale);
             if (st) return fail(st, "cost median: %s", ot_assoc_last_error(helper));
         }
-        const size_t lds = sizeof(double) * (size_t)J + 8;
-        const int mg = (int)std::min<int64_t>(4096, (I + 7) / 8);
-        if (c->kind == OT_COST_EUCLID) {  // distances: the padded FP32 matrix directly
-            EuclidSrc e{};
-            e.dev_xy = (const float*)c->geom.dev_xy;
-            e.rrh_xy = (const float*)c->geom.rrh_xy;
-            e.inv_scale = 1.0 / scale;
-            hipLaunchKernelGGL(k_materialize<EuclidSrc>, dim3(mg), dim3(512), lds, stream, I, J, ld, dst, e);
-            ECHK(this, hipGetLastError());
+        // a job of the admission's two set-up launches: per-device
+        // interference sums (geometry, into the staging block), then the
+        // padded FP32 matrix; non-finite positions surface as a numeric
+        // failure of the solve
+        *geo = GeoJob{};
+        geo->dst = dst;
+        geo->I = I;
+        geo->ld = ld;
+        geo->J = J;
+        if (c->kind == OT_COST_EUCLID) {
+            geo->kind = 1;
+            geo->dist.dev_xy = (const float*)c->geom.dev_xy;
+            geo->dist.rrh_xy = (const float*)c->geom.rrh_xy;
+            geo->dist.inv_scale = 1.0 / scale;
             return OT_OK;
         }
-        // per-device interference sums (the staging block), then the padded
-        // FP32 matrix, both queued on the engine stream without a host wait;
-        // non-finite positions surface as a numeric failure of the solve
-        GeoSrc g{};
+        geo->kind = 0;
+        GeoSrc& g = geo->geo;
         g.dev_xy = (const float*)c->geom.dev_xy;
         g.rrh_xy = (const float*)c->geom.rrh_xy;
-        double* s_all = (double*)stage;
-        double* s_ex = s_all + I;
-        int* j1 = (int*)(s_ex + I);
-        g.s_all = s_all;
-        g.s_ex = s_ex;
-        g.j1 = j1;
+        geo->s_all = (double*)stage;
+        geo->s_ex = geo->s_all + I;
+        geo->j1 = (int*)(geo->s_ex + I);
+        g.s_all = geo->s_all;
+        g.s_ex = geo->s_ex;
+        g.j1 = geo->j1;
         g.k = geo_const(c->geom, scale);
-        const dim3 pg((unsigned)((I + 3) / 4)), pb(256);
-        switch ((J + 63) / 64) {
-            case 1: hipLaunchKernelGGL(k_geo_prepass<1>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
-            case 2: hipLaunchKernelGGL(k_geo_prepass<2>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
-            case 3: case 4: hipLaunchKernelGGL(k_geo_prepass<4>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
-            default: hipLaunchKernelGGL(k_geo_prepass<8>, pg, pb, 0, stream, g, I, J, s_all, s_ex, j1); break;
-        }
-        hipLaunchKernelGGL(k_materialize<GeoSrc>, dim3(mg), dim3(512), lds, stream, I, J, ld, dst, g);
-        ECHK(this, hipGetLastError());
         return OT_OK;
     }
     // dense or rate matrices: a padded-copy job, run for the whole admission
@@ -538,19 +534,21 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
     }
     const int set = adm_set;
     if (ot_status st = wait_staging(set)) return st;
-    // staging block: [AdmJob x n][PadJob x n][host marginals]
+    // staging block: [AdmJob x n][PadJob x n][GeoJob x n][host marginals]
     const size_t n = reqs.size();
     const size_t jobs_b = align_up(sizeof(AdmJob) * n), pads_b = align_up(sizeof(PadJob) * n);
+    const size_t geos_b = align_up(sizeof(GeoJob) * n);
     size_t marg_b = 0;
     for (auto& r : reqs)
         if (!from_positions(r.cost) && r.cost->mem == OT_MEM_HOST)
             marg_b += align_up(sizeof(double) * r.cost->I) + align_up(sizeof(double) * r.cost->J);
-    if (ot_status st = ensure_blob(set, jobs_b + pads_b + marg_b)) return st;
+    if (ot_status st = ensure_blob(set, jobs_b + pads_b + geos_b + marg_b)) return st;
     AdmJob* jobs_h = (AdmJob*)blob_h[set];
     PadJob* pads_h = (PadJob*)(blob_h[set] + jobs_b);
-    char* marg_h = blob_h[set] + jobs_b + pads_b;
-    char* marg_d = blob_d[set] + jobs_b + pads_b;
-    int n_items = 0, n_insts = 0, n_pads = 0;
+    GeoJob* geos_h = (GeoJob*)(blob_h[set] + jobs_b + pads_b);
+    char* marg_h = blob_h[set] + jobs_b + pads_b + geos_b;
+    char* marg_d = blob_d[set] + jobs_b + pads_b + geos_b;
+    int n_items = 0, n_insts = 0, n_pads = 0, n_geos = 0;
     std::vector<char*> stages;
     auto undo = [&]() {
         for (char* x : stages) pool.release(x);
@@ -642,12 +640,14 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         out_slots.push_back(k);
         if (!ref) {
             PadJob pj{};
-            ot_status st = upload_cost(sl, c, C_mem, stage, &pj);
+            GeoJob gj{};
+            ot_status st = upload_cost(sl, c, C_mem, stage, &pj, &gj);
             if (st) {
                 undo();
                 return st;
             }
             if (pj.src) pads_h[n_pads++] = pj;
+            if (gj.dst) geos_h[n_geos++] = gj;
         }
         AdmJob& J1 = jobs_h[n_insts];
         J1 = AdmJob{};
@@ -690,12 +690,28 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         sl.t_admit = now_s();
         sl.adm_seq = seq;
     }
+    // block ranges of the set-up launches
+    int pre_blocks = 0, mat_blocks = 0;
+    for (int q = 0; q < n_geos; ++q) {
+        GeoJob& g = geos_h[q];
+        g.pre_blk0 = pre_blocks;
+        g.pre_nblk = g.kind == 0 ? (int)((g.I + kGeoJobRowsPre - 1) / kGeoJobRowsPre) : 0;
+        g.mat_blk0 = mat_blocks;
+        g.mat_nblk = (int)((g.I + kGeoJobRowsMat - 1) / kGeoJobRowsMat);
+        pre_blocks += g.pre_nblk;
+        mat_blocks += g.mat_nblk;
+    }
     if (n_insts) {
         const size_t used = (size_t)(marg_h - blob_h[set]);
         ECHK(this, hipMemcpyAsync(blob_d[set], blob_h[set], used, hipMemcpyHostToDevice, stream));
         if (n_pads)
             hipLaunchKernelGGL(k_bpad_jobs, dim3(64, n_pads), dim3(256), 0, stream,
                                (const PadJob*)(blob_d[set] + jobs_b));
+        const GeoJob* geos_d = (const GeoJob*)(blob_d[set] + jobs_b + pads_b);
+        if (pre_blocks)
+            hipLaunchKernelGGL(k_bgeo_prepass_jobs, dim3(pre_blocks), dim3(256), 0, stream, geos_d, n_geos);
+        if (mat_blocks)
+            hipLaunchKernelGGL(k_bmat_jobs, dim3(mat_blocks), dim3(512), 0, stream, geos_d, n_geos);
         hipLaunchKernelGGL(k_badmit_jobs, dim3(n_insts), dim3(256), 0, stream, (const AdmJob*)blob_d[set], tab, ctl,
                            L[0]);
         hipLaunchKernelGGL(k_bcount, dim3(1), dim3(64), 0, stream, L[0], n_items, n_insts);
@@ -1143,6 +1159,25 @@ struct Pending {
 // Requests admitted together per admission call of the serving loop.
 constexpr size_t kServeAdmitGroup = 64;
 
+// Device-to-device copies of FP64 vectors passed by value: one launch for a
+// whole set of resident-potential updates, one workgroup per copy.
+constexpr int kCopyPairs = 32;
+struct CopyPairs {
+    const double* src[kCopyPairs];
+    double* dst[kCopyPairs];
+    int64_t cnt[kCopyPairs];
+};
+static __global__ __launch_bounds__(256) void k_copy_pairs(CopyPairs P) {
+    const double* s = P.src[blockIdx.x];
+    double* d = P.dst[blockIdx.x];
+    for (int64_t e = threadIdx.x; e < P.cnt[blockIdx.x]; e += blockDim.x) d[e] = s[e];
+}
+struct PendingCopy {
+    const double* src;
+    double* dst;
+    int64_t cnt;
+};
+
 struct ot_serve {
     BatchEngine eng;
     std::string err;
@@ -1155,7 +1190,26 @@ struct ot_serve {
     std::vector<int> running;  // slots in flight
     std::unordered_map<int, int> warm_of;  // slot -> 1 if warm started
     std::unordered_map<int, uint64_t> pinned_key;
+    std::vector<PendingCopy> copies;  // resident updates not yet queued
 };
+
+// Queues the pending resident updates on the engine stream.
+static ot_status flush_copies(ot_serve* s) {
+    BatchEngine& e = s->eng;
+    for (size_t q0 = 0; q0 < s->copies.size(); q0 += kCopyPairs) {
+        CopyPairs P{};
+        const int n = (int)std::min<size_t>(kCopyPairs, s->copies.size() - q0);
+        for (int q = 0; q < n; ++q) {
+            P.src[q] = s->copies[q0 + q].src;
+            P.dst[q] = s->copies[q0 + q].dst;
+            P.cnt[q] = s->copies[q0 + q].cnt;
+        }
+        hipLaunchKernelGGL(k_copy_pairs, dim3(n), dim3(256), 0, e.stream, P);
+    }
+    s->copies.clear();
+    ECHK(&e, hipGetLastError());
+    return OT_OK;
+}
 
 static ot_status serve_fail(ot_serve* s, ot_status st, const std::string& m) {
     s->err = m;
@@ -1169,6 +1223,7 @@ static ot_status keep_resident(ot_serve* s, const Slot& sl) {
     // (an admission copies from a resident set on the same stream before any
     // later update or reuse of its memory, so no set is ever pinned)
     if (r.mem && (r.I != sl.I || r.J != sl.J)) {
+        if (ot_status st = flush_copies(s)) return st;  // nothing pending may target freed memory
         e.pool.release(r.mem);
         r = Resident{};
     }
@@ -1184,8 +1239,12 @@ static ot_status keep_resident(ot_serve* s, const Slot& sl) {
         r.J = sl.J;
     }
     const int par = sl.fin.result_iter & 1;
-    ECHK(&e, hipMemcpyAsync(r.f, sl.d.f[par], sizeof(double) * sl.I, hipMemcpyDeviceToDevice, e.stream));
-    ECHK(&e, hipMemcpyAsync(r.g, sl.d.g[par], sizeof(double) * sl.J, hipMemcpyDeviceToDevice, e.stream));
+    // the latest completion of a layout wins (pending copies run together)
+    s->copies.erase(std::remove_if(s->copies.begin(), s->copies.end(),
+                                   [&](const PendingCopy& c) { return c.dst == r.f || c.dst == r.g; }),
+                    s->copies.end());
+    s->copies.push_back(PendingCopy{sl.d.f[par], r.f, sl.I});
+    s->copies.push_back(PendingCopy{sl.d.g[par], r.g, sl.J});
     r.last_use = ++s->tick;
     return OT_OK;
 }
@@ -1198,6 +1257,7 @@ static bool evict_one(ot_serve* s, uint64_t keep_key) {
         if (victim == s->resident.end() || it->second.last_use < victim->second.last_use) victim = it;
     }
     if (victim == s->resident.end()) return false;
+    if (flush_copies(s)) return false;  // nothing pending may target freed memory
     s->eng.pool.release(victim->second.mem);
     s->resident.erase(victim);
     return true;
@@ -1348,7 +1408,9 @@ ot_status ot_serve_progress(ot_serve* s, ot_completion* out, int max_out, int* n
         if (ot_status st = e.drain_snapshot(&fin)) return serve_fail(s, st, e.err);
         e.snap_pending = -1;
     }
-    // 3. completions: keep the layout's potentials, free the slot
+    // 3. completions: keep the layouts' potentials, then free the slots (once
+    // the resident copies that read them are queued, so that no slot memory
+    // is handed out again while a pending copy still reads it)
     const double t = now_s();
     for (int k : fin) {
         Slot& sl = e.slots[k];
@@ -1367,9 +1429,10 @@ ot_status ot_serve_progress(ot_serve* s, ot_completion* out, int max_out, int* n
         }
         s->warm_of.erase(k);
         s->running.erase(std::remove(s->running.begin(), s->running.end(), k), s->running.end());
-        e.release(k);
         s->done.push_back(c);
     }
+    if (ot_status st = flush_copies(s)) return serve_fail(s, st, e.err);
+    for (int k : fin) e.release(k);
     int n = 0;
     while (n < max_out && !s->done.empty()) {
         out[n++] = s->done.front();

@@ -442,4 +442,64 @@ __global__ void k_bpad_jobs(const PadJob* __restrict__ jobs) {
     }
 }
 
+// Costs regenerated from positions, set up for a whole admission group in
+// two launches. Job k covers the flat block range [blk0, blk0 + nblk) of each
+// launch (prepass: 4 rows per block, geometry only; materialisation: 8 rows
+// per block); a block finds its job by a binary search of the job starts
+// (the last job whose range starts at or before the block).
+struct GeoJob {
+    GeoSrc geo;        // geometry (kind 0): positions, set-up sums, constants
+    EuclidSrc dist;    // distances (kind 1)
+    double* s_all;     // geometry set-up outputs (the arrays geo reads)
+    double* s_ex;
+    int* j1;
+    float* dst;        // I x ld padded FP32 cost
+    int64_t I, ld;
+    int J;
+    int kind;
+    int pre_blk0, pre_nblk;  // prepass blocks (0 for distances)
+    int mat_blk0, mat_nblk;  // materialisation blocks
+};
+
+constexpr int kGeoJobRowsPre = 4;  // 256 threads, a wavefront per row
+constexpr int kGeoJobRowsMat = 8;  // 512 threads, a wavefront per row
+
+__device__ __forceinline__ int find_job(const GeoJob* jobs, int n, int b, bool pre) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((pre ? jobs[mid].pre_blk0 : jobs[mid].mat_blk0) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_bgeo_prepass_jobs(const GeoJob* __restrict__ jobs, int n) {
+    __shared__ float2 xy[kBatchMaxJ];
+    const int k = find_job(jobs, n, blockIdx.x, true);
+    const GeoJob& G = jobs[k];
+    const int rb = (int)blockIdx.x - G.pre_blk0;
+    if (G.kind != 0 || rb < 0 || rb >= G.pre_nblk) return;
+    for (int c = threadIdx.x; c < G.J; c += blockDim.x) xy[c] = reinterpret_cast<const float2*>(G.geo.rrh_xy)[c];
+    __syncthreads();
+    const int64_t i = (int64_t)rb * kGeoJobRowsPre + threadIdx.x / 64;
+    if (i >= G.I) return;
+    geo_prepass_row<kBatchMaxJ / 64>(G.geo, i, G.J, xy, threadIdx.x & 63, G.s_all, G.s_ex, G.j1);
+}
+
+__global__ __launch_bounds__(512) void k_bmat_jobs(const GeoJob* __restrict__ jobs, int n) {
+    __shared__ double sm[kBatchMaxJ + 1];
+    const int k = find_job(jobs, n, blockIdx.x, false);
+    const GeoJob& G = jobs[k];
+    const int rb = (int)blockIdx.x - G.mat_blk0;
+    if (rb < 0 || rb >= G.mat_nblk) return;
+    if (G.kind == 0) G.geo.stage(sm, G.J);
+    else G.dist.stage(sm, G.J);
+    __syncthreads();
+    const int64_t i = (int64_t)rb * kGeoJobRowsMat + threadIdx.x / 64;
+    if (i >= G.I) return;
+    if (G.kind == 0) materialize_row(G.geo, i, G.J, G.ld, G.dst, sm, threadIdx.x & 63);
+    else materialize_row(G.dist, i, G.J, G.ld, G.dst, sm, threadIdx.x & 63);
+}
+
 }  // namespace otk

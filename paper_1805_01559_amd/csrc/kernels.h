@@ -830,13 +830,8 @@ static __global__ void k_ctl_resume(Ctl* ctl) {
 // s_all = sum_j pg_ij + n0n and s_ex = sum_{j != j1} pg_ij + n0n (FP64,
 // per-lane index order, then a fixed butterfly).
 template <int NCH>
-__global__ __launch_bounds__(256) void k_geo_prepass(GeoSrc src, int64_t I, int J, double* s_all, double* s_ex, int* j1) {
-    __shared__ float2 xy[2048];
-    for (int c = threadIdx.x; c < J; c += blockDim.x) xy[c] = reinterpret_cast<const float2*>(src.rrh_xy)[c];
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    if (i >= I) return;
+__device__ __forceinline__ void geo_prepass_row(const GeoSrc& src, int64_t i, int J, const float2* xy, int lane,
+                                                double* s_all, double* s_ex, int* j1) {
     const float2 p = reinterpret_cast<const float2*>(src.dev_xy)[i];
     double pg[NCH];
     double bv = -1.0;
@@ -878,30 +873,46 @@ __global__ __launch_bounds__(256) void k_geo_prepass(GeoSrc src, int64_t I, int 
     }
 }
 
+template <int NCH>
+__global__ __launch_bounds__(256) void k_geo_prepass(GeoSrc src, int64_t I, int J, double* s_all, double* s_ex, int* j1) {
+    __shared__ float2 xy[2048];
+    for (int c = threadIdx.x; c < J; c += blockDim.x) xy[c] = reinterpret_cast<const float2*>(src.rrh_xy)[c];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (i >= I) return;
+    geo_prepass_row<NCH>(src, i, J, xy, lane, s_all, s_ex, j1);
+}
+
 // Materialised FP32 cost: the FP64 functor rounded once to FP32. A lane
 // evaluates kMatCols columns of its row at once (columns past J on a clamped
 // index, their value discarded) so that the long dependent chains of the FP64
 // functors overlap within the lane.
 constexpr int kMatCols = 4;
 template <class Src>
+__device__ __forceinline__ void materialize_row(const Src& src, int64_t i, int J, int64_t ld, float* C,
+                                                const double* sm, int lane) {
+    auto row = src.row(i);
+    for (int j0 = lane; j0 < ld; j0 += 64 * kMatCols) {
+        double v[kMatCols];
+#pragma unroll
+        for (int u = 0; u < kMatCols; ++u) v[u] = src.at64(row, i, min(j0 + 64 * u, J - 1), sm);
+#pragma unroll
+        for (int u = 0; u < kMatCols; ++u) {
+            const int j = j0 + 64 * u;
+            if (j < ld) C[i * ld + j] = j < J ? (float)v[u] : __builtin_huge_valf();
+        }
+    }
+}
+
+template <class Src>
 __global__ void k_materialize(int64_t I, int J, int64_t ld, float* C, Src src) {
     extern __shared__ double sm[];
     src.stage(sm, J);
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int64_t i = (int64_t)blockIdx.x * nw + w; i < I; i += (int64_t)gridDim.x * nw) {
-        auto row = src.row(i);
-        for (int j0 = lane; j0 < ld; j0 += 64 * kMatCols) {
-            double v[kMatCols];
-#pragma unroll
-            for (int u = 0; u < kMatCols; ++u) v[u] = src.at64(row, i, min(j0 + 64 * u, J - 1), sm);
-#pragma unroll
-            for (int u = 0; u < kMatCols; ++u) {
-                const int j = j0 + 64 * u;
-                if (j < ld) C[i * ld + j] = j < J ? (float)v[u] : __builtin_huge_valf();
-            }
-        }
-    }
+    for (int64_t i = (int64_t)blockIdx.x * nw + w; i < I; i += (int64_t)gridDim.x * nw)
+        materialize_row(src, i, J, ld, C, sm, lane);
 }
 
 // Radix-select histogram over the FP32 bit patterns of 1/R (positive, so the
