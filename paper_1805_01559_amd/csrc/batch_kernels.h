@@ -152,13 +152,19 @@ __global__ __launch_bounds__(WAVES * kWave) void k_bsweep(const BInst* __restric
 
 // Per instance of the list: the column combine of the sweep (new g) or of the
 // check, then the phase machine, then the instance's items of the next
-// iteration. One workgroup of 1024 threads = 16 part-lanes x 64 columns.
+// iteration. One workgroup of 1024 threads: thread t takes column
+// (t / 64 mod NC2) 64 + t mod 64 of the NC2 = 2^ceil(log2(J / 64)) column
+// chunks and part group t / (64 NC2) of the PG = 1024 / (64 NC2) groups; a
+// group sums its parts (every PG-th) sixteen loads at a time in a fixed
+// tree, and the groups' sums are added in group order, so each column's sum
+// has one fixed order for given J and part count.
+constexpr int kCombLoads = 16;
 __global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, BList out, BParams P) {
-    __shared__ double red[16][65];
+    __shared__ double red[1024];
     __shared__ double wsum[16][7];
     __shared__ int s_bad, s_list, s_base, s_flags;
     const int n = in.cnt[2];
-    const int tid = threadIdx.x, c = tid & 63, r = tid >> 6, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int q = blockIdx.x; q < n; q += gridDim.x) {
         const int k = in.inst[q];
         const BInst& d = tab[k];
@@ -169,40 +175,41 @@ __global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, B
         const int J = d.J, parts = d.parts;
         const int pin = check ? (ctl->check_iter & 1) : (ctl->iter & 1);
         if (tid == 0) s_bad = 0;
+        int nc2 = 1;
+        while (nc2 * 64 < J) nc2 <<= 1;  // J <= 512: at most 8 chunks
+        const int pg = 1024 / (64 * nc2);
+        const int grp = tid / (64 * nc2);
+        const int j = ((tid >> 6) & (nc2 - 1)) * 64 + lane;
+        double s = 0.0;
+        if (j < J) {
+            const double* cp = d.col_part + j;
+            int p = grp;
+            for (; p + (kCombLoads - 1) * pg < parts; p += kCombLoads * pg) {
+                double x[kCombLoads];
+#pragma unroll
+                for (int u = 0; u < kCombLoads; ++u) x[u] = cp[(int64_t)(p + u * pg) * J];
+#pragma unroll
+                for (int h = kCombLoads / 2; h > 0; h >>= 1)
+#pragma unroll
+                    for (int u = 0; u < h; ++u) x[u] += x[u + h];
+                s += x[0];
+            }
+            for (; p < parts; p += pg) s += cp[(int64_t)p * J];
+        }
+        red[grp * (64 * nc2) + j] = s;  // (j < 64 nc2: every thread has its own slot)
         __syncthreads();
-        // columns, 64 at a time: fixed-order sums over the parts
         double cres = 0.0, gb = 0.0;
-        for (int j0 = 0; j0 < J; j0 += 64) {
-            const int j = j0 + c;
-            double s = 0.0;
-            if (j < J) {
-                // eight independent loads in flight, summed in a fixed order
-                const double* cp = d.col_part + j;
-                int p = r;
-                for (; p + 7 * 16 < parts; p += 8 * 16) {
-                    double x[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) x[u] = cp[(int64_t)(p + u * 16) * J];
-                    s += ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
-                }
-                for (; p < parts; p += 16) s += cp[(int64_t)p * J];
+        if (tid < J) {
+            double cs = 0.0;
+            for (int u = 0; u < pg; ++u) cs += red[u * (64 * nc2) + tid];
+            if (check) {
+                cres = fabs(cs - d.b[tid]);
+                gb = d.g[pin][tid] * d.b[tid];
+            } else {
+                const double gn = d.g[pin][tid] + d.eps * (log(d.b[tid]) - log(cs));
+                if (!isfinite(gn)) s_bad = 1;
+                d.g[pin ^ 1][tid] = gn;
             }
-            red[r][c] = s;
-            __syncthreads();
-            if (tid < 64 && j < J) {
-                double cs = 0.0;
-#pragma unroll
-                for (int u = 0; u < 16; ++u) cs += red[u][c];
-                if (check) {
-                    cres += fabs(cs - d.b[j]);
-                    gb += d.g[pin][j] * d.b[j];
-                } else {
-                    const double gn = d.g[pin][j] + d.eps * (log(d.b[j]) - log(cs));
-                    if (!isfinite(gn)) s_bad = 1;
-                    d.g[pin ^ 1][j] = gn;
-                }
-            }
-            __syncthreads();
         }
         // per-part scalars: the row residual, or the check's five statistics
         double v[7] = {0, 0, 0, 0, 0, 0, 0};
