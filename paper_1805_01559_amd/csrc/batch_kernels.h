@@ -19,7 +19,7 @@
 // batch or on which workgroup ran which item.
 #pragma once
 
-#include "kernels.h"
+#include "setup_kernels.h"
 
 namespace otk {
 

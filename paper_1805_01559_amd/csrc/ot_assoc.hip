@@ -29,6 +29,7 @@
 #include "kernels.h"
 #include "persist_kernels.h"
 #include "assoc_kernels.h"
+#include "setup_kernels.h"
 
 using namespace otk;
 
