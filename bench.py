@@ -92,6 +92,11 @@ def cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale_gpu, snap_As=None):
     _, res = solver.solve_geometry(xy, rxy, L.radio, L.shadow_key, scale, a, b, eps, tol, 2000)
     f, g = solver.potentials()
     acc["on_the_fly"] = errors(C64, f, g, res)
+    # the distance cost with the oracle's own median scale
+    Cd, dscale = O.distance_cost(L, 0.0)
+    _, res = solver.solve_euclid(xy, rxy, dscale, a, b, eps, tol, 2000)
+    f, g = solver.potentials()
+    acc["on_the_fly_distance"] = errors(Cd, f, g, res)
     if snap_As is not None:
         # BF16 snapshot path: two snapshots against the oracle's own solves
         # (the snapshot leg ran before the re-solves above, its state is kept)
@@ -433,6 +438,21 @@ def main():
     ms_sweep_geo = solver.time_sweep(max(10, args.sweep_reps // 4), fp64=False)
     log(f"on-the-fly: {t_geo * 1e3:.3f} ms/solve, iters={res_g.iterations}, sweep {ms_sweep_geo * 1e3:.2f} us")
 
+    # the distance cost of the same layout (Sec. IV cost choice (i)),
+    # regenerated from the positions, normalised by its median
+    dscale = solver.cost_median(A.euclid_desc(xy, rxy, 1.0)[0])
+
+    def step_dist():
+        st, res = solver.solve_euclid(xy, rxy, dscale, a, b, eps, tol, 2000)
+        solver.plan(plan)
+        return res
+
+    t_dist, res_e = timed(step_dist, max(2, args.steps // 2), 1)
+    ms_coop_e, it_coop_e = solver.fast_phase_time()
+    ms_sweep_dist = solver.time_sweep(max(10, args.sweep_reps // 4), fp64=False)
+    log(f"on-the-fly distance: {t_dist * 1e3:.3f} ms/solve, iters={res_e.iterations}, "
+        f"cooperative launch {ms_coop_e * 1e3:.1f} us for {it_coop_e} iterations, sweep {ms_sweep_dist * 1e3:.2f} us")
+
     # copy ceiling of this GPU: a plain device-to-device copy of 256 MiB
     # (read + write), also the calibration kernel of the traffic counters
     src_buf = torch.empty(64 << 20, dtype=torch.float32, device=dev).uniform_()
@@ -550,6 +570,14 @@ def main():
                        "iterations": res_g.iterations, "fp64_iterations": res_g.fp64_iterations,
                        "sweep_us": ms_sweep_geo * 1e3, "cells_per_s_sweep": cells / (ms_sweep_geo * 1e-3),
                        "marginal_violation": res_g.marginal_violation},
+        "on_the_fly_distance": {
+            "workload": "the same layout with C_ij = ||x_i - X_j|| / median, regenerated from the positions",
+            "ms_per_solve": t_dist * 1e3, "cells_per_s": cells * res_e.iterations / t_dist,
+            "iterations": res_e.iterations, "fp64_iterations": res_e.fp64_iterations,
+            "cooperative": bool(res_e.flags & A.OT_RESULT_PERSISTENT),
+            "cooperative_launch_us": ms_coop_e * 1e3, "cooperative_iterations": it_coop_e,
+            "sweep_us": ms_sweep_dist * 1e3, "cells_per_s_sweep": cells / (ms_sweep_dist * 1e-3),
+            "marginal_violation": res_e.marginal_violation},
     }
     snap_As = None
     if args.only in ("all", "snapshots"):

@@ -185,3 +185,43 @@ def test_euclid_rejects_bad_inputs(A, lay):
         # a valid solve on the same handle afterwards
         st, res = s.solve_euclid(L.dev_xy, L.rrh_xy, lay["scale"], L.a, L.b, 0.05, 1e-8, 3000)
         assert st == A.OT_OK
+
+
+def test_euclid_adaptive_and_evaluation(A, oracle_lib):
+    """Alg. 2 and the Sec. II-B evaluation under the distance cost (the
+    paper's policy with Euclidean costs), against the oracle on the same
+    FP64 distances."""
+    announce("Alg. 2 and evaluation under the distance cost, 1500 x 12")
+    import torch
+    dev = torch.device("cuda:0")
+    L = S.make_layout(1500, 12, 1500.0, hot_spots=1, hot_share=0.5, seed=8400)
+    C, scale = oracle_lib.distance_cost(L, 0.0)
+    eps, tol, cap = 0.05, 1e-9, 30
+    want = oracle_lib.adaptive_sinkhorn(C, L.a, eps, tol, 20000, max_outer=cap)
+    xy = torch.from_numpy(L.dev_xy).to(dev)
+    rxy = torch.from_numpy(L.rrh_xy).to(dev)
+    with A.Solver(L.I, L.J) as s:
+        st, q, js, r = s.adaptive(*A.euclid_desc(xy, rxy, scale), torch.from_numpy(L.a).to(dev), eps, tol, 20000,
+                                  0.0, cap)
+        assert st == A.OT_OK
+        loads = s.rrh_loads()
+        f, g = s.potentials()
+        kappa, tau = 0.7 / loads.max(), 2.0
+        rho, en, ev = s.evaluate(kappa, tau)
+    # the handle holds the returned solve; its loads and evaluation against
+    # the oracle's computation from the same potentials
+    np.testing.assert_allclose(loads, oracle_lib.rrh_loads(C, f, g, eps), rtol=1e-12)
+    ref = oracle_lib.evaluate(C, f, g, eps, L.a, kappa, tau)
+    np.testing.assert_allclose(rho, ref["rho"], rtol=1e-12)
+    np.testing.assert_allclose(en, ref["EN"], rtol=1e-11)
+    assert abs(ev.mean_completion - ref["T_mean"]) <= 1e-11 * ref["T_mean"]
+    assert r.max_load <= r.first_max_load
+    chk = oracle_lib.plan_stats(C, L.a, q, f, g, eps)
+    assert chk["marginal_violation"] < tol * 1.05
+    # the same first decision as the oracle unless its two largest loads tie
+    first = oracle_lib.sinkhorn(C, L.a, np.full(L.J, L.a.sum() / L.J), eps, tol, 20000)
+    ld = np.sort(oracle_lib.rrh_loads(C, first.f, first.g, eps))
+    if ld[-1] - ld[-2] > 1e-6 * ld[-1]:
+        assert js[0] == want["history"][0][0]
+    if r.solves == want["solves"]:
+        assert abs(r.max_load - want["max_load"]) <= 1e-6 * want["max_load"]
