@@ -20,15 +20,19 @@ constexpr double kLn2 = 0.69314718055994530942;
 // the same value, in the same order on every call, so results are bitwise
 // reproducible. DPP control codes: quad_perm(1,0,3,2) = 0xB1,
 // quad_perm(2,3,0,1) = 0x4E, row_mirror = 0x140, row_half_mirror = 0x141.
+// Each of these reads a lane of the same 16-lane row, and every row and bank
+// is enabled, so no lane keeps its old value: the moves need no old operand.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+    static_assert(CTRL == 0xB1 || CTRL == 0x4E || CTRL == 0x140 || CTRL == 0x141, "in-row DPP moves only");
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
+    static_assert(CTRL == 0xB1 || CTRL == 0x4E || CTRL == 0x140 || CTRL == 0x141, "in-row DPP moves only");
     const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ double readlane_d(double x, int l) {

@@ -145,18 +145,22 @@ struct PersistArgs {
     const SolveParams* prm;
 };
 
-// Dynamic LDS of k_persist in bytes (the layout the kernel carves).
-__host__ __device__ inline size_t persist_lds_bytes(int rpw, int J, int Jp, int waves) {
+// Dynamic LDS of k_persist in bytes (the layout the kernel carves): the
+// tile, a slack of (CPL - ncl) LPR floats after it, then the row and column
+// vectors.
+__host__ __device__ inline size_t persist_lds_bytes(int rpw, int J, int Jp, int waves, int slack) {
     const size_t Jr2 = (size_t)((J + 1) & ~1), Jr4 = (size_t)((J + 3) & ~3);
-    return (size_t)rpw * Jp * 4 + Jr2 * 8 + 4 * (size_t)rpw * 8 + (size_t)waves * Jr4 * 4;
+    return ((size_t)rpw * Jp + (size_t)slack) * 4 + Jr2 * 8 + 4 * (size_t)rpw * 8 + (size_t)waves * Jr4 * 4;
 }
 
 // Lane layout: a row is handled by LPR lanes (32 or 64); lane `sub` owns
 // columns q LPR + sub, q < CPL, so consecutive lanes read consecutive LDS
-// words. Every cell is processed without a branch (branches around LDS reads
-// would serialise their latencies): cells q >= ncl re-read the row's last
-// chunk and get g = -inf, i.e. a zero term. A wave advances R = 64 / LPR
-// rows per step.
+// words, each at a constant offset from the row (one address per row step).
+// Every cell is processed without a branch (branches around LDS reads would
+// serialise their latencies): cells q >= ncl read on into the next row of
+// the tile, or into a +inf slack after it, and get g = -inf: a zero term
+// (finite or +inf costs only, never a NaN). A wave advances R = 64 / LPR rows
+// per step.
 template <class Src, int CPL, int LPR, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src src) {
     extern __shared__ double sm[];
@@ -169,8 +173,9 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     const int64_t r0 = (int64_t)blk * rpw;
     const int nrows = (int)max((int64_t)0, min((int64_t)rpw, A.I - r0));
     const int Jr2 = (J + 1) & ~1, Jr4 = (J + 3) & ~3;
+    const int slack = (CPL - ncl) * LPR;  // (a multiple of 32 floats: graw stays 8-byte aligned)
     float* tile = reinterpret_cast<float*>(sm);
-    double* graw = reinterpret_cast<double*>(tile + (size_t)rpw * Jp);
+    double* graw = reinterpret_cast<double*>(tile + (size_t)rpw * Jp + slack);
     double* fl = graw + Jr2;   // f_i of the current iterate
     double* al = fl + rpw;     // a_i
     double* lal = al + rpw;    // ln a_i
@@ -215,6 +220,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             for (int j = lane; j < Jp; j += kWave) trow[j] = __builtin_huge_valf();
         }
     }
+    for (int e = threadIdx.x; e < slack; e += T) tile[(size_t)rpw * Jp + e] = __builtin_huge_valf();
     // 2. the rows' a_i, ln a_i and current f_i; the current g
     const double* f_in = A.f[k0 & 1];
     for (int lr = threadIdx.x; lr < rpw; lr += T) {
@@ -276,7 +282,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             const float* trow = tile + (size_t)lr * Jp + sub;
             float cv[CPL];
 #pragma unroll
-            for (int q = 0; q < CPL; ++q) cv[q] = trow[min(q, ncl - 1) * LPR];
+            for (int q = 0; q < CPL; ++q) cv[q] = trow[q * LPR];
             // shift: the row's previous log-sum-exp (any value near the row
             // maximum keeps the FP32 exponentials in range), or the maximum
             double m = lse[lr];
