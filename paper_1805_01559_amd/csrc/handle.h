@@ -46,6 +46,7 @@ struct ot_assoc {
     int64_t I_max = 0, J_max = 0;
     // device workspace
     double *a = nullptr, *b = nullptr;
+    double* la = nullptr;  // ln a_i of the current instance (written by the solve's set-up)
     double *f[2] = {nullptr, nullptr}, *g[2] = {nullptr, nullptr};
     double *col_part = nullptr, *res_part = nullptr, *stat_part = nullptr;
     double* cpart = nullptr;  // per-column-group partials of the check

@@ -87,6 +87,7 @@ struct IterArgs {
     int nch;  // column chunks of 64 * VEC actually used (<= NCH)
     int64_t rows_per_block;
     const double* a;
+    const double* la;    // ln a_i (or null)
     const double* f_in;  // f^(k-1) (read only when ctl->has_prev)
     double* f_out;       // f^k
     const double* g_in;  // g^(k-1)
@@ -152,6 +153,7 @@ struct SweepJob {
     const Ctl* prev_ctl;        // else has_prev is read from here
     const SolveParams* prm;     // kk, eps (read after the first loads are issued)
     const double* a;
+    const double* la;           // ln a_i, or null: the FP32 sweeps then shift every row by its maximum
     const double* f_in;
     double* f_out;
     const double* g_in;
@@ -164,7 +166,7 @@ struct SweepJob {
 // loads are issued before the control block is read and the workgroup does
 // nothing more if the chunk has been stopped. LDS is reused from the previous
 // call of a persistent workgroup only after a barrier.
-template <class Src, bool P64, int VEC, int NCH, int LPR, int WAVES, int RB>
+template <class Src, bool P64, int VEC, int NCH, int LPR, int WAVES, int RB, bool LSE>
 __device__ __forceinline__ void sweep_rows(const SweepJob& A, const Src& src, const Ctl* stop_ctl) {
     // (the dynamic LDS is named here rather than passed in: a pointer
     // parameter loses its address space and turns LDS accesses into flat ones)
@@ -183,15 +185,30 @@ __device__ __forceinline__ void sweep_rows(const SweepJob& A, const Src& src, co
     //    as fully masked, i.e. C = +inf, and get a_i = 0)
     using Raw = typename Src::template Raw<VEC>;
     Raw raw[RB][NCH];
-    double aq[RB];
+    double aq[RB], lq[RB], fq[RB];
+    // With LSE (FP32 sweeps) and ln a known, a row is shifted by its
+    // log-sum-exp of the previous sweep, recovered from f: log2 sum_j
+    // 2^(g_j kk - C_ij kk) = log2(e) ln a_i - kk f_i. That replaces the pass
+    // over the row for its maximum, which runs only without a previous
+    // iterate or when a row sum leaves [2^-100, 2^100] (the wave's rows are
+    // then redone). (It pays where the sweep is bound by instruction issue;
+    // sources that compute their costs and the batch kernel, whose registers
+    // are already at their occupancy limit, keep the maximum.)
+    static_assert(!(LSE && P64), "the log-sum-exp shift is for FP32 sweeps");
+    const bool lse_ok = LSE && A.la != nullptr;
     auto issue = [&](int q, int64_t i) {
         const bool ok = i < r1;
-        auto row = src.row(ok ? i : r0);
+        const int64_t ii = ok ? i : r0;
+        auto row = src.row(ii);
         const int Jl = ok ? J : 0;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
             if (ch < nch) raw[q][ch] = src.template load<VEC>(row, (ch * LPR + sub) * VEC, Jl);
         aq[q] = ok ? A.a[i] : 0.0;
+        if (lse_ok) {
+            lq[q] = A.la[ii];
+            fq[q] = A.f_in[ii];
+        }
     };
 #pragma unroll
     for (int q = 0; q < RB; ++q) issue(q, step_base(q) + rg);
@@ -254,40 +271,78 @@ __device__ __forceinline__ void sweep_rows(const SweepJob& A, const Src& src, co
                 if constexpr (Src::kCheap) return src.template cost<P64, VEC>(row, raw[q][ch], v, i, col, sm);
                 else return (col < Jl) ? src.template cost<P64, VEC>(row, raw[q][ch], v, i, col, sm) : pinf64();
             };
-            // pass 1: row maximum, an FP32 estimate (it only sets the shift)
-            E ck[Src::kCheap ? 1 : NCH][Src::kCheap ? 1 : VEC];
-            float mx = -__builtin_huge_valf();
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-                if (ch < nch)
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) {
-                        const double c = cost_at(ch, v);
-                        if constexpr (!Src::kCheap) ck[ch][v] = (E)c;  // exact: the functor's own precision
-                        mx = fmaxf(mx, fmaf((float)c, -kk32, gs32[(ch * LPR + sub) * VEC + v]));
-                    }
-            // (an all-masked row has max -inf: shift by 0 so its terms are 0)
-            const double m = fmax((double)group_max<LPR>(mx), -1e300);
-            // pass 2: exponentials (arguments in FP64) and the row sum
             E ev[NCH][VEC];
-            E s = 0;
+            double m = 0.0, S = 0.0;
+            if constexpr (LSE) {
+                // shift, exponentials and row sum; a second attempt with the
+                // maximum only when the log-sum-exp shift was used and a valid
+                // row sum left its range (costs are re-read: LSE sources are cheap)
+                static_assert(Src::kCheap, "the log-sum-exp shift re-reads its costs");
+                bool by_lse = lse_ok && has_prev;
+                for (;;) {
+                    if (by_lse) {
+                        m = fma(lq[q], kLog2e, -kk * fq[q]);
+                    } else {
+                        float mx = -__builtin_huge_valf();
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-                if (ch < nch)
+                        for (int ch = 0; ch < NCH; ++ch)
+                            if (ch < nch)
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) {
-                        const double c = Src::kCheap ? cost_at(ch, v) : (double)ck[ch][v];
-                        const double t = fma(c, -kk, gs64[(ch * LPR + sub) * VEC + v]) - m;
-                        E e;
-                        if constexpr (P64) e = exp2(t);
-                        else e = exp2_f32((float)t);
-                        ev[ch][v] = e;
-                        s += e;
+                                for (int v = 0; v < VEC; ++v)
+                                    mx = fmaxf(mx, fmaf((float)cost_at(ch, v), -kk32, gs32[(ch * LPR + sub) * VEC + v]));
+                        m = fmax((double)group_max<LPR>(mx), -1e300);
                     }
+                    E s = 0;
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch)
+                        if (ch < nch)
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) {
+                                const double t = fma(cost_at(ch, v), -kk, gs64[(ch * LPR + sub) * VEC + v]) - m;
+                                const E e = exp2_f32((float)t);
+                                ev[ch][v] = e;
+                                s += e;
+                            }
+                    S = group_sum<LPR>((double)s);
+                    if (!by_lse || !__any(vrow && !(S >= 0x1p-100 && S <= 0x1p100))) break;
+                    by_lse = false;
+                }
+            }
+            E s_row = 0;
+            if constexpr (!LSE) {
+                // pass 1: row maximum, an FP32 estimate (it only sets the shift)
+                E ck[Src::kCheap ? 1 : NCH][Src::kCheap ? 1 : VEC];
+                float mx = -__builtin_huge_valf();
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch)
+                    if (ch < nch)
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) {
+                            const double c = cost_at(ch, v);
+                            if constexpr (!Src::kCheap) ck[ch][v] = (E)c;  // exact: the functor's own precision
+                            mx = fmaxf(mx, fmaf((float)c, -kk32, gs32[(ch * LPR + sub) * VEC + v]));
+                        }
+                // (an all-masked row has max -inf: shift by 0 so its terms are 0)
+                m = fmax((double)group_max<LPR>(mx), -1e300);
+                // pass 2: exponentials (arguments in FP64) and the row sum
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch)
+                    if (ch < nch)
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) {
+                            const double c = Src::kCheap ? cost_at(ch, v) : (double)ck[Src::kCheap ? 0 : ch][Src::kCheap ? 0 : v];
+                            const double t = fma(c, -kk, gs64[(ch * LPR + sub) * VEC + v]) - m;
+                            E e;
+                            if constexpr (P64) e = exp2(t);
+                            else e = exp2_f32((float)t);
+                            ev[ch][v] = e;
+                            s_row += e;
+                        }
+            }
             const double ai = aq[q];
             // slot q is free: load its rows of the next batch
             issue(q, step_base(st0 + q + RB) + rg);
-            const double S = group_sum<LPR>((double)s);
+            if constexpr (!LSE) S = group_sum<LPR>((double)s_row);
             // column partials of the half-iterate plan, pi_ij = e_ij a_i / S_i
             E wq = 0;
             if (vrow) {
@@ -366,13 +421,14 @@ __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu<Src, P64, VEC, NCH, RB>(),
     job.prev_ctl = A.ctl;
     job.prm = A.prm;
     job.a = A.a;
+    job.la = A.la;
     job.f_in = A.f_in;
     job.f_out = A.f_out;
     job.g_in = A.g_in;
     job.col_part = A.col_part;
     job.res_part = A.res_part;
     job.part = blockIdx.x;
-    sweep_rows<Src, P64, VEC, NCH, LPR, WAVES, RB>(job, src, A.ctl);
+    sweep_rows<Src, P64, VEC, NCH, LPR, WAVES, RB, !P64 && Src::kCheap>(job, src, A.ctl);
 }
 
 // -------------------------------------------------------- column combine --

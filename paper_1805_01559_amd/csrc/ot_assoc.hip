@@ -523,7 +523,7 @@ struct Solver {
         const int pin = k_from & 1, pout = pin ^ 1;
         IterArgs A{};
         A.I = I; A.J = J; A.nch = sh.nch; A.rows_per_block = sh.rpb;
-        A.a = h->a; A.f_in = h->f[pin]; A.f_out = h->f[pout]; A.g_in = h->g[pin];
+        A.a = h->a; A.la = h->la; A.f_in = h->f[pin]; A.f_out = h->f[pout]; A.g_in = h->g[pin];
         A.col_part = h->col_part; A.res_part = h->res_part; A.ctl = h->ctl; A.prm = h->prm;
         if (!launch_iter<Src, P64>(sh, A, src, h->stream))
             return fail(h, OT_EINVAL, "no iteration kernel for vec=%d nch=%d waves=%d rb=%d", sh.vec, sh.nchT, sh.waves, sh.rb);
@@ -931,7 +931,7 @@ void ot_assoc_destroy(ot_assoc* h) {
     if (!h) return;
     hipSetDevice(h->device);
     for (auto& e : h->graphs) hipGraphExecDestroy(e.exec);
-    void* bufs[] = {h->a, h->b, h->f[0], h->f[1], h->g[0], h->g[1], h->col_part, h->res_part, h->stat_part,
+    void* bufs[] = {h->a, h->la, h->b, h->f[0], h->f[1], h->g[0], h->g[1], h->col_part, h->res_part, h->stat_part,
                     h->cpart, h->ctl, h->prm, h->bad, h->hist, h->xch,
                     h->xy_dev, h->xy_rrh, h->s_all, h->s_ex, h->j1, h->stage};
     for (void* p : bufs)
@@ -983,6 +983,7 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     hipError_t e = hipSuccess;
     const size_t I8 = sizeof(double) * (size_t)I_max, J8 = sizeof(double) * (size_t)J_max;
     if (e == hipSuccess) e = al((void**)&h->a, I8);
+    if (e == hipSuccess) e = al((void**)&h->la, I8);
     if (e == hipSuccess) e = al((void**)&h->b, J8);
     for (int q = 0; q < 2 && e == hipSuccess; ++q) {
         e = al((void**)&h->f[q], I8);
@@ -1068,6 +1069,7 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
     ia.a_src = a_src;
     ia.b_src = b_src;
     ia.a = h->a;
+    ia.la = h->la;
     ia.b = h->b;
     ia.g0 = h->g[0];
     ia.prm_out = h->prm;
