@@ -196,3 +196,27 @@ def test_cooperative_rejects_bad_inputs(A):
         assert e.value.status == A.OT_EINVAL and "unbalanced" in str(e.value)
         st, res = s.solve_dense(C, a, b, 0.05, 1e-8, 2000)
         assert st == A.OT_OK and res.flags & A.OT_RESULT_PERSISTENT
+
+
+@pytest.mark.parametrize("offset", [20.0, -20.0])
+def test_row_shift_far_from_the_row_sums(A, oracle_lib, offset):
+    """Warm start from potentials f = offset (far from the solution): the row
+    shift recovered from the previous iterate (log2(e) ln a_i - kk f_i) then
+    puts every row sum far outside [2^-100, 2^100], and both the cooperative
+    and the streaming sweeps must redo those rows with the row maximum and
+    converge to the oracle's solution as from a cold start."""
+    announce(f"warm start from f = {offset:+g}: row shifts far off, both paths")
+    C, a, b = random_case(2000, 100, 9191)
+    Cd = C.astype(np.float64)
+    eps, tol = 0.05, 1e-8
+    ref = oracle_lib.sinkhorn(Cd, a, b, eps, 1e-12, 20000)
+
+    def warm(s):
+        s.set_potentials(np.full(2000, offset), np.zeros(100))
+        return s.solve_dense(C, a, b, eps, tol, 3000, warm_start=True)
+
+    out = solve_both(A, 2000, 100, warm)
+    for pers, (st, res, f, g) in out.items():
+        assert st == A.OT_OK, (pers, st)
+        assert bool(res.flags & A.OT_RESULT_PERSISTENT) == bool(pers)
+        check(oracle_lib, Cd, a, b, eps, tol, f, g, res, ref)
