@@ -220,3 +220,22 @@ def test_row_shift_far_from_the_row_sums(A, oracle_lib, offset):
         assert st == A.OT_OK, (pers, st)
         assert bool(res.flags & A.OT_RESULT_PERSISTENT) == bool(pers)
         check(oracle_lib, Cd, a, b, eps, tol, f, g, res, ref)
+
+
+@pytest.mark.parametrize("I,J,seed", [(997, 37, 9301), (1501, 150, 9302), (2003, 300, 9303), (3001, 400, 9304)])
+def test_streaming_geometry_rows_past_the_range(A, oracle_lib, I, J, seed):
+    """Geometry costs on the streaming path with row counts that leave rows
+    of the last wave step past the range: those lanes re-read the job's last
+    row (its positions, interference sums and index alike), so every term
+    stays finite and the solve matches the oracle."""
+    announce(f"geometry {I}x{J} on the streaming path, ragged last step")
+    L = S.make_layout(I, J, 1500.0, hot_spots=2, hot_share=0.4, seed=seed)
+    C64, scale = oracle_lib.cost(L)
+    eps, tol = 0.05, 1e-8
+    ref = oracle_lib.sinkhorn(C64, L.a, L.b, eps, 1e-12, 20000)
+    with A.Solver(I, J, persistent=0) as s:
+        st, res = s.solve_geometry(L.dev_xy, L.rrh_xy, L.radio, L.shadow_key, scale, L.a, L.b, eps, tol, 3000)
+        assert st == A.OT_OK
+        assert not (res.flags & A.OT_RESULT_PERSISTENT)
+        f, g = s.potentials()
+    check(oracle_lib, C64, L.a, L.b, eps, tol, f, g, res, ref)
