@@ -225,3 +225,53 @@ def test_euclid_adaptive_and_evaluation(A, oracle_lib):
         assert js[0] == want["history"][0][0]
     if r.solves == want["solves"]:
         assert abs(r.max_load - want["max_load"]) <= 1e-6 * want["max_load"]
+
+
+def test_euclid_served_requests(A, oracle_lib):
+    """Distance-cost requests through the serving queue (positions and
+    marginals in device memory, the cost materialised at admission): each
+    matches the oracle on the FP32-rounded distances to the FP32-path bar,
+    and a repeat of a layout starts warm."""
+    announce("distance-cost requests through the serving queue")
+    import torch
+    dev = torch.device("cuda:0")
+    eps, tol = 0.05, 1e-8
+    cases, keep = [], []
+    for k, (I, J) in enumerate([(800, 30), (1900, 140), (1200, 333)]):
+        L = S.make_layout(I, J, 1200.0, hot_spots=1, hot_share=0.3, seed=8500 + k)
+        C, scale = oracle_lib.distance_cost(L, 0.0)
+        xy = torch.from_numpy(L.dev_xy).to(dev)
+        rxy = torch.from_numpy(L.rrh_xy).to(dev)
+        ad, bd = torch.from_numpy(L.a).to(dev), torch.from_numpy(L.b).to(dev)
+        keep += [xy, rxy, ad, bd]
+        cases.append((L, C, scale, xy, rxy, ad, bd))
+    with A.Server() as srv:
+        for k, (L, C, scale, xy, rxy, ad, bd) in enumerate(cases):
+            srv.submit(A.euclid_desc(xy, rxy, scale), ad, bd, eps, tol, 3000, layout_key=900 + k, user_tag=k)
+        done = run_until_done(srv, len(cases))
+        for c in done:
+            L, C, scale = cases[c.user_tag][:3]
+            assert c.result.status == A.OT_OK, c.result.status
+            f, g = srv.potentials(900 + c.user_tag, L.I, L.J)
+            Cq = C.astype(np.float32).astype(np.float64)
+            chk = oracle_lib.plan_stats(Cq, L.a, L.b, f, g, eps)
+            ref = oracle_lib.sinkhorn(Cq, L.a, L.b, eps, 1e-12, 20000)
+            rs = oracle_lib.plan_stats(Cq, L.a, L.b, ref.f, ref.g, eps)
+            assert c.result.marginal_violation < tol
+            assert chk["marginal_violation"] < tol * 1.05
+            assert abs(chk["objective"] - rs["objective"]) <= 1e-6 * abs(rs["objective"])
+        # the same layout again: admitted warm from its resident potentials
+        L, C, scale, xy, rxy, ad, bd = cases[1]
+        srv.submit(A.euclid_desc(xy, rxy, scale), ad, bd, eps, tol, 3000, layout_key=901, user_tag=7)
+        (c,) = run_until_done(srv, 1)
+        assert c.result.status == A.OT_OK and c.warm
+    del keep
+
+
+def run_until_done(srv, n, limit=100000):
+    done = []
+    for _ in range(limit):
+        done += srv.progress()
+        if len(done) >= n:
+            return done
+    raise AssertionError("server did not finish")
