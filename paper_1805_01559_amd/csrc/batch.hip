@@ -397,7 +397,7 @@ ot_status BatchEngine::capture(int wi) {
 static size_t slot_bytes(int64_t I, int J, int64_t ld, int parts_cap, bool own_cost) {
     size_t b = 0;
     if (own_cost) b += align_up(sizeof(float) * (size_t)I * ld);
-    b += 2 * align_up(sizeof(double) * I) + align_up(sizeof(double) * J);                  // a, ln a, b
+    b += align_up(sizeof(double) * I) + align_up(sizeof(double) * J);                      // a, b
     b += 2 * align_up(sizeof(double) * I) + 2 * align_up(sizeof(double) * J);              // f, g
     b += align_up(sizeof(double) * (size_t)parts_cap * J) + align_up(sizeof(double) * parts_cap);  // col, res
     b += align_up(sizeof(double) * (size_t)parts_cap * 5) + align_up(sizeof(SolveParams));
@@ -624,7 +624,6 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         d.parts = parts;
         d.rpp = rpp;
         d.a = (double*)carve(sizeof(double) * I);
-        d.la = (double*)carve(sizeof(double) * I);
         d.b = (double*)carve(sizeof(double) * J);
         d.f[0] = (double*)carve(sizeof(double) * I);
         d.f[1] = (double*)carve(sizeof(double) * I);

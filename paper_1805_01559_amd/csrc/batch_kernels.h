@@ -42,7 +42,6 @@ struct BInst {
     int pad_;
     int64_t rpp;  // rows per part
     const double* a;
-    const double* la;   // ln a_i (written at admission)
     const double* b;
     double* f[2];
     double* g[2];
@@ -92,7 +91,7 @@ __device__ __forceinline__ void batch_sweep_item(const BInst& d, const BItem& it
     job.prev_ctl = nullptr;
     job.prm = d.prm;
     job.a = d.a;
-    job.la = d.la;
+    job.la = nullptr;  // (the batch sweeps shift rows by their maximum)
     job.f_in = d.f[pin];
     job.f_out = d.f[pin ^ 1];
     job.g_in = d.g[pin];
@@ -350,7 +349,6 @@ __global__ __launch_bounds__(256) void k_badmit_jobs(const AdmJob* __restrict__ 
     for (int64_t i = threadIdx.x; i < d.I; i += blockDim.x) {
         const double v = J.a_src[i];
         a[i] = v;
-        const_cast<double*>(d.la)[i] = log(v);
         flag |= !(v > 0.0 && isfinite(v));
         sa += v;
         if (J.f0) d.f[0][i] = J.f0[i];
