@@ -763,6 +763,19 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
     return OT_OK;
 }
 
+// ln a_i of the instance, for the row shifts of the streaming FP32 sweeps.
+static __global__ void k_log_a(const double* a, int64_t I, double* la) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += (int64_t)gridDim.x * blockDim.x)
+        la[i] = log(a[i]);
+}
+
+// Moves iterate (f, g) between buffer pairs in one launch.
+static __global__ void k_copy_fg(double* fd, const double* fs, int64_t I, double* gd, const double* gs, int J) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += (int64_t)gridDim.x * blockDim.x)
+        fd[i] = fs[i];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < J; j += gridDim.x * blockDim.x) gd[j] = gs[j];
+}
+
 // The three phases of a solve. `c` enters with the initial control state and
 // leaves with the final one; result_iter names the returned iterate.
 template <class Src>
@@ -798,10 +811,14 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
         // convention that iterate k lives in buffers k & 1
         const int k = c.done ? c.result_iter : c.iter;
         if (((k ^ np) & 1) != 0) {
-            HIPCHK(h, hipMemcpyAsync(h->f[k & 1], h->f[np & 1], sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
-            HIPCHK(h, hipMemcpyAsync(h->g[k & 1], h->g[np & 1], sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
+            hipLaunchKernelGGL(k_copy_fg, dim3((unsigned)std::min<int64_t>(256, (I + 255) / 256)), dim3(256), 0,
+                               h->stream, h->f[k & 1], (const double*)h->f[np & 1], I, h->g[k & 1],
+                               (const double*)h->g[np & 1], J);
+            HIPCHK(h, hipGetLastError());
         }
     } else if (h->opt.precision == OT_PREC_FP32) {
+        hipLaunchKernelGGL(k_log_a, dim3((unsigned)std::min<int64_t>(1024, (I + 255) / 256)), dim3(256), 0, h->stream,
+                           (const double*)h->a, I, h->la);
         if ((st = S.run_phase<Src, false>(src, kModeFast, chunk, stall_below, c))) return st;
         // polish only when the FP32 sweeps stalled short of tol; a residual
         // that met a tol above the FP32 noise threshold goes to the check
@@ -1069,7 +1086,6 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
     ia.a_src = a_src;
     ia.b_src = b_src;
     ia.a = h->a;
-    ia.la = h->la;
     ia.b = h->b;
     ia.g0 = h->g[0];
     ia.prm_out = h->prm;
@@ -1318,6 +1334,9 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
         c.numeric_bad = 0;
         std::memcpy(&h->ctl_h[0], &c, sizeof c);
         hipMemcpyAsync(h->ctl, &h->ctl_h[0], sizeof(Ctl), hipMemcpyHostToDevice, h->stream);
+        // (ln a for the row shifts of the streaming sweeps: a cooperative solve does not compute it)
+        hipLaunchKernelGGL(k_log_a, dim3((unsigned)std::min<int64_t>(1024, (I + 255) / 256)), dim3(256), 0, h->stream,
+                           (const double*)h->a, I, h->la);
         st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
             using S = std::decay_t<decltype(src)>;
             const int vec = vec_for<S>(J, ld_of(h->last), data);

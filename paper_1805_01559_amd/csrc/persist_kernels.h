@@ -539,7 +539,6 @@ struct InitArgs {
     const double* a_src;  // may equal a
     const double* b_src;  // may equal b
     double* a;
-    double* la;  // ln a_i
     double* b;
     double* g0;
     SolveParams* prm_out;
@@ -576,7 +575,6 @@ static __global__ __launch_bounds__(1024) void k_solve_init(InitArgs A) {
             if (i < A.I) {
                 if (!(v[u] > 0.0) || !isfinite(v[u])) bad |= 1;
                 if (A.a != A.a_src) A.a[i] = v[u];
-                A.la[i] = log(v[u]);
                 two_sum_add(sa, ca, v[u]);
             }
         }
