@@ -32,11 +32,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kSnapB = 64;     // snapshots per GEMM (4 column tiles of 16)
 constexpr int kSnapNT = kSnapB / 16;
 
-// Round-to-nearest-even FP32 -> BF16 (bit pattern).
+// Round-to-nearest-even FP32 -> BF16 (bit pattern); infinities pass, NaNs
+// stay NaN (quiet bit set when the payload would round away). Written as a
+// select so that a wave does not branch on it.
 __device__ __forceinline__ unsigned short bf16_bits(float x) {
     const unsigned u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    const unsigned special = (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    const unsigned rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    return (unsigned short)((u & 0x7f800000u) == 0x7f800000u ? special : rne);
 }
 __device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
@@ -123,97 +126,141 @@ __device__ __forceinline__ bf16x8 load8(const unsigned short* p) {
     return *reinterpret_cast<const bf16x8*>(p);
 }
 
-// Stop decision, taken identically by every workgroup of the row pass from
-// the residuals of the last combine (kResParts column quarters per snapshot,
+// Stop decision, taken identically by every wave of the row pass from the
+// residuals of the last combine (kResParts column quarters per snapshot,
 // summed in a fixed order): all live snapshots met tol, or the iteration cap.
+// Lane s takes snapshot s (kSnapB is the wavefront width) and the wave takes
+// the maximum; a NaN residual counts as 0, as in a sequential fmax from 0.
+// Every lane of the wave must be active.
 constexpr int kResParts = 4;
+static_assert(kSnapB == 64, "one snapshot per lane of the stop decision");
 __device__ __forceinline__ double snap_residual(const SnapArgs& S, int s) {
     const double* r = S.res + (int64_t)s * kResParts;
     return ((r[0] + r[1]) + (r[2] + r[3])) / S.mass[s];
 }
-__device__ __forceinline__ bool snap_stop(const SnapArgs& S) {
+__device__ __forceinline__ bool snap_stop(const SnapArgs& S, int lane) {
     if (S.ctl[1]) return true;
-    double r = 0.0;
-    for (int s = 0; s < S.B; ++s) r = fmax(r, snap_residual(S, s));
+    const double r = wave_max(lane < S.B ? fmax(0.0, snap_residual(S, lane)) : 0.0);
     return (r < S.tol) || (S.ctl[0] >= S.ctl[2]);
 }
 
-// One wave's share of a 16 x kSnapB output tile: K-steps k0 = kbeg, kbeg +
-// kstride, ... < kend of A = Ah + Al (16 rows each, the lane's row at ahrow /
-// alrow) times the hi and lo parts of B^T (kSnapB rows, row stride ldb). The
-// next step's fragments are loaded before the current step's products are
-// issued.
-__device__ __forceinline__ void snap_tile(const unsigned short* ahrow, const unsigned short* alrow,
+// One wave's share of RT stacked 16 x kSnapB output tiles: K-steps k0 = kbeg,
+// kbeg + kstride, ... < kend of A = Ah + Al (RT tiles of 16 rows, tile r's
+// lane row at ahrow / alrow + r astride) times the hi and lo parts of B^T
+// (kSnapB rows, row stride ldb). Each B fragment serves all RT tiles. The
+// steps go in groups of G whose fragments are all loaded before the group's
+// first product, so that a wave with at most G steps waits for memory once;
+// a step of a group past kend reads the last step's (in-bounds) fragments
+// and multiplies a zeroed A fragment. kbeg, kend and kstride are multiples
+// of 32.
+template <int RT, int G>
+__device__ __forceinline__ void snap_tile(const unsigned short* ahrow, const unsigned short* alrow, int64_t astride,
                                           const unsigned short* bh, const unsigned short* bl, int64_t ldb,
                                           int64_t kbeg, int64_t kend, int64_t kstride, int lane,
-                                          f32x4 (&acc)[kSnapNT]) {
+                                          f32x4 (&acc)[RT][kSnapNT]) {
     const int m = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
-    for (int t = 0; t < kSnapNT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < kSnapNT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (kbeg >= kend) return;
-    bf16x8 a, al, h[kSnapNT], l[kSnapNT];
-    auto fetch = [&](int64_t k0) {
-        a = load8(ahrow + k0 + kq);
-        al = load8(alrow + k0 + kq);
+    const bf16x8 zero = {};
+    for (int64_t kb = kbeg; kb < kend; kb += G * kstride) {
+        bf16x8 a[G][RT], al[G][RT], h[G][kSnapNT], l[G][kSnapNT];
 #pragma unroll
-        for (int t = 0; t < kSnapNT; ++t) {
-            const int64_t o = (int64_t)(t * 16 + m) * ldb + k0 + kq;
-            h[t] = load8(bh + o);
-            l[t] = load8(bl + o);
+        for (int g = 0; g < G; ++g) {
+            const int64_t k0 = kb + g * kstride;
+            const int64_t kc = k0 < kend ? k0 : kend - 32;
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                a[g][r] = load8(ahrow + r * astride + kc + kq);
+                al[g][r] = load8(alrow + r * astride + kc + kq);
+            }
+#pragma unroll
+            for (int t = 0; t < kSnapNT; ++t) {
+                const int64_t o = (int64_t)(t * 16 + m) * ldb + kc + kq;
+                h[g][t] = load8(bh + o);
+                l[g][t] = load8(bl + o);
+            }
         }
-    };
-    fetch(kbeg);
-    for (int64_t k0 = kbeg; k0 < kend; k0 += kstride) {
-        const bf16x8 ca = a, cal = al;
-        bf16x8 ch[kSnapNT], cl[kSnapNT];
+        // keep the scheduler from sinking the group's loads between its
+        // products (it would, to save registers)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int t = 0; t < kSnapNT; ++t) {
-            ch[t] = h[t];
-            cl[t] = l[t];
-        }
-        if (k0 + kstride < kend) fetch(k0 + kstride);
+        for (int g = 0; g < G; ++g) {
+            const bool live = kb + g * kstride < kend;
 #pragma unroll
-        for (int t = 0; t < kSnapNT; ++t) {
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, ch[t], acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, cl[t], acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cal, ch[t], acc[t], 0, 0, 0);
+            for (int r = 0; r < RT; ++r) {
+                const bf16x8 ca = live ? a[g][r] : zero, cal = live ? al[g][r] : zero;
+#pragma unroll
+                for (int t = 0; t < kSnapNT; ++t) {
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, h[g][t], acc[r][t], 0, 0, 0);
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, l[g][t], acc[r][t], 0, 0, 0);
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cal, h[g][t], acc[r][t], 0, 0, 0);
+                }
+            }
         }
     }
 }
 
-// Sums the four waves' partial tiles through LDS, in wave order; wave 0
-// returns with the total.
-__device__ __forceinline__ void snap_reduce4(f32x4 (&acc)[kSnapNT], int w, int lane) {
-    __shared__ f32x4 red[3][kSnapNT][64];
-    if (w > 0)
+// Sums the four waves' partial tiles through LDS in wave order, for RT
+// tiles; wave w < RT returns with the total of tile w.
+template <int RT>
+__device__ __forceinline__ void snap_reduce4(f32x4 (&acc)[RT][kSnapNT], int w, int lane, f32x4 (&tot)[kSnapNT]) {
+    static_assert(RT <= 4, "one reducing wave per tile");
+    __shared__ f32x4 red[4][RT][kSnapNT][64];
 #pragma unroll
-        for (int t = 0; t < kSnapNT; ++t) red[w - 1][t][lane] = acc[t];
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int t = 0; t < kSnapNT; ++t) red[w][r][t][lane] = acc[r][t];
     __syncthreads();
-    if (w == 0)
+    if (w < RT)
 #pragma unroll
-        for (int t = 0; t < kSnapNT; ++t) acc[t] = ((acc[t] + red[0][t][lane]) + red[1][t][lane]) + red[2][t][lane];
+        for (int t = 0; t < kSnapNT; ++t)
+            tot[t] = ((red[0][w][t][lane] + red[1][w][t][lane]) + red[2][w][t][lane]) + red[3][w][t][lane];
 }
 
-// Row half-step: P = K V for a 16-row tile per workgroup (the four waves take
-// every fourth K-step and are summed in LDS), then u = a / P (0 on padded
-// rows and snapshots), stored as FP32 and as BF16 hi / lo.
+// Row tiles of 16 per wave in the row GEMM, column tiles of 16 per wave in
+// the column GEMM.
+constexpr int kSnapRowRT = 2;
+constexpr int kSnapColRT = 2;
+// K-steps loaded together per wave: 1 measured fastest at 64 snapshots x
+// 20000 x 400 (groups of 2 and 4 lower the occupancy more than they save)
+constexpr int kSnapGroup = 1;
+
+// Row half-step: P = K V for 16 kSnapRowRT rows per workgroup (the four waves
+// take every fourth K-step and are summed in LDS), then u = a / P (0 on
+// padded rows and snapshots), stored as FP32 and as BF16 hi / lo.
 __global__ __launch_bounds__(256) void k_snap_rows(SnapArgs S) {
-    if (snap_stop(S)) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (snap_stop(S, lane)) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && !S.ctl[1]) {
             S.ctl[1] = 1;
             S.ctl[3] = S.ctl[0];
         }
         return;
     }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t i0 = (int64_t)blockIdx.x * 16;
+    const int64_t i0 = (int64_t)blockIdx.x * (16 * kSnapRowRT);
     const int m = lane & 15;
-    f32x4 acc[kSnapNT];
-    snap_tile(S.K + (i0 + m) * S.Jp, S.Kl + (i0 + m) * S.Jp, S.Vh, S.Vl, S.Jp, (int64_t)w * 32, S.Jp, 128, lane, acc);
-    snap_reduce4(acc, w, lane);
-    if (w != 0) return;
-    // D: column = snapshot t * 16 + m, rows i0 + 4 (lane / 16) + q
-    const int64_t ib = i0 + (lane >> 4) * 4;
+    // D: column = snapshot t * 16 + m, rows i0 + 16 w + 4 (lane / 16) + q.
+    // The marginals this wave divides by are loaded first (entry 0 for padded
+    // rows and snapshots, whose u is 0), so that they arrive with the GEMM's
+    // fragments rather than one by one after it.
+    const int64_t ib = i0 + 16 * (w % kSnapRowRT) + (lane >> 4) * 4;
+    double av[kSnapNT][4];
+#pragma unroll
+    for (int t = 0; t < kSnapNT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int s = t * 16 + m;
+            const int64_t i = ib + q;
+            av[t][q] = S.A[(s < S.B && i < S.I) ? (int64_t)s * S.I + i : 0];
+        }
+    f32x4 acc[kSnapRowRT][kSnapNT], tot[kSnapNT];
+    snap_tile<kSnapRowRT, kSnapGroup>(S.K + (i0 + m) * S.Jp, S.Kl + (i0 + m) * S.Jp, 16 * S.Jp, S.Vh, S.Vl, S.Jp,
+                                      (int64_t)w * 32, S.Jp, 128, lane, acc);
+    snap_reduce4<kSnapRowRT>(acc, w, lane, tot);
+    if (w >= kSnapRowRT) return;
 #pragma unroll
     for (int t = 0; t < kSnapNT; ++t) {
         const int s = t * 16 + m;
@@ -221,8 +268,8 @@ __global__ __launch_bounds__(256) void k_snap_rows(SnapArgs S) {
         unsigned short hi[4], lo[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int64_t i = ib + q;
-            u[q] = (s < S.B && i < S.I) ? (float)(S.A[(int64_t)s * S.I + i] / (double)acc[t][q]) : 0.0f;
+            const float x = (float)(av[t][q] / (double)tot[t][q]);
+            u[q] = (s < S.B && ib + q < S.I) ? x : 0.0f;
             split_bf16(u[q], hi[q], lo[q]);
         }
         const int64_t o = (int64_t)s * S.Ip + ib;
@@ -232,27 +279,27 @@ __global__ __launch_bounds__(256) void k_snap_rows(SnapArgs S) {
     }
 }
 
-// Column half-step, split along i: Qpart[split] = K^T[j-tile, rows of split] U
-// for one 16-column tile per workgroup (the four waves take every fourth
-// K-step and are summed in LDS).
+// Column half-step, split along i: Qpart[split] = K^T[j-tiles, rows of
+// split] U for 16 kSnapColRT columns per workgroup (the four waves take
+// every fourth K-step and are summed in LDS).
 __global__ __launch_bounds__(256) void k_snap_cols(SnapArgs S) {
     if (S.ctl[1]) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int jt = blockIdx.x, split = blockIdx.y;
+    const int j0 = blockIdx.x * (16 * kSnapColRT), split = blockIdx.y;
     const int m = lane & 15;
     const int64_t r0 = (int64_t)split * S.rows_per_split;
     const int64_t r1 = min(S.Ip, r0 + S.rows_per_split);
-    f32x4 acc[kSnapNT];
-    snap_tile(S.Kt + (int64_t)(jt * 16 + m) * S.Ip, S.Ktl + (int64_t)(jt * 16 + m) * S.Ip, S.Uh, S.Ul, S.Ip,
-              r0 + (int64_t)w * 32, r1, 128, lane, acc);
-    snap_reduce4(acc, w, lane);
-    if (w != 0) return;
-    const int jb = jt * 16 + (lane >> 4) * 4;
+    f32x4 acc[kSnapColRT][kSnapNT], tot[kSnapNT];
+    snap_tile<kSnapColRT, kSnapGroup>(S.Kt + (int64_t)(j0 + m) * S.Ip, S.Ktl + (int64_t)(j0 + m) * S.Ip, 16 * S.Ip, S.Uh, S.Ul,
+                          S.Ip, r0 + (int64_t)w * 32, r1, 128, lane, acc);
+    snap_reduce4<kSnapColRT>(acc, w, lane, tot);
+    if (w >= kSnapColRT) return;
+    const int jb = j0 + 16 * w + (lane >> 4) * 4;
 #pragma unroll
     for (int t = 0; t < kSnapNT; ++t) {
         const int s = t * 16 + m;
         float* o = S.Qpart + ((int64_t)split * kSnapB + s) * S.Jp + jb;
-        *reinterpret_cast<float4*>(o) = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+        *reinterpret_cast<float4*>(o) = make_float4(tot[t][0], tot[t][1], tot[t][2], tot[t][3]);
     }
 }
 

@@ -171,8 +171,10 @@ ot_status snap_capture(ot_assoc* h, SnapState* s) {
     if (s->graph) hipGraphExecDestroy(s->graph);
     s->graph = nullptr;
     const SnapArgs S = s->S;
-    const unsigned rows_grid = (unsigned)(S.Ip / 16);
-    const dim3 cols_grid((unsigned)(S.Jp / 16), (unsigned)S.splits);
+    // (Ip and Jp are multiples of 32 = 16 x the tiles per wave)
+    static_assert(32 % (16 * kSnapRowRT) == 0 && 32 % (16 * kSnapColRT) == 0, "tiles must divide the padding");
+    const unsigned rows_grid = (unsigned)(S.Ip / (16 * kSnapRowRT));
+    const dim3 cols_grid((unsigned)(S.Jp / (16 * kSnapColRT)), (unsigned)S.splits);
     hipGraph_t g = nullptr;
     SCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     for (int t = 0; t < kSnapChunk; ++t) {
