@@ -12,6 +12,38 @@ constexpr int kWave = 64;
 constexpr double kLog2e = 1.4426950408889634074;  // 1 / ln 2
 constexpr double kLn2 = 0.69314718055994530942;
 
+// 2^t in FP64 by table-driven reduction (P. T. P. Tang, "Table-driven
+// implementation of the exponential function in IEEE floating-point
+// arithmetic", ACM TOMS 15(2), 1989): t = n + j / 64 + r with |r| <= 1/128,
+// 2^(j/64) from a table of 64 entries (tab, filled by exp2_tab_fill), and
+// 2^r - 1 from the Taylor polynomial of degree 6 in x = r ln 2 (|x| < 0.0055,
+// truncation below 3e-20 relative). About 1 ulp; about half the FP64
+// instructions of the library's exp2. For finite t only (results below the
+// smallest subnormal round through ldexp to 0, above the largest double to
+// infinity); callers select away lanes whose t is not finite.
+__device__ __forceinline__ double exp2_tab(double t, const double* tab) {
+    const double k = __builtin_rint(t * 64.0);
+    const double r = fma(k, -1.0 / 64.0, t);  // exact for |t| < 2^46
+    // (the conversion is clamped to keep it defined: beyond |t| = 2^14 the
+    // result is 0 or infinity either way, and a NaN t stays NaN through q)
+    const int ki = (int)fmin(fmax(k, -1048576.0), 1048576.0);
+    const int j = ki & 63, n = ki >> 6;
+    const double x = r * kLn2;
+    double q = fma(x, 1.0 / 720.0, 1.0 / 120.0);
+    q = fma(x, q, 1.0 / 24.0);
+    q = fma(x, q, 1.0 / 6.0);
+    q = fma(x, q, 0.5);
+    q = fma(x, q, 1.0);
+    q *= x;
+    const double T = tab[j];
+    return ldexp(fma(T, q, T), n);
+}
+// Fills tab[j] = 2^(j/64), j < 64, by the first 64 threads of the workgroup;
+// the caller synchronises before use.
+__device__ __forceinline__ void exp2_tab_fill(double* tab) {
+    if (threadIdx.x < 64) tab[threadIdx.x] = exp2((double)threadIdx.x / 64.0);
+}
+
 // ---------------------------------------------------------------- reductions
 // Reductions over the 64 lanes of a wavefront with DPP lane moves: xor-1 and
 // xor-2 quad permutes, the 8-lane half-row mirror and the 16-lane row mirror

@@ -536,6 +536,8 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
     const int ncols = nch * kWave * VEC;
     __syncthreads();  // LDS may still be read by this workgroup's previous job
     src.stage(sm, J);
+    __shared__ double e2tab[64];
+    exp2_tab_fill(e2tab);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     double gsr[NCH][VEC];
 #pragma unroll
@@ -552,26 +554,46 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[ch][v] = 0.0;
     double st[5] = {0, 0, 0, 0, 0};  // rowres, cost, ent, mass, fa (lane 0 of each wave)
-    for (int64_t i = A.r0 + w; i < A.r1; i += WAVES) {
+    // The loads of a row (its costs, f_i and a_i) are issued one row ahead,
+    // so that a wave waits for memory only when a row's arithmetic is shorter
+    // than the load latency.
+    typename Src::template Raw<VEC> nraw[NCH];
+    double nf = 0.0, na = 0.0;
+    auto fetch = [&](int64_t i) {
         auto row = src.row(i);
-        const double fk = A.f[i] * kk;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+            if (ch < nch) nraw[ch] = src.template load<VEC>(row, (ch * kWave + lane) * VEC, J);
+        nf = A.f[i];
+        na = A.a[i];
+    };
+    if (A.r0 + w < A.r1) fetch(A.r0 + w);
+    for (int64_t i = A.r0 + w; i < A.r1; i += WAVES) {
+        typename Src::template Raw<VEC> raw[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) raw[ch] = nraw[ch];
+        const double fi = nf, ai = na;
+        if (i + WAVES < A.r1) fetch(i + WAVES);
+        auto row = src.row(i);
+        const double fk = fi * kk;
         double rs = 0.0, cost = 0.0, ent = 0.0;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             if (ch < nch) {
                 const int col0 = (ch * kWave + lane) * VEC;
-                double c[VEC];
-                src.template get<true, VEC>(row, i, col0, J, sm, c);
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
-                    if (col0 + v < J) {
-                        const double t = fk + fma(c[v], -kk, gsr[ch][v]);  // log2 pi_ij
-                        const double p = exp2(t);
-                        rs += p;
-                        cost = fma(c[v], p, cost);
-                        ent = fma(p, t * kLn2 - 1.0, ent);
-                        acc[ch][v] += p;
-                    }
+                    // a column past J adds exact zeros (p = 0, c = 0), which
+                    // leaves every sum as it was
+                    const bool ok = col0 + v < J;
+                    const double c = ok ? src.template cost<true, VEC>(row, raw[ch], v, i, ok ? col0 + v : J - 1, sm) : 0.0;
+                    const double t = ok ? fk + fma(c, -kk, gsr[ch][v]) : 0.0;  // log2 pi_ij
+                    const double e = exp2_tab(t, e2tab);  // (t = 0 where !ok: no branch)
+                    const double p = ok ? e : 0.0;
+                    rs += p;
+                    cost = fma(c, p, cost);
+                    ent = fma(p, t * kLn2 - 1.0, ent);
+                    acc[ch][v] += p;
                 }
             }
         }
@@ -579,12 +601,11 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
         cost = wave_sum(cost);
         ent = wave_sum(ent);
         if (lane == 0) {
-            const double ai = A.a[i];
             st[0] += fabs(rs - ai);
             st[1] += cost;
             st[2] += ent;
             st[3] += rs;
-            st[4] += A.f[i] * ai;
+            st[4] += fi * ai;
         }
     }
     __syncthreads();
@@ -626,6 +647,8 @@ __device__ __forceinline__ void check_rows_g(const CheckJob& A, const Src& src) 
     const int sub = lane % LPR, rg = lane / LPR;
     __syncthreads();  // LDS may still be read by this workgroup's previous job
     src.stage(sm, J);
+    __shared__ double e2tab[64];
+    exp2_tab_fill(e2tab);
     double gsr[NCH][VEC];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
@@ -656,14 +679,17 @@ __device__ __forceinline__ void check_rows_g(const CheckJob& A, const Src& src) 
                 src.template get<true, VEC>(row, i, col0, vrow ? J : 0, sm, c);
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
-                    if (vrow && col0 + v < J) {
-                        const double t = fk + fma(c[v], -kk, gsr[ch][v]);  // log2 pi_ij
-                        const double p = exp2(t);
-                        rs += p;
-                        cost = fma(c[v], p, cost);
-                        ent = fma(p, t * kLn2 - 1.0, ent);
-                        acc[ch][v] += p;
-                    }
+                    // a row or column outside the job adds exact zeros (p = 0,
+                    // c = 0), which leaves every sum as it was
+                    const bool ok = vrow && col0 + v < J;
+                    const double cv = ok ? c[v] : 0.0;
+                    const double t = ok ? fk + fma(cv, -kk, gsr[ch][v]) : 0.0;  // log2 pi_ij
+                    const double e = exp2_tab(t, e2tab);
+                    const double p = ok ? e : 0.0;
+                    rs += p;
+                    cost = fma(cv, p, cost);
+                    ent = fma(p, t * kLn2 - 1.0, ent);
+                    acc[ch][v] += p;
                 }
             }
         }
