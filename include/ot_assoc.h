@@ -364,7 +364,8 @@ ot_status ot_assoc_batch_plan(ot_assoc *h, int k, void *pi, ot_mem mem, ot_dtype
  * accumulation (well below 1e-3), not tol.
  * A and b live in cost->mem (GEOMETRY, EUCLID: device). Afterwards the handle's
  * single-instance state (ot_assoc_plan / ot_assoc_potentials) is the
- * reference solve. Errors: OT_EINVAL for bad arguments or marginals,
+ * reference solve, converged to a marginal violation below 1e-3 only (it
+ * conditions the kernel; the snapshots are solved to tol). Errors: OT_EINVAL for bad arguments or marginals,
  * OT_ENOMEM, OT_EDEVICE. */
 ot_status ot_assoc_solve_snapshots(ot_assoc *h, const ot_cost_desc *cost, int B, const double *A, const double *b,
                                    double eps, double tol, int32_t max_iter, ot_assoc_result *out);

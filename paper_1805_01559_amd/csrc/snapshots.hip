@@ -277,8 +277,11 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
     dd.data = C;
     dd.ld = ldc == J ? 0 : ldc;
     ot_assoc_result ref{};
-    // (the reference only conditions the kernel: a loose tol suffices)
-    ot_status st = ot_assoc_solve(h, &dd, s->abar, s->bdev, eps, 1e-6, std::max(2000, max_iter), 0, &ref);
+    // (the reference only conditions the kernel, and the snapshots differ
+    // from their mean by far more than its residual: at 20000 x 400 x 64,
+    // tol 1e-3 instead of 1e-6 leaves the snapshot iterations and their
+    // FP64-checked violations as they were and saves a quarter millisecond)
+    ot_status st = ot_assoc_solve(h, &dd, s->abar, s->bdev, eps, 1e-3, std::max(2000, max_iter), 0, &ref);
     if (st < 0) return st;
     if ((st = ot_assoc_potentials(h, s->fbar, s->gbar, OT_MEM_DEVICE))) return st;
     // 3. stabilised kernel as BF16 high / low parts and their transposes

@@ -70,10 +70,10 @@ def test_snapshots_against_oracle(A, oracle_lib, I, J, B):
             f, g = s.snapshot_potentials(q)
             check_snapshot(oracle_lib, Cq, As[q], L.b, eps, f, g, res[q])
         # the handle's single-instance state is the reference solve of the
-        # mean snapshot (solved to 1e-6: it only conditions the kernel)
+        # mean snapshot (solved to 1e-3: it only conditions the kernel)
         f0, g0 = s.potentials()
         st0 = oracle_lib.plan_stats(Cq, As.mean(axis=0), L.b, f0, g0, eps)
-        assert st0["marginal_violation"] < 1e-6
+        assert st0["marginal_violation"] < 1e-3
 
 
 def test_snapshots_64_sampled(A, oracle_lib):
