@@ -786,23 +786,42 @@ struct CheckColArgs {
 };
 
 static __global__ __launch_bounds__(1024) void k_check_cols(CheckColArgs A) {
+    static_assert(kColsPerWg * 64 == 1024, "64 partial sums per column");
     const int c = threadIdx.x % kColsPerWg, r = threadIdx.x / kColsPerWg;
     const int j = blockIdx.x * kColsPerWg + c;
     double s = 0.0;
-    if (j < A.J)
-        for (int q = r; q < A.nb; q += 64) s += A.col_part[(int64_t)q * A.J + j];
+    if (j < A.J) {
+        // (eight loads in flight, added in index order)
+        int q = r;
+        for (; q + 7 * 64 < A.nb; q += 8 * 64) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = A.col_part[(int64_t)(q + u * 64) * A.J + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; q < A.nb; q += 64) s += A.col_part[(int64_t)q * A.J + j];
+    }
     __shared__ double red[64][kColsPerWg + 1];
+    __shared__ double colres[kColsPerWg][2];
     red[r][c] = s;
+    __syncthreads();
+    // one thread per column folds its 64 partials in order, then thread 0
+    // takes the columns in order
+    if (threadIdx.x < kColsPerWg) {
+        const int jj = blockIdx.x * kColsPerWg + threadIdx.x;
+        double cs = 0.0;
+        for (int q = 0; q < 64; ++q) cs += red[q][threadIdx.x];
+        colres[threadIdx.x][0] = jj < A.J ? fabs(cs - A.b[jj]) : 0.0;
+        colres[threadIdx.x][1] = jj < A.J ? A.g[jj] * A.b[jj] : 0.0;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         double cres = 0.0, gb = 0.0;
         for (int cc = 0; cc < kColsPerWg; ++cc) {
-            const int jj = blockIdx.x * kColsPerWg + cc;
-            if (jj >= A.J) break;
-            double cs = 0.0;
-            for (int q = 0; q < 64; ++q) cs += red[q][cc];
-            cres += fabs(cs - A.b[jj]);
-            gb += A.g[jj] * A.b[jj];
+            if (blockIdx.x * kColsPerWg + cc >= A.J) break;
+            cres += colres[cc][0];
+            gb += colres[cc][1];
         }
         A.cpart[blockIdx.x * 2] = cres;
         A.cpart[blockIdx.x * 2 + 1] = gb;
