@@ -251,7 +251,17 @@ constexpr int check_nch() { return VEC == 4 ? 8 : VEC == 2 ? 16 : 32; }  // J <=
 template <class Src, int VEC>
 void launch_check_v(const Shape& s, const CheckArgs& A, const Src& src, hipStream_t st) {
     const size_t lds = check_lds<Src>(s);
-    auto kern = k_check<Src, VEC, check_nch<VEC>(), 8>;
+    // narrow instances (up to a quarter of the column capacity, e.g. J <= 512
+    // at VEC 4) take an instantiation with a quarter of the per-lane column
+    // registers: at 20000 x 400 the wide one holds 241 VGPRs (2 waves / SIMD)
+    constexpr int kWide = check_nch<VEC>(), kNarrow = kWide / 4;
+    if (s.nch <= kNarrow) {
+        auto kern = k_check<Src, VEC, kNarrow, 8>;
+        set_lds(kern, lds);
+        hipLaunchKernelGGL(kern, dim3(s.nb), dim3(512), lds, st, A, src);
+        return;
+    }
+    auto kern = k_check<Src, VEC, kWide, 8>;
     set_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3(s.nb), dim3(512), lds, st, A, src);
 }
