@@ -554,6 +554,7 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[ch][v] = 0.0;
     double st[5] = {0, 0, 0, 0, 0};  // rowres, cost, ent, mass, fa (lane 0 of each wave)
+    double cost = 0.0, ent = 0.0;     // this lane's cells of <C, pi> and sum pi (log pi - 1)
     // The loads of a row (its costs, f_i and a_i) are issued one row ahead,
     // so that a wave waits for memory only when a row's arithmetic is shorter
     // than the load latency.
@@ -576,7 +577,7 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
         if (i + WAVES < A.r1) fetch(i + WAVES);
         auto row = src.row(i);
         const double fk = fi * kk;
-        double rs = 0.0, cost = 0.0, ent = 0.0;
+        double rs = 0.0;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             if (ch < nch) {
@@ -598,14 +599,19 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
             }
         }
         rs = wave_sum(rs);
-        cost = wave_sum(cost);
-        ent = wave_sum(ent);
         if (lane == 0) {
             st[0] += fabs(rs - ai);
-            st[1] += cost;
-            st[2] += ent;
             st[3] += rs;
             st[4] += fi * ai;
+        }
+    }
+    // <C, pi> and the entropy term need no per-row total: each lane sums its
+    // cells over the wave's rows, and the wave folds them once
+    {
+        const double tc = wave_sum(cost), te = wave_sum(ent);
+        if (lane == 0) {
+            st[1] = tc;
+            st[2] = te;
         }
     }
     __syncthreads();
