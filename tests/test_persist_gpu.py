@@ -67,8 +67,11 @@ def solve_both(A, I, J, fn):
     return out
 
 
-@pytest.mark.parametrize("I,J", [(1, 1), (2, 3), (50, 7), (1000, 50), (4097, 130), (6000, 400), (3000, 513), (900, 2048)])
+@pytest.mark.parametrize("I,J", [(1, 1), (2, 3), (50, 7), (1000, 50), (4097, 130), (6000, 400), (1200, 512), (1200, 516),
+                                 (3000, 513), (900, 2048)])
 def test_dense_both_paths(A, oracle_lib, I, J):
+    # (512 and 516 columns sit on either side of the width at which the exact
+    # check changes from its narrow kernel instantiation to its wide one)
     announce(f"dense random {I}x{J}, cooperative and chunked")
     C, a, b = random_case(I, J, 77 * I + J)
     Cd = C.astype(np.float64)
