@@ -73,6 +73,110 @@ def test_rate_closed_forms(oracle_lib):
         np.testing.assert_allclose(R, expect, rtol=1e-12, err_msg=tok[0])
 
 
+# Shadowing pin: layouts in which every link has the same path loss and there
+# is no noise, so the rate is a closed form of the shadowing draws alone
+# (tests/golden/shadow_rates.txt, written from the definitions by
+# make_shadow_golden.py without the oracle). Sec. II-A downlink model.
+RRH_AT_100 = [(100.0, 0.0), (-100.0, 0.0), (0.0, 100.0), (0.0, -100.0)]
+
+
+def _shadow_cases():
+    for ln in open(os.path.join(GOLD, "shadow_rates.txt")):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        t = ln.split()
+        n = int(t[3])
+        per = t[5:5 + 3 * n]
+        rest = list(map(float, t[5 + 3 * n:]))
+        yield dict(name=t[0], key=int(t[1], 16), i=int(t[2]), n=n, sigma=float(t[4]),
+                   h=[int(per[3 * j], 16) for j in range(n)], X=[float(per[3 * j + 1]) for j in range(n)],
+                   R=[float(per[3 * j + 2]) for j in range(n)], R_slip=rest[:n], R_swap=rest[n:])
+
+
+def _shadow_layout(c):
+    radio = dict(S.RADIO, tx_power_w=1.0, ref_gain=10.0 ** -3.8, pathloss_exp=3.5, min_dist_m=10.0,
+                 shadow_sigma_db=c["sigma"], noise_w=0.0, bandwidth_hz=20e6)
+    return S.Layout(dev_xy=np.zeros((c["i"] + 1, 2), dtype=np.float32),
+                    rrh_xy=np.array(RRH_AT_100[:c["n"]], dtype=np.float32), lam=np.ones(c["i"] + 1),
+                    a=np.ones(c["i"] + 1) / (c["i"] + 1), b=np.ones(c["n"]) / c["n"], shadow_key=c["key"],
+                    side_m=1000.0, seed=0, radio=radio)
+
+
+def _shadow_check(shadow_normal, rates_rows):
+    """Returns the first mismatch against the golden, or None."""
+    for c in _shadow_cases():
+        for j in range(c["n"]):
+            x = shadow_normal(c["key"], c["i"], j)
+            if not abs(x - c["X"][j]) <= 1e-13 * max(1.0, abs(c["X"][j])):
+                return f"{c['name']}: X_{j} = {x!r}, golden {c['X'][j]!r}"
+        R = rates_rows(_shadow_layout(c), [c["i"]])[0]
+        if not np.allclose(R, c["R"], rtol=1e-12, atol=0):
+            return f"{c['name']}: R = {R}, golden {c['R']}"
+    return None
+
+
+def test_shadowing_golden(oracle_lib):
+    cases = list(_shadow_cases())
+    assert len(cases) >= 6
+    for c in cases:
+        # the draws come from the pinned SplitMix64 mixer at state key ^ (i 2^32 + j)
+        for j in range(c["n"]):
+            assert oracle_lib.splitmix64(c["key"] ^ ((c["i"] << 32) + j)) == c["h"][j]
+        # the golden separates the reading from the two plausible slips by far more than the tolerance
+        for r, a, b in zip(c["R"], c["R_slip"], c["R_swap"]):
+            assert abs(a - r) > 1e-3 * r and abs(b - r) > 1e-3 * r
+    assert _shadow_check(oracle_lib.shadow_normal, oracle_lib.rates_rows) is None
+
+
+def _mutant_oracle(tmp_path, old, new):
+    """Builds a copy of the oracle with one planted mistake (CPU only) and
+    returns (shadow_normal, rates_rows) bound to it."""
+    import ctypes as ct
+    import subprocess
+
+    from oracle import oracle as O
+
+    src = open(O.SRC_PATH).read()
+    assert src.count(old) == 1, old
+    path = tmp_path / "mut.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                    "-D_DEFAULT_SOURCE", "-o", str(so), str(path), "-lm"], check=True)
+    L = ct.CDLL(str(so))
+    L.ora_shadow_normal.restype = ct.c_double
+    L.ora_shadow_normal.argtypes = [ct.c_uint64, ct.c_int64, ct.c_int64]
+    L.ora_rates_rows.argtypes = [ct.POINTER(ct.c_float), ct.POINTER(ct.c_float), ct.c_int64,
+                                 ct.POINTER(O._Radio), ct.POINTER(ct.c_int64), ct.c_int64, ct.POINTER(ct.c_double)]
+
+    def shadow_normal(key, i, j):
+        return float(L.ora_shadow_normal(ct.c_uint64(key), i, j))
+
+    def rates_rows(layout, rows):
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        dev = np.ascontiguousarray(layout.dev_xy, dtype=np.float32)
+        rrh = np.ascontiguousarray(layout.rrh_xy, dtype=np.float32)
+        out = np.empty((rows.size, layout.J))
+        rad = O.radio_struct(layout)
+        assert L.ora_rates_rows(dev.ctypes.data_as(ct.POINTER(ct.c_float)), rrh.ctypes.data_as(ct.POINTER(ct.c_float)),
+                                layout.J, ct.byref(rad), rows.ctypes.data_as(ct.POINTER(ct.c_int64)), rows.size,
+                                out.ctypes.data_as(ct.POINTER(ct.c_double))) == 0
+        return out
+
+    return shadow_normal, rates_rows
+
+
+@pytest.mark.parametrize("old,new", [
+    ("shadow_sigma_db * X / 10.0", "shadow_sigma_db * X / 20.0"),  # a /20 (amplitude dB) slip
+    ("double u1 = ((double)(h >> 32) + 0.5)", "double u1 = ((double)(h & 0xFFFFFFFFULL) + 0.5)"),  # halves swapped
+    ("double u2 = ((double)(h & 0xFFFFFFFFULL) + 0.5)", "double u2 = ((double)(h >> 32) + 0.5)"),
+    ("cos(2.0 * M_PI * u2)", "sin(2.0 * M_PI * u2)"),
+])
+def test_shadowing_golden_catches_planted_mistakes(tmp_path, old, new):
+    # the same check, run on an oracle with one plausible mistake planted, must fail
+    assert _shadow_check(*_mutant_oracle(tmp_path, old, new)) is not None
+
+
 def test_lower_median(oracle_lib):
     assert oracle_lib.lower_median([3.0, 1.0, 2.0, 4.0]) == 2.0
     assert oracle_lib.lower_median([5.0]) == 5.0
