@@ -16,6 +16,8 @@ What it computes (paper sections in parentheses):
   stopping on the total absolute marginal residual (Sec. III, "Sinkhorn vs LP");
 * ``plan`` / ``plan_stats``: pi = exp((f + g - C)/eps) (the KKT form of
   Sec. III-B), its marginals, <C, pi>, the objective of eq. (5) and the dual;
+  ``geometry_plan_stats``: the marginals and <C, pi> with the rate cost
+  regenerated row by row, for instances whose cost is too large to hold;
 * ``brute_force_ot``: the unregularised OT of eqs. (2)-(4) on tiny square
   instances with uniform marginals, by enumeration of permutations;
 * ``maxsinr_traffic`` and ``lemma1_lower_bound``: the maxSINR rule and the
@@ -83,6 +85,8 @@ def lib():
                                    ct.POINTER(ct.c_int32), dp]
         L.ora_plan.argtypes = [dp, i64, i64, dp, dp, ct.c_double, dp]
         L.ora_plan_stats.argtypes = [dp, i64, i64, dp, dp, dp, dp, ct.c_double, dp, dp, dp]
+        L.ora_geometry_plan_stats.argtypes = [fp, fp, i64, i64, ct.POINTER(_Radio), ct.c_double, dp, dp, dp, dp,
+                                              ct.c_double, dp, dp, dp]
         L.ora_sum.restype = ct.c_double
         L.ora_sum.argtypes = [dp, i64]
         _lib = L
@@ -209,6 +213,24 @@ def plan_stats(C, a, b, f, g, eps) -> dict:
         raise ValueError(f"ora_plan_stats failed: {st}")
     return dict(marginal_violation=out[0], objective=out[1], reg_objective=out[2], dual_objective=out[3],
                 mass=out[4], row_sums=rs, col_sums=cs)
+
+
+def geometry_plan_stats(layout, scale, f, g, eps) -> dict:
+    """Statistics of pi = exp((f + g - C)/eps) for the rate cost
+    C = (1/R) / scale of a layout, regenerated row by row (the cost is never
+    held whole, so this also serves instances too large for ``cost``):
+    marginal violation, transport cost <C, pi>, mass, row and column sums."""
+    dev = np.ascontiguousarray(layout.dev_xy, dtype=np.float32)
+    rrh = np.ascontiguousarray(layout.rrh_xy, dtype=np.float32)
+    a, b, f, g = _c64(layout.a), _c64(layout.b), _c64(f), _c64(g)
+    out, rs, cs = np.empty(3), np.empty(layout.I), np.empty(layout.J)
+    rad = radio_struct(layout)
+    st = lib().ora_geometry_plan_stats(dev.ctypes.data_as(ct.POINTER(ct.c_float)),
+                                       rrh.ctypes.data_as(ct.POINTER(ct.c_float)), layout.I, layout.J, ct.byref(rad),
+                                       float(scale), _d(a), _d(b), _d(f), _d(g), float(eps), _d(out), _d(rs), _d(cs))
+    if st != OK:
+        raise ValueError(f"ora_geometry_plan_stats failed: {st}")
+    return dict(marginal_violation=out[0], objective=out[1], mass=out[2], row_sums=rs, col_sums=cs)
 
 
 def osum(x) -> float:

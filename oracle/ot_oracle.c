@@ -32,6 +32,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_OK 0
 #define ORA_WARN_MAXITER 1
@@ -96,33 +99,43 @@ static double gain(const ora_radio *r, const float *dev_xy, const float *rrh_xy,
     return r->ref_gain * pow(d, -r->pathloss_exp) * pow(10.0, r->shadow_sigma_db * X / 10.0);
 }
 
-/* Rates of the listed rows: R[k*J + j] = W log2(1 + SINR_{j,rows[k]}),
- * SINR_ji = P G_ji / (sum_{l != j} P G_li + N0), the interference sum taken
- * directly over every other RRH. log2(1 + x) is evaluated as log1p(x)/ln 2
- * so that weak links keep their digits. */
+/* Rates of device i to every RRH: R[j] = W log2(1 + SINR_ji),
+ * SINR_ji = P G_ji / (sum_{l != j} P G_li + N0). The interference sum over
+ * every other RRH is taken directly, as two index-ordered compensated sums:
+ * the RRHs before j (ascending) and the RRHs after j (descending), so a row
+ * costs O(J) and no term is ever subtracted. log2(1 + x) is evaluated as
+ * log1p(x)/ln 2 so that weak links keep their digits. pg, pre (J each) are
+ * scratch. */
+static void rate_row(const float *dev_xy, const float *rrh_xy, int64_t J, const ora_radio *r, int64_t i,
+                     double *pg, double *pre, double *R) {
+    for (int64_t j = 0; j < J; ++j) pg[j] = r->tx_power_w * gain(r, dev_xy, rrh_xy, i, j);
+    nsum lo = {0.0, 0.0};
+    for (int64_t j = 0; j < J; ++j) {
+        pre[j] = nsum_get(&lo);
+        nsum_add(&lo, pg[j]);
+    }
+    nsum hi = {0.0, 0.0};
+    for (int64_t j = J - 1; j >= 0; --j) {
+        double sinr = pg[j] / ((pre[j] + nsum_get(&hi)) + r->noise_w);
+        R[j] = r->bandwidth_hz * log1p(sinr) / M_LN2;
+        nsum_add(&hi, pg[j]);
+    }
+}
+
+/* Rates of the listed rows: R[k*J + j] = rate of device rows[k] to RRH j. */
 int ora_rates_rows(const float *dev_xy, const float *rrh_xy, int64_t J, const ora_radio *r,
                    const int64_t *rows, int64_t nrows, double *R) {
     if (!dev_xy || !rrh_xy || !r || !rows || !R || J < 1 || nrows < 0) return ORA_EINVAL;
     int err = 0;
 #pragma omp parallel
     {
-        double *pg = (double *)malloc(sizeof(double) * (size_t)J);
+        double *pg = (double *)malloc(sizeof(double) * (size_t)J * 2);
         if (!pg) {
 #pragma omp atomic write
             err = 1;
         } else {
 #pragma omp for schedule(dynamic, 16)
-            for (int64_t k = 0; k < nrows; ++k) {
-                int64_t i = rows[k];
-                for (int64_t j = 0; j < J; ++j) pg[j] = r->tx_power_w * gain(r, dev_xy, rrh_xy, i, j);
-                for (int64_t j = 0; j < J; ++j) {
-                    nsum interf = {0.0, 0.0};
-                    for (int64_t l = 0; l < J; ++l)
-                        if (l != j) nsum_add(&interf, pg[l]);
-                    double sinr = pg[j] / (nsum_get(&interf) + r->noise_w);
-                    R[k * J + j] = r->bandwidth_hz * log1p(sinr) / M_LN2;
-                }
-            }
+            for (int64_t k = 0; k < nrows; ++k) rate_row(dev_xy, rrh_xy, J, r, rows[k], pg, pg + J, R + k * J);
             free(pg);
         }
     }
@@ -338,4 +351,96 @@ int ora_plan_stats(const double *C, int64_t I, int64_t J, const double *a, const
     if (!col_sums) free(cs);
     free(cost_r); free(ent_r);
     return ORA_OK;
+}
+
+/*
+ * Statistics of the plan pi(f, g) = exp((f_i + g_j - C_ij) / eps) for the
+ * rate cost C_ij = (1 / R_ij) / scale of a geometry (Sec. II-A, Sec. IV cost
+ * choice (ii)), with each row of C regenerated when it is needed and never
+ * held whole, so that instances whose cost does not fit in memory can be
+ * checked (the same quantities as ora_plan_stats):
+ *   out[0] = marginal residual (sum|rowsum - a| + sum|colsum - b|) / sum(a)
+ *   out[1] = transport cost <C, pi>
+ *   out[2] = total mass sum pi
+ * row_sums (I) and col_sums (J) are optional outputs. Row quantities are
+ * compensated sums in column order; a column sum is compensated within each
+ * thread's contiguous block of rows and the blocks are added in row order.
+ */
+int ora_geometry_plan_stats(const float *dev_xy, const float *rrh_xy, int64_t I, int64_t J, const ora_radio *r,
+                            double scale, const double *a, const double *b, const double *f, const double *g,
+                            double eps, double *out, double *row_sums, double *col_sums) {
+    if (!dev_xy || !rrh_xy || !r || !a || !b || !f || !g || !out || I < 1 || J < 1 || !(eps > 0.0) ||
+        !(scale > 0.0))
+        return ORA_EINVAL;
+    double *rs = row_sums ? row_sums : (double *)malloc(sizeof(double) * (size_t)I);
+    double *cost_r = (double *)malloc(sizeof(double) * (size_t)I);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    nsum *cacc = (nsum *)calloc((size_t)nt * (size_t)J, sizeof(nsum));
+    int used = 1, err = (!rs || !cost_r || !cacc) ? 1 : 0;
+    if (!err) {
+#pragma omp parallel num_threads(nt)
+        {
+            int t = 0;
+#ifdef _OPENMP
+            t = omp_get_thread_num();
+#pragma omp single
+            used = omp_get_num_threads();
+#endif
+            double *w = (double *)malloc(sizeof(double) * (size_t)J * 3);
+            nsum *ca = cacc + (size_t)t * (size_t)J;
+            if (!w) {
+#pragma omp atomic write
+                err = 1;
+            }
+#pragma omp barrier
+            if (!err) {
+#pragma omp for schedule(static)
+                for (int64_t i = 0; i < I; ++i) {
+                    double *Rr = w + 2 * J;
+                    rate_row(dev_xy, rrh_xy, J, r, i, w, w + J, Rr);
+                    nsum s = {0.0, 0.0}, sc = {0.0, 0.0};
+                    for (int64_t j = 0; j < J; ++j) {
+                        double c = (1.0 / Rr[j]) / scale;
+                        double p = exp((f[i] + g[j] - c) / eps);
+                        nsum_add(&s, p);
+                        nsum_add(&sc, c * p);
+                        nsum_add(&ca[j], p);
+                    }
+                    rs[i] = nsum_get(&s);
+                    cost_r[i] = nsum_get(&sc);
+                }
+            }
+            free(w);
+        }
+    }
+    if (!err) {
+        /* static scheduling gives thread t the t-th contiguous block of rows */
+        double *cs = col_sums ? col_sums : (double *)malloc(sizeof(double) * (size_t)J);
+        if (!cs) {
+            err = 1;
+        } else {
+            for (int64_t j = 0; j < J; ++j) {
+                nsum s = {0.0, 0.0};
+                for (int t = 0; t < used; ++t) {
+                    nsum_add(&s, cacc[(size_t)t * (size_t)J + j].s);
+                    nsum_add(&s, cacc[(size_t)t * (size_t)J + j].c);
+                }
+                cs[j] = nsum_get(&s);
+            }
+            nsum res = {0.0, 0.0};
+            for (int64_t i = 0; i < I; ++i) nsum_add(&res, fabs(rs[i] - a[i]));
+            for (int64_t j = 0; j < J; ++j) nsum_add(&res, fabs(cs[j] - b[j]));
+            out[0] = nsum_get(&res) / ora_sum(a, I);
+            out[1] = ora_sum(cost_r, I);
+            out[2] = ora_sum(rs, I);
+            if (!col_sums) free(cs);
+        }
+    }
+    if (!row_sums) free(rs);
+    free(cost_r);
+    free(cacc);
+    return err ? ORA_ENOMEM : ORA_OK;
 }

@@ -201,6 +201,47 @@ def test_rate_rows_match_full(oracle_lib):
     np.testing.assert_array_equal(oracle_lib.rates_rows(L, rows), R[rows])
 
 
+def test_rates_against_brute_force_interference(oracle_lib):
+    # Sec. II-A: SINR_ji = P G_ji / (sum over every other RRH of P G_li + N0).
+    # Without shadowing the gain is K0 max(d, d_min)^-alpha; the interference
+    # is summed here term by term with math.fsum (exactly rounded).
+    L = S.make_layout(6, 11, 1000.0, seed=21)
+    L.radio = dict(L.radio, shadow_sigma_db=0.0)
+    R = oracle_lib.rates(L)
+    r = L.radio
+    for i in range(L.I):
+        d = [max(math.hypot(float(L.dev_xy[i, 0]) - float(L.rrh_xy[j, 0]),
+                            float(L.dev_xy[i, 1]) - float(L.rrh_xy[j, 1])), r["min_dist_m"]) for j in range(L.J)]
+        pg = [r["tx_power_w"] * r["ref_gain"] * dj ** -r["pathloss_exp"] for dj in d]
+        for j in range(L.J):
+            interf = math.fsum(pg[k] for k in range(L.J) if k != j)
+            expect = r["bandwidth_hz"] * math.log2(1.0 + pg[j] / (interf + r["noise_w"]))
+            assert R[i, j] == pytest.approx(expect, rel=1e-13)
+    # relabelling the RRHs relabels the columns (no shadowing, so no draw moves)
+    perm = np.random.default_rng(21).permutation(L.J)
+    Lp = S.Layout(dev_xy=L.dev_xy, rrh_xy=L.rrh_xy[perm].copy(), lam=L.lam, a=L.a, b=L.b, shadow_key=L.shadow_key,
+                  side_m=L.side_m, seed=L.seed, radio=L.radio)
+    np.testing.assert_allclose(oracle_lib.rates(Lp), R[:, perm], rtol=1e-14)
+
+
+def test_geometry_plan_stats_matches_dense_stats(oracle_lib):
+    # the row-by-row statistics equal those of the materialised cost
+    L = S.make_layout(300, 17, 1000.0, seed=22)
+    C, scale = oracle_lib.cost(L)
+    rng = np.random.default_rng(22)
+    eps = 0.05
+    r = oracle_lib.sinkhorn(C, L.a, L.b, eps, 1e-6, 1000)
+    f = r.f + rng.normal(0, 1e-3, L.I)
+    g = r.g + rng.normal(0, 1e-3, L.J)
+    ref = oracle_lib.plan_stats(C, L.a, L.b, f, g, eps)
+    got = oracle_lib.geometry_plan_stats(L, scale, f, g, eps)
+    assert got["marginal_violation"] == pytest.approx(ref["marginal_violation"], rel=1e-12)
+    assert got["objective"] == pytest.approx(ref["objective"], rel=1e-13)
+    assert got["mass"] == pytest.approx(ref["mass"], rel=1e-14)
+    np.testing.assert_allclose(got["row_sums"], ref["row_sums"], rtol=1e-14)
+    np.testing.assert_allclose(got["col_sums"], ref["col_sums"], rtol=1e-13)
+
+
 # ------------------------------------------------------------- Sinkhorn -----
 
 def test_P1_separable_cost_gives_product_plan(oracle_lib):
