@@ -25,16 +25,12 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "Sinkhorn cells/s + HBM GB/s at 20000x400; batched solves/s + p99 at fixed error"
-HBM_PEAK_GBS = 8000.0
-# ALU roofline of the cooperative FP32 sweep (derivation in the design doc): per
-# cell and iteration 7 algorithmic flops (argument FMA 2, shift 1, row-sum
-# add 1, column-partial FMA 2, the exponential 1) issued as 7 full-rate VALU
-# slots plus one quarter-rate v_exp_f32 (4 slots); 256 CUs x 4 SIMDs x 16
-# lanes at 2.4 GHz issue 3.93e13 lane-slots per second.
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+# Algorithmic flop of one cell-iteration of the fused sweep, used only for the
+# secondary ALU figure: the FP64 argument FMA (2), the shift (1), the row-sum
+# add (1), the column-partial FMA (2) and the exponential (1).
 FLOP_PER_CELL = 7.0
-ALU_SLOTS_PER_CELL = 11.0
-LANES_PER_CLOCK = 256 * 4 * 16
-CLOCK_HZ = 2.4e9
 
 
 def log(msg):
@@ -54,6 +50,7 @@ def cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale_gpu, snap_As=None):
     t0 = time.perf_counter()
     C64, scale = O.cost(L)
     t_cost = time.perf_counter() - t0
+    per_config = oracle_timings(O)
     # full FP64 solves of the instance, repeated until about 10 s of CPU work
     # (at most 12 solves), timed together
     reps, t_solve = 0, 0.0
@@ -68,7 +65,8 @@ def cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale_gpu, snap_As=None):
         value=cells * r.iters * reps / t_solve, unit="cells/s", cores=cores, kind="oracle",
         sample=(f"{reps} full FP64 solves of the 20000x400 instance, eps={eps}, tol={tol} "
                 f"({r.iters} iterations each, {t_solve:.2f} s in all); cost build {t_cost:.2f} s not included"),
-        seconds=t_solve / reps, iterations=r.iters, solves=reps,
+        seconds=t_solve / reps, iterations=r.iters, solves=reps, cpu_model=cpu_model(), threads=omp_threads(),
+        per_config=per_config,
     )
 
     def errors(C, f, g, res):
@@ -111,7 +109,150 @@ def cpu_baseline(L, eps, tol, solver, xy, rxy, a, b, scale_gpu, snap_As=None):
                              objective_rel_err=abs(st["objective"] - rs["objective"]) / abs(rs["objective"]),
                              plan_l1=float(np.abs(O.plan(C64, fq, gq, 0.02) - O.plan(C64, ref.f, ref.g, 0.02)).sum())))
         acc["snapshots_bf16"] = snap
+    acc["large"] = large_accuracy(A, torch, dev)
     return base, acc
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _gomp():
+    import ctypes
+    try:
+        return ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+
+
+def omp_threads():
+    g = _gomp()
+    return int(g.omp_get_max_threads()) if g else 1
+
+
+def oracle_timings(O):
+    """The FP64 oracle timed per workload on this host: the small workload
+    with every thread and with one, the large one per iteration (its cost
+    built once with the reference scale), and a sample of the batched
+    instances solved one after another."""
+    import scenario as S
+
+    out = {}
+    g = _gomp()
+    nthr = omp_threads()
+    Ls = S.preset_layout("small_1000x50")
+    C0, _ = O.cost(Ls)
+    for label, th in (("all_threads", nthr), ("single_thread", 1)):
+        if g:
+            g.omp_set_num_threads(th)
+        t0 = time.perf_counter()
+        r = O.sinkhorn(C0, Ls.a, Ls.b, 0.05, 1e-9, 2000)
+        t = time.perf_counter() - t0
+        out[f"small_1000x50_{label}"] = dict(threads=th, iterations=r.iters, seconds=t, s_per_iteration=t / r.iters,
+                                             cells_per_s=Ls.I * Ls.J * r.iters / t)
+    if g:
+        g.omp_set_num_threads(nthr)
+    # batched workload: the first 16 of the 256 instances, solved serially
+    # (cost builds are not timed)
+    Lb = S.batch_layouts(16, 3000)
+    Cb = [O.cost(Lk)[0] for Lk in Lb]
+    ts, it = 0.0, 0
+    for Lk, Ck in zip(Lb, Cb):
+        t1 = time.perf_counter()
+        it += O.sinkhorn(Ck, Lk.a, Lk.b, 0.05, 1e-6, 2000).iters
+        ts += time.perf_counter() - t1
+    del Cb
+    out["batch_sample_16_serial"] = dict(solves=len(Lb), seconds=ts, solves_per_s=len(Lb) / ts,
+                                         iterations_total=it)
+    # large workload: one iteration of the FP64 oracle on the materialised
+    # cost (6.4 GB of C and its transpose), times the iterations it needs
+    ref = large_reference()
+    if ref is not None:
+        LL = S.preset_layout("large_200000x2000")
+        t0 = time.perf_counter()
+        CL, _ = O.cost(LL, ref["scale"])
+        t_cost = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.sinkhorn(CL, LL.a, LL.b, ref["eps"], 0.0, 1)
+        t_it = time.perf_counter() - t0
+        del CL
+        out["large_200000x2000"] = dict(s_per_iteration=t_it, cost_build_s=t_cost,
+                                        iterations_to_1e_12=int(ref["iterations"]),
+                                        estimated_solve_s=t_it * ref["iterations"],
+                                        cells_per_s=LL.I * LL.J / t_it,
+                                        note="one measured FP64 iteration (includes the one-time transpose) "
+                                             "x the reference solve's iteration count")
+    return out
+
+
+def large_reference():
+    """The oracle's stored solution of the large workload (tests/golden), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "large_200000x2000_reference.txt")
+    if not os.path.exists(path):
+        return None
+    ref, rows, f = {}, [], []
+    for ln in open(path):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        t = ln.split()
+        if t[0] == "g":
+            ref["g"] = np.array([float(v) for v in t[1:]])
+        elif t[0][0].isdigit():
+            rows.append(int(t[0]))
+            f.append(float(t[1]))
+        else:
+            ref[t[0]] = float(t[1])
+    ref["rows"] = np.array(rows, dtype=np.int64)
+    ref["f_rows"] = np.array(f)
+    return ref
+
+
+def large_accuracy(A, torch, dev):
+    """The large workload solved with the reference's scale, its plan checked
+    by the oracle: both marginals and <C, pi> over all 4e8 cells with the
+    oracle's own FP64 costs, and the plan's L1 distance to the reference plan
+    on the reference's seeded 1 % of the rows."""
+    import scenario as S
+    from oracle import oracle as O
+
+    ref = large_reference()
+    if ref is None:
+        return None
+    L = S.preset_layout("large_200000x2000")
+    eps, tol, scale = ref["eps"], 1e-8, ref["scale"]
+    xy = torch.from_numpy(L.dev_xy).to(dev)
+    rxy = torch.from_numpy(L.rrh_xy).to(dev)
+    a = torch.from_numpy(L.a).to(dev)
+    b = torch.from_numpy(L.b).to(dev)
+    rows = ref["rows"]
+    with A.Solver(L.I, L.J) as s:
+        _, res = s.solve_geometry(xy, rxy, L.radio, L.shadow_key, scale, a, b, eps, tol, 2000)
+        f, g = s.potentials()
+        P = torch.empty((L.I, L.J), dtype=torch.float64, device=dev)
+        s.plan(P)
+        P_rows = P[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        del P
+    t0 = time.perf_counter()
+    chk = O.geometry_plan_stats(L, scale, f, g, eps)
+    t_chk = time.perf_counter() - t0
+    P_ref = O.plan(O.cost_rows(L, rows, scale), ref["f_rows"], ref["g"], eps)
+    l1 = float(np.abs(P_rows - P_ref).sum())
+    out = dict(iterations=res.iterations, marginal_violation_gpu=res.marginal_violation,
+               marginal_violation=chk["marginal_violation"],
+               objective_rel_err=abs(chk["objective"] - ref["objective"]) / ref["objective"],
+               plan_l1_sample=l1, plan_l1_sample_rel=l1 / float(P_ref.sum()), sample_rows=int(rows.size),
+               oracle_check_s=t_chk,
+               note="oracle-side statistics over every cell from the GPU's potentials with FP64 costs regenerated "
+                    "by the oracle; objective and plan against the oracle's solution to 1e-12 (tests/golden)")
+    log(f"large accuracy: violation {out['marginal_violation']:.2e} (oracle side), objective rel err "
+        f"{out['objective_rel_err']:.2e}, plan L1 on 1% of rows {out['plan_l1_sample_rel']:.2e} relative")
+    return out
 
 
 def pad_cols(t, J):
@@ -501,6 +642,14 @@ def main():
     copy_gbps = 2 * src_buf.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src_buf, dst_buf
     log(f"copy ceiling: {copy_gbps:.0f} GB/s")
+    # read ceiling: the library's read-only streaming kernel over 1 GiB (above
+    # the 256 MB last-level cache), HIP events on its stream
+    rbuf = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    solver.time_read(rbuf, 3)
+    ms_read = solver.time_read(rbuf, 20)
+    read_gbps = rbuf.numel() * 4 / (ms_read * 1e-3) / 1e9
+    del rbuf
+    log(f"read ceiling: {read_gbps:.0f} GB/s")
 
     ms_big, gbps_big, resB = None, None, None
     if args.only == "all":
@@ -550,24 +699,28 @@ def main():
                            "the path of instances whose cost does not fit in LDS)",
                  "avg_launch_us": ms_sweep * 1e3, "fp64_sweep_us": ms_sweep64 * 1e3}
     if coop is not None:
-        # dominant kernel: the cooperative FP32 launch. Per cell and iteration
-        # it issues ALU_SLOTS_PER_CELL VALU issue slots (7 full-rate ops and one
-        # quarter-rate v_exp_f32) for FLOP_PER_CELL algorithmic flops; the ALU
-        # peak of that mix follows from the unit counts and the clock.
+        # dominant kernel: the cooperative FP32 launch. Its algorithmic bytes
+        # are those of the fused single-read sweep it replaces, 4 B per
+        # cell-iteration (one FP32 read of C), against the HBM peak; it
+        # actually reads C from HBM once per launch and keeps it in LDS, so
+        # the counted traffic sits far below the algorithmic bytes.
         coop_s, coop_it = coop[0] * 1e-3, coop[1]
-        flops = FLOP_PER_CELL * cells * coop_it
-        achieved_alu = flops / coop_s / 1e12
-        peak_alu = FLOP_PER_CELL * LANES_PER_CLOCK * CLOCK_HZ / ALU_SLOTS_PER_CELL / 1e12
+        hbm_equiv = alg_bytes * coop_it / coop_s / 1e9
         ctraffic, cnote = counter_traffic("k_persist_dense_cran_20000x400_traffic.json", coop_s)
-        roofline = {"bound": "alu", "achieved": achieved_alu, "peak": peak_alu, "unit": "TFLOP/s",
-                    "frac": achieved_alu / peak_alu, "traffic": ctraffic, "traffic_note": cnote,
+        flops = FLOP_PER_CELL * cells * coop_it
+        roofline = {"bound": "hbm", "achieved": hbm_equiv, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": hbm_equiv / HBM_PEAK_GBS, "traffic": ctraffic, "traffic_note": cnote,
                     "kernel": "k_persist<DenseSrc<float>> (cooperative FP32 phase, cost held in LDS)",
                     "avg_launch_us": coop[0] * 1e3, "iterations_per_launch": coop_it,
                     "us_per_iteration": coop[0] * 1e3 / coop_it,
-                    "algorithmic_flop_per_launch": flops,
-                    "hbm_equivalent_gbps": alg_bytes * coop_it / coop_s / 1e9,
-                    "hbm_equivalent_note": "4 B per cell-iteration (a fused single read of C) per unit time, "
-                                           "against 8000 GB/s; the cost itself is read from HBM once per launch"}
+                    "algorithmic_bytes_per_launch": alg_bytes * coop_it,
+                    "algorithmic_note": "4 B per cell-iteration (one FP32 read of C by a fused single-read sweep) "
+                                        "x I J x the launch's iterations, over the launch duration (HIP events)",
+                    "read_ceiling_gbps": read_gbps, "copy_ceiling_gbps": copy_gbps,
+                    "alu_secondary": {"achieved": flops / coop_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                                      "unit": "TFLOP/s", "frac": flops / coop_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                                      "note": f"{FLOP_PER_CELL:.0f} algorithmic flop per cell-iteration against "
+                                              "the published FP32 vector peak"}}
     else:
         roofline = streaming
     out = {
@@ -595,6 +748,7 @@ def main():
         "roofline": roofline,
         "streaming_sweep": streaming,
         "copy_gbps": copy_gbps,
+        "read_gbps": read_gbps,
         "sweep_above_llc": None if resB is None else {
             "workload": "200000x400 dense FP32 (320 MB), same kernel", "sweep_us": ms_big * 1e3,
             "achieved_gbps": gbps_big, "frac": gbps_big / HBM_PEAK_GBS,

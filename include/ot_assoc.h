@@ -26,7 +26,8 @@
  *     RATES matrix in device memory is referenced, not copied, and must stay
  *     valid and unchanged until the next call on the handle that takes a cost
  *     descriptor (ot_assoc_plan and ot_assoc_time_sweep read it again). The
- *     handle owns its device workspace.
+ *     handle owns its device workspace, or borrows the caller's
+ *     (ot_assoc_options.workspace) until ot_assoc_destroy.
  *   - Layout: matrices are row-major I x J (devices are rows, RRHs are
  *     columns) with leading dimension J, contiguous. Positions are I x 2 and
  *     J x 2 float arrays of (x, y) in metres.
@@ -128,6 +129,22 @@ typedef struct {
                            cooperative launch that keeps the cost in LDS when the instance fits
                            (about I * J <= 9.8e6 cells on 256 CUs; dense FP32, FP32 rates or
                            geometry costs); 0 always uses graph-captured chunks of launches */
+    int check_every;    /* ot_assoc_solve: the stop rule (residual below tol, or the FP32 residual
+                           stalled) is evaluated only after iterations k that are multiples of
+                           check_every (default 1: after every iteration); max_iter always stops.
+                           The residual itself is formed in every sweep either way. */
+    void* workspace;    /* optional caller-owned device memory on `device` (e.g. a torch tensor's
+                           data_ptr()), at least ot_assoc_workspace_size() bytes, 256-byte aligned,
+                           valid and not otherwise used until ot_assoc_destroy. Every device buffer
+                           of the single-instance calls (ot_assoc_solve, _plan, _potentials,
+                           _set_potentials, _cost_median, _materialize_cost, the loads, evaluation,
+                           maxSINR and Alg. 2 calls and the timers) is carved from it, so those
+                           calls allocate no device memory; bytes beyond the required size stage
+                           host-memory DENSE / RATES matrices (a host matrix that does not fit
+                           gives OT_ENOMEM). NULL (default): the library allocates one block of
+                           that size itself. The batch, snapshot and serving engines keep their
+                           own device pools either way. */
+    size_t workspace_bytes; /* size of `workspace` (0 when workspace is NULL) */
 } ot_assoc_options;
 
 typedef struct {
@@ -149,11 +166,20 @@ typedef struct {
 /* Fills *opt with the defaults listed above (device 0, default stream). */
 ot_status ot_assoc_default_options(ot_assoc_options *opt);
 
+/* Bytes of caller workspace (ot_assoc_options.workspace) a handle for
+ * instances up to I_max x J_max needs: the O(I_max + J_max) vectors, the
+ * per-workgroup partials, the cooperative phase's exchange block and a
+ * scratch region of 2 (I_max + J_max) doubles. Pure host arithmetic (no
+ * device is touched). Errors: OT_EINVAL for sizes out of range or NULL. */
+ot_status ot_assoc_workspace_size(int64_t I_max, int64_t J_max, size_t *bytes);
+
 /* Creates a handle able to solve instances up to I_max x J_max on
- * opt->device (opt NULL = defaults). Allocates the device workspace:
- * O(I_max + J_max) vectors plus per-workgroup partials, and an
- * I_max x J_max staging matrix only when a host-memory dense or rate cost is
- * later passed. Errors: OT_EINVAL (I_max or J_max < 1), OT_ENOMEM, OT_EDEVICE. */
+ * opt->device (opt NULL = defaults). Takes its device buffers from
+ * opt->workspace when given, else allocates one block of
+ * ot_assoc_workspace_size() bytes, plus (only without a caller workspace) an
+ * I x ld staging matrix when a host-memory dense or rate cost is later passed.
+ * Errors: OT_EINVAL (I_max or J_max out of range, a workspace that is too
+ * small or misaligned, check_every < 0), OT_ENOMEM, OT_EDEVICE. */
 ot_status ot_assoc_create(ot_assoc **h, int64_t I_max, int64_t J_max, const ot_assoc_options *opt);
 
 /* Solves one instance (eq. (5) with the Sinkhorn iteration of Sec. III-B).
@@ -283,6 +309,15 @@ ot_status ot_assoc_adaptive(ot_assoc *h, const ot_cost_desc *cost, const double 
  * Errors: OT_ESTATE before a successful solve, OT_EINVAL for bad reps. */
 ot_status ot_assoc_time_sweep(ot_assoc *h, int32_t reps, int fp64, double *ms_per_launch);
 
+/* (instrumentation) HBM read ceiling: average device duration, in
+ * milliseconds, of a read-only streaming kernel over `bytes` (a multiple of
+ * 16, >= 16) of device memory at `buf` (16-byte aligned; only read), run
+ * `reps` (1..4096) times back to back on the handle's stream between one pair
+ * of HIP events. Bytes / duration is the read bandwidth the device sustains
+ * for a plain coalesced stream, the ceiling beside which the sweeps' HBM
+ * figures are read. Errors: OT_EINVAL for bad arguments, OT_EDEVICE. */
+ot_status ot_assoc_time_read(ot_assoc *h, const void *buf, size_t bytes, int32_t reps, double *ms_per_launch);
+
 /* (instrumentation) Device duration, in milliseconds, of the cooperative
  * launch that ran the FP32 phase of the last successful solve (HIP events on
  * the handle's stream right around that one launch: the LDS fill and every
@@ -291,7 +326,13 @@ ot_status ot_assoc_time_sweep(ot_assoc *h, int32_t reps, int fp64, double *ms_pe
  * (see ot_assoc_result.flags). */
 ot_status ot_assoc_fast_phase_time(ot_assoc *h, double *ms, int32_t *iterations);
 
-/* Frees the handle and its device workspace. NULL-safe. */
+/* (instrumentation) Number of device allocations (hipMalloc) the library has
+ * made in this process so far, over all handles and engines: a caller that
+ * passes a workspace can check that its solves allocate nothing. */
+int64_t ot_assoc_device_allocations(void);
+
+/* Frees the handle and its device workspace (a caller's workspace is left
+ * to the caller). NULL-safe. */
 void ot_assoc_destroy(ot_assoc *h);
 
 /* Human-readable description of the last error on this handle ("" if none).

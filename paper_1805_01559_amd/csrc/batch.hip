@@ -79,9 +79,9 @@ class DevicePool {
             size_t sz = std::min(want, budget - std::min(budget, reserved));
             if (sz < bytes) return nullptr;
             char* base = nullptr;
-            if (hipMalloc(&base, sz) != hipSuccess) {
+            if (otk_host::dev_malloc((void**)&base, sz) != hipSuccess) {
                 (void)hipGetLastError();
-                if (sz > bytes && hipMalloc(&base, bytes) == hipSuccess) sz = bytes;
+                if (sz > bytes && otk_host::dev_malloc((void**)&base, bytes) == hipSuccess) sz = bytes;
                 else { (void)hipGetLastError(); return nullptr; }
             }
             slabs_.push_back({base, sz});
@@ -304,12 +304,12 @@ ot_status BatchEngine::init(int dev, hipStream_t st, int slots_cap, int items_ca
     cap_slots = slots_cap;
     cap_items = items_cap;
     pool.budget = budget;
-    ECHK(this, hipMalloc(&tab, sizeof(BInst) * cap_slots));
-    ECHK(this, hipMalloc(&ctl, sizeof(Ctl) * cap_slots));
+    ECHK(this, otk_host::dev_malloc((void**)&tab, sizeof(BInst) * cap_slots));
+    ECHK(this, otk_host::dev_malloc((void**)&ctl, sizeof(Ctl) * cap_slots));
     const size_t item_bytes = align_up(sizeof(BItem) * (size_t)cap_items);
     const size_t inst_bytes = align_up(sizeof(int) * (size_t)cap_slots);
     const size_t gen_bytes = 2 * item_bytes + inst_bytes + kAlign;
-    ECHK(this, hipMalloc(&lists_mem, 2 * gen_bytes));
+    ECHK(this, otk_host::dev_malloc((void**)&lists_mem, 2 * gen_bytes));
     for (int g = 0; g < 2; ++g) {
         char* p = lists_mem + g * gen_bytes;
         L[g].it32 = (BItem*)p;
@@ -320,7 +320,7 @@ ot_status BatchEngine::init(int dev, hipStream_t st, int slots_cap, int items_ca
     ECHK(this, hipMemsetAsync(lists_mem, 0, 2 * gen_bytes, stream));
     for (int q = 0; q < 2; ++q) ECHK(this, hipEventCreateWithFlags(&ev_adm[q], hipEventDisableTiming));
     ECHK(this, hipHostMalloc(&relay_h, sizeof(int) * 2 * cap_slots));
-    ECHK(this, hipMalloc(&relay_d, sizeof(int) * 2 * cap_slots));
+    ECHK(this, otk_host::dev_malloc((void**)&relay_d, sizeof(int) * 2 * cap_slots));
     for (auto& s : snap) ECHK(this, hipHostMalloc(&s, sizeof(Ctl) * cap_slots));
     for (auto& e : ev_snap) ECHK(this, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     slots.assign(cap_slots, Slot{});
@@ -734,7 +734,7 @@ ot_status BatchEngine::ensure_blob(int set, size_t bytes) {
     blob_cap[set] = 0;
     const size_t cap = std::max(bytes, (size_t)1 << 20);
     ECHK(this, hipHostMalloc(&blob_h[set], cap));
-    ECHK(this, hipMalloc(&blob_d[set], cap));
+    ECHK(this, otk_host::dev_malloc((void**)&blob_d[set], cap));
     blob_cap[set] = cap;
     return OT_OK;
 }
@@ -937,10 +937,10 @@ static ot_status slot_plan(BatchEngine* e, const Slot& s, void* pi, ot_mem mem, 
     const int grid = (int)std::min<int64_t>(4096, (s.I + 7) / 8);
     const DenseSrc<float> src{s.d.C, s.d.ld};
     if (dtype == OT_F32)
-        hipLaunchKernelGGL((k_plan<DenseSrc<float>, float, 4>), dim3(grid), dim3(512), lds, e->stream, s.I, s.J, nch,
+        hipLaunchKernelGGL((k_plan<DenseSrc<float>, float, 4>), dim3(grid), dim3(512), lds, e->stream, (int64_t)0, s.I, s.J, nch,
                            (const double*)s.d.f[par], (const double*)s.d.g[par], (const SolveParams*)s.prm, (float*)dst, src);
     else
-        hipLaunchKernelGGL((k_plan<DenseSrc<float>, double, 4>), dim3(grid), dim3(512), lds, e->stream, s.I, s.J, nch,
+        hipLaunchKernelGGL((k_plan<DenseSrc<float>, double, 4>), dim3(grid), dim3(512), lds, e->stream, (int64_t)0, s.I, s.J, nch,
                            (const double*)s.d.f[par], (const double*)s.d.g[par], (const SolveParams*)s.prm, (double*)dst, src);
     ot_status st = OT_OK;
     hipError_t er = hipGetLastError();

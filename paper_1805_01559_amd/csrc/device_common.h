@@ -169,7 +169,7 @@ struct Ctl {
     uint32_t arrive;       // last-block-done counter of the combine kernel
     uint32_t arrive2;      // same, for the check kernel
     int32_t has_prev;      // 1 if a previous iterate f^(k-1) exists (k >= 1 or warm start)
-    int32_t pad_;
+    int32_t check_every;   // the stop rule is evaluated after iterations k with k % check_every == 0 (0, 1: every k)
     double tol;
     double mass;           // sum(a)
     double r_last;         // residual of iterate (iter - 1), measured during iteration iter

@@ -17,6 +17,11 @@ struct GraphEntry {
     std::string key;
     hipGraphExec_t exec = nullptr;
 };
+
+// Device allocations of the library go through these, which count them
+// (ot_assoc_device_allocations reports the count).
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t dev_free(void* p);
 }  // namespace otk_host
 
 // Constants of the geometry cost functor (relative gains, log2-domain
@@ -65,6 +70,10 @@ struct ot_assoc {
     int* j1 = nullptr;
     void* stage = nullptr;  // host-memory dense / rate matrices are copied here
     size_t stage_bytes = 0;
+    bool stage_in_ws = false;  // the stage is the tail of a caller's workspace (never freed or grown)
+    void* ws = nullptr;        // the single device block all fixed buffers are carved from
+    void* scratch = nullptr;   // 2 (I_max + J_max) doubles of per-call scratch (plan blocks, timers, Alg. 2)
+    bool ws_owned = false;     // allocated by the library (else the caller's workspace)
     // pinned host mirrors
     otk::Ctl* ctl_h = nullptr;  // 2 slots
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_slot[2] = {nullptr, nullptr};

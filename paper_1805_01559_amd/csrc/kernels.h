@@ -117,11 +117,14 @@ __device__ __forceinline__ void bookkeep(Ctl* c, double rsum, int mode, double s
         for (int q = 3; q > 0; --q) c->r_hist[q] = c->r_hist[q - 1];
         c->r_hist[0] = r;
         const double target = c->tol_fast > 0.0 ? c->tol_fast : c->tol;
-        if (r < target || stall || k >= c->max_iter) c->stop = 1;
+        const bool at_check = c->check_every <= 1 || k % c->check_every == 0;
+        if ((at_check && (r < target || stall)) || k >= c->max_iter) c->stop = 1;
     } else {
         c->fp64_iters += 1;
         c->last_fp64 = 1;
-        if (mode == kModeExact && prev64 && r < c->tol) {
+        // (r is the residual of iterate k - 1, the one an exact stop returns)
+        const bool at_check = c->check_every <= 1 || (k - 1) % c->check_every == 0;
+        if (mode == kModeExact && prev64 && r < c->tol && at_check) {
             c->done = 1;
             c->stop = 1;
             c->result_iter = k - 1;
@@ -864,8 +867,9 @@ static __global__ __launch_bounds__(256) void k_check_finish(const double* stat_
 
 // -------------------------------------------------------------------- plan --
 // pi_ij = exp((f_i + g_j - C_ij) / eps) in FP64, stored as OutT.
+// Rows [r0, r1); `out` holds row r0 first.
 template <class Src, typename OutT, int VEC>
-__global__ __launch_bounds__(512) void k_plan(int64_t I, int J, int nch, const double* f, const double* g,
+__global__ __launch_bounds__(512) void k_plan(int64_t r0, int64_t r1, int J, int nch, const double* f, const double* g,
                                               const SolveParams* prm, OutT* out, Src src) {
     const double kk = prm->kk;
     const int ncols = nch * kWave * VEC;
@@ -876,10 +880,10 @@ __global__ __launch_bounds__(512) void k_plan(int64_t I, int J, int nch, const d
     for (int c = threadIdx.x; c < ncols; c += blockDim.x) gs[c] = (c < J) ? g[c] * kk : -pinf64();
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    for (int64_t i = (int64_t)blockIdx.x * nw + w; i < I; i += (int64_t)gridDim.x * nw) {
+    for (int64_t i = r0 + (int64_t)blockIdx.x * nw + w; i < r1; i += (int64_t)gridDim.x * nw) {
         auto row = src.row(i);
         const double fk = f[i] * kk;
-        OutT* o = out + i * J;
+        OutT* o = out + (i - r0) * J;
         for (int ch = 0; ch < nch; ++ch) {
             const int col0 = (ch * kWave + lane) * VEC;
             double c[VEC];

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -43,7 +44,61 @@ constexpr int kGraphCache = 24;
 
 using otk_host::GraphEntry;
 
+// ------------------------------------------------------------- workspace --
+// The handle's fixed device buffers, in one block; each starts on a
+// kWsAlign-byte boundary.
+constexpr int kWsAlign = 256;
+enum {
+    kWsA, kWsLa, kWsB, kWsF0, kWsF1, kWsG0, kWsG1, kWsColPart, kWsResPart, kWsStatPart, kWsCpart, kWsCtl, kWsPrm,
+    kWsBad, kWsHist, kWsXch, kWsXyDev, kWsXyRrh, kWsSAll, kWsSEx, kWsJ1, kWsScratch, kWsCount
+};
+struct WsLayout {
+    size_t off[kWsCount];
+    size_t total;
+};
+// Bytes of the per-solve scratch region: the plan's and the timers' copies of
+// the potentials (I_max + J_max doubles each).
+inline size_t ws_scratch_bytes(int64_t I_max, int64_t J_max) { return sizeof(double) * 2 * (size_t)(I_max + J_max); }
+
+void ws_layout(int64_t I_max, int64_t J_max, WsLayout& L) {
+    const size_t I8 = sizeof(double) * (size_t)I_max, J8 = sizeof(double) * (size_t)J_max;
+    size_t sz[kWsCount];
+    sz[kWsA] = I8; sz[kWsLa] = I8; sz[kWsB] = J8;
+    sz[kWsF0] = I8; sz[kWsF1] = I8; sz[kWsG0] = J8; sz[kWsG1] = J8;
+    sz[kWsColPart] = (size_t)kMaxNb * J8;
+    sz[kWsResPart] = sizeof(double) * kMaxNb;
+    sz[kWsStatPart] = sizeof(double) * 5 * kMaxNb;
+    sz[kWsCpart] = sizeof(double) * 2 * ((kMaxJ + kColsPerWg - 1) / kColsPerWg);
+    sz[kWsCtl] = sizeof(Ctl);
+    sz[kWsPrm] = sizeof(SolveParams);
+    sz[kWsBad] = sizeof(int);
+    sz[kWsHist] = sizeof(unsigned long long) * 2048;
+    sz[kWsXch] = sizeof(double) * persist_exchange_doubles(kMaxCoopGroups, (int)J_max);
+    sz[kWsXyDev] = sizeof(float) * 2 * (size_t)I_max;
+    sz[kWsXyRrh] = sizeof(float) * 2 * (size_t)J_max;
+    sz[kWsSAll] = I8; sz[kWsSEx] = I8;
+    sz[kWsJ1] = sizeof(int) * (size_t)I_max;
+    sz[kWsScratch] = ws_scratch_bytes(I_max, J_max);
+    size_t o = 0;
+    for (int k = 0; k < kWsCount; ++k) {
+        L.off[k] = o;
+        o += (sz[k] + kWsAlign - 1) / kWsAlign * kWsAlign;
+    }
+    L.total = o;
+}
+
+std::atomic<long long> g_dev_allocs{0};
+
 }  // namespace
+
+namespace otk_host {
+hipError_t dev_malloc(void** p, size_t bytes) {
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) g_dev_allocs.fetch_add(1, std::memory_order_relaxed);
+    return e;
+}
+hipError_t dev_free(void* p) { return hipFree(p); }
+}  // namespace otk_host
 
 
 namespace {
@@ -274,23 +329,27 @@ bool launch_check(const Shape& s, const CheckArgs& A, const Src& src, hipStream_
     return false;
 }
 
+// Plan rows [r0, r1) into `out` (row r0 first).
 template <class Src, typename OutT, int VEC>
-void launch_plan_v(const Shape& s, int64_t I, int J, const double* f, const double* g, const SolveParams* prm,
-                   OutT* out, const Src& src, hipStream_t st) {
+void launch_plan_v(const Shape& s, int64_t r0, int64_t r1, int J, const double* f, const double* g,
+                   const SolveParams* prm, OutT* out, const Src& src, hipStream_t st) {
     const size_t ncols = (size_t)s.nch * 64 * VEC;
     const size_t lds = sizeof(double) * (Src::kStageDoubles + 1) * ncols;
     auto kern = k_plan<Src, OutT, VEC>;
     set_lds(kern, lds);
-    const int grid = (int)std::min<int64_t>(4096, (I + 7) / 8);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, st, I, J, s.nch, f, g, prm, out, src);
+    const int grid = (int)std::min<int64_t>(4096, (r1 - r0 + 7) / 8);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, st, r0, r1, J, s.nch, f, g, prm, out, src);
 }
 
 template <class Src, typename OutT>
-bool launch_plan(const Shape& s, int64_t I, int J, const double* f, const double* g, const SolveParams* prm, OutT* out,
-                 const Src& src, hipStream_t st) {
-    if (s.vec == 1) { launch_plan_v<Src, OutT, 1>(s, I, J, f, g, prm, out, src, st); return true; }
+bool launch_plan(const Shape& s, int64_t r0, int64_t r1, int J, const double* f, const double* g,
+                 const SolveParams* prm, OutT* out, const Src& src, hipStream_t st) {
+    if (s.vec == 1) { launch_plan_v<Src, OutT, 1>(s, r0, r1, J, f, g, prm, out, src, st); return true; }
     if constexpr (Src::kVecWide > 1)
-        if (s.vec == Src::kVecWide) { launch_plan_v<Src, OutT, Src::kVecWide>(s, I, J, f, g, prm, out, src, st); return true; }
+        if (s.vec == Src::kVecWide) {
+            launch_plan_v<Src, OutT, Src::kVecWide>(s, r0, r1, J, f, g, prm, out, src, st);
+            return true;
+        }
     return false;
 }
 
@@ -383,10 +442,13 @@ ot_status validate_desc(ot_assoc* h, const ot_cost_desc* c) {
 
 ot_status ensure_stage(ot_assoc* h, size_t bytes) {
     if (h->stage_bytes >= bytes) return OT_OK;
-    if (h->stage) hipFree(h->stage);
+    if (!h->ws_owned)  // a caller's workspace: the library allocates nothing
+        return fail(h, OT_ENOMEM, "staging a host-memory matrix needs %zu bytes beyond the workspace's fixed "
+                                  "buffers (%zu available)", bytes, h->stage_bytes);
+    if (h->stage) otk_host::dev_free(h->stage);
     h->stage = nullptr;
     h->stage_bytes = 0;
-    HIPCHK(h, hipMalloc(&h->stage, bytes));
+    HIPCHK(h, otk_host::dev_malloc(&h->stage, bytes));
     h->stage_bytes = bytes;
     return OT_OK;
 }
@@ -773,6 +835,29 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
     return OT_OK;
 }
 
+// Read-only streaming kernel (the HBM read ceiling of ot_assoc_time_read):
+// 16-byte loads, eight in flight per lane, grid-stride. The XOR of the data
+// is stored only if it equals a value it practically never takes, so the
+// loads are kept and the kernel writes nothing.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+static __global__ __launch_bounds__(256) void k_read_stream(const u32x4* __restrict__ p, size_t n16, uint32_t* sink) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (; q + 7 * stride < n16; q += 8 * stride) {
+        u32x4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(p + q + u * stride);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    for (; q < n16; q += stride) {
+        const u32x4 v = __builtin_nontemporal_load(p + q);
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (acc == 0x9E3779B9u) sink[blockIdx.x & 1023] = acc;
+}
+
 // ln a_i of the instance, for the row shifts of the streaming FP32 sweeps.
 static __global__ void k_log_a(const double* a, int64_t I, double* la) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += (int64_t)gridDim.x * blockDim.x)
@@ -949,8 +1034,19 @@ ot_status ot_assoc_default_options(ot_assoc_options* opt) {
     opt->use_graphs = 1;
     opt->batch_tune = 1;
     opt->persistent = 1;
+    opt->check_every = 1;
     return OT_OK;
 }
+
+ot_status ot_assoc_workspace_size(int64_t I_max, int64_t J_max, size_t* bytes) {
+    if (!bytes || I_max < 1 || J_max < 1 || J_max > kMaxJ || I_max > ((int64_t)1 << 31)) return OT_EINVAL;
+    WsLayout wl;
+    ws_layout(I_max, J_max, wl);
+    *bytes = wl.total;
+    return OT_OK;
+}
+
+int64_t ot_assoc_device_allocations(void) { return g_dev_allocs.load(std::memory_order_relaxed); }
 
 const char* ot_assoc_last_error(const ot_assoc* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
@@ -958,11 +1054,8 @@ void ot_assoc_destroy(ot_assoc* h) {
     if (!h) return;
     hipSetDevice(h->device);
     for (auto& e : h->graphs) hipGraphExecDestroy(e.exec);
-    void* bufs[] = {h->a, h->la, h->b, h->f[0], h->f[1], h->g[0], h->g[1], h->col_part, h->res_part, h->stat_part,
-                    h->cpart, h->ctl, h->prm, h->bad, h->hist, h->xch,
-                    h->xy_dev, h->xy_rrh, h->s_all, h->s_ex, h->j1, h->stage};
-    for (void* p : bufs)
-        if (p) hipFree(p);
+    if (h->ws && h->ws_owned) otk_host::dev_free(h->ws);
+    if (h->stage && !h->stage_in_ws) otk_host::dev_free(h->stage);
     if (h->ctl_h) hipHostFree(h->ctl_h);
     hipEvent_t evs[] = {h->ev_start, h->ev_stop, h->ev_slot[0], h->ev_slot[1], h->ev_coop[0], h->ev_coop[1]};
     for (auto e : evs)
@@ -992,6 +1085,9 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     if (o.sweep_waves != 0 && o.sweep_waves != 4 && o.sweep_waves != 8)
         return fail(nullptr, OT_EINVAL, "sweep_waves must be 0, 4 or 8");
     if (o.chunk == 0) o.chunk = 8;
+    if (o.check_every < 0) return fail(nullptr, OT_EINVAL, "check_every must be >= 0");
+    if (o.check_every == 0) o.check_every = 1;
+    if (!o.workspace && o.workspace_bytes) return fail(nullptr, OT_EINVAL, "workspace_bytes without a workspace");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, OT_EDEVICE, "no HIP device");
     if (o.device < 0 || o.device >= ndev) return fail(nullptr, OT_EINVAL, "device %d out of range", o.device);
@@ -1006,30 +1102,62 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     h->opt = o;
     h->I_max = I_max;
     h->J_max = J_max;
-    auto al = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)); };
+    // every fixed buffer is carved from one device block: the caller's
+    // workspace, or one allocation of the same layout
+    WsLayout wl;
+    ws_layout(I_max, J_max, wl);
     hipError_t e = hipSuccess;
-    const size_t I8 = sizeof(double) * (size_t)I_max, J8 = sizeof(double) * (size_t)J_max;
-    if (e == hipSuccess) e = al((void**)&h->a, I8);
-    if (e == hipSuccess) e = al((void**)&h->la, I8);
-    if (e == hipSuccess) e = al((void**)&h->b, J8);
-    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
-        e = al((void**)&h->f[q], I8);
-        if (e == hipSuccess) e = al((void**)&h->g[q], J8);
+    if (o.workspace) {
+        if (o.workspace_bytes < wl.total) {
+            fail(nullptr, OT_EINVAL, "workspace of %zu bytes is below the %zu bytes this size needs",
+                 o.workspace_bytes, wl.total);
+            delete h;
+            return OT_EINVAL;
+        }
+        if ((uintptr_t)o.workspace % kWsAlign != 0) {
+            fail(nullptr, OT_EINVAL, "workspace must be %d-byte aligned", kWsAlign);
+            delete h;
+            return OT_EINVAL;
+        }
+        h->ws = o.workspace;
+        h->ws_owned = false;
+        // what lies beyond the fixed buffers stages host-memory matrices
+        const size_t tail = o.workspace_bytes - wl.total;
+        if (tail > 0) {
+            h->stage = (char*)o.workspace + wl.total;
+            h->stage_bytes = tail;
+            h->stage_in_ws = true;
+        }
+    } else {
+        e = otk_host::dev_malloc(&h->ws, wl.total);
+        h->ws_owned = (e == hipSuccess);
     }
-    if (e == hipSuccess) e = al((void**)&h->col_part, (size_t)kMaxNb * J8);
-    if (e == hipSuccess) e = al((void**)&h->res_part, sizeof(double) * kMaxNb);
-    if (e == hipSuccess) e = al((void**)&h->stat_part, sizeof(double) * 5 * kMaxNb);
-    if (e == hipSuccess) e = al((void**)&h->cpart, sizeof(double) * 2 * ((kMaxJ + kColsPerWg - 1) / kColsPerWg));
-    if (e == hipSuccess) e = al((void**)&h->ctl, sizeof(Ctl));
-    if (e == hipSuccess) e = al((void**)&h->prm, sizeof(SolveParams));
-    if (e == hipSuccess) e = al((void**)&h->bad, sizeof(int));
-    if (e == hipSuccess) e = al((void**)&h->hist, sizeof(unsigned long long) * 2048);
-    if (e == hipSuccess) e = al((void**)&h->xch, sizeof(double) * persist_exchange_doubles(kMaxCoopGroups, (int)J_max));
-    if (e == hipSuccess) e = al((void**)&h->xy_dev, sizeof(float) * 2 * (size_t)I_max);
-    if (e == hipSuccess) e = al((void**)&h->xy_rrh, sizeof(float) * 2 * (size_t)J_max);
-    if (e == hipSuccess) e = al((void**)&h->s_all, I8);
-    if (e == hipSuccess) e = al((void**)&h->s_ex, I8);
-    if (e == hipSuccess) e = al((void**)&h->j1, sizeof(int) * (size_t)I_max);
+    if (e == hipSuccess) {
+        char* base = (char*)h->ws;
+        auto at = [&](int k) { return (void*)(base + wl.off[k]); };
+        h->a = (double*)at(kWsA);
+        h->la = (double*)at(kWsLa);
+        h->b = (double*)at(kWsB);
+        h->f[0] = (double*)at(kWsF0);
+        h->f[1] = (double*)at(kWsF1);
+        h->g[0] = (double*)at(kWsG0);
+        h->g[1] = (double*)at(kWsG1);
+        h->col_part = (double*)at(kWsColPart);
+        h->res_part = (double*)at(kWsResPart);
+        h->stat_part = (double*)at(kWsStatPart);
+        h->cpart = (double*)at(kWsCpart);
+        h->ctl = (Ctl*)at(kWsCtl);
+        h->prm = (SolveParams*)at(kWsPrm);
+        h->bad = (int*)at(kWsBad);
+        h->hist = (unsigned long long*)at(kWsHist);
+        h->xch = (double*)at(kWsXch);
+        h->xy_dev = (float*)at(kWsXyDev);
+        h->xy_rrh = (float*)at(kWsXyRrh);
+        h->s_all = (double*)at(kWsSAll);
+        h->s_ex = (double*)at(kWsSEx);
+        h->j1 = (int*)at(kWsJ1);
+        h->scratch = at(kWsScratch);
+    }
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->ctl_h, 2 * sizeof(Ctl), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&h->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&h->ev_stop);
@@ -1083,6 +1211,7 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
     }
     Ctl c{};
     c.has_prev = warm_start ? 1 : 0;
+    c.check_every = h->opt.check_every;
     c.last_fp64 = 0;
     c.max_iter = max_iter;
     c.tol = tol;
@@ -1176,27 +1305,33 @@ ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
     if (mem != OT_MEM_HOST && mem != OT_MEM_DEVICE) return fail(h, OT_EINVAL, "bad memory space");
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
     const int64_t I = h->I, J = h->J;
-    const size_t bytes = (size_t)(I * J) * (dtype == OT_F32 ? 4 : 8);
-    void* dst = pi;
-    void* tmp = nullptr;
-    if (mem == OT_MEM_HOST) {
-        HIPCHK(h, hipMalloc(&tmp, bytes));
-        dst = tmp;
-    }
-    ot_status st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
-        using S = std::decay_t<decltype(src)>;
-        const Shape s = row64(make_shape<S>(h, I, J, vec_for<S>(J, ld_of(h->last), data)), J);
-        bool ok = dtype == OT_F32 ? launch_plan<S, float>(s, I, (int)J, h->f[h->res_par], h->g[h->res_par], h->prm, (float*)dst, src, h->stream)
-                                  : launch_plan<S, double>(s, I, (int)J, h->f[h->res_par], h->g[h->res_par], h->prm, (double*)dst, src, h->stream);
-        if (!ok) return fail(h, OT_EINVAL, "no plan kernel for this shape");
-        return OT_OK;
-    });
-    if (!st && mem == OT_MEM_HOST) {
-        hipError_t e = hipMemcpyAsync(pi, tmp, bytes, hipMemcpyDeviceToHost, h->stream);
-        if (e != hipSuccess) st = fail(h, OT_EDEVICE, "plan copy failed: %s", hipGetErrorString(e));
+    const size_t esz = dtype == OT_F32 ? 4 : 8;
+    // device memory: the whole plan in one launch. Host memory: blocks of
+    // rows through the handle's scratch region (nothing is allocated).
+    const int64_t block = mem == OT_MEM_DEVICE ? I : std::max<int64_t>(1, (int64_t)(ws_scratch_bytes(h->I_max, h->J_max) / (esz * (size_t)J)));
+    ot_status st = OT_OK;
+    for (int64_t r0 = 0; r0 < I && !st; r0 += block) {
+        const int64_t r1 = std::min(I, r0 + block);
+        void* dst = mem == OT_MEM_DEVICE ? pi : h->scratch;
+        st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
+            using S = std::decay_t<decltype(src)>;
+            const Shape s = row64(make_shape<S>(h, I, J, vec_for<S>(J, ld_of(h->last), data)), J);
+            const double* f = h->f[h->res_par];
+            const double* g = h->g[h->res_par];
+            bool ok = dtype == OT_F32 ? launch_plan<S, float>(s, r0, r1, (int)J, f, g, h->prm, (float*)dst, src, h->stream)
+                                      : launch_plan<S, double>(s, r0, r1, (int)J, f, g, h->prm, (double*)dst, src, h->stream);
+            if (!ok) return fail(h, OT_EINVAL, "no plan kernel for this shape");
+            return OT_OK;
+        });
+        if (!st && mem == OT_MEM_HOST) {
+            const size_t bytes = (size_t)((r1 - r0) * J) * esz;
+            hipError_t e = hipMemcpyAsync((char*)pi + (size_t)(r0 * J) * esz, h->scratch, bytes, hipMemcpyDeviceToHost,
+                                          h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the scratch is reused by the next block
+            if (e != hipSuccess) st = fail(h, OT_EDEVICE, "plan copy failed: %s", hipGetErrorString(e));
+        }
     }
     hipError_t e = hipStreamSynchronize(h->stream);
-    if (tmp) hipFree(tmp);
     if (!st && e != hipSuccess) st = fail(h, OT_EDEVICE, "plan failed: %s", hipGetErrorString(e));
     return st;
 }
@@ -1325,10 +1460,9 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
     const int64_t I = h->I, J = h->J;
     const int p = h->res_par;
-    double *fs = nullptr, *gs = nullptr;
-    HIPCHK(h, hipMalloc(&fs, sizeof(double) * I));
-    hipError_t e = hipMalloc(&gs, sizeof(double) * J);
-    if (e != hipSuccess) { hipFree(fs); return fail(h, OT_ENOMEM, "hipMalloc failed"); }
+    // the solve's potentials are parked in the scratch region meanwhile
+    double* fs = (double*)h->scratch;
+    double* gs = fs + h->I_max;
     std::vector<hipEvent_t> ev(2, nullptr);
     ot_status st = OT_OK;
     for (auto& x : ev)
@@ -1378,11 +1512,32 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
     }
     for (auto& x : ev)
         if (x) hipEventDestroy(x);
-    hipFree(fs);
-    hipFree(gs);
     return st;
 }
 
+
+ot_status ot_assoc_time_read(ot_assoc* h, const void* buf, size_t bytes, int32_t reps, double* ms_per_launch) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (!buf || !ms_per_launch || bytes < 16 || bytes % 16 != 0 || ((uintptr_t)buf % 16) != 0 || reps < 1 ||
+        reps > 4096)
+        return fail(h, OT_EINVAL, "time_read needs a 16-byte aligned buffer of a multiple of 16 bytes and reps in 1..4096");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    const size_t n16 = bytes / 16;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(1, h->num_cu) * 16,
+                                                                            (int64_t)((n16 + 255) / 256)));
+    uint32_t* sink = (uint32_t*)h->col_part;  // (written only for an impossible checksum)
+    HIPCHK(h, hipEventRecord(h->ev_start, h->stream));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(k_read_stream, dim3(grid), dim3(256), 0, h->stream, (const u32x4*)buf, n16, sink);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipEventRecord(h->ev_stop, h->stream));
+    HIPCHK(h, hipEventSynchronize(h->ev_stop));
+    float ms = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+    *ms_per_launch = (double)ms / reps;
+    return OT_OK;
+}
 
 ot_status ot_assoc_rrh_loads(ot_assoc* h, double* loads, ot_mem mem) {
     if (!h) return OT_EINVAL;
@@ -1460,9 +1615,7 @@ ot_status ot_assoc_maxsinr(ot_assoc* h, const ot_cost_desc* cost, const double* 
     const int nb = (int)((I + rpb - 1) / rpb);
     int32_t* assoc_d = nullptr;
     if (assoc && cost->mem == OT_MEM_DEVICE) assoc_d = assoc;
-    else if (assoc) {
-        HIPCHK(h, hipMalloc(&assoc_d, sizeof(int32_t) * (size_t)std::max<int64_t>(I, 1)));
-    }
+    else if (assoc) assoc_d = (int32_t*)h->scratch;  // (I_max int32 fit in the scratch region)
     st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
         using S = std::decay_t<decltype(src)>;
         const size_t lds = sizeof(double) * (size_t)S::kStageDoubles * (size_t)J + 8;
@@ -1479,7 +1632,6 @@ ot_status ot_assoc_maxsinr(ot_assoc* h, const ot_cost_desc* cost, const double* 
             st = copy_out(h, assoc, assoc_d, sizeof(int32_t) * (size_t)I, OT_MEM_HOST);
     }
     hipError_t e = hipStreamSynchronize(h->stream);
-    if (assoc_d && assoc_d != assoc) hipFree(assoc_d);
     if (st) return st;
     if (e != hipSuccess) return fail(h, OT_EDEVICE, "maxSINR kernels failed: %s", hipGetErrorString(e));
     return OT_OK;
@@ -1503,18 +1655,12 @@ ot_status ot_assoc_adaptive(ot_assoc* h, const ot_cost_desc* cost, const double*
     const double d = delta > 0.0 ? delta : 0.01 * mass / J;
     // device copies reused by every solve: a, q, the best potentials; a
     // host-memory matrix is staged once and then referenced
-    double *a_d = nullptr, *q_d = nullptr, *fb = nullptr, *gb = nullptr;
-    auto release = [&]() {
-        hipFree(a_d);
-        hipFree(q_d);
-        hipFree(fb);
-        hipFree(gb);
-    };
-    if (hipMalloc(&a_d, sizeof(double) * I) != hipSuccess || hipMalloc(&q_d, sizeof(double) * J) != hipSuccess ||
-        hipMalloc(&fb, sizeof(double) * I) != hipSuccess || hipMalloc(&gb, sizeof(double) * J) != hipSuccess) {
-        release();
-        return fail(h, OT_ENOMEM, "adaptive: workspace allocation failed");
-    }
+    // (all four in the scratch region, which holds 2 (I_max + J_max) doubles)
+    double* a_d = (double*)h->scratch;
+    double* q_d = a_d + h->I_max;
+    double* fb = q_d + h->J_max;
+    double* gb = fb + h->I_max;
+    auto release = [&]() {};
     ot_cost_desc dc = *cost;
     auto failed = [&](ot_status s) {
         release();

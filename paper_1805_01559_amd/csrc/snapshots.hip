@@ -146,7 +146,7 @@ ot_status snap_reserve(ot_assoc* h, SnapState* s, int64_t I, int J) {
     add((void**)&s->cstat, 8 * (size_t)kSnapB * kMaxChunks * 5);
     add((void**)&s->cout, 8 * (size_t)kSnapB * 8);
     for (auto& p : parts) off += up(p.second, 256);
-    SCHK(hipMalloc(&s->mem, off));
+    SCHK(otk_host::dev_malloc((void**)&s->mem, off));
     off = 0;
     for (auto& p : parts) {
         *p.first = s->mem + off;
@@ -252,7 +252,7 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
         const void* src = cost->data;
         void* tmp = nullptr;
         if (cost->mem == OT_MEM_HOST) {
-            SCHK(hipMalloc(&tmp, esz * (size_t)(I * lds)));
+            SCHK(otk_host::dev_malloc((void**)&tmp, esz * (size_t)(I * lds)));
             SCHK(hipMemcpyAsync(tmp, cost->data, esz * (size_t)(I * lds), hipMemcpyHostToDevice, h->stream));
             src = tmp;
         }

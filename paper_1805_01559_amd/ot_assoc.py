@@ -30,8 +30,8 @@ OT_RESULT_PERSISTENT = 1
 
 # every symbol include/ot_assoc.h declares
 EXPORTS = [
-    "ot_assoc_default_options", "ot_assoc_create", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
-    "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep",
+    "ot_assoc_default_options", "ot_assoc_workspace_size", "ot_assoc_device_allocations", "ot_assoc_create", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
+    "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep", "ot_assoc_time_read",
     "ot_assoc_fast_phase_time", "ot_assoc_rrh_loads", "ot_assoc_evaluate", "ot_assoc_maxsinr", "ot_assoc_adaptive",
     "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_config",
     "ot_assoc_batch_potentials", "ot_assoc_solve_snapshots", "ot_assoc_snapshot_potentials",
@@ -56,7 +56,8 @@ class ot_assoc_options(ct.Structure):
     _fields_ = [("device", ct.c_int), ("stream", ct.c_void_p), ("precision", ct.c_int), ("polish_iters", ct.c_int),
                 ("chunk", ct.c_int), ("use_graphs", ct.c_int), ("sweep_blocks", ct.c_int), ("sweep_waves", ct.c_int),
                 ("sweep_rows", ct.c_int), ("sweep_lanes", ct.c_int), ("batch_tune", ct.c_int),
-                ("persistent", ct.c_int)]
+                ("persistent", ct.c_int), ("check_every", ct.c_int), ("workspace", ct.c_void_p),
+                ("workspace_bytes", ct.c_size_t)]
 
 
 class ot_assoc_result(ct.Structure):
@@ -109,6 +110,8 @@ def lib():
         vp, i64, d = ct.c_void_p, ct.c_int64, ct.c_double
         L.ot_assoc_default_options.argtypes = [ct.POINTER(ot_assoc_options)]
         L.ot_assoc_create.argtypes = [ct.POINTER(vp), i64, i64, ct.POINTER(ot_assoc_options)]
+        L.ot_assoc_workspace_size.argtypes = [i64, i64, ct.POINTER(ct.c_size_t)]
+        L.ot_assoc_device_allocations.argtypes = []
         L.ot_assoc_solve.argtypes = [vp, ct.POINTER(ot_cost_desc), vp, vp, d, d, ct.c_int32, ct.c_int,
                                      ct.POINTER(ot_assoc_result)]
         L.ot_assoc_plan.argtypes = [vp, vp, ct.c_int, ct.c_int]
@@ -117,6 +120,7 @@ def lib():
         L.ot_assoc_cost_median.argtypes = [vp, ct.POINTER(ot_cost_desc), ct.POINTER(d)]
         L.ot_assoc_materialize_cost.argtypes = [vp, ct.POINTER(ot_cost_desc), vp]
         L.ot_assoc_time_sweep.argtypes = [vp, ct.c_int32, ct.c_int, ct.POINTER(d)]
+        L.ot_assoc_time_read.argtypes = [vp, vp, ct.c_size_t, ct.c_int32, ct.POINTER(d)]
         L.ot_assoc_fast_phase_time.argtypes = [vp, ct.POINTER(d), ct.POINTER(ct.c_int32)]
         L.ot_assoc_rrh_loads.argtypes = [vp, vp, ct.c_int]
         L.ot_assoc_evaluate.argtypes = [vp, d, d, vp, vp, ct.c_int, ct.POINTER(ot_eval_result)]
@@ -151,8 +155,9 @@ def lib():
         L.ot_serve_destroy.restype = None
         for name in EXPORTS:
             if name not in ("ot_assoc_destroy", "ot_assoc_last_error", "ot_serve_now", "ot_serve_last_error",
-                            "ot_serve_destroy"):
+                            "ot_serve_destroy", "ot_assoc_device_allocations"):
                 getattr(L, name).restype = ct.c_int
+        L.ot_assoc_device_allocations.restype = ct.c_int64
         _lib = L
     return _lib
 
@@ -187,6 +192,16 @@ def ot_assoc_create(I_max: int, J_max: int, options: ot_assoc_options | None = N
     st = lib().ot_assoc_create(ct.byref(h), I_max, J_max, ct.byref(options) if options is not None else None)
     _check(None, st)
     return h
+
+
+def ot_assoc_workspace_size(I_max: int, J_max: int) -> int:
+    n = ct.c_size_t()
+    _check(None, lib().ot_assoc_workspace_size(I_max, J_max, ct.byref(n)))
+    return n.value
+
+
+def ot_assoc_device_allocations() -> int:
+    return int(lib().ot_assoc_device_allocations())
 
 
 def ot_assoc_solve(h, desc: ot_cost_desc, a_ptr, b_ptr, eps, tol, max_iter, warm_start=0):
@@ -552,6 +567,13 @@ class Solver:
     def time_sweep(self, reps=50, fp64=False):
         """Average ms of one fused-sweep launch of the last solve's shape."""
         return ot_assoc_time_sweep(self.h, reps, fp64)
+
+    def time_read(self, buf, reps=20):
+        """Average ms of a read-only streaming pass over a device tensor (the HBM read ceiling)."""
+        ms = ct.c_double()
+        _check(self.h, lib().ot_assoc_time_read(self.h, ct.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                                int(reps), ct.byref(ms)))
+        return ms.value
 
     def cost_median(self, desc):
         return ot_assoc_cost_median(self.h, desc)

@@ -71,14 +71,14 @@ def main():
         "# C = (1/R) / scale, eps = 0.01, Sinkhorn to a total marginal residual below 1e-12.",
         "# Written by make_large_reference.py (oracle and scenario generator only).",
         f"# host: {cpu_model()}, {os.cpu_count()} threads; cost {t1 - t0:.0f} s, solve {t2 - t1:.0f} s",
-        f"scale {scale!r}",
+        f"scale {float(scale)!r}",
         f"eps {EPS!r}",
         f"tol {TOL!r}",
         f"iterations {res.iters}",
-        f"residual {st['marginal_violation']!r}",
-        f"objective {st['objective']!r}",
-        f"reg_objective {st['reg_objective']!r}",
-        f"mass {st['mass']!r}",
+        f"residual {float(st['marginal_violation'])!r}",
+        f"objective {float(st['objective'])!r}",
+        f"reg_objective {float(st['reg_objective'])!r}",
+        f"mass {float(st['mass'])!r}",
         f"sample_seed {SAMPLE_SEED}",
         f"g {' '.join(repr(float(v)) for v in res.g)}",
         "# sampled rows: i f_i",

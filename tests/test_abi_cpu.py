@@ -46,7 +46,9 @@ def test_struct_layouts_match_the_header(tmp_path):
               "offsetof(ot_request, user_tag)", "sizeof(ot_completion)", "offsetof(ot_completion, result)",
               "offsetof(ot_completion, t_done)", "offsetof(ot_assoc_options, persistent)",
               "sizeof(ot_eval_result)", "offsetof(ot_eval_result, devices_overloaded)",
-              "sizeof(ot_adaptive_result)", "offsetof(ot_adaptive_result, delta)"]
+              "sizeof(ot_adaptive_result)", "offsetof(ot_adaptive_result, delta)",
+              "offsetof(ot_assoc_options, check_every)", "offsetof(ot_assoc_options, workspace)",
+              "offsetof(ot_assoc_options, workspace_bytes)"]
     fmt = " ".join(["%zu"] * len(fields))
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ot_assoc.h"\n'
                    'int main(void){printf("' + fmt + '\\n", ' + ", ".join(fields) + ');return 0;}\n')
@@ -59,14 +61,16 @@ def test_struct_layouts_match_the_header(tmp_path):
             A.ot_request.layout_key.offset, A.ot_request.user_tag.offset, ct.sizeof(A.ot_completion),
             A.ot_completion.result.offset, A.ot_completion.t_done.offset, A.ot_assoc_options.persistent.offset,
             ct.sizeof(A.ot_eval_result), A.ot_eval_result.devices_overloaded.offset,
-            ct.sizeof(A.ot_adaptive_result), A.ot_adaptive_result.delta.offset]
+            ct.sizeof(A.ot_adaptive_result), A.ot_adaptive_result.delta.offset,
+            A.ot_assoc_options.check_every.offset, A.ot_assoc_options.workspace.offset,
+            A.ot_assoc_options.workspace_bytes.offset]
     assert got == want
 
 
 def test_default_options(lib):
     o = A.ot_assoc_default_options()
-    assert (o.device, o.precision, o.polish_iters, o.chunk, o.use_graphs, o.batch_tune, o.persistent) == \
-        (0, A.OT_PREC_FP32, 1, 8, 1, 1, 1)
+    assert (o.device, o.precision, o.polish_iters, o.chunk, o.use_graphs, o.batch_tune, o.persistent,
+            o.check_every, o.workspace, o.workspace_bytes) == (0, A.OT_PREC_FP32, 1, 8, 1, 1, 1, 1, None, 0)
     s = A.ot_serve_default_options()
     assert (s.polish_iters, s.sweep_waves, s.rows_per_part, s.max_slots, s.budget_bytes) == (1, 8, 128, 0, 0.0)
 
@@ -89,6 +93,29 @@ def test_batch_and_serve_argument_errors_without_a_device(lib):
         A.ot_serve_create(o)
     lib.ot_serve_destroy(None)
     assert lib.ot_serve_now() > 0.0
+
+
+def test_workspace_size_without_a_device(lib):
+    # pure host arithmetic: grows with the instance, 256-byte granular, rejects bad sizes
+    small = A.ot_assoc_workspace_size(1000, 50)
+    big = A.ot_assoc_workspace_size(20000, 400)
+    assert 0 < small < big and small % 256 == 0 and big % 256 == 0
+    # at least the potentials (two parities), marginals and the scratch region
+    assert big >= 8 * (2 * 20000 + 2 * 400 + 20000 + 400 + 2 * (20000 + 400))
+    for I, J in [(0, 10), (10, 0), (10, 5000)]:
+        with pytest.raises(A.OTError):
+            A.ot_assoc_workspace_size(I, J)
+    assert A.ot_assoc_device_allocations() >= 0
+    # a workspace size without a workspace is rejected before any device is touched
+    o = A.ot_assoc_default_options()
+    o.workspace_bytes = 4096
+    with pytest.raises(A.OTError) as e:
+        A.ot_assoc_create(10, 10, o)
+    assert e.value.status == A.OT_EINVAL
+    o = A.ot_assoc_default_options()
+    o.check_every = -1
+    with pytest.raises(A.OTError):
+        A.ot_assoc_create(10, 10, o)
 
 
 def test_argument_errors_without_a_device(lib):
