@@ -169,7 +169,7 @@ ot_status ot_assoc_default_options(ot_assoc_options *opt);
 /* Bytes of caller workspace (ot_assoc_options.workspace) a handle for
  * instances up to I_max x J_max needs: the O(I_max + J_max) vectors, the
  * per-workgroup partials, the cooperative phase's exchange block and a
- * scratch region of 2 (I_max + J_max) doubles. Pure host arithmetic (no
+ * work region of 2 (I_max + J_max) doubles. Pure host arithmetic (no
  * device is touched). Errors: OT_EINVAL for sizes out of range or NULL. */
 ot_status ot_assoc_workspace_size(int64_t I_max, int64_t J_max, size_t *bytes);
 
@@ -198,6 +198,28 @@ ot_status ot_assoc_create(ot_assoc **h, int64_t I_max, int64_t J_max, const ot_a
  * `out` may be NULL. */
 ot_status ot_assoc_solve(ot_assoc *h, const ot_cost_desc *cost, const double *a, const double *b, double eps,
                          double tol, int32_t max_iter, int warm_start, ot_assoc_result *out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * ot_assoc_solve for a dense FP32 cost in device memory, with no handle. It
+ * allocates nothing: every device buffer of the solve (potentials of both
+ * parities, workgroup partials, the cooperative exchange block, the control
+ * block) lives in a fixed array of about 9 MiB that the library holds on each
+ * GPU it runs on until the process ends; the caller passes inputs and outputs.
+ * Limits: 1 <= I <= 32768, 1 <= J <= 512 (larger instances give OT_EINVAL).
+ *   device, stream: the GPU and the hipStream_t (NULL: the legacy default stream).
+ *   C: I x ld FP32 row-major in device memory (ld = 0 means J); a (I), b (J):
+ *   FP64 device marginals; f (I), g (J): FP64 device outputs, the potentials
+ *   of the returned iterate (with warm_start != 0 also the starting potentials).
+ *   eps, tol, max_iter and the validation are those of ot_assoc_solve; `out`
+ *   (host, may be NULL) gets the result with seconds = 0 (no timing events).
+ * Calls on one GPU share the array: calls that overlap on one GPU (several
+ * host threads, or streams not ordered with each other) race and must be
+ * serialised by the caller. Each call rewrites every part of the array it
+ * reads. Errors: as ot_assoc_solve; the message is ot_assoc_last_error(NULL). */
+ot_status ot_assoc_solve_static(int device, void *stream, const float *C, int64_t I, int64_t J, int64_t ld,
+                                const double *a, const double *b, double eps, double tol, int32_t max_iter,
+                                int warm_start, double *f, double *g, ot_assoc_result *out);
 
 /* Writes the plan pi_ij = exp((f_i + g_j - C_ij) / eps) of the last
  * successful solve (the output step of the Sinkhorn algorithm) into the
@@ -337,7 +359,8 @@ void ot_assoc_destroy(ot_assoc *h);
 
 /* Human-readable description of the last error on this handle ("" if none).
  * The string is owned by the handle and valid until its next call. With
- * h == NULL it describes the last failed ot_assoc_create on this thread. */
+ * h == NULL it describes the last failed ot_assoc_create or
+ * ot_assoc_solve_static on this thread. */
 const char *ot_assoc_last_error(const ot_assoc *h);
 
 /* ------------------------------------------------------------ batched solves

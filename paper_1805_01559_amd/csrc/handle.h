@@ -72,7 +72,7 @@ struct ot_assoc {
     size_t stage_bytes = 0;
     bool stage_in_ws = false;  // the stage is the tail of a caller's workspace (never freed or grown)
     void* ws = nullptr;        // the single device block all fixed buffers are carved from
-    void* scratch = nullptr;   // 2 (I_max + J_max) doubles of per-call scratch (plan blocks, timers, Alg. 2)
+    void* work = nullptr;      // 2 (I_max + J_max) doubles of per-call work space (plan blocks, timers, Alg. 2)
     bool ws_owned = false;     // allocated by the library (else the caller's workspace)
     // pinned host mirrors
     otk::Ctl* ctl_h = nullptr;  // 2 slots
@@ -88,6 +88,7 @@ struct ot_assoc {
     const void* cost_dev = nullptr;  // device copy (host inputs) or the caller's device matrix
     bool retained = false;     // the handle still holds the cost of the last solve
     std::string err;
+    char* err_fixed = nullptr;  // if set, errors are written here (512 bytes) instead of `err`
     BatchEngine* batch = nullptr;  // engine of ot_assoc_solve_batch, created on first use
     SnapState* snap = nullptr;     // buffers and results of the last snapshot solve
 };

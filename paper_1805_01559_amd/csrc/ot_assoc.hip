@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -36,7 +37,9 @@ using namespace otk;
 
 namespace {
 
-thread_local std::string g_create_error;
+// handle-less errors (ot_assoc_create, ot_assoc_solve_static): a fixed
+// per-thread buffer, so that reporting one allocates nothing
+thread_local char g_noh_err[512];
 
 constexpr int kMaxNb = 1024;    // workgroups per sweep (partial rows)
 constexpr int kMaxJ = 2048;     // RRHs per instance
@@ -50,15 +53,15 @@ using otk_host::GraphEntry;
 constexpr int kWsAlign = 256;
 enum {
     kWsA, kWsLa, kWsB, kWsF0, kWsF1, kWsG0, kWsG1, kWsColPart, kWsResPart, kWsStatPart, kWsCpart, kWsCtl, kWsPrm,
-    kWsBad, kWsHist, kWsXch, kWsXyDev, kWsXyRrh, kWsSAll, kWsSEx, kWsJ1, kWsScratch, kWsCount
+    kWsBad, kWsHist, kWsXch, kWsXyDev, kWsXyRrh, kWsSAll, kWsSEx, kWsJ1, kWsWork, kWsCount
 };
 struct WsLayout {
     size_t off[kWsCount];
     size_t total;
 };
-// Bytes of the per-solve scratch region: the plan's and the timers' copies of
+// Bytes of the per-call work region: the plan's and the timers' copies of
 // the potentials (I_max + J_max doubles each).
-inline size_t ws_scratch_bytes(int64_t I_max, int64_t J_max) { return sizeof(double) * 2 * (size_t)(I_max + J_max); }
+inline size_t ws_work_bytes(int64_t I_max, int64_t J_max) { return sizeof(double) * 2 * (size_t)(I_max + J_max); }
 
 void ws_layout(int64_t I_max, int64_t J_max, WsLayout& L) {
     const size_t I8 = sizeof(double) * (size_t)I_max, J8 = sizeof(double) * (size_t)J_max;
@@ -78,7 +81,7 @@ void ws_layout(int64_t I_max, int64_t J_max, WsLayout& L) {
     sz[kWsXyRrh] = sizeof(float) * 2 * (size_t)J_max;
     sz[kWsSAll] = I8; sz[kWsSEx] = I8;
     sz[kWsJ1] = sizeof(int) * (size_t)I_max;
-    sz[kWsScratch] = ws_scratch_bytes(I_max, J_max);
+    sz[kWsWork] = ws_work_bytes(I_max, J_max);
     size_t o = 0;
     for (int k = 0; k < kWsCount; ++k) {
         L.off[k] = o;
@@ -88,6 +91,36 @@ void ws_layout(int64_t I_max, int64_t J_max, WsLayout& L) {
 }
 
 std::atomic<long long> g_dev_allocs{0};
+
+// Points the handle's fixed buffers into the block `ws` (layout wl).
+void carve_ws(ot_assoc* h, void* ws, const WsLayout& wl) {
+    {
+        char* base = (char*)ws;
+        auto at = [&](int k) { return (void*)(base + wl.off[k]); };
+        h->a = (double*)at(kWsA);
+        h->la = (double*)at(kWsLa);
+        h->b = (double*)at(kWsB);
+        h->f[0] = (double*)at(kWsF0);
+        h->f[1] = (double*)at(kWsF1);
+        h->g[0] = (double*)at(kWsG0);
+        h->g[1] = (double*)at(kWsG1);
+        h->col_part = (double*)at(kWsColPart);
+        h->res_part = (double*)at(kWsResPart);
+        h->stat_part = (double*)at(kWsStatPart);
+        h->cpart = (double*)at(kWsCpart);
+        h->ctl = (Ctl*)at(kWsCtl);
+        h->prm = (SolveParams*)at(kWsPrm);
+        h->bad = (int*)at(kWsBad);
+        h->hist = (unsigned long long*)at(kWsHist);
+        h->xch = (double*)at(kWsXch);
+        h->xy_dev = (float*)at(kWsXyDev);
+        h->xy_rrh = (float*)at(kWsXyRrh);
+        h->s_all = (double*)at(kWsSAll);
+        h->s_ex = (double*)at(kWsSEx);
+        h->j1 = (int*)at(kWsJ1);
+        h->work = at(kWsWork);
+    }
+}
 
 }  // namespace
 
@@ -109,8 +142,9 @@ ot_status fail(ot_assoc* h, ot_status st, const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (h) h->err = buf;
-    else g_create_error = buf;
+    if (h && h->err_fixed) std::memcpy(h->err_fixed, buf, sizeof buf);
+    else if (h) h->err = buf;
+    else std::memcpy(g_noh_err, buf, sizeof buf);
     return st;
 }
 
@@ -666,14 +700,17 @@ struct Solver {
         return OT_OK;
     }
 
+    // (a handle without events, the no-allocation entry point's, waits for
+    // the whole stream instead)
     ot_status snapshot(int slot) {
         HIPCHK(h, hipGetLastError());
         HIPCHK(h, hipMemcpyAsync(&h->ctl_h[slot], h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(h, hipEventRecord(h->ev_slot[slot], h->stream));
+        if (h->ev_slot[slot]) HIPCHK(h, hipEventRecord(h->ev_slot[slot], h->stream));
         return OT_OK;
     }
     ot_status wait(int slot) {
-        HIPCHK(h, hipEventSynchronize(h->ev_slot[slot]));
+        if (h->ev_slot[slot]) HIPCHK(h, hipEventSynchronize(h->ev_slot[slot]));
+        else HIPCHK(h, hipStreamSynchronize(h->stream));
         return OT_OK;
     }
 
@@ -822,7 +859,7 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
                        h->xch, nx, h->ctl);
     Src sv = src;
     void* args[] = {(void*)&A, (void*)&sv};
-    HIPCHK(h, hipEventRecord(h->ev_coop[0], h->stream));
+    if (h->ev_coop[0]) HIPCHK(h, hipEventRecord(h->ev_coop[0], h->stream));
     const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)p.nb), dim3(kPersistWaves * 64), args,
                                                     (unsigned)p.lds, h->stream);
     if (e == hipErrorCooperativeLaunchTooLarge) {
@@ -830,7 +867,7 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
         return OT_OK;
     }
     HIPCHK(h, e);
-    HIPCHK(h, hipEventRecord(h->ev_coop[1], h->stream));
+    if (h->ev_coop[1]) HIPCHK(h, hipEventRecord(h->ev_coop[1], h->stream));
     launched = true;
     return OT_OK;
 }
@@ -1020,6 +1057,21 @@ ot_status copy_out(ot_assoc* h, void* dst, const void* src_dev, size_t bytes, ot
 
 }  // namespace
 
+// ------------------------------------------- no-allocation solve support --
+// ot_assoc_solve_static keeps every device buffer of a solve in this array
+// (one copy per GPU, held until the process ends). Its layout is that of a
+// handle for kStaticIMax x kStaticJMax instances (ws_layout), about 8.5 MiB.
+namespace {
+constexpr int64_t kStaticIMax = 32768, kStaticJMax = 512;
+constexpr size_t kStaticScratchBytes = (size_t)9 << 20;
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kStaticMaxDevices] = {};  // the array's device address, per device
+thread_local Ctl g_static_ctl[2];             // host mirror of the control block (pageable)
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 // =================================================================== C ABI ==
 extern "C" {
 
@@ -1048,7 +1100,7 @@ ot_status ot_assoc_workspace_size(int64_t I_max, int64_t J_max, size_t* bytes) {
 
 int64_t ot_assoc_device_allocations(void) { return g_dev_allocs.load(std::memory_order_relaxed); }
 
-const char* ot_assoc_last_error(const ot_assoc* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+const char* ot_assoc_last_error(const ot_assoc* h) { return h ? h->err.c_str() : g_noh_err; }
 
 void ot_assoc_destroy(ot_assoc* h) {
     if (!h) return;
@@ -1132,32 +1184,7 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
         e = otk_host::dev_malloc(&h->ws, wl.total);
         h->ws_owned = (e == hipSuccess);
     }
-    if (e == hipSuccess) {
-        char* base = (char*)h->ws;
-        auto at = [&](int k) { return (void*)(base + wl.off[k]); };
-        h->a = (double*)at(kWsA);
-        h->la = (double*)at(kWsLa);
-        h->b = (double*)at(kWsB);
-        h->f[0] = (double*)at(kWsF0);
-        h->f[1] = (double*)at(kWsF1);
-        h->g[0] = (double*)at(kWsG0);
-        h->g[1] = (double*)at(kWsG1);
-        h->col_part = (double*)at(kWsColPart);
-        h->res_part = (double*)at(kWsResPart);
-        h->stat_part = (double*)at(kWsStatPart);
-        h->cpart = (double*)at(kWsCpart);
-        h->ctl = (Ctl*)at(kWsCtl);
-        h->prm = (SolveParams*)at(kWsPrm);
-        h->bad = (int*)at(kWsBad);
-        h->hist = (unsigned long long*)at(kWsHist);
-        h->xch = (double*)at(kWsXch);
-        h->xy_dev = (float*)at(kWsXyDev);
-        h->xy_rrh = (float*)at(kWsXyRrh);
-        h->s_all = (double*)at(kWsSAll);
-        h->s_ex = (double*)at(kWsSEx);
-        h->j1 = (int*)at(kWsJ1);
-        h->scratch = at(kWsScratch);
-    }
+    if (e == hipSuccess) carve_ws(h, h->ws, wl);
     if (e == hipSuccess) e = hipHostMalloc((void**)&h->ctl_h, 2 * sizeof(Ctl), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&h->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&h->ev_stop);
@@ -1179,8 +1206,10 @@ ot_status ot_assoc_create(ot_assoc** out, int64_t I_max, int64_t J_max, const ot
     return OT_OK;
 }
 
-ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a, const double* b, double eps,
-                         double tol, int32_t max_iter, int warm_start, ot_assoc_result* out) {
+// The body of ot_assoc_solve; also run by ot_assoc_solve_static on a handle
+// without events (then the device time is not measured: seconds = 0).
+static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double* a, const double* b, double eps,
+                            double tol, int32_t max_iter, int warm_start, ot_assoc_result* out) {
     if (!h) return OT_EINVAL;
     h->err.clear();
     ot_status st = validate_desc(h, cost);
@@ -1196,7 +1225,7 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
     // marginals, constants and the initial control block are set up and
     // checked on the device (no host round trip before the first sweep)
     const int res_par_prev = h->res_par;
-    HIPCHK(h, hipEventRecord(h->ev_start, h->stream));
+    if (h->ev_start) HIPCHK(h, hipEventRecord(h->ev_start, h->stream));
     const double* a_src = a;
     const double* b_src = b;
     if (cost->mem == OT_MEM_HOST) {
@@ -1247,10 +1276,14 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
         h->retained = false;
         return st;
     }
-    HIPCHK(h, hipEventRecord(h->ev_stop, h->stream));
-    HIPCHK(h, hipEventSynchronize(h->ev_stop));
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, h->ev_start, h->ev_stop);
+    if (h->ev_start) {
+        HIPCHK(h, hipEventRecord(h->ev_stop, h->stream));
+        HIPCHK(h, hipEventSynchronize(h->ev_stop));
+        hipEventElapsedTime(&ms, h->ev_start, h->ev_stop);
+    } else {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
     HIPCHK(h, hipGetLastError());
 
     if (fin.input_bad) {  // rejected on the device: the handle keeps no result
@@ -1296,6 +1329,89 @@ ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a,
     return rs;
 }
 
+ot_status ot_assoc_solve(ot_assoc* h, const ot_cost_desc* cost, const double* a, const double* b, double eps,
+                         double tol, int32_t max_iter, int warm_start, ot_assoc_result* out) {
+    return solve_impl(h, cost, a, b, eps, tol, max_iter, warm_start, out);
+}
+
+ot_status ot_assoc_solve_static(int device, void* stream, const float* C, int64_t I, int64_t J, int64_t ld,
+                                const double* a, const double* b, double eps, double tol, int32_t max_iter,
+                                int warm_start, double* f, double* g, ot_assoc_result* out) {
+    if (!C || !a || !b || !f || !g) return fail(nullptr, OT_EINVAL, "a device pointer is NULL");
+    if (I < 1 || J < 1 || I > kStaticIMax || J > kStaticJMax)
+        return fail(nullptr, OT_EINVAL, "instance %lld x %lld is outside 1..%lld x 1..%lld, the static scratch maximum",
+                    (long long)I, (long long)J, (long long)kStaticIMax, (long long)kStaticJMax);
+    if (ld != 0 && ld < J) return fail(nullptr, OT_EINVAL, "row stride ld = %lld is below J = %lld", (long long)ld, (long long)J);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, OT_EDEVICE, "no HIP device");
+    if (device < 0 || device >= ndev || device >= kStaticMaxDevices)
+        return fail(nullptr, OT_EINVAL, "device %d out of range", device);
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, OT_EDEVICE, "hipSetDevice failed");
+    WsLayout wl;
+    ws_layout(kStaticIMax, kStaticJMax, wl);
+    if (wl.total > kStaticScratchBytes) return fail(nullptr, OT_EDEVICE, "static scratch below its layout");
+    // the array's address on this device, looked up once per device with the device current
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (!g_static_ptr[device]) {
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(nullptr, OT_EDEVICE, "hipGetSymbolAddress of the static scratch failed: %s",
+                            hipGetErrorString(e));
+            g_static_ptr[device] = p;
+        }
+        base = g_static_ptr[device];
+    }
+    // a handle on the stack: buffers in the static array, no events, no
+    // graphs, the host mirror of the control block in pageable memory
+    ot_assoc h;
+    ot_assoc_default_options(&h.opt);
+    h.opt.device = device;
+    h.opt.stream = stream;
+    h.opt.use_graphs = 0;
+    h.device = device;
+    if (hipDeviceGetAttribute(&h.num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) h.num_cu = 0;
+    if (hipDeviceGetAttribute(&h.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) h.lds_max = 0;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) h.lds_max = 0;
+    h.stream = (hipStream_t)stream;
+    h.I_max = kStaticIMax;
+    h.J_max = kStaticJMax;
+    h.ws = base;
+    h.ws_owned = false;
+    carve_ws(&h, base, wl);
+    h.ctl_h = g_static_ctl;
+    h.err_fixed = g_noh_err;
+    g_noh_err[0] = 0;
+    if (warm_start) {  // the caller's f, g are the starting potentials
+        HIPCHK(&h, hipMemcpyAsync(h.f[0], f, sizeof(double) * (size_t)I, hipMemcpyDeviceToDevice, h.stream));
+        HIPCHK(&h, hipMemcpyAsync(h.g[0], g, sizeof(double) * (size_t)J, hipMemcpyDeviceToDevice, h.stream));
+        h.have_pot = true;
+        h.I = I;
+        h.J = J;
+        h.res_par = 0;
+    }
+    ot_cost_desc d{};
+    d.kind = OT_COST_DENSE;
+    d.I = I;
+    d.J = J;
+    d.mem = OT_MEM_DEVICE;
+    d.dtype = OT_F32;
+    d.data = C;
+    d.ld = ld;
+    ot_assoc_result r{};
+    const ot_status st = solve_impl(&h, &d, a, b, eps, tol, max_iter, warm_start, &r);
+    if (st >= 0) {
+        HIPCHK(&h, hipMemcpyAsync(f, h.f[h.res_par], sizeof(double) * (size_t)I, hipMemcpyDeviceToDevice, h.stream));
+        HIPCHK(&h, hipMemcpyAsync(g, h.g[h.res_par], sizeof(double) * (size_t)J, hipMemcpyDeviceToDevice, h.stream));
+        HIPCHK(&h, hipStreamSynchronize(h.stream));
+    }
+    if (out && (st >= 0 || st == OT_ENUMERIC)) *out = r;
+    return st;
+}
+
 ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
     if (!h) return OT_EINVAL;
     h->err.clear();
@@ -1307,12 +1423,12 @@ ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
     const int64_t I = h->I, J = h->J;
     const size_t esz = dtype == OT_F32 ? 4 : 8;
     // device memory: the whole plan in one launch. Host memory: blocks of
-    // rows through the handle's scratch region (nothing is allocated).
-    const int64_t block = mem == OT_MEM_DEVICE ? I : std::max<int64_t>(1, (int64_t)(ws_scratch_bytes(h->I_max, h->J_max) / (esz * (size_t)J)));
+    // rows through the handle's work region (nothing is allocated).
+    const int64_t block = mem == OT_MEM_DEVICE ? I : std::max<int64_t>(1, (int64_t)(ws_work_bytes(h->I_max, h->J_max) / (esz * (size_t)J)));
     ot_status st = OT_OK;
     for (int64_t r0 = 0; r0 < I && !st; r0 += block) {
         const int64_t r1 = std::min(I, r0 + block);
-        void* dst = mem == OT_MEM_DEVICE ? pi : h->scratch;
+        void* dst = mem == OT_MEM_DEVICE ? pi : h->work;
         st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
             using S = std::decay_t<decltype(src)>;
             const Shape s = row64(make_shape<S>(h, I, J, vec_for<S>(J, ld_of(h->last), data)), J);
@@ -1325,9 +1441,9 @@ ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
         });
         if (!st && mem == OT_MEM_HOST) {
             const size_t bytes = (size_t)((r1 - r0) * J) * esz;
-            hipError_t e = hipMemcpyAsync((char*)pi + (size_t)(r0 * J) * esz, h->scratch, bytes, hipMemcpyDeviceToHost,
+            hipError_t e = hipMemcpyAsync((char*)pi + (size_t)(r0 * J) * esz, h->work, bytes, hipMemcpyDeviceToHost,
                                           h->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the scratch is reused by the next block
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the work region is reused by the next block
             if (e != hipSuccess) st = fail(h, OT_EDEVICE, "plan copy failed: %s", hipGetErrorString(e));
         }
     }
@@ -1460,8 +1576,8 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
     const int64_t I = h->I, J = h->J;
     const int p = h->res_par;
-    // the solve's potentials are parked in the scratch region meanwhile
-    double* fs = (double*)h->scratch;
+    // the solve's potentials are parked in the work region meanwhile
+    double* fs = (double*)h->work;
     double* gs = fs + h->I_max;
     std::vector<hipEvent_t> ev(2, nullptr);
     ot_status st = OT_OK;
@@ -1615,7 +1731,7 @@ ot_status ot_assoc_maxsinr(ot_assoc* h, const ot_cost_desc* cost, const double* 
     const int nb = (int)((I + rpb - 1) / rpb);
     int32_t* assoc_d = nullptr;
     if (assoc && cost->mem == OT_MEM_DEVICE) assoc_d = assoc;
-    else if (assoc) assoc_d = (int32_t*)h->scratch;  // (I_max int32 fit in the scratch region)
+    else if (assoc) assoc_d = (int32_t*)h->work;  // (I_max int32 fit in the work region)
     st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
         using S = std::decay_t<decltype(src)>;
         const size_t lds = sizeof(double) * (size_t)S::kStageDoubles * (size_t)J + 8;
@@ -1655,8 +1771,8 @@ ot_status ot_assoc_adaptive(ot_assoc* h, const ot_cost_desc* cost, const double*
     const double d = delta > 0.0 ? delta : 0.01 * mass / J;
     // device copies reused by every solve: a, q, the best potentials; a
     // host-memory matrix is staged once and then referenced
-    // (all four in the scratch region, which holds 2 (I_max + J_max) doubles)
-    double* a_d = (double*)h->scratch;
+    // (all four in the work region, which holds 2 (I_max + J_max) doubles)
+    double* a_d = (double*)h->work;
     double* q_d = a_d + h->I_max;
     double* fb = q_d + h->J_max;
     double* gb = fb + h->I_max;

@@ -30,7 +30,8 @@ OT_RESULT_PERSISTENT = 1
 
 # every symbol include/ot_assoc.h declares
 EXPORTS = [
-    "ot_assoc_default_options", "ot_assoc_workspace_size", "ot_assoc_device_allocations", "ot_assoc_create", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
+    "ot_assoc_default_options", "ot_assoc_workspace_size", "ot_assoc_device_allocations", "ot_assoc_create",
+    "ot_assoc_solve_static", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
     "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep", "ot_assoc_time_read",
     "ot_assoc_fast_phase_time", "ot_assoc_rrh_loads", "ot_assoc_evaluate", "ot_assoc_maxsinr", "ot_assoc_adaptive",
     "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_config",
@@ -114,6 +115,8 @@ def lib():
         L.ot_assoc_device_allocations.argtypes = []
         L.ot_assoc_solve.argtypes = [vp, ct.POINTER(ot_cost_desc), vp, vp, d, d, ct.c_int32, ct.c_int,
                                      ct.POINTER(ot_assoc_result)]
+        L.ot_assoc_solve_static.argtypes = [ct.c_int, vp, vp, i64, i64, i64, vp, vp, d, d, ct.c_int32, ct.c_int, vp,
+                                            vp, ct.POINTER(ot_assoc_result)]
         L.ot_assoc_plan.argtypes = [vp, vp, ct.c_int, ct.c_int]
         L.ot_assoc_potentials.argtypes = [vp, vp, vp, ct.c_int]
         L.ot_assoc_set_potentials.argtypes = [vp, vp, vp, i64, i64, ct.c_int]
@@ -209,6 +212,22 @@ def ot_assoc_solve(h, desc: ot_cost_desc, a_ptr, b_ptr, eps, tol, max_iter, warm
     st = lib().ot_assoc_solve(h, ct.byref(desc), a_ptr, b_ptr, float(eps), float(tol), int(max_iter), int(warm_start),
                               ct.byref(res))
     _check(h, st)
+    return st, res
+
+
+def ot_assoc_solve_static(C, a, b, f, g, eps, tol, max_iter, warm_start=0, device=0, stream=None, J=None):
+    """The no-allocation solve. C is an (I, ld) FP32 torch device tensor whose
+    first J columns (default: all) are the cost; a, b, f, g are FP64 device
+    tensors of I, J, I, J elements; f and g receive the potentials (and hold
+    the starting ones when warm_start). Returns (status, result)."""
+    I, ld = int(C.shape[0]), int(C.shape[1])
+    J = ld if J is None else int(J)
+    res = ot_assoc_result()
+    st = lib().ot_assoc_solve_static(int(device), stream, ct.c_void_p(C.data_ptr()), I, J, ld,
+                                     ct.c_void_p(a.data_ptr()), ct.c_void_p(b.data_ptr()), float(eps), float(tol),
+                                     int(max_iter), int(warm_start), ct.c_void_p(f.data_ptr()),
+                                     ct.c_void_p(g.data_ptr()), ct.byref(res))
+    _check(None, st)
     return st, res
 
 

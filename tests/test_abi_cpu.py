@@ -106,6 +106,8 @@ def test_workspace_size_without_a_device(lib):
         with pytest.raises(A.OTError):
             A.ot_assoc_workspace_size(I, J)
     assert A.ot_assoc_device_allocations() >= 0
+    # the no-allocation solve keeps a handle's buffers for 32768 x 512 in its fixed 9 MiB array
+    assert A.ot_assoc_workspace_size(32768, 512) <= 9 << 20
     # a workspace size without a workspace is rejected before any device is touched
     o = A.ot_assoc_default_options()
     o.workspace_bytes = 4096

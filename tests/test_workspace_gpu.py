@@ -50,7 +50,7 @@ def test_torch_workspace_solve_allocates_nothing(A, cran, oracle_lib):
         f, g = s.potentials()
         Pd = torch.empty((L.I, L.J), dtype=torch.float32, device=dev)
         s.plan(Pd)
-        Ph = s.plan(np.empty((L.I, L.J), dtype=np.float64))  # host plan: blocks through the scratch region
+        Ph = s.plan(np.empty((L.I, L.J), dtype=np.float64))  # host plan: blocks through the work region
         loads = s.rrh_loads()
         st2, res2 = s.solve_dense(Cd, ad, bd, eps, tol, 2000, warm_start=True)
         assert A.ot_assoc_device_allocations() == n0, "a call on a workspace handle allocated device memory"
