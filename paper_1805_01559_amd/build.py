@@ -23,7 +23,8 @@ FLAGS = [
 
 
 def sources():
-    return [os.path.join(CSRC, f) for f in ("ot_assoc.hip", "batch.hip", "snapshots.hip")]
+    return [os.path.join(CSRC, f) for f in ("ot_assoc.hip", "launch_dense.hip", "launch_rates.hip", "launch_geo.hip",
+                                            "batch.hip", "snapshots.hip")]
 
 
 def _compile(src: str, obj: str, inc: str):

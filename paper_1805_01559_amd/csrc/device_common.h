@@ -74,6 +74,31 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 }
 __device__ __forceinline__ float readlane_f(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
 
+// Pair sums across lanes with gfx950's row swaps (v_permlane16_swap,
+// v_permlane32_swap: VALU moves) instead of LDS permutes. xor16_sum gives
+// every lane v[l] + v[l ^ 16] and xor32_sum v[l] + v[l ^ 32], with the lower
+// lane's value first in both lanes of a pair (so both hold the same bits).
+__device__ __forceinline__ double xor16_sum(double v) {
+    const long long b = __double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);  // lower lane's value
+    const double y = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);  // upper lane's value
+    return x + y;
+}
+__device__ __forceinline__ double xor32_sum(double v) {
+    const long long b = __double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+    const double y = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+    return x + y;
+}
+__device__ __forceinline__ float xor32_sum(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     v += dpp_d<0xB1>(v);
     v += dpp_d<0x4E>(v);
@@ -113,8 +138,8 @@ __device__ __forceinline__ double group_sum(double v) {
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x141>(v);
     v += dpp_d<0x140>(v);
-    if constexpr (LPR >= 32) v += __shfl_xor(v, 16, 64);
-    if constexpr (LPR >= 64) v += __shfl_xor(v, 32, 64);
+    if constexpr (LPR >= 32) v = xor16_sum(v);
+    if constexpr (LPR >= 64) v = xor32_sum(v);
     return v;
 }
 template <int LPR>

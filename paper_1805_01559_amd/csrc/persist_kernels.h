@@ -10,10 +10,10 @@
 //      residual of the previous iterate and the column partials of the
 //      half-iterate (FP32 exponentials, FP64 arguments, FP64 sums across
 //      lanes, rows and workgroups), published to an exchange buffer;
-//   2. workgroup w owns columns [w cpw, (w + 1) cpw): it collects their
-//      partials from every workgroup, sums them in a fixed order and
-//      publishes the new g_j; workgroup 0 also sums the residuals and
-//      publishes the stop decision;
+//   2. workgroup w owns the blocks of 8 consecutive columns w, w + nb, ...:
+//      it collects their partials from every workgroup, sums them in a fixed
+//      order and publishes the new g_j; workgroup 0 also sums the residuals
+//      and publishes the stop decision;
 //   3. every workgroup collects the new g and the decision.
 //
 // Only O(I + J) potentials and O(nb J) partials move per iteration; the
@@ -23,21 +23,18 @@
 // coherent with the other XCDs' L2s, and an agent-scope release writes a
 // whole L2 back; so every exchanged value is stored and loaded with
 // agent-scope relaxed atomics (stores that write through the L2, loads served
-// at the device's coherence point), and a reader simply polls each slot
-// until it no longer holds kEmpty, a signalling-NaN bit pattern that no
-// arithmetic produces (results that are NaN are quiet NaNs). Slots are
-// emptied again by their single reader before they are reused:
-//   * partials (2 buffers by iteration parity): the owner of column j
-//     empties its column after reading it; the producer writes it again two
-//     iterations later, after it has read a g that the owner published
-//     after the emptying stores had completed;
-//   * new g (3 buffers by iteration mod 3): at iteration k the owner of
-//     column j empties slot (k + 2) mod 3, whose value (iteration k - 1)
-//     every workgroup has read by then, and readers poll that slot only at
-//     iteration k + 2;
-//   * the decision word carries its iteration number and is never emptied.
-// "Completed" is made explicit: each owner waits for all its memory
-// operations (s_waitcnt vmcnt(0)) before it starts collecting an iteration.
+// at the device's coherence point), and a reader simply polls a slot until it
+// holds the value of the iteration it waits for. Every exchanged double
+// carries its iteration number modulo 4 in the two lowest mantissa bits (a
+// relative change below 2^-50, far under the FP32 phase's own rounding), so
+// slots are never emptied: buffers alternate by iteration parity, a slot's
+// previous content is from two iterations earlier (a different tag), and no
+// producer can get two iterations ahead of a reader (it needs every
+// workgroup's contribution of the iteration in between). The exchange is laid
+// out for the memory system: a producer's column partials are one contiguous
+// row (whole cache lines), the owner of eight consecutive columns reads whole
+// lines, and the new g and the stop decision are written in several replicas
+// so that the 256 polling workgroups do not all wait on the same lines.
 // Every poll is bounded: a workgroup that waits too long sets an abort word
 // that releases every other poller, and the launch ends with its control
 // block marked.
@@ -61,41 +58,59 @@ __device__ __forceinline__ uint64_t get_agent(const uint64_t* p) {
     return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-constexpr uint64_t kEmpty = 0x7FF4000000000BADull;  // signalling NaN with a payload
-__device__ __forceinline__ bool is_empty(double x) { return (uint64_t)__double_as_longlong(x) == kEmpty; }
-
-constexpr int kPollLoads = 4;                   // exchange slots per lane in one poll
-constexpr int kMaxCoopGroups = kPollLoads * kWave;  // workgroups a column owner can collect from
-
-// Layout of the exchange block (doubles):
-//   part  [2][J][nb]   column partials by iteration parity (a column's
-//                      partials are contiguous for its owner)
-//   rpart [2][nb]      row-residual partials by parity
-//   gx    [3][J]       new g by iteration mod 3
-//   dec   [2]          (iteration << 2) | stop, as uint64, by parity
-//   abort [1]          uint64, nonzero once a poll gave up
-__host__ __device__ inline size_t persist_exchange_doubles(int nb, int J) {
-    return (size_t)2 * nb * J + (size_t)2 * nb + (size_t)3 * J + 3;
+// Iteration tags in the two lowest mantissa bits of an exchanged double.
+__device__ __forceinline__ double tag_value(double v, int k) {
+    return __longlong_as_double((__double_as_longlong(v) & ~3ll) | (long long)(k & 3));
 }
+__device__ __forceinline__ bool has_tag(double v, int k) { return (__double_as_longlong(v) & 3) == (long long)(k & 3); }
 
-// Polls up to U slots per lane of one wave, slot u of lane l at
-// base[(u 64 + l) stride] for u 64 + l < n, until none is empty (all loads
-// of a round are in flight together); absent slots read 0. Returns false if
-// the wait gave up (bound reached or abort word set).
+constexpr int kColBlock = 8;        // columns per owner block: one 64-byte line of doubles
+constexpr int kReplicas = 8;        // copies of the new g and of the decision word
+constexpr int kMaxCoopGroups = 256; // workgroups of a cooperative launch (an owner polls 4 per thread)
+
+// Layout of the exchange block (offsets in doubles, each part 64-byte aligned):
+//   part  [2][nb][Jp]      column partials by iteration parity; a producer's
+//                          row is contiguous, Jp = J rounded up to kColBlock
+//   rpart [2][nb]          row-residual partials by parity (padded to a line)
+//   gx    [2][kReplicas][Gs]  new g by parity, Gs = Jp rounded up to 512 (4 KiB
+//                          between replicas)
+//   dec   [2][kReplicas][8]   (iteration << 2) | stop, as uint64, one line per replica
+//   abort [8]              uint64, nonzero once a poll gave up
+struct XchLayout {
+    int Jp, Gs;
+    size_t part, rpart, gx, dec, abort_, total;
+};
+__host__ __device__ inline XchLayout persist_xch_layout(int nb, int J) {
+    XchLayout L;
+    L.Jp = (J + kColBlock - 1) / kColBlock * kColBlock;
+    L.Gs = (L.Jp + 511) / 512 * 512;
+    L.part = 0;
+    L.rpart = L.part + (size_t)2 * nb * L.Jp;
+    L.gx = L.rpart + ((size_t)2 * nb + 7) / 8 * 8;
+    L.dec = L.gx + (size_t)2 * kReplicas * L.Gs;
+    L.abort_ = L.dec + (size_t)2 * kReplicas * 8;
+    L.total = L.abort_ + 8;
+    return L;
+}
+__host__ __device__ inline size_t persist_exchange_doubles(int nb, int J) { return persist_xch_layout(nb, J).total; }
+
+// Polls U tagged slots per lane of one wave (slot u of lane l at
+// base[(u 64 + l) stride] for u 64 + l < n) until each holds tag k; absent
+// slots read 0. Returns false if the wait gave up (bound reached or abort set).
 template <int U>
-__device__ bool poll_slots(const double* base, int64_t stride, int n, double (&x)[U], uint64_t* abort_word,
-                           int max_spin) {
+__device__ bool poll_tagged(const double* base, int64_t stride, int n, int k, double (&x)[U], uint64_t* abort_word,
+                            int max_spin) {
     const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int p = u * kWave + lane;
-        x[u] = p < n ? get_agent(base + (int64_t)p * stride) : 0.0;
+        x[u] = p < n ? get_agent(base + (int64_t)p * stride) : tag_value(0.0, k);
     }
     int spin = 0;
     for (;;) {
         bool pend = false;
 #pragma unroll
-        for (int u = 0; u < U; ++u) pend |= is_empty(x[u]);
+        for (int u = 0; u < U; ++u) pend |= !has_tag(x[u], k);
         if (!__any(pend)) return true;
         if ((++spin & 31) == 0 && (get_agent(abort_word) != 0 || spin > max_spin)) {
             put_agent(abort_word, (uint64_t)1);
@@ -105,26 +120,11 @@ __device__ bool poll_slots(const double* base, int64_t stride, int n, double (&x
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = u * kWave + lane;
-            if (is_empty(x[u])) x[u] = get_agent(base + (int64_t)p * stride);
+            if (!has_tag(x[u], k)) x[u] = get_agent(base + (int64_t)p * stride);
         }
     }
 }
 constexpr int kGPollLoads = 8;  // new-g slots per lane in one poll (512 columns)
-
-// Single-slot poll (one value per thread).
-__device__ bool poll_one(const double* p, double& x, uint64_t* abort_word, int max_spin) {
-    x = get_agent(p);
-    int spin = 0;
-    while (is_empty(x)) {
-        if ((++spin & 31) == 0 && (get_agent(abort_word) != 0 || spin > max_spin)) {
-            put_agent(abort_word, (uint64_t)1);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        x = get_agent(p);
-    }
-    return true;
-}
 
 // ------------------------------------------------------- persistent solve --
 struct PersistArgs {
@@ -133,7 +133,6 @@ struct PersistArgs {
     int Jp;   // LDS row stride of the cost tile (ncl * LPR; padding reads +inf)
     int ncl;  // cells per lane of a row: column q LPR + sub for q < ncl (<= CPL)
     int rpw;  // rows per workgroup: a whole number of wave steps
-    int cpw;  // columns per workgroup in the combine step
     int max_spin;
     double stall_below;
     const double* a;
@@ -150,7 +149,7 @@ struct PersistArgs {
 // vectors.
 __host__ __device__ inline size_t persist_lds_bytes(int rpw, int J, int Jp, int waves, int slack) {
     const size_t Jr2 = (size_t)((J + 1) & ~1), Jr4 = (size_t)((J + 3) & ~3);
-    return ((size_t)rpw * Jp + (size_t)slack) * 4 + Jr2 * 8 + 4 * (size_t)rpw * 8 + (size_t)waves * Jr4 * 4;
+    return ((size_t)rpw * Jp + (size_t)slack) * 4 + Jr2 * 8 + 6 * (size_t)rpw * 8 + (size_t)waves * Jr4 * 4;
 }
 
 // Lane layout: a row is handled by LPR lanes (32 or 64); lane `sub` owns
@@ -180,16 +179,21 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     double* al = fl + rpw;     // a_i
     double* lal = al + rpw;    // ln a_i
     double* lse = lal + rpw;   // log2 sum_j 2^(g_j kk - C_ij kk) of the last row update
-    float* red = reinterpret_cast<float*>(lse + rpw);
+    double* shf = lse + rpw;   // shift of the row's exponentials in this row update
+    double* rsum = shf + rpw;  // sum of those exponentials
+    float* red = reinterpret_cast<float*>(rsum + rpw);
     __shared__ Ctl cs;  // workgroup 0: the control block for the whole launch
     __shared__ double wres[WAVES];
+    __shared__ double ored[WAVES][kColBlock];  // per-wave column sums of an owned block
     __shared__ uint32_t s_dec;
 
-    double* part = A.xch;
-    double* rpart = part + (size_t)2 * nb * J;
-    double* gx = rpart + (size_t)2 * nb;
-    uint64_t* dec = reinterpret_cast<uint64_t*>(gx + (size_t)3 * J);
-    uint64_t* abort_word = dec + 2;
+    const XchLayout X = persist_xch_layout(nb, J);
+    double* part = A.xch + X.part;
+    double* rpart = A.xch + X.rpart;
+    double* gx = A.xch + X.gx;
+    uint64_t* dec = reinterpret_cast<uint64_t*>(A.xch + X.dec);
+    uint64_t* abort_word = reinterpret_cast<uint64_t*>(A.xch + X.abort_);
+    const int rep = blk % kReplicas;  // the replica of g and of the decision this workgroup reads
 
     Ctl* ctl = A.ctl;
     if (ctl->stop | ctl->done) return;  // the same words for every workgroup
@@ -203,21 +207,29 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     src.stage(reinterpret_cast<double*>(red), J);  // per-column source data (positions)
     __syncthreads();
     const double* stage = reinterpret_cast<const double*>(red);
-    for (int lr = w; lr < rpw; lr += WAVES) {
-        float* trow = tile + (size_t)lr * Jp;
-        if (lr < nrows) {
-            const int64_t i = r0 + lr;
-            auto row = src.row(i);
-            for (int j = lane; j < Jp; j += kWave) {
+    // (the tile's cells in row-major order, eight loads in flight per thread)
+    const int ntile = rpw * Jp;
+    for (int e0 = 0; e0 < ntile; e0 += 8 * T) {
+        typename Src::template Raw<1> raw[8];
+        int lr8[8], j8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * T + (int)threadIdx.x;
+            lr8[u] = e / Jp;
+            j8[u] = e - lr8[u] * Jp;
+            if (e < ntile && lr8[u] < nrows && j8[u] < J) raw[u] = src.template load<1>(src.row(r0 + lr8[u]), j8[u], J);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * T + (int)threadIdx.x;
+            if (e < ntile) {
                 float c = __builtin_huge_valf();
-                if (j < J) {
-                    auto raw = src.template load<1>(row, j, J);
-                    c = (float)src.template cost<false, 1>(row, raw, 0, i, j, stage);
+                if (lr8[u] < nrows && j8[u] < J) {
+                    const int64_t i = r0 + lr8[u];
+                    c = (float)src.template cost<false, 1>(src.row(i), raw[u], 0, i, j8[u], stage);
                 }
-                trow[j] = c;
+                tile[e] = c;
             }
-        } else {
-            for (int j = lane; j < Jp; j += kWave) trow[j] = __builtin_huge_valf();
         }
     }
     for (int e = threadIdx.x; e < slack; e += T) tile[(size_t)rpw * Jp + e] = __builtin_huge_valf();
@@ -258,23 +270,9 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
         float acc[CPL];
 #pragma unroll
         for (int q = 0; q < CPL; ++q) acc[q] = 0.0f;
-        double res = 0.0;
-        // Row outputs (f_i, the next shift and the residual term) need only
-        // (shift, S_i): lane L keeps those of the wave's L-th row since the
-        // last flush, and a flush finishes up to 64 rows at once, so the FP64
-        // logarithm and expm1 run once per 64 rows instead of once per row.
-        double stash_m = 0.0, stash_S = 1.0;
-        int stash_lr = -1, nstash = 0;
-        auto flush = [&]() {
-            if (lane < nstash && stash_lr < nrows) {
-                const double L2 = stash_m + log2(stash_S);
-                const double fi = eps * (lal[stash_lr] - kLn2 * L2);
-                if (has_prev) res += al[stash_lr] * fabs(expm1((fl[stash_lr] - fi) * inv_eps));
-                fl[stash_lr] = fi;
-                lse[stash_lr] = L2;
-            }
-            nstash = 0;
-        };
+        // Each row's (shift, sum) goes to LDS; after the steps one thread per
+        // row finishes f_i, the next shift and the residual term (the FP64
+        // logarithm and expm1 then run once per row, on every lane).
         for (int st = 0; st < steps; ++st) {
             const int lr0 = (st * WAVES + w) * R;
             const int lr = lr0 + rg;
@@ -304,6 +302,12 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             // maximum for FP32 exponentials: redo the wave's rows with the maximum
             redo = __any(redo || (vrow && !(S >= 0x1p-100 && S <= 0x1p100)));
             if (redo) {
+                // (the costs are read from LDS again: otherwise the compiler
+                // keeps the FP64 arguments of every cell live across this
+                // rare branch, which costs the common path its registers)
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) cv[q] = trow[q * LPR];
                 float mx = -__builtin_huge_valf();
 #pragma unroll
                 for (int q = 0; q < CPL; ++q) mx = fmaxf(mx, fmaf(cv[q], -kk32, (float)gk[q]));
@@ -324,29 +328,19 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             const float wq = vrow ? (float)al[lr] * __builtin_amdgcn_rcpf((float)S) : 0.0f;
 #pragma unroll
             for (int q = 0; q < CPL; ++q) acc[q] = fmaf(ev[q], wq, acc[q]);
-            // hand (shift, S) of each row group to lane nstash + group
-            const int src_lane = (lane - nstash) * LPR;
-            const int sl = (src_lane < 0 || src_lane >= kWave) ? 0 : src_lane;
-            const double mm = __shfl(m, sl, kWave);
-            const double ss = __shfl(S, sl, kWave);
-            if (lane >= nstash && lane < nstash + R) {
-                stash_m = mm;
-                stash_S = ss;
-                stash_lr = lr0 + (lane - nstash);
+            if (sub == 0 && vrow) {
+                shf[lr] = m;
+                rsum[lr] = S;
             }
-            nstash += R;
-            if (nstash == kWave) flush();
         }
-        flush();
         exact_shift = false;
         // ---- the workgroup's partials: fold the row groups of a wave (lanes
         //      sub + LPR r share columns), then the waves in FP64, published
+        //      as one contiguous row of the partial buffer
+        if constexpr (LPR == 32) {
 #pragma unroll
-        for (int o = LPR; o < kWave; o <<= 1)
-#pragma unroll
-            for (int q = 0; q < CPL; ++q) acc[q] += __shfl_xor(acc[q], o, kWave);
-        res = wave_sum(res);
-        if (lane == 0) wres[w] = res;
+            for (int q = 0; q < CPL; ++q) acc[q] = xor32_sum(acc[q]);
+        }
         if (rg == 0) {
 #pragma unroll
             for (int q = 0; q < CPL; ++q) {
@@ -354,80 +348,114 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
                 if (q < ncl && j < J) red[w * Jr4 + j] = acc[q];
             }
         }
-        // earlier emptying stores of this workgroup have completed (they were
-        // issued an iteration ago, so this costs nothing; waiting after the
-        // partial stores below would add their latency)
-        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        double* pcol = part + (size_t)P * J * nb + blk;
+        // the rows of this workgroup: f_i, the next shift, the residual term
+        double res = 0.0;
+        for (int lr = threadIdx.x; lr < nrows; lr += T) {
+            const double L2 = shf[lr] + log2(rsum[lr]);
+            const double fi = eps * (lal[lr] - kLn2 * L2);
+            if (has_prev) res += al[lr] * fabs(expm1((fl[lr] - fi) * inv_eps));
+            fl[lr] = fi;
+            lse[lr] = L2;
+        }
+        res = wave_sum(res);
+        if (lane == 0) wres[w] = res;
+        __syncthreads();
+        double* prow = part + ((size_t)P * nb + blk) * X.Jp;
         for (int c = threadIdx.x; c < J; c += T) {
             double t = 0.0;
 #pragma unroll
             for (int q = 0; q < WAVES; ++q) t += (double)red[q * Jr4 + c];
-            put_agent(pcol + (size_t)c * nb, t);
+            put_agent(prow + c, tag_value(t, k));
         }
         if (threadIdx.x == 0) {
             double r = 0.0;
 #pragma unroll
             for (int q = 0; q < WAVES; ++q) r += wres[q];
-            put_agent(rpart + (size_t)P * nb + blk, r);
+            put_agent(rpart + (size_t)P * nb + blk, tag_value(r, k));
         }
 
-        // ---- 2. column update of the owned columns, one wave per column
+        // ---- 2. column update of the owned blocks of kColBlock columns: thread
+        //      t takes column t % 8 of producers t / 8 + 64 u (whole lines per
+        //      wave), sums them in a fixed order, publishes the new g in every
+        //      replica
         bool fail = false;
-        for (int q = w; q < A.cpw; q += WAVES) {
-            const int j = blk * A.cpw + q;
-            if (j >= J) break;
-            const double bj = A.b[j];
-            double x[kPollLoads];
-            const double* col = part + ((size_t)P * J + j) * nb;
-            if (!poll_slots(col, 1, nb, x, abort_word, A.max_spin)) { fail = true; break; }
-            double s = 0.0;
+        for (int o = blk; o * kColBlock < J; o += nb) {
+            static_assert(T == 512, "the owner layout assumes 512 threads");
+            const int c = threadIdx.x & (kColBlock - 1), pb = threadIdx.x >> 3;
+            const int j = o * kColBlock + c;
+            const bool cv = j < J;
+            double x[4];
 #pragma unroll
-            for (int u = 0; u < kPollLoads; ++u) s += x[u];
-            const double csum = wave_sum(s);
-            if (lane == 0) {
-                put_agent(gx + (size_t)(k % 3) * J + j, graw[j] + eps * (log(bj) - log(csum)));
-                put_agent(gx + (size_t)((k + 2) % 3) * J + j, __longlong_as_double((long long)kEmpty));
+            for (int u = 0; u < 4; ++u) {
+                const int pr = pb + 64 * u;
+                x[u] = (cv && pr < nb) ? get_agent(part + ((size_t)P * nb + pr) * X.Jp + j) : tag_value(0.0, k);
             }
-            // (emptied after g is published: the slots are reused two iterations on)
+            int spin = 0;
+            for (;;) {
+                bool pend = false;
 #pragma unroll
-            for (int u = 0; u < kPollLoads; ++u) {
-                const int p = u * kWave + lane;
-                if (p < nb) put_agent(const_cast<double*>(col) + p, __longlong_as_double((long long)kEmpty));
+                for (int u = 0; u < 4; ++u) pend |= !has_tag(x[u], k);
+                if (!__any(pend)) break;
+                if ((++spin & 31) == 0 && (get_agent(abort_word) != 0 || spin > A.max_spin)) {
+                    put_agent(abort_word, (uint64_t)1);
+                    fail = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (!has_tag(x[u], k)) x[u] = get_agent(part + ((size_t)P * nb + pb + 64 * u) * X.Jp + j);
             }
+            // (tag bits of the partials stay in the sum: a relative change below 2^-50)
+            double s = ((x[0] + x[1]) + x[2]) + x[3];
+            s += __shfl_xor(s, 8, kWave);   // lanes of one wave with the same column:
+            s += __shfl_xor(s, 16, kWave);  // producers pb .. pb + 7 of this wave
+            s += __shfl_xor(s, 32, kWave);
+            if (lane < kColBlock) ored[w][lane] = s;
+            if (__syncthreads_or(fail)) { fail = true; break; }
+            if (threadIdx.x < kColBlock * kReplicas) {
+                const int cc = threadIdx.x & (kColBlock - 1), r = threadIdx.x >> 3;
+                const int jj = o * kColBlock + cc;
+                if (jj < J) {
+                    double csum = 0.0;
+#pragma unroll
+                    for (int q = 0; q < WAVES; ++q) csum += ored[q][cc];
+                    const double gn = graw[jj] + eps * (log(A.b[jj]) - log(csum));
+                    put_agent(gx + ((size_t)P * kReplicas + r) * X.Gs + jj, tag_value(gn, k));
+                }
+            }
+            __syncthreads();  // ored is reused by the next block
         }
         if (blk == 0 && w == WAVES - 1 && !fail) {  // residual of iterate k - 1 and the stop rule
-            double x[kPollLoads];
-            const double* rp = rpart + (size_t)P * nb;
-            if (!poll_slots(rp, 1, nb, x, abort_word, A.max_spin)) {
+            double x[4];
+            if (!poll_tagged(rpart + (size_t)P * nb, 1, nb, k, x, abort_word, A.max_spin)) {
                 fail = true;
             } else {
                 double r = 0.0;
 #pragma unroll
-                for (int u = 0; u < kPollLoads; ++u) r += x[u];
-#pragma unroll
-                for (int u = 0; u < kPollLoads; ++u) {
-                    const int p = u * kWave + lane;
-                    if (p < nb) put_agent(const_cast<double*>(rp) + p, __longlong_as_double((long long)kEmpty));
-                }
+                for (int u = 0; u < 4; ++u) r += x[u];
                 r = wave_sum(r);
+                int stop = 0;
                 if (lane == 0) {
                     bookkeep(&cs, r, kModeFast, A.stall_below);
-                    put_agent(dec + P, ((uint64_t)k << 2) | (uint64_t)((cs.stop | cs.done) ? 1 : 0));
+                    stop = (cs.stop | cs.done) ? 1 : 0;
                 }
+                stop = __shfl(stop, 0, kWave);
+                const uint64_t d = ((uint64_t)k << 2) | (uint64_t)stop;
+                if (lane < kReplicas) put_agent(dec + ((size_t)P * kReplicas + lane) * 8, d);
             }
         }
 
         __syncthreads();  // the combine above still reads the old g from LDS
 
-        // ---- 3. the new g and the decision
+        // ---- 3. the new g and the decision, from this workgroup's replica
         bool bad = false;
         if (!fail && w == 0) {  // (one wave polls: fewer requests in flight at the coherence point)
-            const double* gk_new = gx + (size_t)(k % 3) * J;
+            const double* gk_new = gx + ((size_t)P * kReplicas + rep) * X.Gs;
             for (int j0 = 0; j0 < J; j0 += kGPollLoads * kWave) {
                 double x[kGPollLoads];
-                if (!poll_slots(gk_new + j0, 1, min(J - j0, kGPollLoads * kWave), x, abort_word, A.max_spin)) {
+                if (!poll_tagged(gk_new + j0, 1, min(J - j0, kGPollLoads * kWave), k, x, abort_word, A.max_spin)) {
                     fail = true;
                     break;
                 }
@@ -442,7 +470,8 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             }
         }
         if (threadIdx.x == (WAVES > 1 ? kWave : 0) && !fail) {  // the decision, polled by another wave
-            uint64_t d = get_agent(dec + P);
+            const uint64_t* dp = dec + ((size_t)P * kReplicas + rep) * 8;
+            uint64_t d = get_agent(dp);
             int spin = 0;
             while ((d >> 2) != (uint64_t)k) {
                 if ((++spin & 31) == 0 && (get_agent(abort_word) != 0 || spin > A.max_spin)) {
@@ -451,7 +480,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                d = get_agent(dec + P);
+                d = get_agent(dp);
             }
             s_dec = (uint32_t)(d & 3);
         }
@@ -490,13 +519,18 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     }
 }
 
-// Empties the exchange block and clears the stop flag before a persistent
-// launch (grid-stride; any grid).
-static __global__ void k_xch_clear(double* xch, size_t n_slots, Ctl* ctl) {
+// Prepares the exchange block and clears the stop flag before a persistent
+// launch (grid-stride; any grid): every exchanged slot gets the tag of
+// iteration k0 + 3, which neither of the first two iterations (k0 + 1,
+// k0 + 2, one per buffer parity) waits for; decision and abort words start at
+// zero.
+static __global__ void k_xch_clear(double* xch, int nb, int J, Ctl* ctl) {
+    const XchLayout X = persist_xch_layout(nb, J);
+    const int k0 = ctl->iter;
+    const double empty = tag_value(0.0, k0 + 3);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    const size_t n = n_slots - 3;  // the decision and abort words start at zero
-    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_slots; q += stride)
-        xch[q] = q < n ? __longlong_as_double((long long)kEmpty) : 0.0;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < X.total; q += stride)
+        xch[q] = q < X.dec ? empty : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->stop = 0;
 }
 
