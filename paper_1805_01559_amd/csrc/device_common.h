@@ -61,7 +61,8 @@ __device__ __forceinline__ float dpp_f(float x) {
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
-    static_assert(CTRL == 0xB1 || CTRL == 0x4E || CTRL == 0x140 || CTRL == 0x141, "in-row DPP moves only");
+    static_assert(CTRL == 0xB1 || CTRL == 0x4E || CTRL == 0x140 || CTRL == 0x141 || CTRL == 0x128,
+                  "in-row DPP moves only");
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);

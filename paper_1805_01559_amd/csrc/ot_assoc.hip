@@ -573,7 +573,7 @@ bool persist_plan(const ot_assoc* h, int64_t I, int J, PersistPlan& p) {
     p.Jp = p.ncl * p.lpr;
     p.rpw = (int)(steps * slots);
     p.nb = (int)((I + p.rpw - 1) / p.rpw);
-    p.lds = persist_lds_bytes(p.rpw, J, p.Jp, kPersistWaves, (p.cpl - p.ncl) * p.lpr);
+    p.lds = persist_lds_bytes(p.rpw, J, p.Jp, kPersistWaves, (p.cpl - p.ncl) * p.lpr, p.nb);
     // (a little LDS stays for the kernel's static arrays)
     return p.nb <= h->num_cu && p.nb <= kMaxCoopGroups && p.lds + 2048 <= (size_t)h->lds_max;
 }

@@ -147,9 +147,15 @@ struct PersistArgs {
 // Dynamic LDS of k_persist in bytes (the layout the kernel carves): the
 // tile, a slack of (CPL - ncl) LPR floats after it, then the row and column
 // vectors.
-__host__ __device__ inline size_t persist_lds_bytes(int rpw, int J, int Jp, int waves, int slack) {
+// Column blocks each workgroup owns at most (workgroup w owns w, w + nb, ...).
+__host__ __device__ inline int persist_owned_blocks(int nb, int J) {
+    const int nblk = (J + kColBlock - 1) / kColBlock;
+    return (nblk + nb - 1) / nb;
+}
+__host__ __device__ inline size_t persist_lds_bytes(int rpw, int J, int Jp, int waves, int slack, int nb) {
     const size_t Jr2 = (size_t)((J + 1) & ~1), Jr4 = (size_t)((J + 3) & ~3);
-    return ((size_t)rpw * Jp + (size_t)slack) * 4 + Jr2 * 8 + 6 * (size_t)rpw * 8 + (size_t)waves * Jr4 * 4;
+    return ((size_t)rpw * Jp + (size_t)slack) * 4 + Jr2 * 8 + 6 * (size_t)rpw * 8 +
+           (size_t)kColBlock * persist_owned_blocks(nb, J) * 8 + (size_t)waves * Jr4 * 4;
 }
 
 // Lane layout: a row is handled by LPR lanes (32 or 64); lane `sub` owns
@@ -181,8 +187,10 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     double* lse = lal + rpw;   // log2 sum_j 2^(g_j kk - C_ij kk) of the last row update
     double* shf = lse + rpw;   // shift of the row's exponentials in this row update
     double* rsum = shf + rpw;  // sum of those exponentials
-    float* red = reinterpret_cast<float*>(rsum + rpw);
-    __shared__ Ctl cs;  // workgroup 0: the control block for the whole launch
+    double* lbl = rsum + rpw;  // ln b_j of the owned columns (8 per owned block)
+    const int nown = persist_owned_blocks(nb, J);
+    float* red = reinterpret_cast<float*>(lbl + (size_t)kColBlock * nown);
+    __shared__ Ctl cs;  // decision workgroup: the control block for the whole launch
     __shared__ double wres[WAVES];
     __shared__ double ored[WAVES][kColBlock];  // per-wave column sums of an owned block
     __shared__ uint32_t s_dec;
@@ -245,7 +253,14 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     }
     const double* g_in = A.g[k0 & 1];
     for (int j = threadIdx.x; j < J; j += T) graw[j] = g_in[j];
-    if (blk == 0 && threadIdx.x == 0) cs = *ctl;
+    for (int e = threadIdx.x; e < kColBlock * nown; e += T) {
+        const int j = (blk + (e / kColBlock) * nb) * kColBlock + e % kColBlock;
+        lbl[e] = j < J ? log(A.b[j]) : 0.0;
+    }
+    // the decision workgroup (the last one: with fewer column blocks than
+    // workgroups it owns none) sums the residuals and takes the stop decision
+    const int dblk = nb - 1;
+    if (blk == dblk && threadIdx.x == 0) cs = *ctl;
     __syncthreads();
 
     // g_j kk of this lane's columns (-inf past J)
@@ -375,12 +390,32 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             put_agent(rpart + (size_t)P * nb + blk, tag_value(r, k));
         }
 
+        bool fail = false;
+        if (blk == dblk && w == WAVES - 1) {  // residual of iterate k - 1 and the stop rule
+            double x[4];
+            if (!poll_tagged(rpart + (size_t)P * nb, 1, nb, k, x, abort_word, A.max_spin)) {
+                fail = true;
+            } else {
+                double r = 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) r += x[u];
+                r = wave_sum(r);
+                int stop = 0;
+                if (lane == 0) {
+                    bookkeep(&cs, r, kModeFast, A.stall_below);
+                    stop = (cs.stop | cs.done) ? 1 : 0;
+                }
+                stop = __shfl(stop, 0, kWave);
+                const uint64_t d = ((uint64_t)k << 2) | (uint64_t)stop;
+                if (lane < kReplicas) put_agent(dec + ((size_t)P * kReplicas + lane) * 8, d);
+            }
+        }
+
         // ---- 2. column update of the owned blocks of kColBlock columns: thread
         //      t takes column t % 8 of producers t / 8 + 64 u (whole lines per
         //      wave), sums them in a fixed order, publishes the new g in every
         //      replica
-        bool fail = false;
-        for (int o = blk; o * kColBlock < J; o += nb) {
+        for (int o = blk, oi = 0; o * kColBlock < J; o += nb, ++oi) {
             static_assert(T == 512, "the owner layout assumes 512 threads");
             const int c = threadIdx.x & (kColBlock - 1), pb = threadIdx.x >> 3;
             const int j = o * kColBlock + c;
@@ -409,9 +444,9 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             }
             // (tag bits of the partials stay in the sum: a relative change below 2^-50)
             double s = ((x[0] + x[1]) + x[2]) + x[3];
-            s += __shfl_xor(s, 8, kWave);   // lanes of one wave with the same column:
-            s += __shfl_xor(s, 16, kWave);  // producers pb .. pb + 7 of this wave
-            s += __shfl_xor(s, 32, kWave);
+            s += dpp_d<0x128>(s);  // lanes of one wave with the same column (producers
+            s = xor16_sum(s);      // pb .. pb + 7 of this wave): lane l ^ 8, l ^ 16, l ^ 32
+            s = xor32_sum(s);
             if (lane < kColBlock) ored[w][lane] = s;
             if (__syncthreads_or(fail)) { fail = true; break; }
             if (threadIdx.x < kColBlock * kReplicas) {
@@ -421,32 +456,12 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
                     double csum = 0.0;
 #pragma unroll
                     for (int q = 0; q < WAVES; ++q) csum += ored[q][cc];
-                    const double gn = graw[jj] + eps * (log(A.b[jj]) - log(csum));
+                    const double gn = graw[jj] + eps * (lbl[oi * kColBlock + cc] - log(csum));
                     put_agent(gx + ((size_t)P * kReplicas + r) * X.Gs + jj, tag_value(gn, k));
                 }
             }
             __syncthreads();  // ored is reused by the next block
         }
-        if (blk == 0 && w == WAVES - 1 && !fail) {  // residual of iterate k - 1 and the stop rule
-            double x[4];
-            if (!poll_tagged(rpart + (size_t)P * nb, 1, nb, k, x, abort_word, A.max_spin)) {
-                fail = true;
-            } else {
-                double r = 0.0;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) r += x[u];
-                r = wave_sum(r);
-                int stop = 0;
-                if (lane == 0) {
-                    bookkeep(&cs, r, kModeFast, A.stall_below);
-                    stop = (cs.stop | cs.done) ? 1 : 0;
-                }
-                stop = __shfl(stop, 0, kWave);
-                const uint64_t d = ((uint64_t)k << 2) | (uint64_t)stop;
-                if (lane < kReplicas) put_agent(dec + ((size_t)P * kReplicas + lane) * 8, d);
-            }
-        }
-
         __syncthreads();  // the combine above still reads the old g from LDS
 
         // ---- 3. the new g and the decision, from this workgroup's replica
@@ -488,7 +503,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
         const bool bad_any = __syncthreads_or(bad);
         has_prev = 1;
         if (s_dec || bad_any) {
-            if (bad_any && blk == 0 && threadIdx.x == 0) {
+            if (bad_any && blk == dblk && threadIdx.x == 0) {
                 cs.numeric_bad = 1;
                 cs.done = 1;
                 cs.stop = 1;
@@ -508,7 +523,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             for (int j = threadIdx.x; j < J; j += T) go[j] = graw[j];
         }
     }
-    if (blk == 0 && threadIdx.x == 0) {
+    if (blk == dblk && threadIdx.x == 0) {
         if (!ok) {
             cs.sync_fail = 1;
             cs.done = 1;
