@@ -124,7 +124,6 @@ __device__ bool poll_tagged(const double* base, int64_t stride, int n, int k, do
         }
     }
 }
-constexpr int kGPollLoads = 8;  // new-g slots per lane in one poll (512 columns)
 
 // ------------------------------------------------------- persistent solve --
 struct PersistArgs {
@@ -464,27 +463,26 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
         }
         __syncthreads();  // the combine above still reads the old g from LDS
 
-        // ---- 3. the new g and the decision, from this workgroup's replica
+        // ---- 3. the new g and the decision, from this workgroup's replica:
+        //      every wave polls 64 columns at a time (one load per lane in
+        //      flight: short poll rounds), the last wave also the decision
         bool bad = false;
-        if (!fail && w == 0) {  // (one wave polls: fewer requests in flight at the coherence point)
+        if (!fail) {
             const double* gk_new = gx + ((size_t)P * kReplicas + rep) * X.Gs;
-            for (int j0 = 0; j0 < J; j0 += kGPollLoads * kWave) {
-                double x[kGPollLoads];
-                if (!poll_tagged(gk_new + j0, 1, min(J - j0, kGPollLoads * kWave), k, x, abort_word, A.max_spin)) {
+            for (int j0 = w * kWave; j0 < J; j0 += WAVES * kWave) {
+                double x[1];
+                if (!poll_tagged(gk_new + j0, 1, min(J - j0, kWave), k, x, abort_word, A.max_spin)) {
                     fail = true;
                     break;
                 }
-#pragma unroll
-                for (int u = 0; u < kGPollLoads; ++u) {
-                    const int j = j0 + u * kWave + lane;
-                    if (j < J) {
-                        graw[j] = x[u];
-                        bad |= !isfinite(x[u]);
-                    }
+                const int j = j0 + lane;
+                if (j < J) {
+                    graw[j] = x[0];
+                    bad |= !isfinite(x[0]);
                 }
             }
         }
-        if (threadIdx.x == (WAVES > 1 ? kWave : 0) && !fail) {  // the decision, polled by another wave
+        if (w == WAVES - 1 && lane == 0 && !fail) {
             const uint64_t* dp = dec + ((size_t)P * kReplicas + rep) * 8;
             uint64_t d = get_agent(dp);
             int spin = 0;
