@@ -162,6 +162,10 @@ typedef struct {
 /* ot_assoc_result.flags: the FP32 phase ran as one cooperative launch with the
    cost held in LDS (ot_assoc_options.persistent). */
 #define OT_RESULT_PERSISTENT 1
+/* ot_assoc_result.flags of a snapshot (ot_assoc_solve_snapshots): its status
+   refers to tol on the BF16 problem, and the exact FP64 check of its
+   potentials found a marginal violation of at least tol. */
+#define OT_RESULT_CHECK_ABOVE_TOL 2
 
 /* Fills *opt with the defaults listed above (device 0, default stream). */
 ot_status ot_assoc_default_options(ot_assoc_options *opt);
@@ -425,7 +429,9 @@ ot_status ot_assoc_batch_plan(ot_assoc *h, int k, void *pi, ot_mem mem, ot_dtype
  * exact FP64 check of snapshot s's potentials fbar + eps ln u_s,
  * gbar + eps ln v_s against C (for RATES / GEOMETRY / EUCLID, its FP32 materialised
  * form): the violation reflects the split-BF16 arithmetic and FP32
- * accumulation (well below 1e-3), not tol.
+ * accumulation (well below 1e-3), not tol. out[s].status is OT_OK when the
+ * BF16 problem met tol; out[s].flags has OT_RESULT_CHECK_ABOVE_TOL when the
+ * exact check's violation is nevertheless at least tol.
  * A and b live in cost->mem (GEOMETRY, EUCLID: device). Afterwards the handle's
  * single-instance state (ot_assoc_plan / ot_assoc_potentials) is the
  * reference solve, converged to a marginal violation below 1e-3 only (it

@@ -209,7 +209,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
     const double kk = A.prm->kk, eps = A.prm->eps, inv_eps = 1.0 / A.prm->eps;
     const float kk32 = (float)kk;
 
-    // 1. this workgroup's rows of C, as the FP32 values the fast sweeps use;
+    // 1. this workgroup's rows of C in FP32 (the FP64 cost rounded once);
     //    padding columns and rows past I hold +inf (a zero plan entry)
     src.stage(reinterpret_cast<double*>(red), J);  // per-column source data (positions)
     __syncthreads();
@@ -233,7 +233,10 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
                 float c = __builtin_huge_valf();
                 if (lr8[u] < nrows && j8[u] < J) {
                     const int64_t i = r0 + lr8[u];
-                    c = (float)src.template cost<false, 1>(src.row(i), raw[u], 0, i, j8[u], stage);
+                    // (the FP64 cost rounded once: for costs regenerated from
+                    // positions the tile then holds exactly the materialised
+                    // FP32 cost, so the FP32 phase iterates on that problem)
+                    c = (float)src.template cost<true, 1>(src.row(i), raw[u], 0, i, j8[u], stage);
                 }
                 tile[e] = c;
             }

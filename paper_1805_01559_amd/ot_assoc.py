@@ -27,6 +27,7 @@ OT_MEM_HOST, OT_MEM_DEVICE = 0, 1
 OT_F32, OT_F64 = 0, 1
 OT_PREC_FP32, OT_PREC_FP64 = 0, 1
 OT_RESULT_PERSISTENT = 1
+OT_RESULT_CHECK_ABOVE_TOL = 2
 
 # every symbol include/ot_assoc.h declares
 EXPORTS = [

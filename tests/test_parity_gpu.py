@@ -46,6 +46,26 @@ def oracle_ref(O, C, a, b, eps):
     return r, st
 
 
+# Cell by cell: on every cell that carries mass (pi_ref above 1e-12 of the
+# largest entry) the plan of the library's potentials is within 100 tol
+# relative of the oracle's plan run to 1e-12, i.e. the gauge-invariant
+# f_i + g_j agree to 100 tol eps. The oracle's own tol-run reaches up to 13 tol
+# on these instances (a row's relative error is bounded by the residual
+# times sum(a) / a_i, far above the typical cell).
+ELEM_FACTOR = 100.0
+
+
+def check_cells(O, C, f, g, ref, eps, tol):
+    P = O.plan(C, f, g, eps)
+    P0 = O.plan(C, ref.f, ref.g, eps)
+    m = P0 > 1e-12 * P0.max()
+    rel = np.abs(P - P0)[m] / P0[m]
+    assert rel.max() <= ELEM_FACTOR * tol, rel.max()
+    dfg = np.abs((f[:, None] + g[None, :]) - (ref.f[:, None] + ref.g[None, :]))[m]
+    assert dfg.max() <= ELEM_FACTOR * tol * eps * 1.0001 + 1e-15, dfg.max()
+    return np.abs(P - P0).sum()
+
+
 def check_against(O, C, a, b, eps, tol, f, g, res, ref_stats, ref=None, plan_l1=PLAN_L1):
     chk = O.plan_stats(C, a, b, f, g, eps)
     assert res.marginal_violation < tol, res.marginal_violation
@@ -56,7 +76,7 @@ def check_against(O, C, a, b, eps, tol, f, g, res, ref_stats, ref=None, plan_l1=
     assert abs(res.objective - chk["objective"]) <= 1e-9 * abs(chk["objective"])
     assert abs(res.marginal_violation - chk["marginal_violation"]) <= 1e-10 + 1e-6 * chk["marginal_violation"]
     if ref is not None:
-        l1 = np.abs(O.plan(C, f, g, eps) - O.plan(C, ref.f, ref.g, eps)).sum()
+        l1 = check_cells(O, C, f, g, ref, eps, tol)
         assert l1 <= plan_l1, l1
     return chk
 
@@ -123,7 +143,7 @@ def test_dense_ragged_shapes(A, oracle_lib, I, J):
         st, res = s.solve_dense(C, a, b, eps, tol, 5000)
         assert st == A.OT_OK
         f, g = s.potentials()
-    check_against(oracle_lib, Cd, a, b, eps, tol, f, g, res, ref_stats, ref, plan_l1=1e-5)
+    check_against(oracle_lib, Cd, a, b, eps, tol, f, g, res, ref_stats, ref)
 
 
 @pytest.mark.parametrize("blocks,waves,lanes,I,J", [(5, 4, 16, 1000, 52), (37, 8, 32, 3001, 400), (64, 8, 64, 2500, 1031),
@@ -143,7 +163,7 @@ def test_dense_launch_shapes(A, oracle_lib, blocks, waves, lanes, I, J):
         st, res = s.solve_dense(C, a, b, eps, tol, 5000)
         assert st == A.OT_OK
         f, g = s.potentials()
-    check_against(oracle_lib, Cd, a, b, eps, tol, f, g, res, ref_stats, ref, plan_l1=1e-5)
+    check_against(oracle_lib, Cd, a, b, eps, tol, f, g, res, ref_stats, ref)
 
 
 def test_dense_fp64_matrix(A, oracle_lib, small_cfg):

@@ -130,3 +130,60 @@ def test_snapshots_errors(A):
         with pytest.raises(A.OTError) as e:
             s.snapshot_potentials(0)
         assert e.value.status == A.OT_ESTATE
+
+
+def test_snapshots_cran_20000x400_b64_every_snapshot(A, oracle_lib):
+    """The snapshot workload at its full shape: the 20000 x 400 layout, B = 64
+    snapshots (lambda resampled, seeds 3500 + s), eps 0.02, tol 1e-6 on the
+    BF16 problem; every snapshot against the oracle's own solve of it (to
+    1e-8, far inside the 1e-3 bar). A snapshot whose exact FP64 check is at or
+    above tol carries OT_RESULT_CHECK_ABOVE_TOL."""
+    announce("64 snapshots of the 20000 x 400 layout, every one against the oracle")
+    import torch
+    eps, tol = 0.02, 1e-6
+    L = S.preset_layout("cran_20000x400")
+    C32 = oracle_lib.cost(L)[0].astype(np.float32)
+    Cq = C32.astype(np.float64)
+    As = S.snapshot_marginals(L.I, 64, seed=3500)
+    dev = torch.device("cuda:0")
+    with A.Solver(L.I, L.J) as s:
+        st, res = s.solve_snapshots(torch.from_numpy(C32).to(dev), torch.from_numpy(As).to(dev),
+                                    torch.from_numpy(L.b).to(dev), eps, tol, 2000)
+        assert st == A.OT_OK, [r.status for r in res]
+        pots = [s.snapshot_potentials(q) for q in range(64)]
+    worst_v, worst_o = 0.0, 0.0
+    for q in range(64):
+        f, g = pots[q]
+        chk = oracle_lib.plan_stats(Cq, As[q], L.b, f, g, eps)
+        ref = oracle_lib.sinkhorn(Cq, As[q], L.b, eps, 1e-8, 5000)
+        rst = oracle_lib.plan_stats(Cq, As[q], L.b, ref.f, ref.g, eps)
+        rel = abs(chk["objective"] - rst["objective"]) / abs(rst["objective"])
+        worst_v, worst_o = max(worst_v, chk["marginal_violation"]), max(worst_o, rel)
+        assert chk["marginal_violation"] < BF16_BAR and rel < BF16_BAR, (q, chk["marginal_violation"], rel)
+        assert abs(res[q].marginal_violation - chk["marginal_violation"]) <= 1e-9 + 1e-6 * chk["marginal_violation"]
+        assert bool(res[q].flags & A.OT_RESULT_CHECK_ABOVE_TOL) == (res[q].marginal_violation >= tol)
+    print(f"[case] worst of 64: violation {worst_v:.2e}, objective {worst_o:.2e}; "
+          f"{sum(bool(r.flags & A.OT_RESULT_CHECK_ABOVE_TOL) for r in res)} flagged above tol", flush=True)
+
+
+def test_snapshots_low_drift(A, oracle_lib):
+    """Snapshots that sit close to their mean (each lambda_i scaled by
+    1 + 0.01 N(0, 1)): the reference solve of the mean then nearly solves every
+    snapshot, and the iteration must still carry each one to its own
+    marginals; all against the oracle."""
+    announce("16 low-drift snapshots of a 1500 x 60 layout")
+    eps = 0.05
+    L = S.make_layout(1500, 60, 1000.0, seed=7777)
+    C32 = oracle_lib.cost(L)[0].astype(np.float32)
+    Cq = C32.astype(np.float64)
+    rng = np.random.default_rng(7778)
+    As = np.empty((16, L.I))
+    for q in range(16):
+        lam = L.lam * (1.0 + 0.01 * rng.standard_normal(L.I))
+        As[q] = lam / lam.sum()
+    with A.Solver(L.I, L.J) as s:
+        st, res = s.solve_snapshots(C32, As, L.b, eps, 1e-6, 3000)
+        assert st == A.OT_OK
+        for q in range(16):
+            f, g = s.snapshot_potentials(q)
+            check_snapshot(oracle_lib, Cq, As[q], L.b, eps, f, g, res[q])
