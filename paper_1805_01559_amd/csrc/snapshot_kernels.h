@@ -9,12 +9,13 @@
 // K-dimension of J and I respectively:
 //   P = K V   (I x J) . (J x B)        Q = K^T U   (J x I) . (I x B)
 // run on the matrix cores (v_mfma_f32_16x16x32_bf16). K (and its transpose,
-// so both GEMMs read their A operand along contiguous memory), U and V are
-// each split into BF16 high and low parts (x = hi + lo: about 16 significant
-// bits instead of BF16's 8, so that a plan concentrated on few RRHs per
-// device does not inherit the 2^-9 relative rounding of a single BF16 K
-// entry as its marginal error). A product is Kh Xh + Kh Xl + Kl Xh (the
-// Kl Xl term is below FP32 accumulation), every product accumulating in FP32.
+// so both GEMMs read their A operand along contiguous memory) is stored split
+// into BF16 high and low parts (x = hi + lo: about 16 significant bits
+// instead of BF16's 8, so that a plan concentrated on few RRHs per device
+// does not inherit the 2^-9 relative rounding of a single BF16 K entry as its
+// marginal error); U and V are kept in FP32 and split the same way when a
+// workgroup stages them in LDS. A product is Kh Xh + Kh Xl + Kl Xh (the Kl Xl
+// term is below FP32 accumulation), every product accumulating in FP32.
 //
 // MFMA 16x16x32 lane layout (lane l of the 64-lane wavefront):
 //   A (16 x 32): row l % 16, k = 8 (l / 16) .. 8 (l / 16) + 7
@@ -50,24 +51,63 @@ struct SnapArgs {
     int B;           // live snapshots (<= kSnapB)
     int splits;      // K-splits of the column GEMM
     int64_t rows_per_split;  // multiple of 32
+    int rows_nt;     // row tiles per workgroup of the row GEMM
+    int cols_nt;     // column tiles per workgroup of the column GEMM
     const unsigned short* K;   // Ip x Jp BF16 high part, zero padded
-    const unsigned short* Kt;  // Jp x Ip BF16 high part, zero padded
+    const unsigned short* Kt;  // K^T BF16 high part, split-major: split p's rows as a Jp x rows_per_split
+                               // matrix (columns i - p rows_per_split), zero padded
     const unsigned short* Kl;  // Ip x Jp BF16 low part
-    const unsigned short* Ktl; // Jp x Ip BF16 low part
+    const unsigned short* Ktl; // K^T BF16 low part, the same layout
     const double* A;           // kSnapB x I marginals a_s (rows >= B unused)
+    float* A32;                // kSnapB x Ip, the marginals rounded to FP32, 0 on padding
     const double* b;           // J
-    float* U;                  // kSnapB x Ip
-    unsigned short* Uh;        // kSnapB x Ip, BF16 high part of U
-    unsigned short* Ul;        // kSnapB x Ip, BF16 low part
-    float* V;                  // kSnapB x Jp
-    unsigned short* Vh;        // kSnapB x Jp
-    unsigned short* Vl;        // kSnapB x Jp
+    float* U;                  // kSnapB x Ip, 0 on padded rows and snapshots
+    float* V;                  // kSnapB x Jp, 0 on padded columns and snapshots
+    unsigned short* Us;        // U split into BF16 high / low, staging layout per column split
+    unsigned short* Vs;        // V split into BF16 high / low, staging layout per row-GEMM chunk
     float* Qpart;              // splits x kSnapB x Jp
-    double* res;               // kSnapB x kResParts: column residual of the last combined iterate
+    double* res;               // kSnapB: column residual of the last combined iterate
     double* mass;              // kSnapB: sum a_s
-    int* ctl;                  // [0] iterations done, [1] stop, [2] max_iter, [3] result iteration
+    int* ctl;                  // [0] iterations done, [1] stop, [2] max_iter, [3] result iteration;
+                               // from int 8: two 64-bit decision slots (below)
     double tol;
+    int cols_groups;           // (column group, split) pairs of the column GEMM
+    int cols_per_xcd;          // of them per XCD (the launch has 8 times as many groups)
 };
+
+// Decision slots: the largest relative column residual of the live snapshots
+// in iteration k, as the bits of a non-negative double (ordered as unsigned
+// integers), gathered with atomic max in slot k % 2 by the combine of
+// iteration k and read by the row pass of iteration k + 1, which also clears
+// the other slot for the combine after it.
+__device__ __forceinline__ unsigned long long* snap_slot(const SnapArgs& S, int k) {
+    return reinterpret_cast<unsigned long long*>(S.ctl + 8) + (k & 1);
+}
+
+// K-values per staged chunk: 448 in the row GEMM (7 K-steps per wave of a
+// pair: all of a 400-RRH layout at once, with 56 fragment VGPRs beside the
+// staging loads for the 3 waves per SIMD of 10-wave groups), 576 in the
+// column GEMM (9 K-steps per wave, 2 waves per SIMD).
+constexpr int kSnapRowPS = 7;
+constexpr int kSnapColPS = 9;
+constexpr int kSnapRowCK = 64 * kSnapRowPS;
+constexpr int kSnapColCK = 64 * kSnapColPS;
+
+// Staging layout of a B operand (V for the row GEMM, U for the column GEMM):
+// per chunk of CK K-values, a BF16 high plane and a low plane of kSnapB rows
+// (snapshots) with a row stride of CK + 8 elements, chunk after chunk. A
+// workgroup copies one chunk into LDS as is (256 (CK + 8) bytes, a whole
+// number of KiB). In LDS a fragment read (16 lanes: snapshots t 16 .. t 16 +
+// 15 at one K offset, 16 bytes each) then covers 16 distinct 4-bank groups:
+// the stride is 4 (4q + 1) dwords for CK = 32 q, and 4q + 1 is odd, so
+// m (4q + 1) mod 16 is distinct for m = 0 .. 15.
+__host__ __device__ constexpr int snap_stage_bytes(int ck) { return 256 * (ck + 8); }
+static_assert(snap_stage_bytes(kSnapRowCK) % 1024 == 0 && snap_stage_bytes(kSnapColCK) % 1024 == 0,
+              "a staged chunk is copied in KiB units");
+// element (s, k) of chunk c (k relative to the chunk) in a staging layout
+__device__ __forceinline__ int64_t snap_stage_at(int ck, int64_t c, int s, int k, int plane) {
+    return c * (snap_stage_bytes(ck) / 2) + ((int64_t)plane * 64 + s) * (ck + 8) + k;
+}
 
 // Splits x (FP32) into BF16 high and low parts.
 __device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
@@ -75,11 +115,24 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned
     lo = bf16_bits(x - bf16_value(hi));
 }
 
+// The same split for two values at once on the gfx950 packed conversion
+// (round to nearest even, as bf16_bits): the BF16 pairs (hi of a, hi of b)
+// and (lo of a, lo of b), element 0 in the low half.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_bf16x2(float a, float b, unsigned& hi, unsigned& lo) {
+    const bf16x2 h = {(__bf16)a, (__bf16)b};
+    hi = __builtin_bit_cast(unsigned, h);
+    const bf16x2 l = {(__bf16)(a - __uint_as_float(hi << 16)), (__bf16)(b - __uint_as_float(hi & 0xffff0000u))};
+    lo = __builtin_bit_cast(unsigned, l);
+}
+
 // Builds the stabilised kernel as BF16 high / low parts and their
 // transposes, through 32 x 32 LDS tiles: K_ij = exp2((fbar_i + gbar_j - C_ij)
-// log2(e) / eps) rounded to FP32, zero outside I x J.
+// log2(e) / eps) rounded to FP32, zero outside I x J. The transposes are
+// split-major (rps rows per column split, a multiple of 32), so that a
+// column-GEMM workgroup reads one contiguous block per part.
 __global__ __launch_bounds__(256) void k_snap_build(const float* C, int64_t ldc, int64_t I, int J, int64_t Ip, int Jp,
-                                                    const double* fbar, const double* gbar, double kk,
+                                                    int64_t rps, const double* fbar, const double* gbar, double kk,
                                                     unsigned short* K, unsigned short* Kt, unsigned short* Kl,
                                                     unsigned short* Ktl) {
     __shared__ unsigned short th[32][33], tl[32][33];
@@ -99,11 +152,22 @@ __global__ __launch_bounds__(256) void k_snap_build(const float* C, int64_t ldc,
         tl[r][tx] = l;
     }
     __syncthreads();
+    const int64_t p = i0 / rps, c0 = i0 - p * rps;  // (a 32-row tile lies in one split)
     for (int r = ty; r < 32; r += 8) {
-        const int64_t o = (int64_t)(j0 + r) * Ip + i0 + tx;
+        const int64_t o = (p * Jp + j0 + r) * rps + c0 + tx;
         Kt[o] = th[tx][r];
         Ktl[o] = tl[tx][r];
     }
+}
+
+// Writes v (s, j) in FP32 and as its staged BF16 split.
+__device__ __forceinline__ void snap_put_v(const SnapArgs& S, int s, int j, float v) {
+    S.V[(int64_t)s * S.Jp + j] = v;
+    unsigned short hi, lo;
+    split_bf16(v, hi, lo);
+    const int c = j / kSnapRowCK, k = j - c * kSnapRowCK;
+    S.Vs[snap_stage_at(kSnapRowCK, c, s, k, 0)] = hi;
+    S.Vs[snap_stage_at(kSnapRowCK, c, s, k, 1)] = lo;
 }
 
 // Sets the scaling vectors of a cold start: v = 1 on live (s, j), 0 elsewhere.
@@ -111,239 +175,334 @@ __global__ void k_snap_init(SnapArgs S) {
     const int64_t n = (int64_t)kSnapB * S.Jp;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int s = (int)(e / S.Jp), j = (int)(e - (int64_t)s * S.Jp);
-        const float v = (s < S.B && j < S.J) ? 1.0f : 0.0f;
-        unsigned short hi, lo;
-        split_bf16(v, hi, lo);
-        S.V[e] = v;
-        S.Vh[e] = hi;
-        S.Vl[e] = lo;
+        snap_put_v(S, s, j, (s < S.B && j < S.J) ? 1.0f : 0.0f);
     }
     if (blockIdx.x == 0)
-        for (int q = threadIdx.x; q < kSnapB * 4; q += blockDim.x) S.res[q] = __builtin_huge_val();
+        for (int q = threadIdx.x; q < kSnapB; q += blockDim.x) S.res[q] = __builtin_huge_val();
 }
 
 __device__ __forceinline__ bf16x8 load8(const unsigned short* p) {
     return *reinterpret_cast<const bf16x8*>(p);
 }
 
-// Stop decision, taken identically by every wave of the row pass from the
-// residuals of the last combine (kResParts column quarters per snapshot,
-// summed in a fixed order): all live snapshots met tol, or the iteration cap.
-// Lane s takes snapshot s (kSnapB is the wavefront width) and the wave takes
-// the maximum; a NaN residual counts as 0, as in a sequential fmax from 0.
-// Every lane of the wave must be active.
-constexpr int kResParts = 4;
-static_assert(kSnapB == 64, "one snapshot per lane of the stop decision");
-__device__ __forceinline__ double snap_residual(const SnapArgs& S, int s) {
-    const double* r = S.res + (int64_t)s * kResParts;
-    return ((r[0] + r[1]) + (r[2] + r[3])) / S.mass[s];
+
+// LDS of a GEMM workgroup: one staged chunk of the larger of the two chunk
+// widths (the pair sums reuse it).
+constexpr int kSnapChunkK = kSnapColCK;
+constexpr int kSnapLdsBytes = snap_stage_bytes(kSnapChunkK);
+constexpr int kSnapMaxNT = 6;  // A tiles per workgroup (2 waves each)
+static_assert(kSnapLdsBytes <= 160 * 1024, "one chunk must fit the LDS of a workgroup");
+static_assert(kSnapMaxNT * 4 * 64 * 16 <= kSnapLdsBytes, "the pair sums reuse the staging area");
+
+// Raw buffer access (gfx9 resource word 3): loads at or beyond `bytes` from
+// the base return 0, so a resource sized to the valid data bounds its reads.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t snap_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
-__device__ __forceinline__ bool snap_stop(const SnapArgs& S, int lane) {
-    if (S.ctl[1]) return true;
-    const double r = wave_max(lane < S.B ? fmax(0.0, snap_residual(S, lane)) : 0.0);
-    return (r < S.tol) || (S.ctl[0] >= S.ctl[2]);
+__device__ __forceinline__ bf16x8 snap_bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 snap_uload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
-// One wave's share of RT stacked 16 x kSnapB output tiles: K-steps k0 = kbeg,
-// kbeg + kstride, ... < kend of A = Ah + Al (RT tiles of 16 rows, tile r's
-// lane row at ahrow / alrow + r astride) times the hi and lo parts of B^T
-// (kSnapB rows, row stride ldb). Each B fragment serves all RT tiles. The
-// steps go in groups of G whose fragments are all loaded before the group's
-// first product, so that a wave with at most G steps waits for memory once;
-// a step of a group past kend reads the last step's (in-bounds) fragments
-// and multiplies a zeroed A fragment. kbeg, kend and kstride are multiples
-// of 32.
-template <int RT, int G>
-__device__ __forceinline__ void snap_tile(const unsigned short* ahrow, const unsigned short* alrow, int64_t astride,
-                                          const unsigned short* bh, const unsigned short* bl, int64_t ldb,
-                                          int64_t kbeg, int64_t kend, int64_t kstride, int lane,
-                                          f32x4 (&acc)[RT][kSnapNT]) {
-    const int m = lane & 15, kq = (lane >> 4) * 8;
+// One workgroup's part of a stacked product D (16 NT x kSnapB) = A (16 NT x K)
+// B (K x kSnapB) over the K-range [k0, k1) (multiples of 32) in chunks of
+// CK = 64 PS K-values, with 2 NT waves: wave w multiplies A tile w / 2 over
+// the K-steps of parity w % 2 of each chunk (at most PS), into acc (one
+// 16 x 16 tile per 16 snapshots). A is read from its BF16 high / low rows (row
+// stride lda elements, `live` tiles of 16 rows from Ah / Al). B comes in the
+// staging layout, chunk after chunk from Bs, and is copied into LDS as is.
+// Each product is Ah Bh + Ah Bl + Al Bh, accumulated in FP32.
+// A chunk's B copy is issued first and its A fragments after it, so that the
+// copy is waited for alone and each K-step then waits for its own fragments
+// only (their loads overlap the products of the steps before). `gate` runs
+// after the first chunk's loads are issued; it must give every thread the
+// same answer, and on true the function waits for them and returns false
+// without writing anything. `pre` runs once, when the first chunk is staged.
+// Offsets are 32-bit: 16 NT lda elements and the staged chunks stay far below
+// 2^31 bytes.
+template <int NT, int PS, typename Gate, typename Pre>
+__device__ __forceinline__ bool snap_block(const unsigned short* Ah, const unsigned short* Al, int64_t lda, int live,
+                                           const unsigned short* Bs, int64_t k0, int64_t k1, unsigned short* lds,
+                                           Gate gate, Pre pre, f32x4 (&acc)[kSnapNT]) {
+    constexpr int NW = 2 * NT;
+    constexpr int CK = 64 * PS;
+    constexpr int UNITS = snap_stage_bytes(CK) / 1024;  // KiB units of a staged chunk
+    constexpr int UPW = (UNITS + NW - 1) / NW;          // units per wave
+    constexpr int RU = UPW < 16 ? UPW : 16;             // units per wave in flight (groups of few waves: rounds)
+    static_assert(CK <= kSnapChunkK, "chunk beyond the staging area");
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = w >> 1, par = w & 1, m = lane & 15, kq = (lane >> 4) * 8;
+    const bool mine = tile < live;
+    const unsigned arow = (unsigned)(16 * live) * (unsigned)lda * 2u;
+    const __amdgpu_buffer_rsrc_t rh = snap_rsrc(Ah, arow), rl = snap_rsrc(Al, arow);
+    const unsigned avoff = ((unsigned)(16 * tile + m) * (unsigned)lda + kq + 32 * par) * 2u;
+    const unsigned nchunk = (unsigned)((k1 - k0 + CK - 1) / CK);
+    const __amdgpu_buffer_rsrc_t rb = snap_rsrc(Bs, nchunk * (unsigned)snap_stage_bytes(CK));
+    const unsigned short* hi = lds;
+    const unsigned short* lo = lds + kSnapB * (CK + 8);
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
+    for (int t = 0; t < kSnapNT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t c0 = k0; c0 < k1; c0 += CK) {
+        const unsigned cbase = (unsigned)((c0 - k0) / CK) * (unsigned)snap_stage_bytes(CK);
+        const int cw = (int)min((int64_t)CK, k1 - c0);
+        const int ns = ((cw >> 5) - par + 1) >> 1;  // this wave's steps: par, par + 2, ... < cw / 32
+        if (c0 != k0) __syncthreads();  // every wave is done with the previous chunk's B
+        // B copy: wave w takes KiB units w, w + NW, ...; slots past the last
+        // unit repeat it (the same bytes written twice to the same place),
+        // so that no load or store sits behind a branch and each wait
+        // counts exactly the loads before it
+        u32x4 x[RU];
 #pragma unroll
-        for (int t = 0; t < kSnapNT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (kbeg >= kend) return;
-    const bf16x8 zero = {};
-    for (int64_t kb = kbeg; kb < kend; kb += G * kstride) {
-        bf16x8 a[G][RT], al[G][RT], h[G][kSnapNT], l[G][kSnapNT];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t k0 = kb + g * kstride;
-            const int64_t kc = k0 < kend ? k0 : kend - 32;
-#pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                a[g][r] = load8(ahrow + r * astride + kc + kq);
-                al[g][r] = load8(alrow + r * astride + kc + kq);
-            }
-#pragma unroll
-            for (int t = 0; t < kSnapNT; ++t) {
-                const int64_t o = (int64_t)(t * 16 + m) * ldb + kc + kq;
-                h[g][t] = load8(bh + o);
-                l[g][t] = load8(bl + o);
-            }
-        }
-        // keep the scheduler from sinking the group's loads between its
-        // products (it would, to save registers)
+        for (int u = 0; u < RU; ++u)
+            x[u] = snap_uload(rb, 16u * lane, cbase + 1024u * (unsigned)min(w + NW * u, UNITS - 1));
         __builtin_amdgcn_sched_barrier(0);
+        // A fragments, also without branches: steps past this wave's last one
+        // repeat it, and the rows of a tile past `live` lie outside the
+        // resource and read as 0 (neither is multiplied)
+        bf16x8 fa[PS], fl[PS];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const bool live = kb + g * kstride < kend;
-#pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                const bf16x8 ca = live ? a[g][r] : zero, cal = live ? al[g][r] : zero;
-#pragma unroll
-                for (int t = 0; t < kSnapNT; ++t) {
-                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, h[g][t], acc[r][t], 0, 0, 0);
-                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, l[g][t], acc[r][t], 0, 0, 0);
-                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cal, h[g][t], acc[r][t], 0, 0, 0);
-                }
-            }
+        for (int q = 0; q < PS; ++q) {
+            const unsigned soff = (unsigned)c0 * 2u + 128u * (unsigned)min(q, ns - 1);
+            fa[q] = snap_bload(rh, avoff, soff);
+            fl[q] = snap_bload(rl, avoff, soff);
         }
+        __builtin_amdgcn_sched_barrier(0);
+        if (c0 == k0 && gate()) {
+            __builtin_amdgcn_s_waitcnt(0);
+            return false;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) *reinterpret_cast<u32x4*>(lds + 512 * min(w + NW * u, UNITS - 1) + 8 * lane) = x[u];
+        for (int r0 = RU; r0 < UPW; r0 += RU) {  // (only with few waves per group)
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+                x[u] = snap_uload(rb, 16u * lane, cbase + 1024u * (unsigned)min(w + NW * (r0 + u), UNITS - 1));
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+                *reinterpret_cast<u32x4*>(lds + 512 * min(w + NW * (r0 + u), UNITS - 1) + 8 * lane) = x[u];
+        }
+        __syncthreads();
+        if (c0 == k0) pre();
+        if (mine) {
+#pragma clang loop unroll(full)
+            for (int q = 0; q < PS; ++q)
+                if (q < ns) {
+                    const int kk = (2 * q + par) * 32 + kq;
+                    bf16x8 bh[kSnapNT], bl[kSnapNT];
+#pragma unroll
+                    for (int t = 0; t < kSnapNT; ++t) {
+                        const int o = (t * 16 + m) * (CK + 8) + kk;
+                        bh[t] = *reinterpret_cast<const bf16x8*>(hi + o);
+                        bl[t] = *reinterpret_cast<const bf16x8*>(lo + o);
+                    }
+#pragma unroll
+                    for (int t = 0; t < kSnapNT; ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[q], bh[t], acc[t], 0, 0, 0);
+#pragma unroll
+                    for (int t = 0; t < kSnapNT; ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[q], bl[t], acc[t], 0, 0, 0);
+#pragma unroll
+                    for (int t = 0; t < kSnapNT; ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[q], bh[t], acc[t], 0, 0, 0);
+                }
+        }
+    }
+    return true;
+}
+
+// Sums the two K-parities of each A tile through LDS (reusing the staging
+// area): the wave of parity p keeps snapshot tiles 2 p and 2 p + 1 and
+// returns them in tot as (its part + its partner's part).
+template <int NT>
+__device__ __forceinline__ void snap_pair_sum(const f32x4 (&acc)[kSnapNT], unsigned short* lds, f32x4 (&tot)[2]) {
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = w >> 1, par = w & 1;
+    f32x4* give = reinterpret_cast<f32x4*>(lds) + ((tile * 2 + par) * 2) * 64 + lane;
+    const f32x4* take = reinterpret_cast<const f32x4*>(lds) + ((tile * 2 + (1 - par)) * 2) * 64 + lane;
+    __syncthreads();  // every wave is done with the staged B
+    // (branches on the wave-uniform parity, so that acc is only ever indexed
+    // by constants and stays in registers)
+    if (par) {
+        give[0] = acc[0];
+        give[64] = acc[1];
+    } else {
+        give[0] = acc[2];
+        give[64] = acc[3];
+    }
+    __syncthreads();
+    if (par) {
+        tot[0] = acc[2] + take[0];
+        tot[1] = acc[3] + take[64];
+    } else {
+        tot[0] = acc[0] + take[0];
+        tot[1] = acc[1] + take[64];
     }
 }
 
-// Sums the four waves' partial tiles through LDS in wave order, for RT
-// tiles; wave w < RT returns with the total of tile w.
-template <int RT>
-__device__ __forceinline__ void snap_reduce4(f32x4 (&acc)[RT][kSnapNT], int w, int lane, f32x4 (&tot)[kSnapNT]) {
-    static_assert(RT <= 4, "one reducing wave per tile");
-    __shared__ f32x4 red[4][RT][kSnapNT][64];
+// Row half-step: P = K V for NT row tiles of 16 per workgroup, then
+// u = a / P (0 on padded rows and snapshots), stored in FP32 and in the
+// column GEMM's staging layout. The stop decision (every live snapshot's
+// relative column residual of the last iterate below tol, or the iteration
+// cap) is taken from scalar loads after the group's loads are issued; group
+// 0 records it, or clears the decision slot of this iteration's combine.
+template <int NT>
+__global__ __launch_bounds__(128 * NT) void k_snap_rows(SnapArgs S) {
+    extern __shared__ unsigned short snap_lds[];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = w >> 1, par = w & 1, m = lane & 15;
+    const int64_t i0 = (int64_t)blockIdx.x * (16 * NT);
+    const int live = (int)min((int64_t)NT, (S.Ip - i0) / 16);
+    // D: column = snapshot t 16 + m, rows i0 + 16 tile + 4 (lane / 16) + q;
+    // this wave finishes snapshot tiles 2 par and 2 par + 1, whose marginals
+    // are loaded before the products
+    const int64_t ib = i0 + 16 * tile + (lane >> 4) * 4;
+    float4 av[2] = {};
+    auto load_a = [&] {
+        if (tile < live)
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int t = 0; t < kSnapNT; ++t) red[w][r][t][lane] = acc[r][t];
-    __syncthreads();
-    if (w < RT)
-#pragma unroll
-        for (int t = 0; t < kSnapNT; ++t)
-            tot[t] = ((red[0][w][t][lane] + red[1][w][t][lane]) + red[2][w][t][lane]) + red[3][w][t][lane];
-}
-
-// Row tiles of 16 per wave in the row GEMM, column tiles of 16 per wave in
-// the column GEMM.
-constexpr int kSnapRowRT = 2;
-constexpr int kSnapColRT = 2;
-// K-steps loaded together per wave: 1 measured fastest at 64 snapshots x
-// 20000 x 400 (groups of 2 and 4 lower the occupancy more than they save)
-constexpr int kSnapGroup = 1;
-
-// Row half-step: P = K V for 16 kSnapRowRT rows per workgroup (the four waves
-// take every fourth K-step and are summed in LDS), then u = a / P (0 on
-// padded rows and snapshots), stored as FP32 and as BF16 hi / lo.
-__global__ __launch_bounds__(256) void k_snap_rows(SnapArgs S) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (snap_stop(S, lane)) {
+            for (int u = 0; u < 2; ++u)
+                av[u] = *reinterpret_cast<const float4*>(S.A32 + (int64_t)((2 * par + u) * 16 + m) * S.Ip + ib);
+    };
+    const int done = S.ctl[0];  // iterations done (advanced by the column pass)
+    auto stop = [&] {
+        const double r = __longlong_as_double((long long)*snap_slot(S, done));
+        return S.ctl[1] != 0 || r < S.tol || done >= S.ctl[2];
+    };
+    auto pre = [&] {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *snap_slot(S, done + 1) = 0ull;
+        load_a();
+    };
+    f32x4 acc[kSnapNT];
+    if (!snap_block<NT, kSnapRowPS>(S.K + i0 * S.Jp, S.Kl + i0 * S.Jp, S.Jp, live, S.Vs, 0, S.Jp, snap_lds, stop,
+                                    pre, acc)) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && !S.ctl[1]) {
+            S.ctl[3] = done;
             S.ctl[1] = 1;
-            S.ctl[3] = S.ctl[0];
         }
         return;
     }
-    const int64_t i0 = (int64_t)blockIdx.x * (16 * kSnapRowRT);
-    const int m = lane & 15;
-    // D: column = snapshot t * 16 + m, rows i0 + 16 w + 4 (lane / 16) + q.
-    // The marginals this wave divides by are loaded first (entry 0 for padded
-    // rows and snapshots, whose u is 0), so that they arrive with the GEMM's
-    // fragments rather than one by one after it.
-    const int64_t ib = i0 + 16 * (w % kSnapRowRT) + (lane >> 4) * 4;
-    double av[kSnapNT][4];
+    f32x4 tot[2];
+    snap_pair_sum<NT>(acc, snap_lds, tot);
+    if (tile >= live) return;
+    // (ib .. ib + 3 lie in one column split: splits are multiples of 32 rows)
+    const int64_t split = ib / S.rows_per_split;
+    const int k = (int)(ib - split * S.rows_per_split);
 #pragma unroll
-    for (int t = 0; t < kSnapNT; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int s = t * 16 + m;
-            const int64_t i = ib + q;
-            av[t][q] = S.A[(s < S.B && i < S.I) ? (int64_t)s * S.I + i : 0];
-        }
-    f32x4 acc[kSnapRowRT][kSnapNT], tot[kSnapNT];
-    snap_tile<kSnapRowRT, kSnapGroup>(S.K + (i0 + m) * S.Jp, S.Kl + (i0 + m) * S.Jp, 16 * S.Jp, S.Vh, S.Vl, S.Jp,
-                                      (int64_t)w * 32, S.Jp, 128, lane, acc);
-    snap_reduce4<kSnapRowRT>(acc, w, lane, tot);
-    if (w >= kSnapRowRT) return;
-#pragma unroll
-    for (int t = 0; t < kSnapNT; ++t) {
-        const int s = t * 16 + m;
-        float u[4];
-        unsigned short hi[4], lo[4];
+    for (int u = 0; u < 2; ++u) {
+        const int s = (2 * par + u) * 16 + m;
+        const float a4[4] = {av[u].x, av[u].y, av[u].z, av[u].w};
+        float x[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float x = (float)(av[t][q] / (double)tot[t][q]);
-            u[q] = (s < S.B && ib + q < S.I) ? x : 0.0f;
-            split_bf16(u[q], hi[q], lo[q]);
+            const float v = (float)((double)a4[q] / (double)tot[u][q]);
+            x[q] = (s < S.B && ib + q < S.I) ? v : 0.0f;
         }
-        const int64_t o = (int64_t)s * S.Ip + ib;
-        *reinterpret_cast<float4*>(S.U + o) = make_float4(u[0], u[1], u[2], u[3]);
-        *reinterpret_cast<ushort4*>(S.Uh + o) = make_ushort4(hi[0], hi[1], hi[2], hi[3]);
-        *reinterpret_cast<ushort4*>(S.Ul + o) = make_ushort4(lo[0], lo[1], lo[2], lo[3]);
+        *reinterpret_cast<float4*>(S.U + (int64_t)s * S.Ip + ib) = make_float4(x[0], x[1], x[2], x[3]);
+        unsigned h01, l01, h23, l23;
+        split_bf16x2(x[0], x[1], h01, l01);
+        split_bf16x2(x[2], x[3], h23, l23);
+        *reinterpret_cast<uint2*>(S.Us + snap_stage_at(kSnapColCK, split, s, k, 0)) = make_uint2(h01, h23);
+        *reinterpret_cast<uint2*>(S.Us + snap_stage_at(kSnapColCK, split, s, k, 1)) = make_uint2(l01, l23);
     }
 }
 
-// Column half-step, split along i: Qpart[split] = K^T[j-tiles, rows of
-// split] U for 16 kSnapColRT columns per workgroup (the four waves take
-// every fourth K-step and are summed in LDS).
-__global__ __launch_bounds__(256) void k_snap_cols(SnapArgs S) {
-    if (S.ctl[1]) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int j0 = blockIdx.x * (16 * kSnapColRT), split = blockIdx.y;
-    const int m = lane & 15;
+// Column half-step, split along i: Qpart[split] = K^T U over the split's
+// rows (at most one staged chunk), for NT column tiles of 16 per workgroup.
+// Workgroups go round-robin over the 8 XCDs, so group b runs on XCD b % 8:
+// each XCD takes a contiguous range of (split, column group) pairs, and the
+// column groups of one split share its staged U in that XCD's L2. Group 0
+// of the pass counts the iteration.
+template <int NT>
+__global__ __launch_bounds__(128 * NT) void k_snap_cols(SnapArgs S) {
+    extern __shared__ unsigned short snap_lds[];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = w >> 1, par = w & 1, m = lane & 15;
+    const int slot = blockIdx.x >> 3;
+    if (slot >= S.cols_per_xcd) return;
+    const int g = (blockIdx.x & 7) * S.cols_per_xcd + slot;
+    if (g >= S.cols_groups) return;
+    const int jgroups = S.cols_groups / S.splits;
+    const int split = g / jgroups, j0 = (g - split * jgroups) * (16 * NT);
+    const int live = min(NT, (S.Jp - j0) / 16);
     const int64_t r0 = (int64_t)split * S.rows_per_split;
     const int64_t r1 = min(S.Ip, r0 + S.rows_per_split);
-    f32x4 acc[kSnapColRT][kSnapNT], tot[kSnapNT];
-    snap_tile<kSnapColRT, kSnapGroup>(S.Kt + (int64_t)(j0 + m) * S.Ip, S.Ktl + (int64_t)(j0 + m) * S.Ip, 16 * S.Ip, S.Uh, S.Ul,
-                          S.Ip, r0 + (int64_t)w * 32, r1, 128, lane, acc);
-    snap_reduce4<kSnapColRT>(acc, w, lane, tot);
-    if (w >= kSnapColRT) return;
-    const int jb = j0 + 16 * w + (lane >> 4) * 4;
+    f32x4 acc[kSnapNT];
+    const unsigned short* Bs = S.Us + (int64_t)split * (snap_stage_bytes(kSnapColCK) / 2);
+    const int64_t ao = ((int64_t)split * S.Jp + j0) * S.rows_per_split;
+    if (!snap_block<NT, kSnapColPS>(S.Kt + ao, S.Ktl + ao, S.rows_per_split, live, Bs, 0, r1 - r0,
+                                    snap_lds, [&] { return S.ctl[1] != 0; },
+                                    [&] {
+                                        if (g == 0 && threadIdx.x == 0) S.ctl[0] += 1;
+                                    },
+                                    acc))
+        return;
+    f32x4 tot[2];
+    snap_pair_sum<NT>(acc, snap_lds, tot);
+    if (tile >= live) return;
+    const int jb = j0 + 16 * tile + (lane >> 4) * 4;
 #pragma unroll
-    for (int t = 0; t < kSnapNT; ++t) {
-        const int s = t * 16 + m;
+    for (int u = 0; u < 2; ++u) {
+        const int s = (2 * par + u) * 16 + m;
         float* o = S.Qpart + ((int64_t)split * kSnapB + s) * S.Jp + jb;
-        *reinterpret_cast<float4*>(o) = make_float4(tot[t][0], tot[t][1], tot[t][2], tot[t][3]);
+        *reinterpret_cast<float4*>(o) = make_float4(tot[u][0], tot[u][1], tot[u][2], tot[u][3]);
     }
 }
 
-// Column combine, workgroup (s, quarter): for its quarter of the columns,
-// Q = sum of the splits (fixed order, FP64), the column residual of the
-// iterate (u, v_old) and v = b / Q.
-__global__ __launch_bounds__(256) void k_snap_combine(SnapArgs S) {
+// Sum over the column splits of one column partial (fixed order, FP64),
+// R split loads in flight at a time (indices past the last split repeat it
+// and are not added).
+template <int R>
+__device__ __forceinline__ double snap_sum_splits(const float* qp, int64_t step, int np) {
+    double q = 0.0;
+    for (int p = 0; p < np; p += R) {
+        float x[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) x[u] = qp[(int64_t)min(p + u, np - 1) * step];
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (p + u < np) q += (double)x[u];
+    }
+    return q;
+}
+
+// Column combine, workgroup s (one per snapshot): Q = sum of the splits
+// (fixed order, FP64), the column residual of the iterate (u, v_old) and
+// v = b / Q (FP32 and staged). A live snapshot puts its relative residual
+// (NaN counted as 0, as in a sequential fmax from 0) into this iteration's
+// decision slot.
+__global__ __launch_bounds__(512) void k_snap_combine(SnapArgs S) {
     if (S.ctl[1]) return;
-    const int s = blockIdx.x, quarter = blockIdx.y;
-    const int jq = (S.Jp / 4 + 63) / 64 * 64;  // columns per quarter
-    __shared__ double red[4];
+    const int s = blockIdx.x;
+    __shared__ double red[8];
     double r = 0.0;
-    const int jend = min(S.Jp, (quarter + 1) * jq);
-    for (int j = quarter * jq + threadIdx.x; j < jend; j += blockDim.x) {
-        const int64_t e = (int64_t)s * S.Jp + j;
+    const int64_t step = (int64_t)kSnapB * S.Jp;
+    for (int j = threadIdx.x; j < S.Jp; j += blockDim.x) {
         float v = 0.0f;
         if (s < S.B && j < S.J) {
             const float* qp = S.Qpart + (int64_t)s * S.Jp + j;
-            const int64_t step = (int64_t)kSnapB * S.Jp;
-            double q = 0.0;
-            int p = 0;
-            for (; p + 8 <= S.splits; p += 8) {
-                float x[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = qp[(p + u) * step];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) q += (double)x[u];
-            }
-            for (; p < S.splits; ++p) q += (double)qp[p * step];
-            r += fabs((double)S.V[e] * q - S.b[j]);
+            const double q = S.splits <= 16   ? snap_sum_splits<16>(qp, step, S.splits)
+                             : S.splits <= 32 ? snap_sum_splits<32>(qp, step, S.splits)
+                                              : snap_sum_splits<64>(qp, step, S.splits);
+            r += fabs((double)S.V[(int64_t)s * S.Jp + j] * q - S.b[j]);
             v = (float)(S.b[j] / q);
         }
-        unsigned short hi, lo;
-        split_bf16(v, hi, lo);
-        S.V[e] = v;
-        S.Vh[e] = hi;
-        S.Vl[e] = lo;
+        snap_put_v(S, s, j, v);
     }
     r = wave_sum(r);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
     __syncthreads();
     if (threadIdx.x == 0) {
-        S.res[(int64_t)s * kResParts + quarter] = (red[0] + red[1]) + (red[2] + red[3]);
-        if (s == 0 && quarter == 0) S.ctl[0] += 1;
+        const double t = ((red[0] + red[1]) + (red[2] + red[3])) + ((red[4] + red[5]) + (red[6] + red[7]));
+        S.res[s] = t;
+        if (s < S.B) {
+            const double rel = fmax(0.0, t / S.mass[s]);
+            __hip_atomic_fetch_max(snap_slot(S, S.ctl[0]), (unsigned long long)__double_as_longlong(rel),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -364,13 +523,17 @@ __global__ void k_snap_mean(const double* A, int B, int64_t I, double* abar, int
 }
 
 // mass[s] = sum_i A[s][i] (fixed order), one workgroup per snapshot; 1 for
-// padded snapshots.
-__global__ __launch_bounds__(256) void k_snap_mass(const double* A, int B, int64_t I, double* mass) {
+// padded snapshots. Also A32[s][i] = A[s][i] rounded to FP32, 0 on padding.
+__global__ __launch_bounds__(256) void k_snap_mass(const double* A, int B, int64_t I, int64_t Ip, double* mass,
+                                                   float* A32) {
     const int s = blockIdx.x;
     __shared__ double red[4];
     double t = 0.0;
-    if (s < B)
-        for (int64_t i = threadIdx.x; i < I; i += blockDim.x) t += A[(int64_t)s * I + i];
+    for (int64_t i = threadIdx.x; i < Ip; i += blockDim.x) {
+        const double v = (s < B && i < I) ? A[(int64_t)s * I + i] : 0.0;
+        t += v;
+        A32[(int64_t)s * Ip + i] = (float)v;
+    }
     t = wave_sum(t);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
     __syncthreads();

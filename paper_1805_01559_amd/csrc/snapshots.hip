@@ -29,6 +29,28 @@ namespace {
 
 constexpr int kSnapChunk = 8;
 constexpr int kMaxChunks = 64;  // row chunks per snapshot in the exact check
+constexpr int kSnapCUs = 256;   // workgroups that fill the GPU once (one per CU)
+
+const void* snap_rows_kernel(int nt) {
+    switch (nt) {
+        case 1: return (const void*)k_snap_rows<1>;
+        case 2: return (const void*)k_snap_rows<2>;
+        case 3: return (const void*)k_snap_rows<3>;
+        case 4: return (const void*)k_snap_rows<4>;
+        case 5: return (const void*)k_snap_rows<5>;
+        case 6: return (const void*)k_snap_rows<6>;
+        default: return nullptr;
+    }
+}
+const void* snap_cols_kernel(int nt) {
+    switch (nt) {
+        case 1: return (const void*)k_snap_cols<1>;
+        case 2: return (const void*)k_snap_cols<2>;
+        case 3: return (const void*)k_snap_cols<3>;
+        case 4: return (const void*)k_snap_cols<4>;
+        default: return nullptr;
+    }
+}
 
 size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -101,9 +123,19 @@ __global__ void k_snap_conv(const T* src, int64_t I, int J, int64_t lds, double 
 ot_status snap_reserve(ot_assoc* h, SnapState* s, int64_t I, int J) {
     const int64_t Ip = (int64_t)up((size_t)I, 32);
     const int Jp = (int)up((size_t)J, 32);
-    // K-splits of the column GEMM: 512 rows (16 K-steps, four per wave) per
-    // split, more when that would give more than 64 splits
-    const int64_t rps = std::max<int64_t>(512, (int64_t)up((size_t)((Ip + 63) / 64), 128));
+    // Workgroups hold one LDS chunk each, one per CU: the row GEMM takes
+    // enough row tiles per group for about one group per CU (at most
+    // kSnapMaxNT); the column GEMM groups 4 column tiles and splits the rows
+    // so that all (column group, split) pairs fill the CUs once, at least 64
+    // rows (one K-step per wave of a pair) and at most one staged chunk per
+    // split
+    const int64_t tiles_i = Ip / 16;
+    const int rows_nt = (int)std::min<int64_t>(kSnapMaxNT, std::max<int64_t>(1, (tiles_i + kSnapCUs - 1) / kSnapCUs));
+    const int tiles_j = Jp / 16;
+    const int cols_nt = std::min(4, tiles_j);
+    const int jgroups = (tiles_j + cols_nt - 1) / cols_nt;
+    const int64_t target = std::max(1, kSnapCUs / jgroups);
+    const int64_t rps = std::min<int64_t>(kSnapColCK, std::max<int64_t>(64, (int64_t)up((size_t)((Ip + target - 1) / target), 32)));
     const int splits = (int)((Ip + rps - 1) / rps);
     if (s->mem && I <= s->cap_I && J <= s->cap_J && splits <= s->cap_splits && Ip == s->S.Ip && Jp == s->S.Jp) {
         s->S.I = I;
@@ -120,19 +152,20 @@ ot_status snap_reserve(ot_assoc* h, SnapState* s, int64_t I, int J) {
     S = SnapArgs{};
     auto add = [&](void** p, size_t b) { parts.push_back({p, b}); };
     add((void**)&S.K, 2 * (size_t)Ip * Jp);
-    add((void**)&S.Kt, 2 * (size_t)Jp * Ip);
+    add((void**)&S.Kt, 2 * (size_t)Jp * splits * rps);
     add((void**)&S.Kl, 2 * (size_t)Ip * Jp);
-    add((void**)&S.Ktl, 2 * (size_t)Jp * Ip);
+    add((void**)&S.Ktl, 2 * (size_t)Jp * splits * rps);
     add((void**)&S.A, 8 * (size_t)kSnapB * I);
+    add((void**)&S.A32, 4 * (size_t)kSnapB * Ip);
     add((void**)&S.b, 8 * (size_t)J);
     add((void**)&S.U, 4 * (size_t)kSnapB * Ip);
-    add((void**)&S.Uh, 2 * (size_t)kSnapB * Ip);
-    add((void**)&S.Ul, 2 * (size_t)kSnapB * Ip);
     add((void**)&S.V, 4 * (size_t)kSnapB * Jp);
-    add((void**)&S.Vh, 2 * (size_t)kSnapB * Jp);
-    add((void**)&S.Vl, 2 * (size_t)kSnapB * Jp);
+    const size_t us_bytes = (size_t)splits * snap_stage_bytes(kSnapColCK);
+    const size_t vs_bytes = (size_t)((Jp + kSnapRowCK - 1) / kSnapRowCK) * snap_stage_bytes(kSnapRowCK);
+    add((void**)&S.Us, us_bytes);
+    add((void**)&S.Vs, vs_bytes);
     add((void**)&S.Qpart, 4 * (size_t)splits * kSnapB * Jp);
-    add((void**)&S.res, 8 * (size_t)kSnapB * kResParts);
+    add((void**)&S.res, 8 * (size_t)kSnapB);
     add((void**)&S.mass, 8 * (size_t)kSnapB);
     add((void**)&S.ctl, 64);
     add((void**)&s->fbar, 8 * (size_t)I);
@@ -153,6 +186,10 @@ ot_status snap_reserve(ot_assoc* h, SnapState* s, int64_t I, int J) {
         off += up(p.second, 256);
     }
     s->bytes = off;
+    // the staging layouts' padding is never written by the iteration: zero
+    // it once (it is never read either)
+    SCHK(hipMemsetAsync(S.Us, 0, us_bytes, h->stream));
+    SCHK(hipMemsetAsync(S.Vs, 0, vs_bytes, h->stream));
     if (!s->ctl_h) SCHK(hipHostMalloc(&s->ctl_h, 64));
     S.I = I;
     S.Ip = Ip;
@@ -160,6 +197,10 @@ ot_status snap_reserve(ot_assoc* h, SnapState* s, int64_t I, int J) {
     S.Jp = Jp;
     S.splits = splits;
     S.rows_per_split = rps;
+    S.rows_nt = rows_nt;
+    S.cols_nt = cols_nt;
+    S.cols_groups = jgroups * splits;
+    S.cols_per_xcd = (S.cols_groups + 7) / 8;
     s->cap_I = I;
     s->cap_J = J;
     s->cap_splits = splits;
@@ -170,17 +211,22 @@ ot_status snap_capture(ot_assoc* h, SnapState* s) {
     if (s->graph && std::memcmp(&s->graph_args, &s->S, sizeof(SnapArgs)) == 0) return OT_OK;
     if (s->graph) hipGraphExecDestroy(s->graph);
     s->graph = nullptr;
-    const SnapArgs S = s->S;
-    // (Ip and Jp are multiples of 32 = 16 x the tiles per wave)
-    static_assert(32 % (16 * kSnapRowRT) == 0 && 32 % (16 * kSnapColRT) == 0, "tiles must divide the padding");
-    const unsigned rows_grid = (unsigned)(S.Ip / (16 * kSnapRowRT));
-    const dim3 cols_grid((unsigned)(S.Jp / (16 * kSnapColRT)), (unsigned)S.splits);
+    SnapArgs S = s->S;
+    const void* rows_k = snap_rows_kernel(S.rows_nt);
+    const void* cols_k = snap_cols_kernel(S.cols_nt);
+    if (!rows_k || !cols_k) return sfail(h, OT_EINVAL, "no snapshot kernel for this shape");
+    SCHK(hipFuncSetAttribute(rows_k, hipFuncAttributeMaxDynamicSharedMemorySize, kSnapLdsBytes));
+    SCHK(hipFuncSetAttribute(cols_k, hipFuncAttributeMaxDynamicSharedMemorySize, kSnapLdsBytes));
+    // (Ip and Jp are multiples of 32, so every tile of 16 is whole)
+    const dim3 rows_grid((unsigned)((S.Ip / 16 + S.rows_nt - 1) / S.rows_nt));
+    const dim3 cols_grid((unsigned)(8 * S.cols_per_xcd));
+    void* args[] = {&S};
     hipGraph_t g = nullptr;
     SCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     for (int t = 0; t < kSnapChunk; ++t) {
-        hipLaunchKernelGGL(k_snap_rows, dim3(rows_grid), dim3(256), 0, h->stream, S);
-        hipLaunchKernelGGL(k_snap_cols, cols_grid, dim3(256), 0, h->stream, S);
-        hipLaunchKernelGGL(k_snap_combine, dim3(kSnapB, kResParts), dim3(256), 0, h->stream, S);
+        (void)hipLaunchKernel(rows_k, rows_grid, dim3(128 * S.rows_nt), args, kSnapLdsBytes, h->stream);
+        (void)hipLaunchKernel(cols_k, cols_grid, dim3(128 * S.cols_nt), args, kSnapLdsBytes, h->stream);
+        hipLaunchKernelGGL(k_snap_combine, dim3(kSnapB), dim3(512), 0, h->stream, S);
     }
     hipError_t e1 = hipStreamEndCapture(h->stream, &g);
     if (e1 != hipSuccess) return sfail(h, OT_EDEVICE, std::string("capture failed: ") + hipGetErrorString(e1));
@@ -226,7 +272,8 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
     SCHK(hipMemsetAsync(S.ctl + 4, 0, sizeof(int), h->stream));
     hipLaunchKernelGGL(k_snap_mean, dim3((unsigned)std::min<int64_t>(1024, (I + 255) / 256)), dim3(256), 0, h->stream,
                        (const double*)S.A, B, I, s->abar, S.ctl + 4);
-    hipLaunchKernelGGL(k_snap_mass, dim3(kSnapB), dim3(256), 0, h->stream, (const double*)S.A, B, I, S.mass);
+    hipLaunchKernelGGL(k_snap_mass, dim3(kSnapB), dim3(256), 0, h->stream, (const double*)S.A, B, I, S.Ip, S.mass,
+                       S.A32);
     std::vector<double> mass64(kSnapB), bh(J);
     SCHK(hipMemcpyAsync(mass64.data(), S.mass, sizeof(double) * kSnapB, hipMemcpyDeviceToHost, h->stream));
     SCHK(hipMemcpyAsync(bh.data(), s->bdev, sizeof(double) * J, hipMemcpyDeviceToHost, h->stream));
@@ -287,7 +334,7 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
     // 3. stabilised kernel as BF16 high / low parts and their transposes
     const double kk = std::log2(std::exp(1.0)) / eps;
     hipLaunchKernelGGL(k_snap_build, dim3((unsigned)(S.Jp / 32), (unsigned)(S.Ip / 32)), dim3(256), 0, h->stream, C, ldc,
-                       I, J, S.Ip, S.Jp, (const double*)s->fbar, (const double*)s->gbar, kk, (unsigned short*)S.K,
+                       I, J, S.Ip, S.Jp, S.rows_per_split, (const double*)s->fbar, (const double*)s->gbar, kk, (unsigned short*)S.K,
                        (unsigned short*)S.Kt, (unsigned short*)S.Kl, (unsigned short*)S.Ktl);
     // 4. the snapshot iteration
     SCHK(hipMemcpyAsync((double*)S.b, s->bdev, sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
@@ -295,7 +342,11 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
     s->ctl_h[1] = 0;
     s->ctl_h[2] = max_iter;
     s->ctl_h[3] = 0;
-    SCHK(hipMemcpyAsync(S.ctl, s->ctl_h, 4 * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    s->ctl_h[4] = 0;
+    // decision slots: +inf for the first row pass, 0 for the first combine
+    const unsigned long long slots[2] = {0x7ff0000000000000ull, 0ull};
+    std::memcpy(s->ctl_h + 8, slots, sizeof(slots));
+    SCHK(hipMemcpyAsync(S.ctl, s->ctl_h, 12 * sizeof(int), hipMemcpyHostToDevice, h->stream));
     hipLaunchKernelGGL(k_snap_init, dim3(64), dim3(256), 0, h->stream, S);
     SCHK(hipGetLastError());
     if ((st = snap_capture(h, s))) return st;
@@ -318,12 +369,8 @@ ot_status ot_assoc_solve_snapshots(ot_assoc* h, const ot_cost_desc* cost, int B,
     hipEventDestroy(e1);
     const bool converged = s->ctl_h[1] != 0 && s->ctl_h[3] < max_iter;
     const int iters = s->ctl_h[1] ? s->ctl_h[3] : s->ctl_h[0];
-    std::vector<double> rq((size_t)kSnapB * kResParts), resid(kSnapB);
-    SCHK(hipMemcpy(rq.data(), S.res, sizeof(double) * rq.size(), hipMemcpyDeviceToHost));
-    for (int q = 0; q < kSnapB; ++q) {
-        const double* r4 = rq.data() + (size_t)q * kResParts;
-        resid[q] = (r4[0] + r4[1]) + (r4[2] + r4[3]);
-    }
+    std::vector<double> resid(kSnapB);
+    SCHK(hipMemcpy(resid.data(), S.res, sizeof(double) * kSnapB, hipMemcpyDeviceToHost));
     // 5. potentials of every snapshot and their exact FP64 check, in three
     //    launches and one read-back
     const dim3 pg(64, (unsigned)B);
