@@ -124,7 +124,12 @@ typedef struct {
     int sweep_rows;     /* 0 = choose automatically; else 1, 2, 4 or 8 row steps in flight per wave */
     int sweep_lanes;    /* 0 = choose automatically; else 16, 32 or 64 lanes per row */
     int batch_tune;     /* ot_assoc_solve_batch: 1 (default) times the (waves, rows per part)
-                           candidates once per batch shape and keeps the fastest; 0 uses 8, 128 */
+                           candidates once per batch shape (device and histogram of the
+                           instances' log2 I, log2 J buckets) and keeps the default 8, 128 unless
+                           another is 3 % faster; the choice is cached for the process and, when
+                           the environment variable OT_ASSOC_TUNE_CACHE names a file, read from
+                           and appended to it, so a later process takes it without timing (a
+                           batch's results are bitwise reproducible for one choice); 0 uses 8, 128 */
     int persistent;     /* ot_assoc_solve, FP32 precision: 1 (default) runs the FP32 phase as one
                            cooperative launch that keeps the cost in LDS when the instance fits
                            (about I * J <= 9.8e6 cells on 256 CUs; dense FP32, FP32 rates or
@@ -343,6 +348,15 @@ ot_status ot_assoc_time_sweep(ot_assoc *h, int32_t reps, int fp64, double *ms_pe
  * for a plain coalesced stream, the ceiling beside which the sweeps' HBM
  * figures are read. Errors: OT_EINVAL for bad arguments, OT_EDEVICE. */
 ot_status ot_assoc_time_read(ot_assoc *h, const void *buf, size_t bytes, int32_t reps, double *ms_per_launch);
+
+/* (test hook) Makes the next cooperative FP32 launch started by the calling
+ * thread withhold the new g at its `iteration`-th iteration (1-based; 0
+ * cancels) and bound every wait at a few milliseconds, so that the waits
+ * after it end by giving up: every workgroup then leaves the kernel normally
+ * and that solve returns OT_EDEVICE ("gave up waiting") with no solution
+ * held; the next solve on the handle runs as usual. For tests of the
+ * give-up path. Errors: OT_EINVAL for a negative iteration. */
+ot_status ot_assoc_test_hold_exchange(int32_t iteration);
 
 /* (instrumentation) Device duration, in milliseconds, of the cooperative
  * launch that ran the FP32 phase of the last successful solve (HIP events on

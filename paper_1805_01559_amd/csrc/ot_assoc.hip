@@ -52,6 +52,7 @@ namespace {
 // handle-less errors (ot_assoc_create, ot_assoc_solve_static): a fixed
 // per-thread buffer, so that reporting one allocates nothing
 thread_local char g_noh_err[512];
+thread_local int g_test_hold = 0;  // ot_assoc_test_hold_exchange
 
 
 constexpr int kMaxJ = 2048;     // RRHs per instance
@@ -603,6 +604,12 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
     A.ncl = p.ncl;
     A.rpw = p.rpw;
     A.max_spin = 1 << 20;  // polls of at least ~1 us each: ~1 s before a wait gives up
+    if (g_test_hold > 0) {
+        // (test hook, one launch): withhold g at that iteration; waits give up after ~5 ms
+        A.hold_iter = g_test_hold;
+        A.max_spin = 1 << 12;
+        g_test_hold = 0;
+    }
     A.stall_below = stall_below;
     A.a = h->a;
     A.b = h->b;
@@ -1390,6 +1397,12 @@ ot_status ot_assoc_time_sweep(ot_assoc* h, int32_t reps, int fp64, double* ms_pe
     return st;
 }
 
+
+ot_status ot_assoc_test_hold_exchange(int32_t iteration) {
+    if (iteration < 0) return OT_EINVAL;
+    g_test_hold = iteration;
+    return OT_OK;
+}
 
 ot_status ot_assoc_time_read(ot_assoc* h, const void* buf, size_t bytes, int32_t reps, double* ms_per_launch) {
     if (!h) return OT_EINVAL;

@@ -133,6 +133,8 @@ struct PersistArgs {
     int ncl;  // cells per lane of a row: column q LPR + sub for q < ncl (<= CPL)
     int rpw;  // rows per workgroup: a whole number of wave steps
     int max_spin;
+    int hold_iter;  // > 0: at iteration k0 + hold_iter of the launch no new g is published, so
+                    // every wait after it ends by giving up (exercises that path); else 0
     double stall_below;
     const double* a;
     const double* b;
@@ -454,7 +456,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_persist(PersistArgs A, Src sr
             if (threadIdx.x < kColBlock * kReplicas) {
                 const int cc = threadIdx.x & (kColBlock - 1), r = threadIdx.x >> 3;
                 const int jj = o * kColBlock + cc;
-                if (jj < J) {
+                if (jj < J && k - k0 != A.hold_iter) {
                     double csum = 0.0;
 #pragma unroll
                     for (int q = 0; q < WAVES; ++q) csum += ored[q][cc];

@@ -34,6 +34,7 @@ EXPORTS = [
     "ot_assoc_default_options", "ot_assoc_workspace_size", "ot_assoc_device_allocations", "ot_assoc_create",
     "ot_assoc_solve_static", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
     "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep", "ot_assoc_time_read",
+    "ot_assoc_test_hold_exchange",
     "ot_assoc_fast_phase_time", "ot_assoc_rrh_loads", "ot_assoc_evaluate", "ot_assoc_maxsinr", "ot_assoc_adaptive",
     "ot_assoc_destroy", "ot_assoc_last_error", "ot_assoc_solve_batch", "ot_assoc_batch_config",
     "ot_assoc_batch_potentials", "ot_assoc_solve_snapshots", "ot_assoc_snapshot_potentials",
@@ -125,6 +126,7 @@ def lib():
         L.ot_assoc_materialize_cost.argtypes = [vp, ct.POINTER(ot_cost_desc), vp]
         L.ot_assoc_time_sweep.argtypes = [vp, ct.c_int32, ct.c_int, ct.POINTER(d)]
         L.ot_assoc_time_read.argtypes = [vp, vp, ct.c_size_t, ct.c_int32, ct.POINTER(d)]
+        L.ot_assoc_test_hold_exchange.argtypes = [ct.c_int32]
         L.ot_assoc_fast_phase_time.argtypes = [vp, ct.POINTER(d), ct.POINTER(ct.c_int32)]
         L.ot_assoc_rrh_loads.argtypes = [vp, vp, ct.c_int]
         L.ot_assoc_evaluate.argtypes = [vp, d, d, vp, vp, ct.c_int, ct.POINTER(ot_eval_result)]
@@ -206,6 +208,12 @@ def ot_assoc_workspace_size(I_max: int, J_max: int) -> int:
 
 def ot_assoc_device_allocations() -> int:
     return int(lib().ot_assoc_device_allocations())
+
+
+def ot_assoc_test_hold_exchange(iteration: int) -> int:
+    """Test hook: the calling thread's next cooperative FP32 launch withholds
+    g at that iteration so its waits give up (the solve returns OT_EDEVICE)."""
+    return int(lib().ot_assoc_test_hold_exchange(int(iteration)))
 
 
 def ot_assoc_solve(h, desc: ot_cost_desc, a_ptr, b_ptr, eps, tol, max_iter, warm_start=0):

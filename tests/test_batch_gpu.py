@@ -292,3 +292,69 @@ def test_batch_256_uneven_tuned_against_oracle(A, oracle_lib):
         assert l1 <= 10 * tol, (int(k), l1)
     print(f"[case] worst of 64: violation {worst[0]:.2e}, objective {worst[1]:.2e}, plan L1 {worst[2]:.2e}",
           flush=True)
+
+
+CHILD = r'''
+import hashlib, json, sys
+import numpy as np
+import torch
+from paper_1805_01559_amd import ot_assoc as A
+d = np.load(sys.argv[1])
+n = int(d["n"])
+costs = [np.ascontiguousarray(d[f"C{k}"]) for k in range(n)]
+aa = [d[f"a{k}"] for k in range(n)]
+bb = [d[f"b{k}"] for k in range(n)]
+with A.Solver(16, 16) as s:
+    st, res = s.solve_batch(costs, aa, bb, 0.05, 1e-6, 2000)
+    w, r = s.batch_config()
+    h = hashlib.sha256()
+    for k in range(n):
+        f, g = s.batch_potentials(k)
+        h.update(f.tobytes()); h.update(g.tobytes())
+print(json.dumps(dict(status=int(st), waves=int(w), rpp=int(r), digest=h.hexdigest(),
+                      viol=max(x.marginal_violation for x in res))), flush=True)
+'''
+
+
+def test_batch_tune_cache_persists_choice(A, oracle_lib, tmp_path):
+    """The autotuner's choice is written to OT_ASSOC_TUNE_CACHE and a later
+    process takes it from there: two fresh processes on the same batch report
+    the same configuration and bitwise the same potentials; a process given an
+    edited cache runs the edited configuration (it times nothing)."""
+    import json, os, subprocess, sys
+    announce("autotuner cache across processes (48 uneven instances)")
+    Ls = S.batch_layouts(48, 3100)
+    arrs = {"n": np.array(len(Ls))}
+    for k, L in enumerate(Ls):
+        arrs[f"C{k}"] = oracle_lib.cost(L)[0].astype(np.float32)
+        arrs[f"a{k}"], arrs[f"b{k}"] = L.a, L.b
+    data = tmp_path / "batch.npz"
+    np.savez(data, **arrs)
+    child = tmp_path / "child.py"
+    child.write_text(CHILD)
+    cache = tmp_path / "tune.txt"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, OT_ASSOC_TUNE_CACHE=str(cache),
+               PYTHONPATH=os.pathsep.join([root, os.environ.get("PYTHONPATH", "")]))
+
+    def run():
+        out = subprocess.run([sys.executable, "-u", str(child), str(data)], env=env, cwd=root, capture_output=True,
+                             text=True, timeout=240)
+        assert out.returncode == 0, out.stderr[-2000:]
+        return json.loads(out.stdout.strip().splitlines()[-1])
+
+    first = run()
+    lines = [ln.split() for ln in cache.read_text().splitlines() if ln.strip()]
+    print(f"[case] first process: {first}; cache: {lines}", flush=True)
+    assert first["status"] == A.OT_OK and first["viol"] < 1e-6
+    assert len(lines) == 1 and int(lines[0][1]) == first["waves"] and int(lines[0][2]) == first["rpp"]
+    second = run()
+    assert second == first
+    assert len(cache.read_text().splitlines()) == 1  # nothing new was tuned
+    # an edited entry is honoured as it stands
+    other = (4 if first["waves"] == 8 else 8, 256 if first["rpp"] != 256 else 64)
+    cache.write_text(f"{lines[0][0]} {other[0]} {other[1]}\n")
+    third = run()
+    print(f"[case] edited cache -> {third}", flush=True)
+    assert (third["waves"], third["rpp"]) == other
+    assert third["status"] == A.OT_OK and third["viol"] < 1e-6

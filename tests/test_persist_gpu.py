@@ -255,3 +255,35 @@ def test_streaming_geometry_rows_past_the_range(A, oracle_lib, I, J, seed):
         assert not (res.flags & A.OT_RESULT_PERSISTENT)
         f, g = s.potentials()
     check(oracle_lib, C64, L.a, L.b, eps, tol, f, g, res, ref)
+
+
+def test_cooperative_wait_gives_up_and_recovers(A):
+    """The bounded waits of the cooperative FP32 phase, forced from the host:
+    the launch withholds g at its third iteration, every later wait gives up,
+    all workgroups leave the kernel normally and the solve returns OT_EDEVICE;
+    the next solve on the same handle runs as usual, bitwise as on a fresh
+    handle."""
+    import time
+    announce("cooperative phase: withheld exchange at iteration 3 -> give-up, then recovery")
+    C, a, b = random_case(20000, 400, 77)
+    eps, tol = 0.05, 1e-8
+    with A.Solver(20000, 400) as s:
+        assert A.ot_assoc_test_hold_exchange(3) == A.OT_OK
+        t0 = time.perf_counter()
+        with pytest.raises(A.OTError) as e:
+            s.solve_dense(C, a, b, eps, tol, 2000)
+        dt = time.perf_counter() - t0
+        print(f"[case] gave up after {dt * 1e3:.1f} ms: {e.value}", flush=True)
+        assert e.value.status == A.OT_EDEVICE
+        assert "gave up" in str(e.value)
+        assert dt < 5.0
+        st, res = s.solve_dense(C, a, b, eps, tol, 2000)
+        assert st == A.OT_OK and res.flags & A.OT_RESULT_PERSISTENT
+        f, g = s.potentials()
+    with A.Solver(20000, 400) as s:
+        st0, res0 = s.solve_dense(C, a, b, eps, tol, 2000)
+        f0, g0 = s.potentials()
+    assert res.iterations == res0.iterations
+    np.testing.assert_array_equal(f, f0)
+    np.testing.assert_array_equal(g, g0)
+    assert A.ot_assoc_test_hold_exchange(-1) == A.OT_EINVAL
