@@ -28,9 +28,14 @@ METRIC = "Sinkhorn cells/s + HBM GB/s at 20000x400; batched solves/s + p99 at fi
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 # Algorithmic flop of one cell-iteration of the fused sweep, used only for the
-# secondary ALU figure: the FP64 argument FMA (2), the shift (1), the row-sum
-# add (1), the column-partial FMA (2) and the exponential (1).
+# secondary ALU figure when no instruction count is committed: the FP64
+# argument FMA (2), the shift (1), the row-sum add (1), the column-partial FMA
+# (2) and the exponential (1).
 FLOP_PER_CELL = 7.0
+# VALU issue peak in lane-instructions per second: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz, i.e. the published FP32 vector peak over 4 (a packed FMA does
+# 2 x 2 flop per lane-instruction)
+VALU_PEAK_TLANE = FP32_VECTOR_PEAK_TFLOPS / 4.0
 
 
 def log(msg):
@@ -691,13 +696,32 @@ def main():
                 f"{t['hbm_bytes']:.4g} B per launch from FETCH_SIZE + WRITE_SIZE (copy-calibrated), "
                 f"{t['ratio']:.3f} x the algorithmic bytes")
 
+    def counter_valu(name, seconds, units):
+        """VALU issue rate of a kernel from its committed SQ_INSTS_VALU count
+        (wave-instructions x 64 lanes per cell-iteration), while its sources are
+        the ones the counter was taken on."""
+        from paper_1805_01559_amd import profiling
+        tpath = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(tpath):
+            return None
+        t = json.load(open(tpath))
+        if t.get("source_hash") != profiling.source_hash(t["sources"]):
+            return None
+        lane = t["lane_insts_per_cell_iteration"] * units
+        return {"achieved": lane / seconds / 1e12, "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instructions/s",
+                "frac": lane / seconds / 1e12 / VALU_PEAK_TLANE,
+                "note": f"SQ_INSTS_VALU: {t['lane_insts_per_cell_iteration']:.1f} lane-instructions per "
+                        f"cell-iteration (whole kernel: exchange and waits included) against the VALU issue peak "
+                        f"(the published FP32 vector peak / 4)"}
+
     traffic, traffic_note = counter_traffic("k_iter_dense_cran_20000x400_traffic.json", ms_sweep * 1e-3)
     streaming = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
                  "algorithmic_bytes_per_launch": alg_bytes,
                  "kernel": "k_iter<DenseSrc<float>, fp32 exp> (streaming fused row update + column partials; "
                            "the path of instances whose cost does not fit in LDS)",
-                 "avg_launch_us": ms_sweep * 1e3, "fp64_sweep_us": ms_sweep64 * 1e3}
+                 "avg_launch_us": ms_sweep * 1e3, "fp64_sweep_us": ms_sweep64 * 1e3,
+                 "alu_secondary": counter_valu("k_iter_dense_cran_20000x400_valu.json", ms_sweep * 1e-3, cells)}
     if coop is not None:
         # dominant kernel: the cooperative FP32 launch. Its algorithmic bytes
         # are those of the fused single-read sweep it replaces, 4 B per
@@ -717,7 +741,9 @@ def main():
                     "algorithmic_note": "4 B per cell-iteration (one FP32 read of C by a fused single-read sweep) "
                                         "x I J x the launch's iterations, over the launch duration (HIP events)",
                     "read_ceiling_gbps": read_gbps, "copy_ceiling_gbps": copy_gbps,
-                    "alu_secondary": {"achieved": flops / coop_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                    "alu_secondary": counter_valu("k_persist_dense_cran_20000x400_valu.json", coop_s,
+                                                  cells * coop_it) or
+                                     {"achieved": flops / coop_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                                       "unit": "TFLOP/s", "frac": flops / coop_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
                                       "note": f"{FLOP_PER_CELL:.0f} algorithmic flop per cell-iteration against "
                                               "the published FP32 vector peak"}}
@@ -781,6 +807,10 @@ def main():
         out["cpu_baseline"] = cb
         out["accuracy_vs_oracle"] = acc
     solver.close()
+    # nothing of the library is left alive at exit: every handle is closed and
+    # the device is idle before the interpreter shuts down
+    del C, plan, xy, rxy, a, b, keep
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

@@ -6,7 +6,7 @@
 
 `stats` prints the kernel table of a `--kernel-trace --stats` run.
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs into HBM bytes
-per launch of one kernel. Both counters are in KiB per dispatch; each is
+per launch of one kernel (`--first N`: its first N dispatches only). Both counters are in KiB per dispatch; each is
 scaled by what it reads for the largest plain device copy in the same run
 (a copy of known size: it reads and writes `--copy-bytes / 2` each), so that
 the figure is in bytes the copy would have moved. The kernel's figure is the
@@ -70,13 +70,14 @@ def _counter(d: str):
 
 
 def traffic(fetch_dir: str, write_dir: str, kernel: str, alg_bytes: float, copy_bytes: float,
-            sources=SWEEP_SOURCES) -> dict:
+            sources=SWEEP_SOURCES, first: int = 0) -> dict:
     res = {}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _counter(d) if r["Counter_Name"] == name]
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
         cal_kib = max(copies) if copies else None
-        vals = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
+        mine = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows if kernel in r["Kernel_Name"])
+        vals = [v for _, v in (mine[:first] if first > 0 else mine)]
         if not vals or not cal_kib:
             raise SystemExit(f"{name}: no dispatches of '{kernel}' or no copy calibration in {d}")
         factor = (copy_bytes / 2) / (cal_kib * 1024.0)
@@ -101,12 +102,14 @@ def main(argv=None):
     b.add_argument("--bytes", type=float, required=True)
     b.add_argument("--copy-bytes", type=float, default=float(2 * (256 << 20)))
     b.add_argument("--coop", action="store_true", help="the kernel is the cooperative phase (persist_kernels.h)")
+    b.add_argument("--first", type=int, default=0,
+                   help="use only the kernel's first N dispatches (the bench's main leg runs first)")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print(stats(args.dir, args.top))
     else:
         t = traffic(args.fetch_dir, args.write_dir, args.kernel, args.bytes, args.copy_bytes,
-                    COOP_SOURCES if args.coop else SWEEP_SOURCES)
+                    COOP_SOURCES if args.coop else SWEEP_SOURCES, args.first)
         f, w = t["fetch"], t["write"]
         print(f"kernel: {t['kernel']}")
         print(f"FETCH_SIZE median {f['median_kib']:.1f} KiB over {f['dispatches']} dispatches; copy reads "
