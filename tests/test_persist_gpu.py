@@ -287,3 +287,29 @@ def test_cooperative_wait_gives_up_and_recovers(A):
     np.testing.assert_array_equal(f, f0)
     np.testing.assert_array_equal(g, g0)
     assert A.ot_assoc_test_hold_exchange(-1) == A.OT_EINVAL
+
+
+@pytest.mark.parametrize("I,J", [(1000, 50), (4097, 130), (6000, 400)])
+def test_iteration_counts_against_oracle(A, oracle_lib, I, J):
+    """Iteration counts near tol, anchored on the oracle run to the same tol
+    with the same stop rule: the all-FP64 path within 2 iterations of it; the
+    FP32 paths (cooperative and chunked) no earlier than 2 before it and at
+    most 8 after it: their FP32 phase stops at the first stall once the FP32
+    residual is in its noise band (r < 1e-7 and not 5 % below the least of
+    the last four), which can lie a few iterations past the iterate where the
+    FP64 residual would have met tol, before the FP64 polish and check."""
+    announce(f"iteration counts against the oracle at tol, {I}x{J}")
+    C, a, b = random_case(I, J, 991 * I + J)
+    Cd = C.astype(np.float64)
+    eps, tol = 0.05, 1e-8
+    ref = oracle_lib.sinkhorn(Cd, a, b, eps, tol, 20000)
+    with A.Solver(I, J, precision=A.OT_PREC_FP64) as s:
+        st, r64 = s.solve_dense(C, a, b, eps, tol, 2000)
+        assert st == A.OT_OK
+    out = solve_both(A, I, J, lambda s: s.solve_dense(C, a, b, eps, tol, 2000))
+    k32 = {p: out[p][1].iterations for p in out}
+    print(f"[case] oracle {ref.iters}, FP64 path {r64.iterations}, FP32 cooperative {k32[1]}, chunked {k32[0]}",
+          flush=True)
+    assert abs(r64.iterations - ref.iters) <= 2
+    for p in (1, 0):
+        assert ref.iters - 2 <= k32[p] <= ref.iters + 8, (p, k32[p], ref.iters)
