@@ -430,6 +430,42 @@ def leg_snapshots(args, A, S, torch, dev, solver, C, L):
             "plain_ms_per_solve": t_plain * 1e3, "speedup_vs_plain": B / t_snap * t_plain}, As
 
 
+def leg_adaptive(args, A, torch, solver, C, a, b, J, eps, tol):
+    """Alg. 2 (Sec. IV) over the main workload's resident cost: at most 8
+    solves (eps and tol of the main leg), each warm-started from the one
+    before, whose RRH loads the solves' final exact checks sum. Beside it
+    the pass those loads take without that fusion: rrh_loads after a plain
+    solve (a sweep over the cost, its column sums and the copy of J doubles),
+    and the same call once the loads are known."""
+    cap = 8
+    d, keep = A.matrix_desc(C, A.OT_COST_DENSE)
+    solver.adaptive(d, keep, a, eps, tol, 2000, 0.0, cap)
+    torch.cuda.synchronize()
+    K = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        st, q, js, r = solver.adaptive(d, keep, a, eps, tol, 2000, 0.0, cap)
+    torch.cuda.synchronize()
+    t_ad = (time.perf_counter() - t0) / K
+
+    def time_loads(reps=20):
+        solver.rrh_loads()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            solver.rrh_loads()
+        return (time.perf_counter() - t1) / reps
+
+    t_fused = time_loads()
+    solver.solve_dense(C, a, b, eps, tol, 2000)
+    t_pass = time_loads()
+    log(f"adaptive (Alg. 2): {t_ad * 1e3:.2f} ms for {r.solves} solves ({t_ad / r.solves * 1e3:.3f} ms per solve, "
+        f"{r.iterations} iterations); loads read {t_fused * 1e6:.0f} us fused vs {t_pass * 1e6:.0f} us by a pass")
+    return {"workload": f"Alg. 2 over the cran_20000x400 dense FP32 cost, eps={eps}, tol={tol}, at most {cap} solves",
+            "ms_per_call": t_ad * 1e3, "solves": r.solves, "best": r.best, "iterations": r.iterations,
+            "ms_per_solve": t_ad / r.solves * 1e3, "max_load": r.max_load, "first_max_load": r.first_max_load,
+            "rrh_loads_us_fused": t_fused * 1e6, "rrh_loads_us_pass": t_pass * 1e6}
+
+
 def leg_serve(args, A, S, torch, dev):
     """Request stream: Poisson arrivals (seed 4000) of association solves for
     `layouts` layouts x 10 snapshots (5 m drift per step), sizes as the batch,
@@ -539,7 +575,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0 skips it)")
     ap.add_argument("--serve-layouts", type=int, default=200, help="layouts of the serving leg (0 skips it)")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the serving leg (requests/s)")
-    ap.add_argument("--only", choices=["all", "main", "batch", "serve", "snapshots"], default="all",
+    ap.add_argument("--only", choices=["all", "main", "batch", "serve", "snapshots", "adaptive"], default="all",
                     help="run one leg (for profiling): main = the 20000x400 solve and its sweep")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -792,6 +828,8 @@ def main():
             "sweep_us": ms_sweep_dist * 1e3, "cells_per_s_sweep": cells / (ms_sweep_dist * 1e-3),
             "marginal_violation": res_e.marginal_violation},
     }
+    if args.only in ("all", "adaptive"):
+        out["adaptive"] = leg_adaptive(args, A, torch, solver, C, a, b, J, eps, tol)
     if args.only == "all":
         out["large_on_the_fly"] = leg_large(args, A, S, torch, dev)
     snap_As = None

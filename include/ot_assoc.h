@@ -271,8 +271,10 @@ ot_status ot_assoc_materialize_cost(ot_assoc *h, const ot_cost_desc *cost, float
 
 /* Per-RRH load of the last successful solve's plan: load_j = sum_i C_ij x_ij
  * in FP64 (the FP64 cost, x = exp((f + g - C)/eps)). loads: J doubles in
- * `mem`. Errors: OT_ESTATE before a successful solve (or after a call that
- * replaced the handle's cost). */
+ * `mem`. After ot_assoc_adaptive (J <= 512) the loads were summed by the
+ * solves' final exact checks and are copied out; otherwise they take one
+ * pass over the cost. Errors: OT_ESTATE before a successful solve (or after
+ * a call that replaced the handle's cost). */
 ot_status ot_assoc_rrh_loads(ot_assoc *h, double *loads, ot_mem mem);
 
 typedef struct {

@@ -122,26 +122,60 @@ __global__ __launch_bounds__(WAVES * kWave) void k_loads(LoadArgs A, Src src) {
     }
 }
 
-// Column sums of `nb` workgroup partials in block order (one thread per
-// column): out[j] = scale * sum_b part[b][j]; with en set, en[j] =
-// out[j] / (1 - out[j]) for out[j] < 1, else +inf.
-static __global__ void k_cols_fin(const double* part, int nb, int J, double scale, double* out, double* en) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= J) return;
+// Column sums of `nb` workgroup partials: out[j] = scale * sum_b part[b][j];
+// with en set, en[j] = out[j] / (1 - out[j]) for out[j] < 1, else +inf.
+// kFinCols columns per workgroup of 1024 threads; the 64 threads of a column
+// each add every 64th partial (eight loads in flight), then one thread adds
+// their 64 sums in order: a fixed order, with a thousand partials in flight
+// per column instead of one after another.
+constexpr int kFinCols = 16;
+static __global__ __launch_bounds__(1024) void k_cols_fin(const double* part, int nb, int J, double scale, double* out,
+                                                          double* en) {
+    static_assert(kFinCols * 64 == 1024, "64 threads per column");
+    const int c = threadIdx.x % kFinCols, r = threadIdx.x / kFinCols;
+    const int j = blockIdx.x * kFinCols + c;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * J + j];
-    s *= scale;
-    out[j] = s;
-    if (en) en[j] = s < 1.0 ? s / (1.0 - s) : pinf64();
+    if (j < J) {
+        int q = r;
+        for (; q + 7 * 64 < nb; q += 8 * 64) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = part[(int64_t)(q + u * 64) * J + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; q < nb; q += 64) s += part[(int64_t)q * J + j];
+    }
+    __shared__ double red[64][kFinCols + 1];
+    red[r][c] = s;
+    __syncthreads();
+    const int jj = blockIdx.x * kFinCols + (int)threadIdx.x;
+    if (threadIdx.x < kFinCols && jj < J) {
+        double t = 0.0;
+        for (int q = 0; q < 64; ++q) t += red[q][threadIdx.x];
+        t *= scale;
+        out[jj] = t;
+        if (en) en[jj] = t < 1.0 ? t / (1.0 - t) : pinf64();
+    }
 }
 
-// Sum of the time pass's workgroup pairs in block order: out[0] = sum T_i /
-// tau, out[1] = devices using an overloaded RRH.
-static __global__ void k_rows_fin(const double* row_part, int nb, double* out) {
+// Sum of the time pass's workgroup pairs: out[0] = sum T_i / tau, out[1] =
+// devices using an overloaded RRH. One workgroup of 256 threads: thread t
+// adds pairs t, t + 256, ..., then thread 0 adds the 256 sums in order.
+static __global__ __launch_bounds__(256) void k_rows_fin(const double* row_part, int nb, double* out) {
+    __shared__ double red[256][2];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        s0 += row_part[(int64_t)b * 2];
+        s1 += row_part[(int64_t)b * 2 + 1];
+    }
+    red[threadIdx.x][0] = s0;
+    red[threadIdx.x][1] = s1;
+    __syncthreads();
     if (threadIdx.x < 2) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += row_part[(int64_t)b * 2 + threadIdx.x];
-        out[threadIdx.x] = s;
+        double t = 0.0;
+        for (int q = 0; q < 256; ++q) t += red[q][threadIdx.x];
+        out[threadIdx.x] = t;
     }
 }
 

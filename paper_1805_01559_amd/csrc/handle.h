@@ -60,6 +60,7 @@ struct ot_assoc {
     int* bad = nullptr;
     unsigned long long* hist = nullptr;
     double* xch = nullptr;     // exchange block of the cooperative FP32 phase
+    double* loads = nullptr;   // J_max: RRH loads summed by the last check (when fused)
     int lds_max = 0;           // LDS bytes a workgroup may allocate
     bool last_persistent = false;  // the last solve's FP32 phase was one cooperative launch
     int last_fast_iters = 0;       // ... and the FP32 iterations it ran
@@ -83,6 +84,9 @@ struct ot_assoc {
     bool have_pot = false;
     int64_t I = 0, J = 0;
     int res_par = 0;  // parity of the buffers holding the returned iterate
+    bool want_loads = false;   // checks also sum the RRH loads into `loads` (Alg. 2's solves)
+    bool loads_fresh = false;  // the last check did, for the potentials it checked
+    bool loads_valid = false;  // `loads` holds the loads of the returned potentials
     double eps = 0.0;
     ot_cost_desc last{};       // descriptor of the retained cost (pointers below replace the caller's)
     const void* cost_dev = nullptr;  // device copy (host inputs) or the caller's device matrix

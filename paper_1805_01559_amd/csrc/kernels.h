@@ -515,10 +515,13 @@ struct CheckArgs {
     double* col_part;   // gridDim.x x J
     double* stat_part;  // gridDim.x x 5
     const SolveParams* prm;
+    double* load_part;  // gridDim.x x J partial RRH loads (the instantiation with loads only)
 };
 
 // The exact statistics of rows [r0, r1) by one workgroup (one wavefront per
-// row): column partials of pi and the five row statistics.
+// row): column partials of pi and the five row statistics; with LOADS also
+// the column partials of c_ij pi_ij, the RRH loads of Sec. II-B, from the same
+// cells (so the loads of the returned plan need no pass of their own).
 struct CheckJob {
     int64_t r0, r1;
     int J;
@@ -529,9 +532,10 @@ struct CheckJob {
     const double* g;
     double* col_out;   // J
     double* stat_out;  // 5
+    double* load_out = nullptr;  // J: sum_i c_ij pi_ij of the rows (with LOADS)
 };
 
-template <class Src, int VEC, int NCH, int WAVES>
+template <class Src, int VEC, int NCH, int WAVES, bool LOADS = false>
 __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
     extern __shared__ double sm[];
     const double kk = A.kk;
@@ -551,11 +555,11 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
             gsr[ch][v] = (ch < nch && col < J) ? A.g[col] * kk : -pinf64();
         }
     __syncthreads();
-    double acc[NCH][VEC];
+    double acc[NCH][VEC], accl[NCH][VEC];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[ch][v] = 0.0;
+        for (int v = 0; v < VEC; ++v) acc[ch][v] = accl[ch][v] = 0.0;
     double st[5] = {0, 0, 0, 0, 0};  // rowres, cost, ent, mass, fa (lane 0 of each wave)
     double cost = 0.0, ent = 0.0;     // this lane's cells of <C, pi> and sum pi (log pi - 1)
     // The loads of a row (its costs, f_i and a_i) are issued one row ahead,
@@ -598,6 +602,7 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
                     cost = fma(c, p, cost);
                     ent = fma(p, t * kLn2 - 1.0, ent);
                     acc[ch][v] += p;
+                    if constexpr (LOADS) accl[ch][v] = fma(c, p, accl[ch][v]);
                 }
             }
         }
@@ -636,6 +641,21 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
             double r = 0.0;
             for (int q = 0; q < WAVES; ++q) r += wst[q][lane];
             A.stat_out[lane] = r;
+        }
+    }
+    if constexpr (LOADS) {
+        // (the tree above ended on a barrier and wave 0 has not touched the
+        // LDS since, so the second tree can start at once)
+        block_tree<NCH, VEC, WAVES>(accl, nch, sm, ncols, w, lane);
+        if (w == 0) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch < nch)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        const int col = (ch * kWave + lane) * VEC + v;
+                        if (col < J) A.load_out[col] = accl[ch][v];
+                    }
         }
     }
 }
@@ -767,7 +787,7 @@ __device__ __forceinline__ void check_rows_g(const CheckJob& A, const Src& src) 
     }
 }
 
-template <class Src, int VEC, int NCH, int WAVES>
+template <class Src, int VEC, int NCH, int WAVES, bool LOADS = false>
 __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
     CheckJob job;
     job.r0 = (int64_t)blockIdx.x * A.rows_per_block;
@@ -780,40 +800,48 @@ __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
     job.g = A.g;
     job.col_out = A.col_part + (int64_t)blockIdx.x * A.J;
     job.stat_out = A.stat_part + (int64_t)blockIdx.x * 5;
-    check_rows<Src, VEC, NCH, WAVES>(job, src);
+    if constexpr (LOADS) job.load_out = A.load_part + (int64_t)blockIdx.x * A.J;
+    check_rows<Src, VEC, NCH, WAVES, LOADS>(job, src);
 }
 
 // Column sums of the check: per column |colsum_j - b_j| and g_j b_j, summed
-// per workgroup of 16 columns (same layout as k_colsum).
+// per workgroup of 16 columns (same layout as k_colsum); with load partials
+// also each RRH's load, their fixed-order column sum.
 struct CheckColArgs {
     int J;
     int nb;
     const double* b;
     const double* g;
     const double* col_part;
-    double* cpart;  // gridDim.x x 2
+    double* cpart;            // gridDim.x x 2
+    const double* load_part;  // nb x J, or null
+    double* loads;            // J (with load_part)
 };
 
 static __global__ __launch_bounds__(1024) void k_check_cols(CheckColArgs A) {
     static_assert(kColsPerWg * 64 == 1024, "64 partial sums per column");
     const int c = threadIdx.x % kColsPerWg, r = threadIdx.x / kColsPerWg;
     const int j = blockIdx.x * kColsPerWg + c;
-    double s = 0.0;
-    if (j < A.J) {
-        // (eight loads in flight, added in index order)
+    // (eight loads in flight, added in index order)
+    auto fold = [&](const double* part) {
+        double s = 0.0;
         int q = r;
         for (; q + 7 * 64 < A.nb; q += 8 * 64) {
             double x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = A.col_part[(int64_t)(q + u * 64) * A.J + j];
+            for (int u = 0; u < 8; ++u) x[u] = part[(int64_t)(q + u * 64) * A.J + j];
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += x[u];
         }
-        for (; q < A.nb; q += 64) s += A.col_part[(int64_t)q * A.J + j];
-    }
+        for (; q < A.nb; q += 64) s += part[(int64_t)q * A.J + j];
+        return s;
+    };
+    const bool with_loads = A.load_part != nullptr;
     __shared__ double red[64][kColsPerWg + 1];
+    __shared__ double redl[64][kColsPerWg + 1];
     __shared__ double colres[kColsPerWg][2];
-    red[r][c] = s;
+    red[r][c] = j < A.J ? fold(A.col_part) : 0.0;
+    if (with_loads) redl[r][c] = j < A.J ? fold(A.load_part) : 0.0;
     __syncthreads();
     // one thread per column folds its 64 partials in order, then thread 0
     // takes the columns in order
@@ -823,6 +851,11 @@ static __global__ __launch_bounds__(1024) void k_check_cols(CheckColArgs A) {
         for (int q = 0; q < 64; ++q) cs += red[q][threadIdx.x];
         colres[threadIdx.x][0] = jj < A.J ? fabs(cs - A.b[jj]) : 0.0;
         colres[threadIdx.x][1] = jj < A.J ? A.g[jj] * A.b[jj] : 0.0;
+        if (with_loads && jj < A.J) {
+            double ls = 0.0;
+            for (int q = 0; q < 64; ++q) ls += redl[q][threadIdx.x];
+            A.loads[jj] = ls;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {

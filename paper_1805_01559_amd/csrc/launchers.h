@@ -202,29 +202,46 @@ bool launch_iter(const Shape& s, const IterArgs& A, const Src& src, hipStream_t 
 template <int VEC>
 constexpr int check_nch() { return VEC == 4 ? 8 : VEC == 2 ? 16 : 32; }  // J <= 2048
 
+// Whether the check of this shape can also sum the RRH loads: only the
+// narrow instantiation (J <= 512) has the registers for a second set of
+// column accumulators; the wide one is at the register limit without them
+// (with them it spills, at eight waves and at four).
+inline bool check_fuses_loads(const Shape& s) {
+    const int wide = s.vec == 4 ? 8 : s.vec == 2 ? 16 : 32;
+    return s.lpr == 64 && s.nch <= wide / 4;
+}
+
 template <class Src, int VEC>
-void launch_check_v(const Shape& s, const CheckArgs& A, const Src& src, hipStream_t st) {
+bool launch_check_v(const Shape& s, const CheckArgs& A, const Src& src, hipStream_t st) {
     const size_t lds = check_lds<Src>(s);
     // narrow instances (up to a quarter of the column capacity, e.g. J <= 512
     // at VEC 4) take an instantiation with a quarter of the per-lane column
     // registers: at 20000 x 400 the wide one holds 241 VGPRs (2 waves / SIMD)
     constexpr int kWide = check_nch<VEC>(), kNarrow = kWide / 4;
+    if (A.load_part) {  // the check that also sums the RRH loads (narrow instances only)
+        if (s.nch > kNarrow) return false;
+        auto kern = k_check<Src, VEC, kNarrow, 8, true>;
+        set_lds(kern, lds);
+        hipLaunchKernelGGL(kern, dim3(s.nb), dim3(512), lds, st, A, src);
+        return true;
+    }
     if (s.nch <= kNarrow) {
         auto kern = k_check<Src, VEC, kNarrow, 8>;
         set_lds(kern, lds);
         hipLaunchKernelGGL(kern, dim3(s.nb), dim3(512), lds, st, A, src);
-        return;
+        return true;
     }
     auto kern = k_check<Src, VEC, kWide, 8>;
     set_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3(s.nb), dim3(512), lds, st, A, src);
+    return true;
 }
 
 template <class Src>
 bool launch_check(const Shape& s, const CheckArgs& A, const Src& src, hipStream_t st) {
-    if (s.vec == 1) { launch_check_v<Src, 1>(s, A, src, st); return true; }
+    if (s.vec == 1) return launch_check_v<Src, 1>(s, A, src, st);
     if constexpr (Src::kVecWide > 1)
-        if (s.vec == Src::kVecWide) { launch_check_v<Src, Src::kVecWide>(s, A, src, st); return true; }
+        if (s.vec == Src::kVecWide) return launch_check_v<Src, Src::kVecWide>(s, A, src, st);
     return false;
 }
 

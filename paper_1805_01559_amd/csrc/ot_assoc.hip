@@ -66,7 +66,7 @@ using otk_host::GraphEntry;
 constexpr int kWsAlign = 256;
 enum {
     kWsA, kWsLa, kWsB, kWsF0, kWsF1, kWsG0, kWsG1, kWsColPart, kWsResPart, kWsStatPart, kWsCpart, kWsCtl, kWsPrm,
-    kWsBad, kWsHist, kWsXch, kWsXyDev, kWsXyRrh, kWsSAll, kWsSEx, kWsJ1, kWsWork, kWsCount
+    kWsBad, kWsHist, kWsXch, kWsXyDev, kWsXyRrh, kWsSAll, kWsSEx, kWsJ1, kWsLoads, kWsWork, kWsCount
 };
 struct WsLayout {
     size_t off[kWsCount];
@@ -94,6 +94,7 @@ void ws_layout(int64_t I_max, int64_t J_max, WsLayout& L) {
     sz[kWsXyRrh] = sizeof(float) * 2 * (size_t)J_max;
     sz[kWsSAll] = I8; sz[kWsSEx] = I8;
     sz[kWsJ1] = sizeof(int) * (size_t)I_max;
+    sz[kWsLoads] = J8;
     sz[kWsWork] = ws_work_bytes(I_max, J_max);
     size_t o = 0;
     for (int k = 0; k < kWsCount; ++k) {
@@ -131,6 +132,7 @@ void carve_ws(ot_assoc* h, void* ws, const WsLayout& wl) {
         h->s_all = (double*)at(kWsSAll);
         h->s_ex = (double*)at(kWsSEx);
         h->j1 = (int*)at(kWsJ1);
+        h->loads = (double*)at(kWsLoads);
         h->work = at(kWsWork);
     }
 }
@@ -524,18 +526,38 @@ struct Solver {
 
     template <class Src>
     ot_status run_check(const Src& src, int k, Ctl& out) {
-        const Shape cs = row64(shape64, J);
+        return run_check_then(src, k, out, [] {});
+    }
+    // the check, then `after` (work that the host would otherwise issue once
+    // this wait is over), then one wait
+    // With h->want_loads (and a narrow enough J) the check also sums the RRH
+    // loads of the potentials it checks into h->loads; their partials take
+    // the second half of the column-partial block, so the grid is capped at
+    // half of its rows.
+    template <class Src, class After>
+    ot_status run_check_then(const Src& src, int k, Ctl& out, After after) {
+        Shape cs = row64(shape64, J);
+        const bool fuse = h->want_loads && check_fuses_loads(cs);
+        if (fuse && 2 * cs.nb > kMaxNb) {
+            cs.rpb = (I + kMaxNb / 2 - 1) / (kMaxNb / 2);
+            cs.nb = (int)((I + cs.rpb - 1) / cs.rpb);
+        }
         CheckArgs A{};
         A.I = I; A.J = J; A.nch = cs.nch; A.rows_per_block = cs.rpb;
         A.a = h->a; A.f = h->f[k & 1]; A.g = h->g[k & 1];
         A.col_part = h->col_part; A.stat_part = h->stat_part; A.prm = h->prm;
+        A.load_part = fuse ? h->col_part + (size_t)cs.nb * (size_t)J : nullptr;
+        h->loads_fresh = false;
         if (!launch_check<Src>(cs, A, src, h->stream)) return fail(h, OT_EINVAL, "no check kernel for this shape");
         CheckColArgs B{};
         const int ncb = (J + kColsPerWg - 1) / kColsPerWg;
-        B.J = J; B.nb = shape64.nb; B.b = h->b; B.g = h->g[k & 1]; B.col_part = h->col_part; B.cpart = h->cpart;
+        B.J = J; B.nb = cs.nb; B.b = h->b; B.g = h->g[k & 1]; B.col_part = h->col_part; B.cpart = h->cpart;
+        B.load_part = A.load_part; B.loads = h->loads;
         hipLaunchKernelGGL(k_check_cols, dim3((unsigned)ncb), dim3(1024), 0, h->stream, B);
-        hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(256), 0, h->stream, (const double*)h->stat_part, shape64.nb,
+        hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(256), 0, h->stream, (const double*)h->stat_part, cs.nb,
                            (const double*)h->cpart, ncb, h->ctl, (const SolveParams*)h->prm);
+        h->loads_fresh = fuse;
+        after();
         ot_status st = snapshot(0);
         if (st || (st = wait(0))) return st;
         out = h->ctl_h[0];
@@ -674,6 +696,23 @@ static __global__ void k_copy_fg(double* fd, const double* fs, int64_t I, double
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < J; j += gridDim.x * blockDim.x) gd[j] = gs[j];
 }
 
+// After the check of the cooperative path: the returned iterate k (the
+// control block's result iteration when done, else its last iteration) sits
+// in the buffers of parity np & 1; moves it to parity k & 1 when they differ,
+// decided on the device so that the host waits once for check and copy.
+static __global__ void k_copy_fg_ctl(const Ctl* ctl, int np, double* f0, double* f1, int64_t I, double* g0,
+                                     double* g1, int J) {
+    const int k = ctl->done ? ctl->result_iter : ctl->iter;
+    if (((k ^ np) & 1) == 0) return;
+    double* fd = (k & 1) ? f1 : f0;
+    double* gd = (k & 1) ? g1 : g0;
+    const double* fs = (np & 1) ? f1 : f0;
+    const double* gs = (np & 1) ? g1 : g0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += (int64_t)gridDim.x * blockDim.x)
+        fd[i] = fs[i];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < J; j += gridDim.x * blockDim.x) gd[j] = gs[j];
+}
+
 // The three phases of a solve. `c` enters with the initial control state and
 // leaves with the final one; result_iter names the returned iterate.
 template <class Src>
@@ -702,18 +741,16 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
         hipLaunchKernelGGL(k_polish_gate, dim3(gb), dim3(256), 0, h->stream, h->ctl, h->f[0], h->f[1], h->g[0],
                            h->g[1], I, J, tol, stall_below, np);
         if (np > 0 && (st = S.issue_chunk<Src, true>(src, 0, np, kModePolish, 0.0))) return st;
-        if ((st = S.run_check<Src>(src, np, c))) return st;
+        // the iterate sits in the buffers of parity np & 1; the convention
+        // that iterate k lives in buffers k & 1 is restored on the device
+        // right after the check
+        if ((st = S.run_check_then(src, np, c, [&] {
+                 hipLaunchKernelGGL(k_copy_fg_ctl, dim3((unsigned)std::min<int64_t>(256, (I + 255) / 256)), dim3(256),
+                                    0, h->stream, (const Ctl*)h->ctl, np, h->f[0], h->f[1], I, h->g[0], h->g[1], J);
+             })))
+            return st;
         checked = true;
         h->last_fast_iters = c.iter - c.fp64_iters;  // (the solve starts at iteration 0)
-        // the iterate sits in the buffers of parity np & 1; restore the
-        // convention that iterate k lives in buffers k & 1
-        const int k = c.done ? c.result_iter : c.iter;
-        if (((k ^ np) & 1) != 0) {
-            hipLaunchKernelGGL(k_copy_fg, dim3((unsigned)std::min<int64_t>(256, (I + 255) / 256)), dim3(256), 0,
-                               h->stream, h->f[k & 1], (const double*)h->f[np & 1], I, h->g[k & 1],
-                               (const double*)h->g[np & 1], J);
-            HIPCHK(h, hipGetLastError());
-        }
     } else if (h->opt.precision == OT_PREC_FP32) {
         hipLaunchKernelGGL(k_log_a, dim3((unsigned)std::min<int64_t>(1024, (I + 255) / 256)), dim3(256), 0, h->stream,
                            (const double*)h->a, I, h->la);
@@ -733,11 +770,13 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
     }
     if (c.done) {  // inputs rejected, or a numeric failure in the fast phase
         result_iter = c.result_iter;
+        h->loads_fresh = false;
         return OT_OK;
     }
     if (!checked && (st = S.run_check<Src>(src, c.iter, c))) return st;
     if (c.done) {  // inputs rejected (seen first by the check of an FP64-precision solve)
         result_iter = c.result_iter;
+        h->loads_fresh = false;
         return OT_OK;
     }
     result_iter = c.iter;
@@ -804,13 +843,19 @@ ot_status run_loads(ot_assoc* h, const double* rho, int& nb_out) {
 }
 
 // load_j (scale 1) or rho_j = kappa load_j and E[N_j] into device buffers.
+// When the solve's final check summed the loads (h->loads_valid) they are
+// taken from there (one partial row) instead of another pass over the cost.
 ot_status device_loads(ot_assoc* h, double scale, double* out_dev, double* en_dev) {
-    int nb = 0;
-    ot_status st = run_loads(h, nullptr, nb);
-    if (st) return st;
+    int nb = 1;
+    const double* part = h->loads;
+    if (!h->loads_valid) {
+        ot_status st = run_loads(h, nullptr, nb);
+        if (st) return st;
+        part = h->col_part;
+    }
     const int J = (int)h->J;
-    hipLaunchKernelGGL(k_cols_fin, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, h->stream,
-                       (const double*)h->col_part, nb, J, scale, out_dev, en_dev);
+    hipLaunchKernelGGL(k_cols_fin, dim3((unsigned)((J + kFinCols - 1) / kFinCols)), dim3(1024), 0, h->stream,
+                       part, nb, J, scale, out_dev, en_dev);
     HIPCHK(h, hipGetLastError());
     return OT_OK;
 }
@@ -988,6 +1033,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
     if (warm_start && !(h->have_pot && h->I == I && h->J == J))
         return fail(h, OT_ESTATE, "warm start needs potentials of a %lld x %lld instance", (long long)I, (long long)J);
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
+    h->loads_valid = h->loads_fresh = false;
     // marginals, constants and the initial control block are set up and
     // checked on the device (no host round trip before the first sweep)
     const int res_par_prev = h->res_par;
@@ -1037,7 +1083,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
             return solve_with(h, src, data, I, (int)J, tol, max_iter, fin, result_iter);
         });
     if (st) {
-        h->solved = false;
+        h->solved = h->loads_valid = false;
         h->have_pot = false;
         h->retained = false;
         return st;
@@ -1053,7 +1099,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
     HIPCHK(h, hipGetLastError());
 
     if (fin.input_bad) {  // rejected on the device: the handle keeps no result
-        h->solved = false;
+        h->solved = h->loads_valid = false;
         h->have_pot = false;
         h->retained = false;
         const int fb = fin.input_bad;
@@ -1067,7 +1113,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
                                                               : "rate matrix has entries that are not finite and positive");
     }
     if (fin.sync_fail) {
-        h->solved = false;
+        h->solved = h->loads_valid = false;
         h->have_pot = false;
         return fail(h, OT_EDEVICE, "a grid barrier of the cooperative FP32 phase gave up waiting");
     }
@@ -1080,6 +1126,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
     if (fin.numeric_bad || !std::isfinite(fin.chk_violation)) rs = OT_ENUMERIC;
     else if (!(fin.chk_violation < tol)) rs = OT_WARN_MAXITER;
     h->solved = (rs >= 0);
+    h->loads_valid = h->solved && h->loads_fresh;
     if (out) {
         out->iterations = result_iter;
         out->fp64_iterations = fin.fp64_iters;
@@ -1244,7 +1291,7 @@ ot_status ot_assoc_set_potentials(ot_assoc* h, const double* f, const double* g,
     h->J = J;
     h->res_par = 0;
     h->have_pot = true;
-    h->solved = false;
+    h->solved = h->loads_valid = false;
     return OT_OK;
 }
 
@@ -1264,7 +1311,7 @@ ot_status ot_assoc_cost_median(ot_assoc* h, const ot_cost_desc* cost, double* me
     uint64_t rank = (uint64_t)((I * J - 1) / 2);
     uint32_t prefix = 0;
     std::vector<unsigned long long> hh(2048);
-    h->solved = false;  // the handle's retained cost is replaced below
+    h->solved = h->loads_valid = false;  // the handle's retained cost is replaced below
     st = upload_cost(h, &c, kCheckNow);
     if (st) return st;
     st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
@@ -1306,7 +1353,7 @@ ot_status ot_assoc_materialize_cost(ot_assoc* h, const ot_cost_desc* cost, float
     if (st) return st;
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
     const int64_t I = cost->I, J = cost->J;
-    h->solved = false;  // the handle's retained cost is replaced below
+    h->solved = h->loads_valid = false;  // the handle's retained cost is replaced below
     st = upload_cost(h, cost, kCheckNow);
     if (st) return st;
     st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
@@ -1460,7 +1507,7 @@ ot_status ot_assoc_evaluate(ot_assoc* h, double kappa, double tau, double* rho, 
     if (st) return st;
     int nb = 0;
     if ((st = run_loads(h, rho_d, nb))) return st;
-    hipLaunchKernelGGL(k_rows_fin, dim3(1), dim3(64), 0, h->stream, (const double*)h->stat_part, nb, tot_d);
+    hipLaunchKernelGGL(k_rows_fin, dim3(1), dim3(256), 0, h->stream, (const double*)h->stat_part, nb, tot_d);
     std::vector<double> hr((size_t)J + 2);
     HIPCHK(h, hipMemcpyAsync(hr.data(), rho_d, sizeof(double) * J, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(hr.data() + J, tot_d, sizeof(double) * 2, hipMemcpyDeviceToHost, h->stream));
@@ -1494,7 +1541,7 @@ ot_status ot_assoc_maxsinr(ot_assoc* h, const ot_cost_desc* cost, const double* 
     if ((st = read_vec(h, a, I, cost->mem, ah))) return st;
     for (double v : ah)
         if (!(v >= 0.0) || !std::isfinite(v)) return fail(h, OT_EINVAL, "device traffic a must be non-negative and finite");
-    h->solved = false;  // the handle's retained cost is replaced below
+    h->solved = h->loads_valid = false;  // the handle's retained cost is replaced below
     HIPCHK(h, hipMemcpyAsync(h->a, ah.data(), sizeof(double) * I, hipMemcpyHostToDevice, h->stream));
     if ((st = upload_cost(h, cost, kCheckNow))) return st;
     // rows per workgroup: a multiple of the 64-row chunk, at most kMaxNb workgroups
@@ -1513,7 +1560,7 @@ ot_status ot_assoc_maxsinr(ot_assoc* h, const ot_cost_desc* cost, const double* 
     });
     if (!st) {
         double* lam_d = h->xch;
-        hipLaunchKernelGGL(k_cols_fin, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, h->stream,
+        hipLaunchKernelGGL(k_cols_fin, dim3((unsigned)((J + kFinCols - 1) / kFinCols)), dim3(1024), 0, h->stream,
                            (const double*)h->col_part, nb, J, 1.0, lam_d, (double*)nullptr);
         st = copy_out(h, Lambda, lam_d, sizeof(double) * J, cost->mem);
         if (!st && assoc && assoc_d != assoc)
@@ -1549,6 +1596,14 @@ ot_status ot_assoc_adaptive(ot_assoc* h, const ot_cost_desc* cost, const double*
     double* fb = q_d + h->J_max;
     double* gb = fb + h->I_max;
     auto release = [&]() {};
+    // the solves' final checks also sum the RRH loads (J <= 512), so that
+    // reading them needs no pass over the cost of its own
+    struct WantLoads {
+        ot_assoc* h;
+        bool prev;
+        ~WantLoads() { h->want_loads = prev; }
+    } want_guard{h, h->want_loads};
+    h->want_loads = true;
     ot_cost_desc dc = *cost;
     auto failed = [&](ot_status s) {
         release();
@@ -1568,7 +1623,7 @@ ot_status ot_assoc_adaptive(ot_assoc* h, const ot_cost_desc* cost, const double*
     } else if (cost->mem == OT_MEM_HOST) {
         return failed(fail(h, OT_EINVAL, "adaptive: pass geometry positions in device memory"));
     }
-    std::vector<double> qv((size_t)J, mass / J), best_q, loads((size_t)J);
+    std::vector<double> qv((size_t)J, mass / J), best_q, loads((size_t)J), best_loads;
     int best = -1, solves = 0, iters = 0;
     double best_max = 0.0, first_max = 0.0;
     ot_assoc_result best_res{};
@@ -1591,6 +1646,7 @@ ot_status ot_assoc_adaptive(ot_assoc* h, const ot_cost_desc* cost, const double*
         best = k;
         best_max = mx;
         best_q = qv;
+        best_loads = loads;
         best_res = res;
         HIPCHK(h, hipMemcpyAsync(fb, h->f[h->res_par], sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(gb, h->g[h->res_par], sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
@@ -1604,7 +1660,10 @@ ot_status ot_assoc_adaptive(ot_assoc* h, const ot_cost_desc* cost, const double*
     // the handle holds the best solve's potentials (same instance and eps)
     HIPCHK(h, hipMemcpyAsync(h->f[h->res_par], fb, sizeof(double) * I, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->g[h->res_par], gb, sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
+    // ... and that solve's loads
+    HIPCHK(h, hipMemcpyAsync(h->loads, best_loads.data(), sizeof(double) * J, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->loads_valid = h->solved;
     release();
     std::memcpy(q, best_q.data(), sizeof(double) * J);
     ot_adaptive_result r{};

@@ -186,3 +186,30 @@ def test_adaptive_sinkhorn_against_oracle(A, oracle_lib, I, J, seed):
     chk = oracle_lib.plan_stats(Cq, L.a, q, f, g, eps)
     assert chk["marginal_violation"] < tol * 1.05
     assert r.max_load <= r.first_max_load
+
+
+@pytest.mark.parametrize("I,J,seed", [(3000, 400, 6363), (2500, 600, 6464)])
+def test_adaptive_loads_from_the_final_check(A, oracle_lib, I, J, seed):
+    """Alg. 2's RRH loads: at J <= 512 the solves' final exact checks sum
+    them beside the marginals (the second case, J = 600, takes a pass of
+    their own). The returned loads against the oracle's loads of the handle's
+    potentials (1e-12), the reported maximum load equal to their maximum,
+    and rho_j = kappa load_j exactly."""
+    announce(f"Alg. 2 loads from the final check, {I} x {J}")
+    L = S.make_layout(I, J, 3000.0, hot_spots=2, hot_share=0.4, seed=seed)
+    C64, scale = oracle_lib.cost(L)
+    C32 = C64.astype(np.float32)
+    Cq = C32.astype(np.float64)
+    eps, tol, cap = 0.05, 1e-9, 3
+    with A.Solver(I, J) as s:
+        st, q, js, r = s.adaptive(*A.matrix_desc(C32, A.OT_COST_DENSE), L.a, eps, tol, 20000, 0.0, cap)
+        assert st == A.OT_OK
+        loads = s.rrh_loads()
+        f, g = s.potentials()
+        kappa = 0.5 / loads.max()
+        rho, en, ev = s.evaluate(kappa, 1.0)
+    np.testing.assert_allclose(loads, oracle_lib.rrh_loads(Cq, f, g, eps), rtol=1e-12)
+    assert loads.max() == r.max_load
+    np.testing.assert_array_equal(rho, kappa * loads)
+    assert 1 <= r.solves <= cap and (js[:r.solves] >= 0).all() and (js[:r.solves] < J).all()
+
