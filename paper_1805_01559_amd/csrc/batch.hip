@@ -550,6 +550,7 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
     char* marg_h = blob_h[set] + jobs_b + pads_b + geos_b;
     char* marg_d = blob_d[set] + jobs_b + pads_b + geos_b;
     int n_items = 0, n_insts = 0, n_pads = 0, n_geos = 0;
+    int64_t pad_rows = 0;  // rows of the largest padded copy
     std::vector<char*> stages;
     auto undo = [&]() {
         for (char* x : stages) pool.release(x);
@@ -647,7 +648,10 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
                 undo();
                 return st;
             }
-            if (pj.src) pads_h[n_pads++] = pj;
+            if (pj.src) {
+                pads_h[n_pads++] = pj;
+                pad_rows = std::max(pad_rows, pj.I);
+            }
             if (gj.dst) geos_h[n_geos++] = gj;
         }
         AdmJob& J1 = jobs_h[n_insts];
@@ -706,8 +710,10 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         const size_t used = (size_t)(marg_h - blob_h[set]);
         ECHK(this, hipMemcpyAsync(blob_d[set], blob_h[set], used, hipMemcpyHostToDevice, stream));
         if (n_pads)
-            hipLaunchKernelGGL(k_bpad_jobs, dim3(64, n_pads), dim3(256), 0, stream,
-                               (const PadJob*)(blob_d[set] + jobs_b));
+            hipLaunchKernelGGL(k_bpad_jobs,
+                               dim3((unsigned)std::min<int64_t>(256, (pad_rows + kPadRowsPerBlock - 1) / kPadRowsPerBlock),
+                                    n_pads),
+                               dim3(256), 0, stream, (const PadJob*)(blob_d[set] + jobs_b));
         const GeoJob* geos_d = (const GeoJob*)(blob_d[set] + jobs_b + pads_b);
         if (pre_blocks)
             hipLaunchKernelGGL(k_bgeo_prepass_jobs, dim3(pre_blocks), dim3(256), 0, stream, geos_d, n_geos);

@@ -435,18 +435,35 @@ struct PadJob {
     int pad_;
 };
 
-__global__ void k_bpad_jobs(const PadJob* __restrict__ jobs) {
+// One wavefront per row (4 per workgroup, rows grid-strided over
+// gridDim.x workgroups per job): lane l writes the 16-byte groups l, l + 64,
+// ... of the padded row (ld / 4 <= 128 of them), reading its four source
+// elements one by one (the source stride need not be a multiple of 4).
+constexpr int kPadRowsPerBlock = 4;
+__global__ __launch_bounds__(256) void k_bpad_jobs(const PadJob* __restrict__ jobs) {
     const PadJob& P = jobs[blockIdx.y];
-    const int64_t n = P.I * P.ld;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / P.ld;
-        const int j = (int)(e - i * P.ld);
-        float v = __builtin_huge_valf();
-        if (j < P.J) {
-            const double x = P.f64 ? ((const double*)P.src)[i * P.lds + j] : (double)((const float*)P.src)[i * P.lds + j];
-            v = P.kind == 0 ? (float)x : (float)((1.0 / x) * P.inv_scale);
+    const int lane = threadIdx.x & 63;
+    const int nq = (int)(P.ld / 4);
+    const float* s32 = (const float*)P.src;
+    const double* s64 = (const double*)P.src;
+    for (int64_t i = (int64_t)blockIdx.x * kPadRowsPerBlock + (threadIdx.x >> 6); i < P.I;
+         i += (int64_t)gridDim.x * kPadRowsPerBlock) {
+        float4* drow = reinterpret_cast<float4*>(P.dst + i * P.ld);
+        const int64_t e0 = i * P.lds;
+        for (int q = lane; q < nq; q += 64) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = 4 * q + u;
+                float x = __builtin_huge_valf();
+                if (j < P.J) {
+                    const double c = P.f64 ? s64[e0 + j] : (double)s32[e0 + j];
+                    x = P.kind == 0 ? (float)c : (float)((1.0 / c) * P.inv_scale);
+                }
+                v[u] = x;
+            }
+            drow[q] = make_float4(v[0], v[1], v[2], v[3]);
         }
-        P.dst[e] = v;
     }
 }
 

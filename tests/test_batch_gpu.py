@@ -232,7 +232,11 @@ def test_batch_constant_cost_closed_form(A):
 
 
 def test_batch_row_padded_inputs_in_place(A, oracle_lib, inst):
-    announce("batch of row-padded device matrices (NaN padding): J % 4 == 0 in place, others copied")
+    """Row-padded device matrices whose padding holds NaN: those with J a
+    multiple of 4 are referenced in place (no 16-byte vector reaches the
+    padding), the others copied into the engine's +inf-padded layout; against
+    the oracle, and bitwise equal to the same instances copied from the host."""
+    announce("batch of row-padded device matrices (NaN padding), and the same costs copied from the host")
     import torch
     dev = torch.device("cuda:0")
     picks = [0, 2, 3, 4, 5]
@@ -248,12 +252,19 @@ def test_batch_row_padded_inputs_in_place(A, oracle_lib, inst):
         costs.append(A.matrix_desc(t, A.OT_COST_DENSE, J=J))
         aa.append(torch.from_numpy(x["L"].a).to(dev))
         bb.append(torch.from_numpy(x["L"].b).to(dev))
-    with A.Solver(16, 16) as s:
+    with A.Solver(16, 16, batch_tune=0) as s:
         st, res = s.solve_batch(costs, aa, bb, EPS, TOL, 2000)
         assert st == A.OT_OK, [r.status for r in res]
+        placed = [s.batch_potentials(q) for q in range(len(picks))]
         for q, k in enumerate(picks):
+            check(oracle_lib, inst[k], *placed[q], res[q])
+        st, res2 = s.solve_batch([inst[k]["C32"] for k in picks], [inst[k]["L"].a for k in picks],
+                                 [inst[k]["L"].b for k in picks], EPS, TOL, 2000)
+        assert st == A.OT_OK
+        for q in range(len(picks)):
             f, g = s.batch_potentials(q)
-            check(oracle_lib, inst[k], f, g, res[q])
+            assert np.array_equal(f, placed[q][0]) and np.array_equal(g, placed[q][1]), picks[q]
+            assert res2[q].iterations == res[q].iterations
 
 
 def test_batch_256_uneven_tuned_against_oracle(A, oracle_lib):
