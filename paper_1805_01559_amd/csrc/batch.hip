@@ -39,6 +39,7 @@ using namespace otk;
 namespace {
 
 constexpr int kChunk = 8;  // iterations per captured chunk (even: list generations alternate)
+constexpr int64_t kTailItems = 256;  // at most this many items left: the chunk runs on the tail grids
 constexpr double kBatchStallBelow = 1e-7;  // FP32 sweeps are not trusted below this residual
 constexpr size_t kAlign = 256;
 
@@ -216,11 +217,14 @@ struct BatchEngine {
     std::vector<int> free_slots;
     int hi_slot = 0;  // slots [0, hi_slot) may be live
     int n_live_running = 0;
-    int64_t items_running = 0;  // parts of admitted, unfinished instances (bounds the lists)
+    int64_t items_running = 0;  // parts at the finest layout of admitted, unfinished instances (bounds the lists)
     long seq = 0;               // snapshots taken so far
 
-    // captured chunks, per FP32 workgroup size
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // captured chunks, per FP32 workgroup size (wi) and grid set (bulk, or the
+    // tail: at most kTailItems items left at the finest layout, launched on
+    // smaller grids); index 2 wi + tail
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    int graph_polish[4] = {-1, -1, -1, -1};  // polish_iters each graph was captured with
     int grid32[2] = {0, 0}, grid64 = 0, gridc = 0;
     size_t lds32[2] = {0, 0}, lds64 = 0;
 
@@ -250,6 +254,7 @@ struct BatchEngine {
     std::string tune_key(const std::vector<int>& batch_slots) const;
     ot_status relayout(const std::vector<int>& batch_slots, int w, int64_t rpp);
     int widx() const { return waves == 4 ? 0 : 1; }
+    int gidx() const { return 2 * widx() + (items_running <= kTailItems ? 1 : 0); }
 };
 
 #define ECHK(e, call)                                                                                          \
@@ -366,8 +371,19 @@ ot_status BatchEngine::prepare_kernels() {
     return OT_OK;
 }
 
-ot_status BatchEngine::capture(int wi) {
-    if (graph[wi]) return OT_OK;
+ot_status BatchEngine::capture(int gi) {
+    if (graph[gi] && graph_polish[gi] == polish_iters) return OT_OK;
+    if (graph[gi]) {
+        hipGraphExecDestroy(graph[gi]);
+        graph[gi] = nullptr;
+    }
+    const int wi = gi >> 1;
+    const bool tail = (gi & 1) != 0;
+    // (grid sizes only change which workgroup takes which item: results are
+    // the same on either grid set)
+    const int g32 = tail ? std::min(grid32[wi], num_cu) : grid32[wi];
+    const int g64 = tail ? std::min(grid64, 64) : grid64;
+    const int gc = tail ? std::min(gridc, 32) : gridc;
     BParams P{polish_iters, kBatchStallBelow};
     hipGraph_t g = nullptr;
     ECHK(this, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -376,18 +392,19 @@ ot_status BatchEngine::capture(int wi) {
         const BList& out = L[(t + 1) & 1];
         const BInst* T = tab;
         if (wi == 0)
-            hipLaunchKernelGGL((k_bsweep<false, 4>), dim3(grid32[0]), dim3(256), lds32[0], stream, T,
+            hipLaunchKernelGGL((k_bsweep<false, 4>), dim3(g32), dim3(256), lds32[0], stream, T,
                                (const BItem*)in.it32, (const int*)in.cnt, out.cnt);
         else
-            hipLaunchKernelGGL((k_bsweep<false, 8>), dim3(grid32[1]), dim3(512), lds32[1], stream, T,
+            hipLaunchKernelGGL((k_bsweep<false, 8>), dim3(g32), dim3(512), lds32[1], stream, T,
                                (const BItem*)in.it32, (const int*)in.cnt, out.cnt);
-        hipLaunchKernelGGL((k_bsweep<true, 8>), dim3(grid64), dim3(512), lds64, stream, T, (const BItem*)in.it64,
+        hipLaunchKernelGGL((k_bsweep<true, 8>), dim3(g64), dim3(512), lds64, stream, T, (const BItem*)in.it64,
                            (const int*)in.cnt, out.cnt);
-        hipLaunchKernelGGL(k_bcombine, dim3(gridc), dim3(1024), 0, stream, tab, in, out, P);
+        hipLaunchKernelGGL(k_bcombine, dim3(gc), dim3(1024), 0, stream, tab, in, out, P);
     }
     hipError_t e1 = hipStreamEndCapture(stream, &g);
     if (e1 != hipSuccess) return fail(OT_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
-    hipError_t e2 = hipGraphInstantiate(&graph[wi], g, nullptr, nullptr, 0);
+    graph_polish[gi] = polish_iters;
+    hipError_t e2 = hipGraphInstantiate(&graph[gi], g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e2 != hipSuccess) return fail(OT_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e2));
     return OT_OK;
@@ -550,6 +567,7 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
     char* marg_h = blob_h[set] + jobs_b + pads_b + geos_b;
     char* marg_d = blob_d[set] + jobs_b + pads_b + geos_b;
     int n_items = 0, n_insts = 0, n_pads = 0, n_geos = 0;
+    int64_t n_cap = 0;  // items of this admission at the finest layout
     int64_t pad_rows = 0;  // rows of the largest padded copy
     std::vector<char*> stages;
     auto undo = [&]() {
@@ -566,13 +584,16 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         const ot_cost_desc* c = r.cost;
         const int64_t I = c->I;
         const int J = (int)c->J;
-        const int parts_cap = (int)parts_of(I, 64);  // the finest layout the tuner may choose
+        // the finest layout: the tuner's smallest rows per part and the layout of
+        // instances still running after kFineIter iterations (item counts and
+        // the partial buffers are bounded by it)
+        const int parts_cap = (int)parts_of(I, kFineRows);
         const int parts = (int)parts_of(I, rpp);
         const int64_t lds = c->ld ? c->ld : J;
         const bool ref = c->kind == OT_COST_DENSE && c->mem == OT_MEM_DEVICE && c->dtype == OT_F32 && J % 4 == 0 &&
                          lds % 4 == 0 && ((uintptr_t)c->data % 16) == 0;
         const int64_t ld = ref ? lds : (J + 3) / 4 * 4;
-        if (free_slots.empty() || items_running + n_items + parts > cap_items) {
+        if (free_slots.empty() || items_running + n_cap + parts_cap > cap_items) {
             if (strict) {
                 undo();
                 return fail(OT_ENOMEM, "batch exceeds %d slots / %d work items", cap_slots, cap_items);
@@ -691,6 +712,7 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         J1.item_base = n_items;
         J1.inst_pos = n_insts;
         n_items += parts;
+        n_cap += parts_cap;
         ++n_insts;
         sl.t_admit = now_s();
         sl.adm_seq = seq;
@@ -727,7 +749,7 @@ ot_status BatchEngine::admit(const std::vector<AdmitReq>& reqs, std::vector<int>
         adm_pending[set] = true;
         adm_set ^= 1;
         n_live_running += n_insts;
-        items_running += n_items;
+        items_running += n_cap;
     }
     for (char* x : stages) pool.release(x);
     return OT_OK;
@@ -759,7 +781,7 @@ void BatchEngine::release(int k) {
     if (!s.live) return;
     if (!s.finished) {
         --n_live_running;
-        items_running -= s.d.parts;
+        items_running -= s.parts_cap;
     }
     pool.release(s.mem);
     s = Slot{};
@@ -768,8 +790,9 @@ void BatchEngine::release(int k) {
 }
 
 ot_status BatchEngine::launch_chunk() {
-    if (ot_status st = capture(widx())) return st;
-    ECHK(this, hipGraphLaunch(graph[widx()], stream));
+    const int gi = gidx();
+    if (ot_status st = capture(gi)) return st;
+    ECHK(this, hipGraphLaunch(graph[gi], stream));
     ++chunks;
     return OT_OK;
 }
@@ -803,7 +826,7 @@ void BatchEngine::apply_snapshot(int which, int hi, std::vector<int>* finished) 
             s.fin = c;
             s.finished = true;
             --n_live_running;
-            items_running -= s.d.parts;
+            items_running -= s.parts_cap;
             if (finished) finished->push_back(k);
         }
     }
@@ -828,10 +851,8 @@ ot_status BatchEngine::relayout(const std::vector<int>& ks, int w, int64_t rpp) 
     const int n = (int)ks.size();
     for (int q = 0; q < n; ++q) {
         Slot& s = slots[ks[q]];
-        items_running -= s.d.parts;
         s.d.rpp = rpp;
         s.d.parts = (int)parts_of(s.I, rpp);
-        items_running += s.d.parts;
         relay_h[q] = ks[q];
         relay_h[n + q] = n_items;
         n_items += s.d.parts;

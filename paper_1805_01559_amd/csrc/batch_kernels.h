@@ -159,11 +159,18 @@ __global__ __launch_bounds__(WAVES * kWave) void k_bsweep(const BInst* __restric
 // group sums its parts (every PG-th) sixteen loads at a time in a fixed
 // tree, and the groups' sums are added in group order, so each column's sum
 // has one fixed order for given J and part count.
+// An instance still running after kFineIter iterations (the few slow ones
+// that remain at the end of a batch) continues in parts of kFineRows rows, so
+// that a sweep spreads it over more workgroups when little else runs. The
+// switch depends on the instance's own iteration count only, so its result
+// does not depend on its neighbours in the batch.
 constexpr int kCombLoads = 16;
-__global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, BList out, BParams P) {
+constexpr int kFineIter = 32;
+constexpr int64_t kFineRows = 64;
+__global__ __launch_bounds__(1024) void k_bcombine(BInst* tab, BList in, BList out, BParams P) {
     __shared__ double red[1024];
     __shared__ double wsum[16][7];
-    __shared__ int s_bad, s_list, s_base, s_flags;
+    __shared__ int s_bad, s_list, s_base, s_flags, s_parts;
     const int n = in.cnt[2];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int q = blockIdx.x; q < n; q += gridDim.x) {
@@ -295,16 +302,23 @@ __global__ __launch_bounds__(1024) void k_bcombine(const BInst* tab, BList in, B
             }
             s_list = next;
             if (next >= 0) {
+                int np = parts;
+                if (ctl->iter >= kFineIter && d.rpp > kFineRows) {
+                    np = (int)((d.I + kFineRows - 1) / kFineRows);
+                    tab[k].rpp = kFineRows;
+                    tab[k].parts = np;
+                }
+                s_parts = np;
                 const int par = (next == 2 ? ctl->check_iter : ctl->iter) & 1;
                 s_flags = (ctl->has_prev ? kItPrev : 0) | (par ? kItPar : 0) | (next == 2 ? kItCheck : 0);
-                s_base = atomicAdd(&out.cnt[next == 0 ? 0 : 1], parts);
+                s_base = atomicAdd(&out.cnt[next == 0 ? 0 : 1], np);
                 out.inst[atomicAdd(&out.cnt[2], 1)] = k;
             }
         }
         __syncthreads();
         if (s_list >= 0) {
             BItem* dst = (s_list == 0 ? out.it32 : out.it64) + s_base;
-            for (int p = tid; p < parts; p += 1024) dst[p] = BItem{k, p, s_flags, 0};
+            for (int p = tid; p < s_parts; p += 1024) dst[p] = BItem{k, p, s_flags, 0};
         }
         __syncthreads();  // shared state is rewritten by the next instance
     }
