@@ -238,6 +238,19 @@ ot_status ot_assoc_solve_static(int device, void *stream, const float *C, int64_
  * replaced the retained cost, OT_EINVAL for NULL pi. */
 ot_status ot_assoc_plan(ot_assoc *h, void *pi, ot_mem mem, ot_dtype dtype);
 
+/* Asks the following solves on the handle to write their plan (as
+ * ot_assoc_plan would, element type `dtype`) into the device buffer pi,
+ * from the cells their final exact check computes anyway, so that the plan
+ * takes no pass over the cost of its own (Sec. III-B output step). pi must
+ * hold I x J elements of every instance solved while it is set (I_max x
+ * J_max always suffice) and stay valid; NULL stops it. A following
+ * ot_assoc_plan(h, pi, OT_MEM_DEVICE, dtype) with the same buffer and type
+ * returns at once; any other plan call, and a solve that ends without that
+ * check (rejected inputs, a numeric failure), computes the plan as before.
+ * The solves of ot_assoc_adaptive do not write it. Errors: OT_EINVAL for a
+ * bad dtype. */
+ot_status ot_assoc_set_plan_output(ot_assoc *h, void *pi, ot_dtype dtype);
+
 /* Copies out the FP64 potentials (f: I, g: J) of the last solve. Either
  * pointer may be NULL. Errors: OT_ESTATE before any solve. */
 ot_status ot_assoc_potentials(ot_assoc *h, double *f, double *g, ot_mem mem);

@@ -87,6 +87,10 @@ struct ot_assoc {
     bool want_loads = false;   // checks also sum the RRH loads into `loads` (Alg. 2's solves)
     bool loads_fresh = false;  // the last check did, for the potentials it checked
     bool loads_valid = false;  // `loads` holds the loads of the returned potentials
+    void* plan_out = nullptr;  // device plan the checks write (ot_assoc_set_plan_output), or null
+    int plan_dtype = 0;        // OT_F32 / OT_F64 of plan_out
+    bool plan_fresh = false;   // the last check wrote plan_out for the potentials it checked
+    bool plan_valid = false;   // plan_out holds the plan of the returned potentials
     double eps = 0.0;
     ot_cost_desc last{};       // descriptor of the retained cost (pointers below replace the caller's)
     const void* cost_dev = nullptr;  // device copy (host inputs) or the caller's device matrix

@@ -516,12 +516,17 @@ struct CheckArgs {
     double* stat_part;  // gridDim.x x 5
     const SolveParams* prm;
     double* load_part;  // gridDim.x x J partial RRH loads (the instantiation with loads only)
+    void* plan_out;     // I x J row-major plan, FP32 or FP64 (the instantiations with a plan only)
+    int plan_f64;
 };
 
 // The exact statistics of rows [r0, r1) by one workgroup (one wavefront per
 // row): column partials of pi and the five row statistics; with LOADS also
 // the column partials of c_ij pi_ij, the RRH loads of Sec. II-B, from the same
-// cells (so the loads of the returned plan need no pass of their own).
+// cells (so the loads of the returned plan need no pass of their own); with
+// PlanT float or double it also writes each pi_ij it computes, in that type,
+// to the row-major plan (so a plan asked for before the solve needs no pass
+// of its own either).
 struct CheckJob {
     int64_t r0, r1;
     int J;
@@ -533,10 +538,12 @@ struct CheckJob {
     double* col_out;   // J
     double* stat_out;  // 5
     double* load_out = nullptr;  // J: sum_i c_ij pi_ij of the rows (with LOADS)
+    void* plan_out = nullptr;    // I x J row-major plan of PlanT (with PlanT not void)
 };
 
-template <class Src, int VEC, int NCH, int WAVES, bool LOADS = false>
+template <class Src, int VEC, int NCH, int WAVES, bool LOADS = false, typename PlanT = void>
 __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
+    constexpr bool kPlan = !std::is_void<PlanT>::value;
     extern __shared__ double sm[];
     const double kk = A.kk;
     const int J = A.J, nch = A.nch;
@@ -585,6 +592,8 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
         auto row = src.row(i);
         const double fk = fi * kk;
         double rs = 0.0;
+        using PlanS = typename std::conditional<kPlan, PlanT, float>::type;
+        PlanS* prow = kPlan ? reinterpret_cast<PlanS*>(A.plan_out) + i * (int64_t)J : nullptr;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             if (ch < nch) {
@@ -603,6 +612,9 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
                     ent = fma(p, t * kLn2 - 1.0, ent);
                     acc[ch][v] += p;
                     if constexpr (LOADS) accl[ch][v] = fma(c, p, accl[ch][v]);
+                    if constexpr (kPlan) {
+                        if (ok) prow[col0 + v] = (PlanS)p;
+                    }
                 }
             }
         }
@@ -787,7 +799,7 @@ __device__ __forceinline__ void check_rows_g(const CheckJob& A, const Src& src) 
     }
 }
 
-template <class Src, int VEC, int NCH, int WAVES, bool LOADS = false>
+template <class Src, int VEC, int NCH, int WAVES, bool LOADS = false, typename PlanT = void>
 __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
     CheckJob job;
     job.r0 = (int64_t)blockIdx.x * A.rows_per_block;
@@ -801,7 +813,8 @@ __global__ __launch_bounds__(WAVES * kWave) void k_check(CheckArgs A, Src src) {
     job.col_out = A.col_part + (int64_t)blockIdx.x * A.J;
     job.stat_out = A.stat_part + (int64_t)blockIdx.x * 5;
     if constexpr (LOADS) job.load_out = A.load_part + (int64_t)blockIdx.x * A.J;
-    check_rows<Src, VEC, NCH, WAVES, LOADS>(job, src);
+    job.plan_out = A.plan_out;
+    check_rows<Src, VEC, NCH, WAVES, LOADS, PlanT>(job, src);
 }
 
 // Column sums of the check: per column |colsum_j - b_j| and g_j b_j, summed

@@ -225,6 +225,16 @@ bool launch_check_v(const Shape& s, const CheckArgs& A, const Src& src, hipStrea
         hipLaunchKernelGGL(kern, dim3(s.nb), dim3(512), lds, st, A, src);
         return true;
     }
+    if (A.plan_out) {  // the check that also writes the plan
+        auto pick = [&](auto narrow, auto wide) {
+            auto kern = s.nch <= kNarrow ? narrow : wide;
+            set_lds(kern, lds);
+            hipLaunchKernelGGL(kern, dim3(s.nb), dim3(512), lds, st, A, src);
+        };
+        if (A.plan_f64) pick(k_check<Src, VEC, kNarrow, 8, false, double>, k_check<Src, VEC, kWide, 8, false, double>);
+        else pick(k_check<Src, VEC, kNarrow, 8, false, float>, k_check<Src, VEC, kWide, 8, false, float>);
+        return true;
+    }
     if (s.nch <= kNarrow) {
         auto kern = k_check<Src, VEC, kNarrow, 8>;
         set_lds(kern, lds);

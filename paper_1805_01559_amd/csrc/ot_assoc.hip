@@ -547,7 +547,9 @@ struct Solver {
         A.a = h->a; A.f = h->f[k & 1]; A.g = h->g[k & 1];
         A.col_part = h->col_part; A.stat_part = h->stat_part; A.prm = h->prm;
         A.load_part = fuse ? h->col_part + (size_t)cs.nb * (size_t)J : nullptr;
-        h->loads_fresh = false;
+        A.plan_out = fuse ? nullptr : h->plan_out;  // (Alg. 2's solves sum the loads; their plans are not asked for)
+        A.plan_f64 = h->plan_dtype == OT_F64 ? 1 : 0;
+        h->loads_fresh = h->plan_fresh = false;
         if (!launch_check<Src>(cs, A, src, h->stream)) return fail(h, OT_EINVAL, "no check kernel for this shape");
         CheckColArgs B{};
         const int ncb = (J + kColsPerWg - 1) / kColsPerWg;
@@ -557,6 +559,7 @@ struct Solver {
         hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(256), 0, h->stream, (const double*)h->stat_part, cs.nb,
                            (const double*)h->cpart, ncb, h->ctl, (const SolveParams*)h->prm);
         h->loads_fresh = fuse;
+        h->plan_fresh = A.plan_out != nullptr;
         after();
         ot_status st = snapshot(0);
         if (st || (st = wait(0))) return st;
@@ -770,13 +773,13 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
     }
     if (c.done) {  // inputs rejected, or a numeric failure in the fast phase
         result_iter = c.result_iter;
-        h->loads_fresh = false;
+        h->loads_fresh = h->plan_fresh = false;
         return OT_OK;
     }
     if (!checked && (st = S.run_check<Src>(src, c.iter, c))) return st;
     if (c.done) {  // inputs rejected (seen first by the check of an FP64-precision solve)
         result_iter = c.result_iter;
-        h->loads_fresh = false;
+        h->loads_fresh = h->plan_fresh = false;
         return OT_OK;
     }
     result_iter = c.iter;
@@ -1034,6 +1037,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
         return fail(h, OT_ESTATE, "warm start needs potentials of a %lld x %lld instance", (long long)I, (long long)J);
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
     h->loads_valid = h->loads_fresh = false;
+    h->plan_valid = h->plan_fresh = false;
     // marginals, constants and the initial control block are set up and
     // checked on the device (no host round trip before the first sweep)
     const int res_par_prev = h->res_par;
@@ -1083,7 +1087,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
             return solve_with(h, src, data, I, (int)J, tol, max_iter, fin, result_iter);
         });
     if (st) {
-        h->solved = h->loads_valid = false;
+        h->solved = h->loads_valid = h->plan_valid = false;
         h->have_pot = false;
         h->retained = false;
         return st;
@@ -1099,7 +1103,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
     HIPCHK(h, hipGetLastError());
 
     if (fin.input_bad) {  // rejected on the device: the handle keeps no result
-        h->solved = h->loads_valid = false;
+        h->solved = h->loads_valid = h->plan_valid = false;
         h->have_pot = false;
         h->retained = false;
         const int fb = fin.input_bad;
@@ -1113,7 +1117,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
                                                               : "rate matrix has entries that are not finite and positive");
     }
     if (fin.sync_fail) {
-        h->solved = h->loads_valid = false;
+        h->solved = h->loads_valid = h->plan_valid = false;
         h->have_pot = false;
         return fail(h, OT_EDEVICE, "a grid barrier of the cooperative FP32 phase gave up waiting");
     }
@@ -1127,6 +1131,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
     else if (!(fin.chk_violation < tol)) rs = OT_WARN_MAXITER;
     h->solved = (rs >= 0);
     h->loads_valid = h->solved && h->loads_fresh;
+    h->plan_valid = h->solved && h->plan_fresh;
     if (out) {
         out->iterations = result_iter;
         out->fp64_iterations = fin.fp64_iters;
@@ -1225,6 +1230,16 @@ ot_status ot_assoc_solve_static(int device, void* stream, const float* C, int64_
     return st;
 }
 
+ot_status ot_assoc_set_plan_output(ot_assoc* h, void* pi, ot_dtype dtype) {
+    if (!h) return OT_EINVAL;
+    h->err.clear();
+    if (pi && dtype != OT_F32 && dtype != OT_F64) return fail(h, OT_EINVAL, "bad dtype");
+    h->plan_out = pi;
+    h->plan_dtype = dtype;
+    h->plan_valid = h->plan_fresh = false;
+    return OT_OK;
+}
+
 ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
     if (!h) return OT_EINVAL;
     h->err.clear();
@@ -1232,6 +1247,8 @@ ot_status ot_assoc_plan(ot_assoc* h, void* pi, ot_mem mem, ot_dtype dtype) {
     if (!pi) return fail(h, OT_EINVAL, "plan buffer is NULL");
     if (dtype != OT_F32 && dtype != OT_F64) return fail(h, OT_EINVAL, "bad dtype");
     if (mem != OT_MEM_HOST && mem != OT_MEM_DEVICE) return fail(h, OT_EINVAL, "bad memory space");
+    // written by the solve's final check already (the solve waited for it)
+    if (h->plan_valid && mem == OT_MEM_DEVICE && pi == h->plan_out && (int)dtype == h->plan_dtype) return OT_OK;
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
     const int64_t I = h->I, J = h->J;
     const size_t esz = dtype == OT_F32 ? 4 : 8;
@@ -1291,7 +1308,7 @@ ot_status ot_assoc_set_potentials(ot_assoc* h, const double* f, const double* g,
     h->J = J;
     h->res_par = 0;
     h->have_pot = true;
-    h->solved = h->loads_valid = false;
+    h->solved = h->loads_valid = h->plan_valid = false;
     return OT_OK;
 }
 
@@ -1311,7 +1328,7 @@ ot_status ot_assoc_cost_median(ot_assoc* h, const ot_cost_desc* cost, double* me
     uint64_t rank = (uint64_t)((I * J - 1) / 2);
     uint32_t prefix = 0;
     std::vector<unsigned long long> hh(2048);
-    h->solved = h->loads_valid = false;  // the handle's retained cost is replaced below
+    h->solved = h->loads_valid = h->plan_valid = false;  // the handle's retained cost is replaced below
     st = upload_cost(h, &c, kCheckNow);
     if (st) return st;
     st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
@@ -1353,7 +1370,7 @@ ot_status ot_assoc_materialize_cost(ot_assoc* h, const ot_cost_desc* cost, float
     if (st) return st;
     if (hipSetDevice(h->device) != hipSuccess) return fail(h, OT_EDEVICE, "hipSetDevice failed");
     const int64_t I = cost->I, J = cost->J;
-    h->solved = h->loads_valid = false;  // the handle's retained cost is replaced below
+    h->solved = h->loads_valid = h->plan_valid = false;  // the handle's retained cost is replaced below
     st = upload_cost(h, cost, kCheckNow);
     if (st) return st;
     st = with_retained(h, [&](const auto& src, const void*) -> ot_status {
@@ -1541,7 +1558,7 @@ ot_status ot_assoc_maxsinr(ot_assoc* h, const ot_cost_desc* cost, const double* 
     if ((st = read_vec(h, a, I, cost->mem, ah))) return st;
     for (double v : ah)
         if (!(v >= 0.0) || !std::isfinite(v)) return fail(h, OT_EINVAL, "device traffic a must be non-negative and finite");
-    h->solved = h->loads_valid = false;  // the handle's retained cost is replaced below
+    h->solved = h->loads_valid = h->plan_valid = false;  // the handle's retained cost is replaced below
     HIPCHK(h, hipMemcpyAsync(h->a, ah.data(), sizeof(double) * I, hipMemcpyHostToDevice, h->stream));
     if ((st = upload_cost(h, cost, kCheckNow))) return st;
     // rows per workgroup: a multiple of the 64-row chunk, at most kMaxNb workgroups

@@ -32,7 +32,7 @@ OT_RESULT_CHECK_ABOVE_TOL = 2
 # every symbol include/ot_assoc.h declares
 EXPORTS = [
     "ot_assoc_default_options", "ot_assoc_workspace_size", "ot_assoc_device_allocations", "ot_assoc_create",
-    "ot_assoc_solve_static", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_potentials",
+    "ot_assoc_solve_static", "ot_assoc_solve", "ot_assoc_plan", "ot_assoc_set_plan_output", "ot_assoc_potentials",
     "ot_assoc_set_potentials", "ot_assoc_cost_median", "ot_assoc_materialize_cost", "ot_assoc_time_sweep", "ot_assoc_time_read",
     "ot_assoc_test_hold_exchange",
     "ot_assoc_fast_phase_time", "ot_assoc_rrh_loads", "ot_assoc_evaluate", "ot_assoc_maxsinr", "ot_assoc_adaptive",
@@ -120,6 +120,7 @@ def lib():
         L.ot_assoc_solve_static.argtypes = [ct.c_int, vp, vp, i64, i64, i64, vp, vp, d, d, ct.c_int32, ct.c_int, vp,
                                             vp, ct.POINTER(ot_assoc_result)]
         L.ot_assoc_plan.argtypes = [vp, vp, ct.c_int, ct.c_int]
+        L.ot_assoc_set_plan_output.argtypes = [vp, vp, ct.c_int]
         L.ot_assoc_potentials.argtypes = [vp, vp, vp, ct.c_int]
         L.ot_assoc_set_potentials.argtypes = [vp, vp, vp, i64, i64, ct.c_int]
         L.ot_assoc_cost_median.argtypes = [vp, ct.POINTER(ot_cost_desc), ct.POINTER(d)]
@@ -576,6 +577,22 @@ class Solver:
             raise ValueError("numpy plan buffer must be contiguous")
         ot_assoc_plan(self.h, p, m, OT_F32 if dt == np.float32 else OT_F64)
         return out
+
+    def set_plan_output(self, out):
+        """Have the following solves write their plan into the device tensor
+        `out` (float32 or float64, at least I x J elements) from their final
+        check; plan(out) then returns at once. None stops it."""
+        if out is None:
+            _check(self.h, lib().ot_assoc_set_plan_output(self.h, None, OT_F32))
+            self._plan_keep = None
+            return
+        if not _is_torch(out) or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("the plan output must be a contiguous device tensor")
+        dt = OT_F32 if str(out.dtype) == "torch.float32" else OT_F64 if str(out.dtype) == "torch.float64" else None
+        if dt is None:
+            raise ValueError("the plan output must be float32 or float64")
+        _check(self.h, lib().ot_assoc_set_plan_output(self.h, ct.c_void_p(out.data_ptr()), dt))
+        self._plan_keep = out
 
     def potentials(self):
         f = np.empty(self._I)

@@ -346,3 +346,62 @@ def test_dense_row_padded_matrix(A, oracle_lib, torch_mod, where):
         ref, ref_stats = oracle_ref(oracle_lib, Cq, L.a, L.b, 0.05)
         check_against(oracle_lib, Cq, L.a, L.b, 0.05, 1e-9, f, g, res, ref_stats, ref)
         assert np.allclose(P, oracle_lib.plan(Cq, f, g, 0.05), rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("kind,I,J,persistent,tol", [
+    ("dense", 1000, 50, 1, 1e-9), ("dense", 1000, 50, 0, 1e-11), ("dense", 777, 1031, 1, 1e-8),
+    ("geometry", 2000, 120, 1, 1e-9), ("geometry", 1500, 600, 0, 1e-8)])
+def test_plan_written_by_the_final_check(A, oracle_lib, torch_mod, kind, I, J, persistent, tol):
+    """A plan asked for before the solve (ot_assoc_set_plan_output) is written
+    by the final exact check from the cells it computes: against the plan
+    pass over the same potentials (FP64 within a few ulps of its FP64
+    exponentials, FP32 equal up to one ulp) and against the oracle's plan of
+    those potentials (1e-12; for geometry costs on the entries above 1e-12 of
+    the largest, as the two sides' FP64 costs differ by ulps that an exponent
+    of a few hundred amplifies in the tiny ones). tol 1e-11 makes the check
+    miss on the FP32 path
+    and run the FP64 phase and a second check, whose plan must be the one
+    left."""
+    torch = torch_mod
+    announce(f"plan from the final check, {kind} {I}x{J}, persistent={persistent}, tol={tol}")
+    dev = torch.device("cuda:0")
+    eps = 0.05
+    L = S.make_layout(I, J, 2000.0, hot_spots=2, hot_share=0.4, seed=7100 + I + J)
+    a = torch.from_numpy(L.a).to(dev)
+    b = torch.from_numpy(L.b).to(dev)
+    with A.Solver(I, J, persistent=persistent) as s:
+        if kind == "dense":
+            C64, _ = oracle_lib.cost(L)
+            C32 = C64.astype(np.float32)
+            Cq = C32.astype(np.float64)
+            Cd = torch.from_numpy(C32).to(dev)
+            solve = lambda: s.solve_dense(Cd, a, b, eps, tol, 20000)
+        else:
+            xy = torch.from_numpy(L.dev_xy).to(dev)
+            rxy = torch.from_numpy(L.rrh_xy).to(dev)
+            d, keep = A.geometry_desc(xy, rxy, L.radio, L.shadow_key, 1.0)
+            scale = s.cost_median(d)
+            Cq, _ = oracle_lib.cost(L, scale=scale)
+            solve = lambda: s.solve_geometry(xy, rxy, L.radio, L.shadow_key, scale, a, b, eps, tol, 20000)
+        for dt in (torch.float64, torch.float32):
+            fused = torch.full((I, J), float("nan"), dtype=dt, device=dev)
+            s.set_plan_output(fused)
+            st, res = solve()
+            assert st == A.OT_OK
+            back = s.plan(fused)  # returns at once: written by the check
+            assert back is fused
+            s.set_plan_output(None)
+            sep = s.plan(torch.empty((I, J), dtype=dt, device=dev))
+            P, Q = fused.cpu().numpy(), sep.cpu().numpy()
+            assert np.isfinite(P).all()
+            if dt == torch.float64:
+                np.testing.assert_allclose(P, Q, rtol=4e-15, atol=1e-300)
+                f, g = s.potentials()
+                R = oracle_lib.plan(Cq, f, g, eps)
+                # (geometry: the two sides' FP64 costs differ by ulps, which an
+                # exponent of a few hundred carries into the tiny entries; the
+                # entries that carry mass are held to 1e-12)
+                m = R > 1e-12 * R.max() if kind == "geometry" else np.ones(R.shape, bool)
+                np.testing.assert_allclose(P[m], R[m], rtol=1e-12, atol=1e-300)
+            else:
+                assert (np.abs(P - Q) <= np.spacing(np.maximum(np.abs(P), np.abs(Q))) * 1.0 + 1e-45).all()
