@@ -239,17 +239,17 @@ ot_status ot_assoc_solve_static(int device, void *stream, const float *C, int64_
 ot_status ot_assoc_plan(ot_assoc *h, void *pi, ot_mem mem, ot_dtype dtype);
 
 /* Asks the following solves on the handle to write their plan (as
- * ot_assoc_plan would, element type `dtype`) into the device buffer pi,
- * from the cells their final exact check computes anyway, so that the plan
- * takes no pass over the cost of its own (Sec. III-B output step). pi must
- * hold I x J elements of every instance solved while it is set (I_max x
- * J_max always suffice) and stay valid; NULL stops it. A following
+ * ot_assoc_plan would, element type `dtype`) into the device buffer pi of
+ * `capacity` elements, from the cells their final exact check computes
+ * anyway, so that the plan takes no pass over the cost of its own (Sec. III-B
+ * output step). A solve writes it only when its I x J fits in capacity; pi
+ * must stay valid while it is set; NULL stops it. A following
  * ot_assoc_plan(h, pi, OT_MEM_DEVICE, dtype) with the same buffer and type
- * returns at once; any other plan call, and a solve that ends without that
- * check (rejected inputs, a numeric failure), computes the plan as before.
- * The solves of ot_assoc_adaptive do not write it. Errors: OT_EINVAL for a
- * bad dtype. */
-ot_status ot_assoc_set_plan_output(ot_assoc *h, void *pi, ot_dtype dtype);
+ * after such a solve returns at once; any other plan call, and a solve that
+ * ends without that check (rejected inputs, a numeric failure) or did not
+ * write it, computes the plan as before. The solves of ot_assoc_adaptive do
+ * not write it. Errors: OT_EINVAL for a bad dtype. */
+ot_status ot_assoc_set_plan_output(ot_assoc *h, void *pi, ot_dtype dtype, int64_t capacity);
 
 /* Copies out the FP64 potentials (f: I, g: J) of the last solve. Either
  * pointer may be NULL. Errors: OT_ESTATE before any solve. */

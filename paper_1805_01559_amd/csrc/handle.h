@@ -89,6 +89,7 @@ struct ot_assoc {
     bool loads_valid = false;  // `loads` holds the loads of the returned potentials
     void* plan_out = nullptr;  // device plan the checks write (ot_assoc_set_plan_output), or null
     int plan_dtype = 0;        // OT_F32 / OT_F64 of plan_out
+    int64_t plan_cap = 0;      // its elements
     bool plan_fresh = false;   // the last check wrote plan_out for the potentials it checked
     bool plan_valid = false;   // plan_out holds the plan of the returned potentials
     double eps = 0.0;

@@ -547,7 +547,8 @@ struct Solver {
         A.a = h->a; A.f = h->f[k & 1]; A.g = h->g[k & 1];
         A.col_part = h->col_part; A.stat_part = h->stat_part; A.prm = h->prm;
         A.load_part = fuse ? h->col_part + (size_t)cs.nb * (size_t)J : nullptr;
-        A.plan_out = fuse ? nullptr : h->plan_out;  // (Alg. 2's solves sum the loads; their plans are not asked for)
+        // (Alg. 2's solves sum the loads; their plans are not asked for)
+        A.plan_out = (fuse || (int64_t)I * J > h->plan_cap) ? nullptr : h->plan_out;
         A.plan_f64 = h->plan_dtype == OT_F64 ? 1 : 0;
         h->loads_fresh = h->plan_fresh = false;
         if (!launch_check<Src>(cs, A, src, h->stream)) return fail(h, OT_EINVAL, "no check kernel for this shape");
@@ -1230,12 +1231,13 @@ ot_status ot_assoc_solve_static(int device, void* stream, const float* C, int64_
     return st;
 }
 
-ot_status ot_assoc_set_plan_output(ot_assoc* h, void* pi, ot_dtype dtype) {
+ot_status ot_assoc_set_plan_output(ot_assoc* h, void* pi, ot_dtype dtype, int64_t capacity) {
     if (!h) return OT_EINVAL;
     h->err.clear();
     if (pi && dtype != OT_F32 && dtype != OT_F64) return fail(h, OT_EINVAL, "bad dtype");
     h->plan_out = pi;
     h->plan_dtype = dtype;
+    h->plan_cap = pi ? std::max<int64_t>(0, capacity) : 0;
     h->plan_valid = h->plan_fresh = false;
     return OT_OK;
 }

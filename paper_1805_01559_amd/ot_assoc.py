@@ -120,7 +120,7 @@ def lib():
         L.ot_assoc_solve_static.argtypes = [ct.c_int, vp, vp, i64, i64, i64, vp, vp, d, d, ct.c_int32, ct.c_int, vp,
                                             vp, ct.POINTER(ot_assoc_result)]
         L.ot_assoc_plan.argtypes = [vp, vp, ct.c_int, ct.c_int]
-        L.ot_assoc_set_plan_output.argtypes = [vp, vp, ct.c_int]
+        L.ot_assoc_set_plan_output.argtypes = [vp, vp, ct.c_int, ct.c_int64]
         L.ot_assoc_potentials.argtypes = [vp, vp, vp, ct.c_int]
         L.ot_assoc_set_potentials.argtypes = [vp, vp, vp, i64, i64, ct.c_int]
         L.ot_assoc_cost_median.argtypes = [vp, ct.POINTER(ot_cost_desc), ct.POINTER(d)]
@@ -583,7 +583,7 @@ class Solver:
         `out` (float32 or float64, at least I x J elements) from their final
         check; plan(out) then returns at once. None stops it."""
         if out is None:
-            _check(self.h, lib().ot_assoc_set_plan_output(self.h, None, OT_F32))
+            _check(self.h, lib().ot_assoc_set_plan_output(self.h, None, OT_F32, 0))
             self._plan_keep = None
             return
         if not _is_torch(out) or not out.is_cuda or not out.is_contiguous():
@@ -591,7 +591,7 @@ class Solver:
         dt = OT_F32 if str(out.dtype) == "torch.float32" else OT_F64 if str(out.dtype) == "torch.float64" else None
         if dt is None:
             raise ValueError("the plan output must be float32 or float64")
-        _check(self.h, lib().ot_assoc_set_plan_output(self.h, ct.c_void_p(out.data_ptr()), dt))
+        _check(self.h, lib().ot_assoc_set_plan_output(self.h, ct.c_void_p(out.data_ptr()), dt, out.numel()))
         self._plan_keep = out
 
     def potentials(self):

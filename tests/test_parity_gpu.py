@@ -359,9 +359,8 @@ def test_plan_written_by_the_final_check(A, oracle_lib, torch_mod, kind, I, J, p
     those potentials (1e-12; for geometry costs on the entries above 1e-12 of
     the largest, as the two sides' FP64 costs differ by ulps that an exponent
     of a few hundred amplifies in the tiny ones). tol 1e-11 makes the check
-    miss on the FP32 path
-    and run the FP64 phase and a second check, whose plan must be the one
-    left."""
+    miss on the FP32 path and run the FP64 phase and a second check, whose
+    plan must be the one left. A buffer smaller than I x J is not written."""
     torch = torch_mod
     announce(f"plan from the final check, {kind} {I}x{J}, persistent={persistent}, tol={tol}")
     dev = torch.device("cuda:0")
@@ -405,3 +404,9 @@ def test_plan_written_by_the_final_check(A, oracle_lib, torch_mod, kind, I, J, p
                 np.testing.assert_allclose(P[m], R[m], rtol=1e-12, atol=1e-300)
             else:
                 assert (np.abs(P - Q) <= np.spacing(np.maximum(np.abs(P), np.abs(Q))) * 1.0 + 1e-45).all()
+        # a buffer too small for I x J is left alone
+        small = torch.full((I * J - 1,), float("nan"), dtype=torch.float32, device=dev)
+        s.set_plan_output(small)
+        st, res = solve()
+        assert st == A.OT_OK and bool(torch.isnan(small).all())
+        s.set_plan_output(None)
