@@ -421,13 +421,30 @@ def leg_snapshots(args, A, S, torch, dev, solver, C, L):
     t_plain = float(np.mean(times))
     log(f"plain per snapshot: {t_plain * 1e3:.2f} ms = {1 / t_plain:.0f} solves/s; snapshot speed-up "
         f"{B / t_snap * t_plain:.1f}x")
+    # the same snapshots with the kernel in BF16 alone (snapshot_k_split 0:
+    # two products per GEMM step and half the kernel bytes)
+    with A.Solver(L.I, L.J, snapshot_k_split=0) as s2:
+        s2.solve_snapshots(C, Ad, bd, eps, tol, 2000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            st1, res1 = s2.solve_snapshots(C, Ad, bd, eps, tol, 2000)
+        torch.cuda.synchronize()
+        t_single = (time.perf_counter() - t0) / K
+    it1 = res1[0].iterations
+    single = {"ms_per_64": t_single * 1e3, "snapshot_solves_per_s": B / t_single, "iterations": it1,
+              "gemm_ms": res1[0].seconds * 1e3, "us_per_iteration": res1[0].seconds / it1 * 1e6,
+              "max_marginal_violation_fp64_check": max(r.marginal_violation for r in res1)}
+    log(f"snapshots, kernel in BF16 alone: {t_single * 1e3:.2f} ms for {B}; {it1} iterations in "
+        f"{res1[0].seconds * 1e3:.2f} ms; violation max {single['max_marginal_violation_fp64_check']:.2e}")
     return {"workload": f"cran_20000x400 cost, B={B} snapshots (lambda resampled), eps={eps}, tol={tol} on the BF16 "
                         "problem, K, u and v split into BF16 hi + lo (3 products per GEMM step), FP32 accumulation",
             "ms_per_64": t_snap * 1e3, "snapshot_solves_per_s": B / t_snap, "iterations": iters,
             "gemm_ms": gemm_s * 1e3, "mfma_tflops": flops / gemm_s / 1e12,
             "mfma_frac_bf16_dense_peak": flops / gemm_s / 2.5e15,
             "max_marginal_violation_fp64_check": max(viol),
-            "plain_ms_per_solve": t_plain * 1e3, "speedup_vs_plain": B / t_snap * t_plain}, As
+            "plain_ms_per_solve": t_plain * 1e3, "speedup_vs_plain": B / t_snap * t_plain,
+            "kernel_bf16_alone": single}, As
 
 
 def leg_adaptive(args, A, torch, solver, C, a, b, J, eps, tol):

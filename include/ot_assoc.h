@@ -150,6 +150,11 @@ typedef struct {
                            that size itself. The batch, snapshot and serving engines keep their
                            own device pools either way. */
     size_t workspace_bytes; /* size of `workspace` (0 when workspace is NULL) */
+    int snapshot_k_split;   /* ot_assoc_solve_snapshots: 1 (default) holds the stabilised kernel
+                               in BF16 high and low parts (three BF16 products per GEMM step,
+                               marginals about 1e-6 of the FP64 problem's); 0 in BF16 alone
+                               (two products and half the kernel bytes per GEMM; 3e-4 on the
+                               20000 x 400 x 64 layout, up to about 1.1e-3 on a distance cost) */
 } ot_assoc_options;
 
 typedef struct {

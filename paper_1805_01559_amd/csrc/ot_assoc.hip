@@ -902,6 +902,7 @@ ot_status ot_assoc_default_options(ot_assoc_options* opt) {
     opt->batch_tune = 1;
     opt->persistent = 1;
     opt->check_every = 1;
+    opt->snapshot_k_split = 1;
     return OT_OK;
 }
 

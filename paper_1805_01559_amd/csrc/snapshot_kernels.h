@@ -214,7 +214,8 @@ __device__ __forceinline__ u32x4 snap_uload(__amdgpu_buffer_rsrc_t r, unsigned v
 // 16 x 16 tile per 16 snapshots). A is read from its BF16 high / low rows (row
 // stride lda elements, `live` tiles of 16 rows from Ah / Al). B comes in the
 // staging layout, chunk after chunk from Bs, and is copied into LDS as is.
-// Each product is Ah Bh + Ah Bl + Al Bh, accumulated in FP32.
+// Each product is Ah Bh + Ah Bl + Al Bh, accumulated in FP32; with KLO
+// false the low part of A is not read (Ah Bh + Ah Bl: A in BF16 alone).
 // A chunk's B copy is issued first and its A fragments after it, so that the
 // copy is waited for alone and each K-step then waits for its own fragments
 // only (their loads overlap the products of the steps before). `gate` runs
@@ -223,7 +224,7 @@ __device__ __forceinline__ u32x4 snap_uload(__amdgpu_buffer_rsrc_t r, unsigned v
 // without writing anything. `pre` runs once, when the first chunk is staged.
 // Offsets are 32-bit: 16 NT lda elements and the staged chunks stay far below
 // 2^31 bytes.
-template <int NT, int PS, typename Gate, typename Pre>
+template <int NT, int PS, bool KLO, typename Gate, typename Pre>
 __device__ __forceinline__ bool snap_block(const unsigned short* Ah, const unsigned short* Al, int64_t lda, int live,
                                            const unsigned short* Bs, int64_t k0, int64_t k1, unsigned short* lds,
                                            Gate gate, Pre pre, f32x4 (&acc)[kSnapNT]) {
@@ -238,7 +239,7 @@ __device__ __forceinline__ bool snap_block(const unsigned short* Ah, const unsig
     const int tile = w >> 1, par = w & 1, m = lane & 15, kq = (lane >> 4) * 8;
     const bool mine = tile < live;
     const unsigned arow = (unsigned)(16 * live) * (unsigned)lda * 2u;
-    const __amdgpu_buffer_rsrc_t rh = snap_rsrc(Ah, arow), rl = snap_rsrc(Al, arow);
+    const __amdgpu_buffer_rsrc_t rh = snap_rsrc(Ah, arow), rl = snap_rsrc(KLO ? Al : Ah, arow);
     const unsigned avoff = ((unsigned)(16 * tile + m) * (unsigned)lda + kq + 32 * par) * 2u;
     const unsigned nchunk = (unsigned)((k1 - k0 + CK - 1) / CK);
     const __amdgpu_buffer_rsrc_t rb = snap_rsrc(Bs, nchunk * (unsigned)snap_stage_bytes(CK));
@@ -263,12 +264,12 @@ __device__ __forceinline__ bool snap_block(const unsigned short* Ah, const unsig
         // A fragments, also without branches: steps past this wave's last one
         // repeat it, and the rows of a tile past `live` lie outside the
         // resource and read as 0 (neither is multiplied)
-        bf16x8 fa[PS], fl[PS];
+        bf16x8 fa[PS], fl[KLO ? PS : 1];
 #pragma unroll
         for (int q = 0; q < PS; ++q) {
             const unsigned soff = (unsigned)c0 * 2u + 128u * (unsigned)min(q, ns - 1);
             fa[q] = snap_bload(rh, avoff, soff);
-            fl[q] = snap_bload(rl, avoff, soff);
+            if constexpr (KLO) fl[q] = snap_bload(rl, avoff, soff);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (c0 == k0 && gate()) {
@@ -305,9 +306,11 @@ __device__ __forceinline__ bool snap_block(const unsigned short* Ah, const unsig
 #pragma unroll
                     for (int t = 0; t < kSnapNT; ++t)
                         acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[q], bl[t], acc[t], 0, 0, 0);
+                    if constexpr (KLO) {
 #pragma unroll
-                    for (int t = 0; t < kSnapNT; ++t)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[q], bh[t], acc[t], 0, 0, 0);
+                        for (int t = 0; t < kSnapNT; ++t)
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[KLO ? q : 0], bh[t], acc[t], 0, 0, 0);
+                    }
                 }
         }
     }
@@ -349,7 +352,7 @@ __device__ __forceinline__ void snap_pair_sum(const f32x4 (&acc)[kSnapNT], unsig
 // relative column residual of the last iterate below tol, or the iteration
 // cap) is taken from scalar loads after the group's loads are issued; group
 // 0 records it, or clears the decision slot of this iteration's combine.
-template <int NT>
+template <int NT, bool KLO>
 __global__ __launch_bounds__(128 * NT) void k_snap_rows(SnapArgs S) {
     extern __shared__ unsigned short snap_lds[];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -377,7 +380,7 @@ __global__ __launch_bounds__(128 * NT) void k_snap_rows(SnapArgs S) {
         load_a();
     };
     f32x4 acc[kSnapNT];
-    if (!snap_block<NT, kSnapRowPS>(S.K + i0 * S.Jp, S.Kl + i0 * S.Jp, S.Jp, live, S.Vs, 0, S.Jp, snap_lds, stop,
+    if (!snap_block<NT, kSnapRowPS, KLO>(S.K + i0 * S.Jp, S.Kl + i0 * S.Jp, S.Jp, live, S.Vs, 0, S.Jp, snap_lds, stop,
                                     pre, acc)) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && !S.ctl[1]) {
             S.ctl[3] = done;
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(128 * NT) void k_snap_rows(SnapArgs S) {
 // each XCD takes a contiguous range of (split, column group) pairs, and the
 // column groups of one split share its staged U in that XCD's L2. Group 0
 // of the pass counts the iteration.
-template <int NT>
+template <int NT, bool KLO>
 __global__ __launch_bounds__(128 * NT) void k_snap_cols(SnapArgs S) {
     extern __shared__ unsigned short snap_lds[];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(128 * NT) void k_snap_cols(SnapArgs S) {
     f32x4 acc[kSnapNT];
     const unsigned short* Bs = S.Us + (int64_t)split * (snap_stage_bytes(kSnapColCK) / 2);
     const int64_t ao = ((int64_t)split * S.Jp + j0) * S.rows_per_split;
-    if (!snap_block<NT, kSnapColPS>(S.Kt + ao, S.Ktl + ao, S.rows_per_split, live, Bs, 0, r1 - r0,
+    if (!snap_block<NT, kSnapColPS, KLO>(S.Kt + ao, S.Ktl + ao, S.rows_per_split, live, Bs, 0, r1 - r0,
                                     snap_lds, [&] { return S.ctl[1] != 0; },
                                     [&] {
                                         if (g == 0 && threadIdx.x == 0) S.ctl[0] += 1;

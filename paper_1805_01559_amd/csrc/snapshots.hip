@@ -31,26 +31,31 @@ constexpr int kSnapChunk = 8;
 constexpr int kMaxChunks = 64;  // row chunks per snapshot in the exact check
 constexpr int kSnapCUs = 256;   // workgroups that fill the GPU once (one per CU)
 
-const void* snap_rows_kernel(int nt) {
+template <bool KLO>
+const void* snap_rows_kernel_t(int nt) {
     switch (nt) {
-        case 1: return (const void*)k_snap_rows<1>;
-        case 2: return (const void*)k_snap_rows<2>;
-        case 3: return (const void*)k_snap_rows<3>;
-        case 4: return (const void*)k_snap_rows<4>;
-        case 5: return (const void*)k_snap_rows<5>;
-        case 6: return (const void*)k_snap_rows<6>;
+        case 1: return (const void*)k_snap_rows<1, KLO>;
+        case 2: return (const void*)k_snap_rows<2, KLO>;
+        case 3: return (const void*)k_snap_rows<3, KLO>;
+        case 4: return (const void*)k_snap_rows<4, KLO>;
+        case 5: return (const void*)k_snap_rows<5, KLO>;
+        case 6: return (const void*)k_snap_rows<6, KLO>;
         default: return nullptr;
     }
 }
-const void* snap_cols_kernel(int nt) {
+template <bool KLO>
+const void* snap_cols_kernel_t(int nt) {
     switch (nt) {
-        case 1: return (const void*)k_snap_cols<1>;
-        case 2: return (const void*)k_snap_cols<2>;
-        case 3: return (const void*)k_snap_cols<3>;
-        case 4: return (const void*)k_snap_cols<4>;
+        case 1: return (const void*)k_snap_cols<1, KLO>;
+        case 2: return (const void*)k_snap_cols<2, KLO>;
+        case 3: return (const void*)k_snap_cols<3, KLO>;
+        case 4: return (const void*)k_snap_cols<4, KLO>;
         default: return nullptr;
     }
 }
+// (klo: K in BF16 high and low parts; else in BF16 alone)
+const void* snap_rows_kernel(int nt, bool klo) { return klo ? snap_rows_kernel_t<true>(nt) : snap_rows_kernel_t<false>(nt); }
+const void* snap_cols_kernel(int nt, bool klo) { return klo ? snap_cols_kernel_t<true>(nt) : snap_cols_kernel_t<false>(nt); }
 
 size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -212,8 +217,9 @@ ot_status snap_capture(ot_assoc* h, SnapState* s) {
     if (s->graph) hipGraphExecDestroy(s->graph);
     s->graph = nullptr;
     SnapArgs S = s->S;
-    const void* rows_k = snap_rows_kernel(S.rows_nt);
-    const void* cols_k = snap_cols_kernel(S.cols_nt);
+    const bool klo = h->opt.snapshot_k_split != 0;
+    const void* rows_k = snap_rows_kernel(S.rows_nt, klo);
+    const void* cols_k = snap_cols_kernel(S.cols_nt, klo);
     if (!rows_k || !cols_k) return sfail(h, OT_EINVAL, "no snapshot kernel for this shape");
     SCHK(hipFuncSetAttribute(rows_k, hipFuncAttributeMaxDynamicSharedMemorySize, kSnapLdsBytes));
     SCHK(hipFuncSetAttribute(cols_k, hipFuncAttributeMaxDynamicSharedMemorySize, kSnapLdsBytes));

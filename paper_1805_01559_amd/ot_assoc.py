@@ -60,7 +60,7 @@ class ot_assoc_options(ct.Structure):
                 ("chunk", ct.c_int), ("use_graphs", ct.c_int), ("sweep_blocks", ct.c_int), ("sweep_waves", ct.c_int),
                 ("sweep_rows", ct.c_int), ("sweep_lanes", ct.c_int), ("batch_tune", ct.c_int),
                 ("persistent", ct.c_int), ("check_every", ct.c_int), ("workspace", ct.c_void_p),
-                ("workspace_bytes", ct.c_size_t)]
+                ("workspace_bytes", ct.c_size_t), ("snapshot_k_split", ct.c_int)]
 
 
 class ot_assoc_result(ct.Structure):

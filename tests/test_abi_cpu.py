@@ -48,7 +48,7 @@ def test_struct_layouts_match_the_header(tmp_path):
               "sizeof(ot_eval_result)", "offsetof(ot_eval_result, devices_overloaded)",
               "sizeof(ot_adaptive_result)", "offsetof(ot_adaptive_result, delta)",
               "offsetof(ot_assoc_options, check_every)", "offsetof(ot_assoc_options, workspace)",
-              "offsetof(ot_assoc_options, workspace_bytes)"]
+              "offsetof(ot_assoc_options, workspace_bytes)", "offsetof(ot_assoc_options, snapshot_k_split)"]
     fmt = " ".join(["%zu"] * len(fields))
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ot_assoc.h"\n'
                    'int main(void){printf("' + fmt + '\\n", ' + ", ".join(fields) + ');return 0;}\n')
@@ -63,14 +63,15 @@ def test_struct_layouts_match_the_header(tmp_path):
             ct.sizeof(A.ot_eval_result), A.ot_eval_result.devices_overloaded.offset,
             ct.sizeof(A.ot_adaptive_result), A.ot_adaptive_result.delta.offset,
             A.ot_assoc_options.check_every.offset, A.ot_assoc_options.workspace.offset,
-            A.ot_assoc_options.workspace_bytes.offset]
+            A.ot_assoc_options.workspace_bytes.offset, A.ot_assoc_options.snapshot_k_split.offset]
     assert got == want
 
 
 def test_default_options(lib):
     o = A.ot_assoc_default_options()
     assert (o.device, o.precision, o.polish_iters, o.chunk, o.use_graphs, o.batch_tune, o.persistent,
-            o.check_every, o.workspace, o.workspace_bytes) == (0, A.OT_PREC_FP32, 1, 8, 1, 1, 1, 1, None, 0)
+            o.check_every, o.workspace, o.workspace_bytes, o.snapshot_k_split) == (0, A.OT_PREC_FP32, 1, 8, 1, 1, 1,
+                                                                                    1, None, 0, 1)
     s = A.ot_serve_default_options()
     assert (s.polish_iters, s.sweep_waves, s.rows_per_part, s.max_slots, s.budget_bytes) == (1, 8, 128, 0, 0.0)
 
