@@ -476,20 +476,27 @@ __device__ __forceinline__ double snap_sum_splits(const float* qp, int64_t step,
 // (fixed order, FP64), the column residual of the iterate (u, v_old) and
 // v = b / Q (FP32 and staged). A live snapshot puts its relative residual
 // (NaN counted as 0, as in a sequential fmax from 0) into this iteration's
-// decision slot.
+// decision slot. The first column's split loads are issued before the stop
+// flag is read (reading partials is harmless after the stop; nothing is
+// stored then), so the two latencies overlap.
 __global__ __launch_bounds__(512) void k_snap_combine(SnapArgs S) {
-    if (S.ctl[1]) return;
     const int s = blockIdx.x;
     __shared__ double red[8];
     double r = 0.0;
     const int64_t step = (int64_t)kSnapB * S.Jp;
+    auto col_sum = [&](int j) {
+        const float* qp = S.Qpart + (int64_t)s * S.Jp + j;
+        return S.splits <= 16   ? snap_sum_splits<16>(qp, step, S.splits)
+               : S.splits <= 32 ? snap_sum_splits<32>(qp, step, S.splits)
+                                : snap_sum_splits<64>(qp, step, S.splits);
+    };
+    const bool first = s < S.B && (int)threadIdx.x < S.J;
+    const double q0 = first ? col_sum(threadIdx.x) : 0.0;
+    if (S.ctl[1]) return;  // (the same for every thread)
     for (int j = threadIdx.x; j < S.Jp; j += blockDim.x) {
         float v = 0.0f;
         if (s < S.B && j < S.J) {
-            const float* qp = S.Qpart + (int64_t)s * S.Jp + j;
-            const double q = S.splits <= 16   ? snap_sum_splits<16>(qp, step, S.splits)
-                             : S.splits <= 32 ? snap_sum_splits<32>(qp, step, S.splits)
-                                              : snap_sum_splits<64>(qp, step, S.splits);
+            const double q = j == (int)threadIdx.x ? q0 : col_sum(j);
             r += fabs((double)S.V[(int64_t)s * S.Jp + j] * q - S.b[j]);
             v = (float)(S.b[j] / q);
         }
