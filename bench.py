@@ -592,7 +592,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg (0 skips it)")
     ap.add_argument("--serve-layouts", type=int, default=200, help="layouts of the serving leg (0 skips it)")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the serving leg (requests/s)")
-    ap.add_argument("--only", choices=["all", "main", "batch", "serve", "snapshots", "adaptive"], default="all",
+    ap.add_argument("--only", choices=["all", "main", "batch", "serve", "snapshots", "adaptive", "large"], default="all",
                     help="run one leg (for profiling): main = the 20000x400 solve and its sweep")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -850,7 +850,7 @@ def main():
     }
     if args.only in ("all", "adaptive"):
         out["adaptive"] = leg_adaptive(args, A, torch, solver, C, a, b, J, eps, tol)
-    if args.only == "all":
+    if args.only in ("all", "large"):
         out["large_on_the_fly"] = leg_large(args, A, S, torch, dev)
     snap_As = None
     if args.only in ("all", "snapshots"):

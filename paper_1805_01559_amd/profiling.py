@@ -4,7 +4,12 @@
     python -m paper_1805_01559_amd.profiling traffic <fetch_dir> <write_dir> <kernel-substring> \
         --bytes <algorithmic bytes per launch> [--copy-bytes 536870912]
 
+    python -m paper_1805_01559_amd.profiling valu <pmc_dir> <kernel-substring> --cells <cells per dispatch>
+
 `stats` prints the kernel table of a `--kernel-trace --stats` run.
+`valu` turns a `--pmc` run of SQ_INSTS_* counters into lane-instructions per
+cell of one kernel (median wave-instructions per working dispatch x 64 /
+cells).
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs into HBM bytes
 per launch of one kernel (`--first N`: its first N dispatches only). Both counters are in KiB per dispatch; each is
 scaled by what it reads for the largest plain device copy in the same run
@@ -89,6 +94,28 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, alg_bytes: float, copy_
                 source_hash=source_hash(sources))
 
 
+def valu(d: str, kernel: str, cells: float) -> dict:
+    """Median per dispatch of every SQ_INSTS_* counter of the kernels whose
+    name contains `kernel`, as lane-instructions per cell, over the dispatches
+    that did a sweep's work: those with at least half the largest
+    SQ_INSTS_VALU (a captured chunk's launches after the stop exit at once)."""
+    rows = [r for r in _counter(d) if kernel in r["Kernel_Name"] and r["Counter_Name"].startswith("SQ_INSTS_")]
+    if not rows:
+        raise SystemExit(f"no SQ_INSTS_ counters of '{kernel}' in {d}")
+    total = {r["Dispatch_Id"]: float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == "SQ_INSTS_VALU"}
+    if total:
+        top = max(total.values())
+        busy = {k for k, v in total.items() if v >= 0.5 * top}
+        rows = [r for r in rows if r["Dispatch_Id"] in busy]
+    out = {}
+    for name in sorted({r["Counter_Name"] for r in rows}):
+        vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == name]
+        out[name] = dict(dispatches=len(vals), median_wave_insts=statistics.median(vals),
+                         lane_insts_per_cell=statistics.median(vals) * 64.0 / cells)
+    names = {r["Kernel_Name"] for r in rows}
+    return dict(kernel=kernel, kernels_matched=sorted(names), cells=cells, counters=out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -104,9 +131,20 @@ def main(argv=None):
     b.add_argument("--coop", action="store_true", help="the kernel is the cooperative phase (persist_kernels.h)")
     b.add_argument("--first", type=int, default=0,
                    help="use only the kernel's first N dispatches (the bench's main leg runs first)")
+    c = sub.add_parser("valu")
+    c.add_argument("dir")
+    c.add_argument("kernel")
+    c.add_argument("--cells", type=float, required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print(stats(args.dir, args.top))
+    elif args.cmd == "valu":
+        v = valu(args.dir, args.kernel, args.cells)
+        for k in v["kernels_matched"]:
+            print(f"kernel: {k}")
+        for name, x in v["counters"].items():
+            print(f"{name}: {x['lane_insts_per_cell']:.2f} lane-instructions per cell "
+                  f"(median {x['median_wave_insts']:.4g} wave-instructions over {x['dispatches']} dispatches)")
     else:
         t = traffic(args.fetch_dir, args.write_dir, args.kernel, args.bytes, args.copy_bytes,
                     COOP_SOURCES if args.coop else SWEEP_SOURCES, args.first)
