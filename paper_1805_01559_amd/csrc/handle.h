@@ -62,6 +62,8 @@ struct ot_assoc {
     double* xch = nullptr;     // exchange block of the cooperative FP32 phase
     double* loads = nullptr;   // J_max: RRH loads summed by the last check (when fused)
     int lds_max = 0;           // LDS bytes a workgroup may allocate
+    bool xch_zeroed = false;       // this solve's init launch zeroed the exchange block
+    bool stop_recorded = false;    // ev_stop was recorded with the last control-block copy
     bool last_persistent = false;  // the last solve's FP32 phase was one cooperative launch
     int last_fast_iters = 0;       // ... and the FP32 iterations it ran
     hipEvent_t ev_coop[2] = {nullptr, nullptr};  // around that launch

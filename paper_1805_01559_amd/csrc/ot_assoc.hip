@@ -488,9 +488,15 @@ struct Solver {
 
     // (a handle without events, the no-allocation entry point's, waits for
     // the whole stream instead)
+    // (ev_stop goes with every copy: when the host has waited for the last
+    // one, the solve's device time is known without another round trip)
     ot_status snapshot(int slot) {
         HIPCHK(h, hipGetLastError());
         HIPCHK(h, hipMemcpyAsync(&h->ctl_h[slot], h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+        if (h->ev_stop) {
+            HIPCHK(h, hipEventRecord(h->ev_stop, h->stream));
+            h->stop_recorded = true;
+        }
         if (h->ev_slot[slot]) HIPCHK(h, hipEventRecord(h->ev_slot[slot], h->stream));
         return OT_OK;
     }
@@ -646,9 +652,14 @@ ot_status run_persist(ot_assoc* h, const Src& src, int64_t I, int J, const Persi
     A.xch = h->xch;
     A.ctl = h->ctl;
     A.prm = h->prm;
-    const size_t nx = persist_exchange_doubles(p.nb, J);
-    hipLaunchKernelGGL(k_xch_clear, dim3((unsigned)std::min<size_t>(512, (nx + 255) / 256)), dim3(256), 0, h->stream,
-                       h->xch, p.nb, J, h->ctl);
+    // (the solve's init launch has zeroed the exchange block, unless it
+    // could not know that this launch would follow)
+    if (!h->xch_zeroed) {
+        const size_t nx = persist_exchange_doubles(p.nb, J);
+        hipLaunchKernelGGL(k_xch_clear, dim3((unsigned)std::min<size_t>(512, (nx + 255) / 256)), dim3(256), 0,
+                           h->stream, h->xch, p.nb, J, h->ctl);
+    }
+    h->xch_zeroed = false;
     Src sv = src;
     void* args[] = {(void*)&A, (void*)&sv};
     if (h->ev_coop[0]) HIPCHK(h, hipEventRecord(h->ev_coop[0], h->stream));
@@ -1078,7 +1089,18 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
     ia.ctl_out = h->ctl;
     ia.prm = SolveParams{std::log2(std::exp(1.0)) / eps, eps};
     ia.ctl = c;
-    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(1024), 0, h->stream, ia);
+    // a solve that may take the cooperative FP32 phase has its exchange
+    // block zeroed by this launch (nb <= num_cu bounds the launch's layout)
+    unsigned init_groups = 1;
+    h->xch_zeroed = false;
+    h->stop_recorded = false;
+    if (h->opt.precision == OT_PREC_FP32 && h->opt.persistent && h->xch && h->num_cu > 0) {
+        ia.xch = h->xch;
+        ia.nx = (int64_t)persist_exchange_doubles(std::min(h->num_cu, kMaxCoopGroups), (int)J);
+        init_groups = 1 + (unsigned)std::min<int64_t>(32, (ia.nx + 4095) / 4096);
+        h->xch_zeroed = true;
+    }
+    hipLaunchKernelGGL(k_solve_init, dim3(init_groups), dim3(1024), 0, h->stream, ia);
     HIPCHK(h, hipGetLastError());
 
     Ctl fin = c;
@@ -1095,8 +1117,9 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
         return st;
     }
     float ms = 0.0f;
+    h->xch_zeroed = false;
     if (h->ev_start) {
-        HIPCHK(h, hipEventRecord(h->ev_stop, h->stream));
+        if (!h->stop_recorded) HIPCHK(h, hipEventRecord(h->ev_stop, h->stream));
         HIPCHK(h, hipEventSynchronize(h->ev_stop));
         hipEventElapsedTime(&ms, h->ev_start, h->ev_stop);
     } else {

@@ -597,6 +597,8 @@ struct InitArgs {
     Ctl* ctl_out;
     SolveParams prm;
     Ctl ctl;
+    double* xch;  // exchange block zeroed by the workgroups past the first (nx doubles), or nullptr
+    int64_t nx;
 };
 
 __device__ __forceinline__ void two_sum_add(double& s, double& c, double x) {
@@ -605,7 +607,19 @@ __device__ __forceinline__ void two_sum_add(double& s, double& c, double x) {
     s = t;
 }
 
+// Workgroup 0 checks and sums the marginals and writes the constants and
+// the control block. The workgroups past it zero the cooperative exchange
+// block, for a cooperative launch that starts from iteration 0: a zero slot
+// carries tag 0, which neither of the launch's first two iterations (1 and
+// 2, one per buffer parity) waits for, and zero decision and abort words;
+// so the launch needs no clearing pass of its own.
 static __global__ __launch_bounds__(1024) void k_solve_init(InitArgs A) {
+    if (blockIdx.x > 0) {
+        const size_t stride = (size_t)(gridDim.x - 1) * blockDim.x;
+        for (size_t q = (size_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x; q < (size_t)A.nx; q += stride)
+            A.xch[q] = 0.0;
+        return;
+    }
     __shared__ double ss[2][1024], sc[2][1024];
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
