@@ -313,3 +313,36 @@ def test_iteration_counts_against_oracle(A, oracle_lib, I, J):
     assert abs(r64.iterations - ref.iters) <= 2
     for p in (1, 0):
         assert ref.iters - 2 <= k32[p] <= ref.iters + 8, (p, k32[p], ref.iters)
+
+
+@pytest.mark.parametrize("pers", [1, 0])
+def test_reported_device_time_covers_the_solve(A, pers):
+    """The result's device time runs from the solve's first launch to its last
+    control-block copy: positive, within the call's wall-clock time, and (on
+    the cooperative path) at least the cooperative launch it contains; the
+    same on a second solve of the handle, when the exchange block is zeroed by
+    the init launch again."""
+    import time
+
+    import torch
+    announce(f"device time of a 4000 x 130 solve, persistent={pers}")
+    C, a, b = random_case(4000, 130, 4130)
+    dev = torch.device("cuda:0")
+    Cd, ad, bd = (torch.from_numpy(x).to(dev) for x in (C, a, b))
+    with A.Solver(4000, 130, persistent=pers) as s:
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, res = s.solve_dense(Cd, ad, bd, 0.05, 1e-8, 2000)
+            wall = time.perf_counter() - t0
+            assert st == A.OT_OK
+            assert bool(res.flags & A.OT_RESULT_PERSISTENT) == bool(pers)
+            assert 0.0 < res.seconds <= wall, (rep, res.seconds, wall)
+            if pers:
+                ms, it = s.fast_phase_time()
+                assert 0.0 < ms * 1e-3 <= res.seconds and it >= 1, (rep, ms, res.seconds)
+            if rep == 0:
+                f0, g0 = s.potentials()
+            else:
+                f1, g1 = s.potentials()
+                assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
