@@ -58,8 +58,10 @@ def check_snapshot(O, Cq, a, b, eps, f, g, res, bar=BF16_BAR):
     return chk["marginal_violation"], rel
 
 
-@pytest.mark.parametrize("I,J,B", [(1500, 60, 8), (1001, 37, 1), (2048, 130, 17)])
+@pytest.mark.parametrize("I,J,B", [(1500, 60, 8), (1001, 37, 1), (2048, 130, 17), (1200, 613, 5)])
 def test_snapshots_against_oracle(A, oracle_lib, I, J, B):
+    """(1200 x 613: rows longer than one staged chunk of the row GEMM, so its
+    workgroups stage v in two chunks.)"""
     announce(f"snapshots {I}x{J}, B={B}")
     eps = 0.05
     L, C32, Cq, As = oracle_case(oracle_lib, I, J, B, 7000 + I, eps)
