@@ -711,28 +711,13 @@ static __global__ void k_copy_fg(double* fd, const double* fs, int64_t I, double
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < J; j += gridDim.x * blockDim.x) gd[j] = gs[j];
 }
 
-// After the check of the cooperative path: the returned iterate k (the
-// control block's result iteration when done, else its last iteration) sits
-// in the buffers of parity np & 1; moves it to parity k & 1 when they differ,
-// decided on the device so that the host waits once for check and copy.
-static __global__ void k_copy_fg_ctl(const Ctl* ctl, int np, double* f0, double* f1, int64_t I, double* g0,
-                                     double* g1, int J) {
-    const int k = ctl->done ? ctl->result_iter : ctl->iter;
-    if (((k ^ np) & 1) == 0) return;
-    double* fd = (k & 1) ? f1 : f0;
-    double* gd = (k & 1) ? g1 : g0;
-    const double* fs = (np & 1) ? f1 : f0;
-    const double* gs = (np & 1) ? g1 : g0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += (int64_t)gridDim.x * blockDim.x)
-        fd[i] = fs[i];
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < J; j += gridDim.x * blockDim.x) gd[j] = gs[j];
-}
-
 // The three phases of a solve. `c` enters with the initial control state and
-// leaves with the final one; result_iter names the returned iterate.
+// leaves with the final one; result_iter names the returned iterate and
+// result_par the parity of the buffers that hold it (the iteration's parity,
+// except after the cooperative path's check: see there).
 template <class Src>
 ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, int J, double tol, int32_t max_iter,
-                     Ctl& c, int& result_iter) {
+                     Ctl& c, int& result_iter, int& result_par) {
     const int vec = vec_for<Src>(J, ld_of(h->last), data);
     Solver S{h, I, J, make_shape<Src>(h, I, J, vec, false), make_shape<Src>(h, I, J, vec, true), h->opt.use_graphs != 0};
     fit_grid<Src, false>(h, I, S.shape);
@@ -746,6 +731,7 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
     bool checked = false;
     PersistPlan pp;
     bool persisted = false;
+    int coop_par = -1;  // buffers of the iterate the cooperative path checked
     if (h->opt.precision == OT_PREC_FP32 && h->opt.persistent && persist_plan<Src>(h, I, J, pp))
         if ((st = run_persist<Src>(h, src, I, J, pp, stall_below, persisted))) return st;
     h->last_persistent = persisted;
@@ -756,14 +742,12 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
         hipLaunchKernelGGL(k_polish_gate, dim3(gb), dim3(256), 0, h->stream, h->ctl, h->f[0], h->f[1], h->g[0],
                            h->g[1], I, J, tol, stall_below, np);
         if (np > 0 && (st = S.issue_chunk<Src, true>(src, 0, np, kModePolish, 0.0))) return st;
-        // the iterate sits in the buffers of parity np & 1; the convention
-        // that iterate k lives in buffers k & 1 is restored on the device
-        // right after the check
-        if ((st = S.run_check_then(src, np, c, [&] {
-                 hipLaunchKernelGGL(k_copy_fg_ctl, dim3((unsigned)std::min<int64_t>(256, (I + 255) / 256)), dim3(256),
-                                    0, h->stream, (const Ctl*)h->ctl, np, h->f[0], h->f[1], I, h->g[0], h->g[1], J);
-             })))
-            return st;
+        // the iterate sits in the buffers of parity np & 1 whatever its
+        // iteration number (the gate put it there): it is checked and
+        // returned from there, and moved to the buffers of its iteration's
+        // parity only if more sweeps follow
+        if ((st = S.run_check(src, np, c))) return st;
+        coop_par = np & 1;
         checked = true;
         h->last_fast_iters = c.iter - c.fp64_iters;  // (the solve starts at iteration 0)
     } else if (h->opt.precision == OT_PREC_FP32) {
@@ -785,17 +769,24 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
     }
     if (c.done) {  // inputs rejected, or a numeric failure in the fast phase
         result_iter = c.result_iter;
+        result_par = coop_par >= 0 ? coop_par : result_iter & 1;
         h->loads_fresh = h->plan_fresh = false;
         return OT_OK;
     }
     if (!checked && (st = S.run_check<Src>(src, c.iter, c))) return st;
     if (c.done) {  // inputs rejected (seen first by the check of an FP64-precision solve)
         result_iter = c.result_iter;
+        result_par = result_iter & 1;
         h->loads_fresh = h->plan_fresh = false;
         return OT_OK;
     }
     result_iter = c.iter;
+    result_par = coop_par >= 0 ? coop_par : result_iter & 1;
     if (!(c.chk_violation < tol) && c.iter < max_iter) {
+        if (coop_par >= 0 && ((c.iter ^ coop_par) & 1))  // (the FP64 sweeps start from parity c.iter & 1)
+            hipLaunchKernelGGL(k_copy_fg, dim3((unsigned)std::min<int64_t>(256, (I + 255) / 256)), dim3(256), 0,
+                               h->stream, h->f[c.iter & 1], (const double*)h->f[coop_par], I, h->g[c.iter & 1],
+                               (const double*)h->g[coop_par], J);
         if ((st = S.run_phase<Src, true>(src, kModeExact, chunk, 0.0, c))) return st;
         const int k = c.done ? c.result_iter : c.iter;
         const Ctl loop = c;
@@ -805,6 +796,7 @@ ot_status solve_with(ot_assoc* h, const Src& src, const void* data, int64_t I, i
         c.iter = loop.iter;
         c.fp64_iters = loop.fp64_iters;
         result_iter = k;
+        result_par = k & 1;
     }
     return OT_OK;
 }
@@ -1104,11 +1096,11 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
     HIPCHK(h, hipGetLastError());
 
     Ctl fin = c;
-    int result_iter = 0;
+    int result_iter = 0, result_par = 0;
     st = upload_cost(h, cost, kCheckDeferred);
     if (!st)
         st = with_retained(h, [&](const auto& src, const void* data) -> ot_status {
-            return solve_with(h, src, data, I, (int)J, tol, max_iter, fin, result_iter);
+            return solve_with(h, src, data, I, (int)J, tol, max_iter, fin, result_iter, result_par);
         });
     if (st) {
         h->solved = h->loads_valid = h->plan_valid = false;
@@ -1149,7 +1141,7 @@ static ot_status solve_impl(ot_assoc* h, const ot_cost_desc* cost, const double*
     h->I = I;
     h->J = J;
     h->eps = eps;
-    h->res_par = result_iter & 1;
+    h->res_par = result_par;
     h->have_pot = true;
     ot_status rs = OT_OK;
     if (fin.numeric_bad || !std::isfinite(fin.chk_violation)) rs = OT_ENUMERIC;
