@@ -5,8 +5,13 @@
         --bytes <algorithmic bytes per launch> [--copy-bytes 536870912]
 
     python -m paper_1805_01559_amd.profiling valu <pmc_dir> <kernel-substring> --cells <cells per dispatch>
+    python -m paper_1805_01559_amd.profiling timeline <trace_dir> <kernel-substring> [--index -3] [--after 12]
 
 `stats` prints the kernel table of a `--kernel-trace --stats` run.
+`timeline` interleaves the HIP API calls and the kernels of a
+`--runtime-trace --kernel-trace` run around one dispatch of a kernel (the
+`--index`-th, Python-style), from the end of the dispatch before it to the end
+of the `--after`-th one after it, in microseconds from the first event.
 `valu` turns a `--pmc` run of SQ_INSTS_* counters into lane-instructions per
 cell of one kernel (median wave-instructions per working dispatch x 64 /
 cells).
@@ -116,6 +121,27 @@ def valu(d: str, kernel: str, cells: float) -> dict:
     return dict(kernel=kernel, kernels_matched=sorted(names), cells=cells, counters=out)
 
 
+def timeline(d: str, kernel: str, index: int = -3, after: int = 12) -> str:
+    api = list(csv.DictReader(open(_find(d, "hip_api_trace.csv"))))
+    ker = sorted(csv.DictReader(open(_find(d, "kernel_trace.csv"))), key=lambda r: int(r["Start_Timestamp"]))
+    hits = [i for i, r in enumerate(ker) if kernel in r["Kernel_Name"]]
+    if not hits:
+        raise SystemExit(f"no dispatch of '{kernel}' in {d}")
+    i = hits[index]
+    lo = int(ker[i - 1]["End_Timestamp"]) if i > 0 else int(ker[i]["Start_Timestamp"])
+    hi = int(ker[min(len(ker) - 1, i + after)]["End_Timestamp"])
+    ev = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), "API", r["Function"]) for r in api
+          if lo <= int(r["Start_Timestamp"]) <= hi]
+    ev += [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), "GPU", r["Kernel_Name"].split("(")[0]) for r in ker
+           if lo <= int(r["Start_Timestamp"]) <= hi]
+    ev.sort()
+    t0 = ev[0][0]
+    out = ["| start (us) | duration (us) | | call or kernel |", "|---:|---:|---|---|"]
+    for s, e, k, n in ev:
+        out.append(f"| {(s - t0) / 1e3:.1f} | {(e - s) / 1e3:.1f} | {k} | `{n[:90]}` |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -135,8 +161,15 @@ def main(argv=None):
     c.add_argument("dir")
     c.add_argument("kernel")
     c.add_argument("--cells", type=float, required=True)
+    t = sub.add_parser("timeline")
+    t.add_argument("dir")
+    t.add_argument("kernel")
+    t.add_argument("--index", type=int, default=-3)
+    t.add_argument("--after", type=int, default=12)
     args = ap.parse_args(argv)
-    if args.cmd == "stats":
+    if args.cmd == "timeline":
+        print(timeline(args.dir, args.kernel, args.index, args.after))
+    elif args.cmd == "stats":
         print(stats(args.dir, args.top))
     elif args.cmd == "valu":
         v = valu(args.dir, args.kernel, args.cells)
