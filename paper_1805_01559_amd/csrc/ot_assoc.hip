@@ -530,18 +530,14 @@ struct Solver {
         }
     }
 
-    template <class Src>
-    ot_status run_check(const Src& src, int k, Ctl& out) {
-        return run_check_then(src, k, out, [] {});
-    }
-    // the check, then `after` (work that the host would otherwise issue once
-    // this wait is over), then one wait
-    // With h->want_loads (and a narrow enough J) the check also sums the RRH
+    // The exact check of the iterate in buffers k & 1, then one wait. With
+    // h->want_loads (and a narrow enough J) the check also sums the RRH
     // loads of the potentials it checks into h->loads; their partials take
     // the second half of the column-partial block, so the grid is capped at
-    // half of its rows.
-    template <class Src, class After>
-    ot_status run_check_then(const Src& src, int k, Ctl& out, After after) {
+    // half of its rows. A plan buffer named by ot_assoc_set_plan_output is
+    // written by the same pass when it holds I x J.
+    template <class Src>
+    ot_status run_check(const Src& src, int k, Ctl& out) {
         Shape cs = row64(shape64, J);
         const bool fuse = h->want_loads && check_fuses_loads(cs);
         if (fuse && 2 * cs.nb > kMaxNb) {
@@ -567,7 +563,6 @@ struct Solver {
                            (const double*)h->cpart, ncb, h->ctl, (const SolveParams*)h->prm);
         h->loads_fresh = fuse;
         h->plan_fresh = A.plan_out != nullptr;
-        after();
         ot_status st = snapshot(0);
         if (st || (st = wait(0))) return st;
         out = h->ctl_h[0];
