@@ -8,7 +8,7 @@ written to HBM. The cost matrix is materialised once on the device before the
 timed region (it is the solve's input); the same solve with the cost
 regenerated on the fly from positions is reported beside it.
 
-Prints one JSON line. With --gpus N > 1 it exits: this build runs on one GPU.
+Prints one JSON line. With --gpus N > 1 it exits: the solver runs on one GPU.
 """
 
 from __future__ import annotations
@@ -600,8 +600,8 @@ def main():
                     help="run one leg (for profiling): main = the 20000x400 solve and its sweep")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU execution is not part of this build",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): each solve runs on one device and "
+              "multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
