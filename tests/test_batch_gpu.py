@@ -123,7 +123,7 @@ def test_batch_input_kinds(A, oracle_lib, inst):
             f, g = s.batch_potentials(q)
             if k in (6, 7):
                 # rates / geometry: the batch rounds its own FP64 cost to FP32;
-                # judge it against the oracle's FP64 cost at the FP32 bar
+                # check it against the oracle's FP64 cost at the FP32 bar
                 x = inst[k]
                 chk = oracle_lib.plan_stats(x["C64"], x["L"].a, x["L"].b, f, g, EPS)
                 ref = oracle_lib.sinkhorn(x["C64"], x["L"].a, x["L"].b, EPS, 1e-12, 20000)

@@ -1,6 +1,7 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
 
-Tolerances (targets of the FP32 path, derived in the design doc):
+Tolerances (targets of the FP32 path: FP32 exponentials feed FP64 sums and
+an FP64 polish, so what remains is the stop rule's tol):
 * marginal violation of the returned plan < tol (1e-8 / 1e-9 here), both as
   the library reports it and as the oracle recomputes it from the library's
   potentials with its own cost;
