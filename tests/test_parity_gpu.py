@@ -351,15 +351,16 @@ def test_dense_row_padded_matrix(A, oracle_lib, torch_mod, where):
 
 @pytest.mark.parametrize("kind,I,J,persistent,tol", [
     ("dense", 1000, 50, 1, 1e-9), ("dense", 1000, 50, 0, 1e-11), ("dense", 777, 1031, 1, 1e-8),
-    ("geometry", 2000, 120, 1, 1e-9), ("geometry", 1500, 600, 0, 1e-8)])
+    ("geometry", 2000, 120, 1, 1e-9), ("geometry", 1500, 600, 0, 1e-8), ("euclid", 1800, 90, 1, 1e-9)])
 def test_plan_written_by_the_final_check(A, oracle_lib, torch_mod, kind, I, J, persistent, tol):
     """A plan asked for before the solve (ot_assoc_set_plan_output) is written
     by the final exact check from the cells it computes: against the plan
     pass over the same potentials (FP64 within a few ulps of its FP64
     exponentials, FP32 equal up to one ulp) and against the oracle's plan of
-    those potentials (1e-12; for geometry costs on the entries above 1e-12 of
-    the largest, as the two sides' FP64 costs differ by ulps that an exponent
-    of a few hundred amplifies in the tiny ones). tol 1e-11 makes the check
+    those potentials (1e-12; for costs regenerated from positions, geometry
+    and distance, on the entries above 1e-12 of the largest, as the two
+    sides' FP64 costs differ by ulps that an exponent of a few hundred
+    amplifies in the tiny ones). tol 1e-11 makes the check
     miss on the FP32 path and run the FP64 phase and a second check, whose
     plan must be the one left. A buffer smaller than I x J is not written."""
     torch = torch_mod
@@ -376,6 +377,11 @@ def test_plan_written_by_the_final_check(A, oracle_lib, torch_mod, kind, I, J, p
             Cq = C32.astype(np.float64)
             Cd = torch.from_numpy(C32).to(dev)
             solve = lambda: s.solve_dense(Cd, a, b, eps, tol, 20000)
+        elif kind == "euclid":
+            xy = torch.from_numpy(L.dev_xy).to(dev)
+            rxy = torch.from_numpy(L.rrh_xy).to(dev)
+            Cq, scale = oracle_lib.distance_cost(L, 0.0)
+            solve = lambda: s.solve_euclid(xy, rxy, scale, a, b, eps, tol, 20000)
         else:
             xy = torch.from_numpy(L.dev_xy).to(dev)
             rxy = torch.from_numpy(L.rrh_xy).to(dev)
@@ -398,10 +404,11 @@ def test_plan_written_by_the_final_check(A, oracle_lib, torch_mod, kind, I, J, p
                 np.testing.assert_allclose(P, Q, rtol=4e-15, atol=1e-300)
                 f, g = s.potentials()
                 R = oracle_lib.plan(Cq, f, g, eps)
-                # (geometry: the two sides' FP64 costs differ by ulps, which an
-                # exponent of a few hundred carries into the tiny entries; the
-                # entries that carry mass are held to 1e-12)
-                m = R > 1e-12 * R.max() if kind == "geometry" else np.ones(R.shape, bool)
+                # (costs regenerated from positions: the two sides' FP64 costs
+                # differ by ulps, which an exponent of a few hundred carries
+                # into the tiny entries; the entries that carry mass are held
+                # to 1e-12)
+                m = R > 1e-12 * R.max() if kind != "dense" else np.ones(R.shape, bool)
                 np.testing.assert_allclose(P[m], R[m], rtol=1e-12, atol=1e-300)
             else:
                 assert (np.abs(P - Q) <= np.spacing(np.maximum(np.abs(P), np.abs(Q))) * 1.0 + 1e-45).all()

@@ -78,7 +78,7 @@ def test_snapshots_against_oracle(A, oracle_lib, I, J, B):
         assert st0["marginal_violation"] < 1e-3
 
 
-@pytest.mark.parametrize("I,J,B", [(1500, 60, 8), (2048, 130, 17)])
+@pytest.mark.parametrize("I,J,B", [(1500, 60, 8), (2048, 130, 17), (1200, 613, 5)])
 def test_snapshots_single_bf16_kernel(A, oracle_lib, I, J, B):
     """The option that holds the kernel in BF16 alone (snapshot_k_split 0:
     two products per GEMM step, half the kernel bytes): each snapshot within
