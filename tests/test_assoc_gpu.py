@@ -188,24 +188,34 @@ def test_adaptive_sinkhorn_against_oracle(A, oracle_lib, I, J, seed):
     assert r.max_load <= r.first_max_load
 
 
-@pytest.mark.parametrize("I,J,seed,persistent", [(3000, 400, 6363, 1), (2500, 600, 6464, 1), (3000, 400, 6565, 0),
-                                                  (20000, 100, 6666, 1)])
-def test_adaptive_loads_from_the_final_check(A, oracle_lib, I, J, seed, persistent):
+@pytest.mark.parametrize("I,J,seed,persistent,kind", [(3000, 400, 6363, 1, "dense"), (2500, 600, 6464, 1, "dense"),
+                                                       (3000, 400, 6565, 0, "dense"), (20000, 100, 6666, 1, "dense"),
+                                                       (3000, 400, 6767, 1, "geometry")])
+def test_adaptive_loads_from_the_final_check(A, oracle_lib, I, J, seed, persistent, kind):
     """Alg. 2's RRH loads: at J <= 512 the solves' final exact checks sum
     them beside the marginals (the second case, J = 600, takes a pass of
     their own). The returned loads against the oracle's loads of the handle's
     potentials (1e-12), the reported maximum load equal to their maximum,
     and rho_j = kappa load_j exactly. The chunked path (persistent 0) checks
     through the same kernels; at 20000 rows the check's grid is capped at
-    half of the partial rows so that the load partials fit beside them."""
-    announce(f"Alg. 2 loads from the final check, {I} x {J}, persistent={persistent}")
+    half of the partial rows so that the load partials fit beside them. A
+    geometry cost sums its loads from the FP64 functor's costs, against the
+    oracle's own FP64 costs."""
+    announce(f"Alg. 2 loads from the final check, {kind} {I} x {J}, persistent={persistent}")
     L = S.make_layout(I, J, 3000.0, hot_spots=2, hot_share=0.4, seed=seed)
     C64, scale = oracle_lib.cost(L)
     C32 = C64.astype(np.float32)
-    Cq = C32.astype(np.float64)
+    Cq = C32.astype(np.float64) if kind == "dense" else C64
     eps, tol, cap = 0.05, 1e-9, (3 if I < 10000 else 2)
     with A.Solver(I, J, persistent=persistent) as s:
-        st, q, js, r = s.adaptive(*A.matrix_desc(C32, A.OT_COST_DENSE), L.a, eps, tol, 20000, 0.0, cap)
+        if kind == "dense":
+            desc, a_in = A.matrix_desc(C32, A.OT_COST_DENSE), L.a
+        else:  # (Alg. 2 takes positions in device memory)
+            import torch
+            dev = torch.device("cuda:0")
+            xy, rxy = torch.from_numpy(L.dev_xy).to(dev), torch.from_numpy(L.rrh_xy).to(dev)
+            desc, a_in = A.geometry_desc(xy, rxy, L.radio, L.shadow_key, scale), torch.from_numpy(L.a).to(dev)
+        st, q, js, r = s.adaptive(*desc, a_in, eps, tol, 20000, 0.0, cap)
         assert st == A.OT_OK
         loads = s.rrh_loads()
         f, g = s.potentials()
