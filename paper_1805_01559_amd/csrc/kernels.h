@@ -541,6 +541,40 @@ struct CheckJob {
     void* plan_out = nullptr;    // I x J row-major plan of PlanT (with PlanT not void)
 };
 
+// Stores VEC consecutive plan values of one lane: as 16-byte (or 8-byte)
+// vector stores when `whole` (the VEC columns lie below J and the address is
+// aligned to the vector), else one by one for the columns below J.
+template <typename T, int VEC>
+__device__ __forceinline__ void store_plan(T* dst, const T (&v)[VEC], bool whole, int nvalid) {
+    if (whole) {
+        if constexpr (sizeof(T) == 4 && VEC == 4) {
+            *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+            return;
+        } else if constexpr (sizeof(T) == 4 && VEC == 2) {
+            *reinterpret_cast<float2*>(dst) = make_float2(v[0], v[1]);
+            return;
+        } else if constexpr (sizeof(T) == 8 && VEC == 4) {
+            reinterpret_cast<double2*>(dst)[0] = make_double2(v[0], v[1]);
+            reinterpret_cast<double2*>(dst)[1] = make_double2(v[2], v[3]);
+            return;
+        } else if constexpr (sizeof(T) == 8 && VEC == 2) {
+            *reinterpret_cast<double2*>(dst) = make_double2(v[0], v[1]);
+            return;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+        if (q < nvalid) dst[q] = v[q];
+}
+
+// True when rows of J values of T starting at `base` keep every lane's VEC
+// values aligned to the vector store of store_plan.
+template <typename T, int VEC>
+__device__ __forceinline__ bool plan_rows_aligned(const void* base, int J) {
+    constexpr int a = (int)sizeof(T) * VEC >= 16 ? 16 : (int)sizeof(T) * VEC;
+    return J % VEC == 0 && (reinterpret_cast<uintptr_t>(base) % (uintptr_t)a) == 0;
+}
+
 template <class Src, int VEC, int NCH, int WAVES, bool LOADS = false, typename PlanT = void>
 __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
     constexpr bool kPlan = !std::is_void<PlanT>::value;
@@ -569,6 +603,8 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
         for (int v = 0; v < VEC; ++v) acc[ch][v] = accl[ch][v] = 0.0;
     double st[5] = {0, 0, 0, 0, 0};  // rowres, cost, ent, mass, fa (lane 0 of each wave)
     double cost = 0.0, ent = 0.0;     // this lane's cells of <C, pi> and sum pi (log pi - 1)
+    bool plan_vec = false;            // the plan's rows take vector stores
+    if constexpr (kPlan) plan_vec = plan_rows_aligned<PlanT, VEC>(A.plan_out, J);
     // The loads of a row (its costs, f_i and a_i) are issued one row ahead,
     // so that a wave waits for memory only when a row's arithmetic is shorter
     // than the load latency.
@@ -598,6 +634,7 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
         for (int ch = 0; ch < NCH; ++ch) {
             if (ch < nch) {
                 const int col0 = (ch * kWave + lane) * VEC;
+                PlanS pv[VEC];
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
                     // a column past J adds exact zeros (p = 0, c = 0), which
@@ -612,10 +649,9 @@ __device__ __forceinline__ void check_rows(const CheckJob& A, const Src& src) {
                     ent = fma(p, t * kLn2 - 1.0, ent);
                     acc[ch][v] += p;
                     if constexpr (LOADS) accl[ch][v] = fma(c, p, accl[ch][v]);
-                    if constexpr (kPlan) {
-                        if (ok) prow[col0 + v] = (PlanS)p;
-                    }
+                    pv[v] = (PlanS)p;
                 }
+                if constexpr (kPlan) store_plan<PlanS, VEC>(prow + col0, pv, plan_vec && col0 + VEC <= J, J - col0);
             }
         }
         rs = wave_sum(rs);
